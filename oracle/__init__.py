@@ -1,0 +1,16 @@
+"""CPU oracle for the fast bilinear matrix product.
+
+TEST INFRASTRUCTURE ONLY: a plain, slow, obviously correct implementation
+used by the tests, by the smoke check and by the CPU-baseline leg of the
+benchmark to judge the HIP path.  The product library never imports, links
+or calls anything in this package, and this package shares no code with it.
+
+Parity status: every function here is pinned by not-gpu tests against facts
+fixed by the paper or by mathematics (the paper's worked example, Brent
+equations, the textbook product, brute force on tiny inputs, closed forms,
+planted mistakes).  No function is parity-unpinned.
+"""
+from .algebra import (Algo, brent_violations, canonical, classical_algo, compose, power,  # noqa: F401
+                      rebase, single_coefficient_columns, transpose_index)
+from .matmul import (classical_mm, componentwise_error, fast_mm, fast_mm_divisible,  # noqa: F401
+                     flops, levels_taken, max_scaled_error, rel_fro_error, rows_reference)

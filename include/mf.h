@@ -1,0 +1,147 @@
+/*
+ * mf.h - C ABI of the fast bilinear matrix-multiplication library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The library executes a fast algorithm <n0,n0,n0;R>, given by its factor
+ * matrices U, V, W, on square row-major matrices: C = A B with A, B, C of
+ * size n x n.  With the split factor p the operands are partitioned into
+ * p x p blocks numbered row-major (A_k, k = i*p + j; the partition equations
+ * of Section 2 of D'Alberto, "Strassen's Matrix Multiplication Algorithm Is
+ * Still Faster", arXiv 2312.12732) and the algorithm computes (equation
+ * "strassen" of Section 2)
+ *
+ *     T_r = sum_k U[k,r] A_k,   S_r = sum_l V[l,r] B_l,   P_r = T_r S_r,
+ *     C_c = sum_r W[c,r] P_r,                             r = 0..R-1.
+ *
+ * Execution is a data flow of three phases on the caller's HIP stream:
+ * pre-additions (linear combinations of operand blocks), R block products
+ * (GEMM) and post-additions (fused into the GEMM epilogue).  Recursion to
+ * depth d is executed as one level of the composed algorithm of split factor
+ * p^d (the Kronecker construction of Section 2).
+ *
+ * Conventions for every entry point:
+ *  - Device pointers are HIP device allocations; host pointers are ordinary
+ *    host memory.  The library never takes ownership of caller memory.
+ *  - Matrices are dense, row-major, contiguous (leading dimension n), with
+ *    at least 8-byte alignment.  C must not overlap A or B (MF_ERR_ARG).
+ *  - `stream` is a hipStream_t passed as a pointer; NULL means the default
+ *    stream.  Calls are asynchronous with respect to the host: launch errors
+ *    are returned as MF_ERR_HIP; faults surface at the caller's
+ *    synchronisation.
+ *  - Every entry point returns an mf_status; on error mf_last_error() gives a
+ *    message for the calling thread.  Nothing aborts or throws across the
+ *    ABI.
+ *  - An mf_algo is immutable once created and may be shared between threads
+ *    and streams.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mf_algo mf_algo;
+typedef void* mf_stream; /* a hipStream_t */
+
+typedef enum {
+  MF_OK = 0,
+  MF_ERR_ARG = -1,         /* invalid argument (null, negative size, overlap, unknown code) */
+  MF_ERR_BRENT = -2,       /* U, V, W do not define a correct product algorithm */
+  MF_ERR_SHAPE = -3,       /* sizes inconsistent with the algorithm or the workspace */
+  MF_ERR_NOMEM = -4,       /* device or host allocation failed */
+  MF_ERR_HIP = -5,         /* a HIP runtime call or kernel launch failed */
+  MF_ERR_UNSUPPORTED = -6  /* valid request that this build does not implement */
+} mf_status;
+
+/* Element type of A, B, C (low byte) and precision of the leaf products
+ * (second byte).  Pre- and post-additions always run in the storage type. */
+enum {
+  MF_F64 = 1,               /* double storage */
+  MF_F32 = 2,               /* float storage */
+  MF_LEAF_NATIVE = 0 << 8,  /* leaves in the storage type (FP64 or FP32 MFMA) */
+  MF_LEAF_F32 = 1 << 8,     /* FP32 MFMA leaves (FP32 storage only) */
+  MF_LEAF_BF16 = 2 << 8,    /* BF16 MFMA, FP32 accumulation (FP32 storage only) */
+  MF_LEAF_BF16X3 = 3 << 8   /* split-BF16 x3 compensated products, FP32 accumulation (FP32 storage only) */
+};
+
+/* Row convention of W handed to mf_algo_from_uvw. */
+enum {
+  MF_W_ROWMAJOR_C = 0,  /* row c of W gives the coefficients of C_c (c = i*n0 + j) */
+  MF_W_DEEPMIND_CT = 1  /* row t gives the coefficients of the C block with the transposed
+                           2-d index, as in the c^t matrix printed in Section 2 (rows
+                           labelled C_0, C_2, C_1, C_3 for n0 = 2) */
+};
+
+/* Build an algorithm from host arrays U, V, W, each n0*n0 x R, row-major
+ * (entry [k*R + r]).  Coefficients are real; integer coefficients are checked
+ * exactly.  The Brent equations (sum_r U[a,r] V[b,r] W[c,r] equals 1 when the
+ * blocks a = (i,k), b = (k,j), c = (i,j) match and 0 otherwise; Section 2,
+ * "prove them correct") are verified for all n0^6 index triples; a failure
+ * returns MF_ERR_BRENT and no handle.  1 <= n0 <= 8, 1 <= R <= 4096.  The
+ * caller owns *out and releases it with mf_algo_free. */
+mf_status mf_algo_from_uvw(int n0, int R, const double* U, const double* V, const double* W,
+                           int w_convention, mf_algo** out);
+
+/* Built-in algorithms: "strassen" (the paper's printed form), "winograd"
+ * (Strassen-Winograd), "strassen1969", "classical2", "classical3"
+ * (the textbook <p,p,p;p^3> of equation "recursion"). */
+mf_status mf_algo_builtin(const char* name, mf_algo** out);
+
+/* Compose: apply `outer` first and `inner` to each of its products
+ * (Kronecker construction of Section 2); split factor n0_outer*n0_inner,
+ * R_outer*R_inner products.  The result is Brent-checked. */
+mf_status mf_algo_compose(const mf_algo* outer, const mf_algo* inner, mf_algo** out);
+
+/* Re-base by integer n0 x n0 matrices X, Y, Z with determinant +-1 (host,
+ * row-major int64): the algorithm applied to X A Y^-1 and Y B Z^-1 yields
+ * U'_r = X^T U_r Y^-T, V'_r = Y^T V_r Z^-T, W'_r = X^-1 W_r Z (U_r = column r
+ * of U as an n0 x n0 matrix).  MF_ERR_ARG if a matrix is not unimodular. */
+mf_status mf_algo_rebase(const mf_algo* a, const int64_t* X, const int64_t* Y, const int64_t* Z,
+                         mf_algo** out);
+
+/* Shape and sparsity of an algorithm (any output pointer may be NULL). */
+mf_status mf_algo_info(const mf_algo* a, int* n0, int* R, int* nnz_u, int* nnz_v, int* nnz_w);
+
+/* Copy the canonical coefficients (W rows index C row-major) into host arrays
+ * of n0*n0*R doubles each (any pointer may be NULL). */
+mf_status mf_algo_get_uvw(const mf_algo* a, double* U, double* V, double* W);
+
+/* Release an algorithm (NULL is ignored). */
+void mf_algo_free(mf_algo* a);
+
+/* C = A B with `depth` levels of `algo`.  A level is taken while levels
+ * remain and the current size exceeds `cutoff`; depth 0 (or cutoff >= n) is
+ * the classical product.  Sizes that the split factor does not divide are
+ * handled by virtual zero padding (no copy of A, B or C).  Temporaries come
+ * from a stream-ordered pool owned by the library.  A, B, C: device
+ * pointers to n x n matrices of the storage type of `dtype`. */
+mf_status mf_fastmm(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C,
+                    int64_t n, int dtype, mf_stream stream);
+
+/* C = A B by the library's own MFMA GEMM (no fast algorithm). */
+mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int dtype, mf_stream stream);
+
+/* Bytes of device workspace mf_fastmm_ws needs for this request (0 for a
+ * classical product). */
+mf_status mf_workspace_bytes(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
+                             size_t* bytes);
+
+/* As mf_fastmm, with caller-owned device workspace of ws_bytes bytes
+ * (256-byte aligned; MF_ERR_SHAPE if smaller than mf_workspace_bytes).  The
+ * workspace must not be used by other work until the call has completed on
+ * `stream`. */
+mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C,
+                       int64_t n, int dtype, void* workspace, size_t ws_bytes, mf_stream stream);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* mf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MF_H */

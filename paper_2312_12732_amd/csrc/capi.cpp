@@ -1,0 +1,265 @@
+// C ABI of the mf library: argument validation, algorithm handles, plan
+// lookup, workspace and the launch sequence of one fast product.
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "mf_internal.h"
+
+namespace mf {
+
+namespace {
+thread_local std::string t_err;
+std::atomic<uint64_t> g_next_id{1};
+}  // namespace
+
+mf_status fail(mf_status st, const std::string& msg) {
+  t_err = msg;
+  return st;
+}
+void clear_error() { t_err.clear(); }
+
+namespace {
+
+constexpr int64_t kMaxN = 1 << 20;
+
+// Fused split factors with a compiled pre-addition kernel.
+bool fused_supported(int P) { return P == 1 || P == 2 || P == 3 || P == 4 || P == 6 || P == 8 || P == 9; }
+
+mf_status new_handle(const Algo& a, mf_algo** out) {
+  const int64_t bad = brent_violations(a);
+  if (bad != 0)
+    return fail(MF_ERR_BRENT, "the Brent equations fail for " + std::to_string(bad) + " index triples");
+  mf_algo* h = new (std::nothrow) mf_algo;
+  if (!h) return fail(MF_ERR_NOMEM, "host allocation failed");
+  h->a = a;
+  h->id = g_next_id.fetch_add(1);
+  *out = h;
+  return MF_OK;
+}
+
+bool overlaps(const void* x, const void* y, size_t bytes) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(x), b = reinterpret_cast<uintptr_t>(y);
+  return a < b + bytes && b < a + bytes;
+}
+
+mf_status check_request(const mf_algo* algo, bool need_algo, int depth, int cutoff, const void* A,
+                        const void* B, void* C, int64_t n, int dtype) {
+  if (need_algo && !algo) return fail(MF_ERR_ARG, "algo is NULL");
+  if (depth < 0) return fail(MF_ERR_ARG, "depth must be >= 0");
+  if (cutoff < 0) return fail(MF_ERR_ARG, "cutoff must be >= 0");
+  if (n < 0) return fail(MF_ERR_ARG, "n must be >= 0");
+  if (n > kMaxN) return fail(MF_ERR_SHAPE, "n exceeds the supported maximum (2^20)");
+  const int storage = dtype & 0xff, leaf = (dtype >> 8) & 0xff;
+  if ((dtype & ~0xffff) != 0 || (storage != MF_F64 && storage != MF_F32) || leaf > 3)
+    return fail(MF_ERR_ARG, "unknown dtype code");
+  if (storage == MF_F64 && leaf != 0)
+    return fail(MF_ERR_UNSUPPORTED, "reduced-precision leaves need FP32 storage");
+  if (storage == MF_F32) return fail(MF_ERR_UNSUPPORTED, "FP32 storage is not implemented in this build");
+  if (n == 0) return MF_OK;
+  if (!A || !B || !C) return fail(MF_ERR_ARG, "A, B and C must be non-NULL");
+  const size_t elem = storage == MF_F64 ? 8 : 4;
+  const uintptr_t mask = elem - 1;
+  if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(C)) & mask)
+    return fail(MF_ERR_ARG, "A, B and C must be aligned to the element size");
+  const size_t bytes = (size_t)n * (size_t)n * elem;
+  if (overlaps(C, A, bytes) || overlaps(C, B, bytes)) return fail(MF_ERR_ARG, "C overlaps A or B");
+  return MF_OK;
+}
+
+mf_status plan_for(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
+                   std::shared_ptr<const Plan>* pl) {
+  if (algo && depth > 0) {
+    int P = 1, d = 0;
+    int64_t size = n;
+    while (d < depth && size > cutoff && algo->a.p > 1) {
+      size = (size + algo->a.p - 1) / algo->a.p;
+      P *= algo->a.p;
+      ++d;
+      if (P > 9) break;
+    }
+    if (!fused_supported(P))
+      return fail(MF_ERR_UNSUPPORTED, "fused split factor " + std::to_string(P) + " has no pre-addition kernel");
+  }
+  return get_plan(depth > 0 ? algo : nullptr, depth, cutoff, n, dtype, pl);
+}
+
+mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, hipStream_t s) {
+  mf_status st = ensure_device(pl);
+  if (st != MF_OK) return st;
+  const bool vec_in = (pl.n % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0;
+  hipError_t e = launch_preadd_f64(pl, A, B, ws, vec_in, s);
+  if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("pre-addition launch: ") + hipGetErrorString(e));
+  e = launch_gemm_f64(pl, A, B, C, ws, vec_in, s);
+  if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("GEMM launch: ") + hipGetErrorString(e));
+  return MF_OK;
+}
+
+}  // namespace
+}  // namespace mf
+
+using namespace mf;
+
+extern "C" {
+
+const char* mf_last_error(void) { return t_err.c_str(); }
+
+mf_status mf_algo_from_uvw(int n0, int R, const double* U, const double* V, const double* W, int w_convention,
+                           mf_algo** out) {
+  clear_error();
+  if (!out) return fail(MF_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n0 < 1 || n0 > 8) return fail(MF_ERR_ARG, "n0 must be in [1, 8]");
+  if (R < 1 || R > 4096) return fail(MF_ERR_ARG, "R must be in [1, 4096]");
+  if (!U || !V || !W) return fail(MF_ERR_ARG, "U, V and W must be non-NULL");
+  if (w_convention != MF_W_ROWMAJOR_C && w_convention != MF_W_DEEPMIND_CT)
+    return fail(MF_ERR_ARG, "unknown W convention");
+  const int P2 = n0 * n0;
+  const size_t cnt = (size_t)P2 * R;
+  for (size_t i = 0; i < cnt; ++i)
+    if (!std::isfinite(U[i]) || !std::isfinite(V[i]) || !std::isfinite(W[i]))
+      return fail(MF_ERR_ARG, "coefficients must be finite");
+  Algo a;
+  a.p = n0;
+  a.R = R;
+  a.U.assign(U, U + cnt);
+  a.V.assign(V, V + cnt);
+  a.W.assign((size_t)P2 * R, 0.0);
+  for (int t = 0; t < P2; ++t) {
+    // DeepMind-style rows index C transposed: row t = (x, y) belongs to C_(y, x).
+    const int c = w_convention == MF_W_DEEPMIND_CT ? (t % n0) * n0 + (t / n0) : t;
+    memcpy(&a.W[(size_t)c * R], &W[(size_t)t * R], sizeof(double) * R);
+  }
+  return new_handle(a, out);
+}
+
+mf_status mf_algo_builtin(const char* name, mf_algo** out) {
+  clear_error();
+  if (!out || !name) return fail(MF_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  Algo a;
+  if (!builtin(name, &a)) return fail(MF_ERR_ARG, std::string("unknown built-in algorithm: ") + name);
+  return new_handle(a, out);
+}
+
+mf_status mf_algo_compose(const mf_algo* outer, const mf_algo* inner, mf_algo** out) {
+  clear_error();
+  if (!outer || !inner || !out) return fail(MF_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  if (outer->a.p * inner->a.p > 8) return fail(MF_ERR_ARG, "composed split factor must be <= 8");
+  if ((int64_t)outer->a.R * inner->a.R > 4096) return fail(MF_ERR_ARG, "composed R must be <= 4096");
+  return new_handle(compose(outer->a, inner->a), out);
+}
+
+mf_status mf_algo_rebase(const mf_algo* a, const int64_t* X, const int64_t* Y, const int64_t* Z, mf_algo** out) {
+  clear_error();
+  if (!a || !X || !Y || !Z || !out) return fail(MF_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  Algo b;
+  if (!rebase(a->a, X, Y, Z, &b)) return fail(MF_ERR_ARG, "X, Y and Z must be unimodular integer matrices");
+  return new_handle(b, out);
+}
+
+mf_status mf_algo_info(const mf_algo* a, int* n0, int* R, int* nnz_u, int* nnz_v, int* nnz_w) {
+  clear_error();
+  if (!a) return fail(MF_ERR_ARG, "algo is NULL");
+  auto nnz = [](const std::vector<double>& x) {
+    int c = 0;
+    for (double v : x) c += v != 0.0;
+    return c;
+  };
+  if (n0) *n0 = a->a.p;
+  if (R) *R = a->a.R;
+  if (nnz_u) *nnz_u = nnz(a->a.U);
+  if (nnz_v) *nnz_v = nnz(a->a.V);
+  if (nnz_w) *nnz_w = nnz(a->a.W);
+  return MF_OK;
+}
+
+mf_status mf_algo_get_uvw(const mf_algo* a, double* U, double* V, double* W) {
+  clear_error();
+  if (!a) return fail(MF_ERR_ARG, "algo is NULL");
+  const size_t cnt = a->a.U.size();
+  if (U) memcpy(U, a->a.U.data(), cnt * sizeof(double));
+  if (V) memcpy(V, a->a.V.data(), cnt * sizeof(double));
+  if (W) memcpy(W, a->a.W.data(), cnt * sizeof(double));
+  return MF_OK;
+}
+
+void mf_algo_free(mf_algo* a) {
+  if (!a) return;
+  drop_plans(a->id);
+  delete a;
+}
+
+mf_status mf_workspace_bytes(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, size_t* bytes) {
+  clear_error();
+  if (!bytes) return fail(MF_ERR_ARG, "bytes is NULL");
+  *bytes = 0;
+  // Validate everything except the pointers.
+  static const double dummy[3] = {0, 0, 0};
+  mf_status st = check_request(algo, true, depth, cutoff, &dummy[0], &dummy[1], (void*)&dummy[2], 0, dtype);
+  if (st != MF_OK) return st;
+  if (n < 0) return fail(MF_ERR_ARG, "n must be >= 0");
+  if (n > kMaxN) return fail(MF_ERR_SHAPE, "n exceeds the supported maximum (2^20)");
+  if (n == 0) return MF_OK;
+  std::shared_ptr<const Plan> pl;
+  st = plan_for(algo, depth, cutoff, n, dtype, &pl);
+  if (st != MF_OK) return st;
+  *bytes = pl->ws_bytes;
+  return MF_OK;
+}
+
+mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C,
+                       int64_t n, int dtype, void* workspace, size_t ws_bytes, mf_stream stream) {
+  clear_error();
+  mf_status st = check_request(algo, true, depth, cutoff, A, B, C, n, dtype);
+  if (st != MF_OK || n == 0) return st;
+  std::shared_ptr<const Plan> pl;
+  st = plan_for(algo, depth, cutoff, n, dtype, &pl);
+  if (st != MF_OK) return st;
+  if (pl->ws_bytes > 0) {
+    if (!workspace) return fail(MF_ERR_ARG, "workspace is NULL");
+    if (ws_bytes < pl->ws_bytes) return fail(MF_ERR_SHAPE, "workspace too small");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(MF_ERR_ARG, "workspace must be 256-byte aligned");
+  }
+  return run(*pl, A, B, C, workspace, static_cast<hipStream_t>(stream));
+}
+
+mf_status mf_fastmm(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C, int64_t n,
+                    int dtype, mf_stream stream) {
+  clear_error();
+  mf_status st = check_request(algo, true, depth, cutoff, A, B, C, n, dtype);
+  if (st != MF_OK || n == 0) return st;
+  std::shared_ptr<const Plan> pl;
+  st = plan_for(algo, depth, cutoff, n, dtype, &pl);
+  if (st != MF_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  if (pl->ws_bytes > 0) {
+    hipError_t e = hipMallocAsync(&ws, pl->ws_bytes, s);
+    if (e != hipSuccess || !ws) {
+      (void)hipGetLastError();
+      return fail(MF_ERR_NOMEM, "workspace allocation of " + std::to_string(pl->ws_bytes) + " bytes failed");
+    }
+  }
+  st = run(*pl, A, B, C, ws, s);
+  if (ws) {
+    hipError_t e = hipFreeAsync(ws, s);
+    if (e != hipSuccess && st == MF_OK) st = fail(MF_ERR_HIP, "workspace release failed");
+  }
+  return st;
+}
+
+mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int dtype, mf_stream stream) {
+  clear_error();
+  mf_status st = check_request(nullptr, false, 0, 0, A, B, C, n, dtype);
+  if (st != MF_OK || n == 0) return st;
+  std::shared_ptr<const Plan> pl;
+  st = get_plan(nullptr, 0, 0, n, dtype, &pl);
+  if (st != MF_OK) return st;
+  return run(*pl, A, B, C, nullptr, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,215 @@
+"""Thin ctypes binding of the mf C ABI (include/mf.h).
+
+Argument marshalling only: every step of a product runs in libmf.so's HIP
+kernels.  Torch is used for device memory (``tensor.data_ptr()``) and streams
+(``torch.cuda.current_stream().cuda_stream``).  If the library is missing the
+import fails; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmf.so")
+
+MF_OK = 0
+MF_ERR_ARG = -1
+MF_ERR_BRENT = -2
+MF_ERR_SHAPE = -3
+MF_ERR_NOMEM = -4
+MF_ERR_HIP = -5
+MF_ERR_UNSUPPORTED = -6
+STATUS_NAMES = {0: "MF_OK", -1: "MF_ERR_ARG", -2: "MF_ERR_BRENT", -3: "MF_ERR_SHAPE", -4: "MF_ERR_NOMEM",
+                -5: "MF_ERR_HIP", -6: "MF_ERR_UNSUPPORTED"}
+
+MF_F64 = 1
+MF_F32 = 2
+MF_LEAF_NATIVE = 0 << 8
+MF_LEAF_F32 = 1 << 8
+MF_LEAF_BF16 = 2 << 8
+MF_LEAF_BF16X3 = 3 << 8
+MF_W_ROWMAJOR_C = 0
+MF_W_DEEPMIND_CT = 1
+
+EXPORTED = ["mf_algo_from_uvw", "mf_algo_builtin", "mf_algo_compose", "mf_algo_rebase", "mf_algo_info",
+            "mf_algo_get_uvw", "mf_algo_free", "mf_fastmm", "mf_classical_mm", "mf_workspace_bytes",
+            "mf_fastmm_ws", "mf_last_error"]
+
+
+class MFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_12732_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    I64 = ctypes.c_int64
+    DP = ctypes.POINTER(ctypes.c_double)
+    LP = ctypes.POINTER(ctypes.c_int64)
+    AP = ctypes.POINTER(P)
+    sig = {
+        "mf_algo_from_uvw": ([I, I, DP, DP, DP, I, AP], I),
+        "mf_algo_builtin": ([ctypes.c_char_p, AP], I),
+        "mf_algo_compose": ([P, P, AP], I),
+        "mf_algo_rebase": ([P, LP, LP, LP, AP], I),
+        "mf_algo_info": ([P] + [ctypes.POINTER(I)] * 5, I),
+        "mf_algo_get_uvw": ([P, DP, DP, DP], I),
+        "mf_algo_free": ([P], None),
+        "mf_fastmm": ([P, I, I, P, P, P, I64, I, P], I),
+        "mf_classical_mm": ([P, P, P, I64, I, P], I),
+        "mf_workspace_bytes": ([P, I, I, I64, I, ctypes.POINTER(ctypes.c_size_t)], I),
+        "mf_fastmm_ws": ([P, I, I, P, P, P, I64, I, P, ctypes.c_size_t, P], I),
+        "mf_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(st: int):
+    if st != MF_OK:
+        raise MFError(st, lib.mf_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Algo:
+    """Owning wrapper of an mf_algo handle."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        free = getattr(lib, "mf_algo_free", None) if lib is not None else None
+        if h is not None and h.value and free is not None:
+            free(h)
+            self._h = ctypes.c_void_p(0)
+
+    def info(self):
+        vals = [ctypes.c_int() for _ in range(5)]
+        _check(lib.mf_algo_info(self._h, *[ctypes.byref(v) for v in vals]))
+        n0, R, nu, nv, nw = (v.value for v in vals)
+        return {"n0": n0, "R": R, "nnz_u": nu, "nnz_v": nv, "nnz_w": nw}
+
+    def uvw(self):
+        inf = self.info()
+        shape = (inf["n0"] ** 2, inf["R"])
+        U, V, W = (np.zeros(shape, dtype=np.float64) for _ in range(3))
+        _check(lib.mf_algo_get_uvw(self._h, _dptr(U), _dptr(V), _dptr(W)))
+        return U, V, W
+
+
+def mf_algo_from_uvw(n0: int, U, V, W, w_convention: int = MF_W_ROWMAJOR_C) -> Algo:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    if U.ndim != 2 or U.shape != V.shape or U.shape != W.shape:
+        raise ValueError("U, V, W must be 2-d arrays of equal shape")
+    out = ctypes.c_void_p()
+    _check(lib.mf_algo_from_uvw(n0, U.shape[1], _dptr(U), _dptr(V), _dptr(W), w_convention, ctypes.byref(out)))
+    return Algo(out.value)
+
+
+def mf_algo_builtin(name: str) -> Algo:
+    out = ctypes.c_void_p()
+    _check(lib.mf_algo_builtin(name.encode(), ctypes.byref(out)))
+    return Algo(out.value)
+
+
+def mf_algo_compose(outer: Algo, inner: Algo) -> Algo:
+    out = ctypes.c_void_p()
+    _check(lib.mf_algo_compose(outer.handle, inner.handle, ctypes.byref(out)))
+    return Algo(out.value)
+
+
+def mf_algo_rebase(a: Algo, X, Y, Z) -> Algo:
+    mats = [np.ascontiguousarray(M, dtype=np.int64) for M in (X, Y, Z)]
+    ptrs = [M.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) for M in mats]
+    out = ctypes.c_void_p()
+    _check(lib.mf_algo_rebase(a.handle, *ptrs, ctypes.byref(out)))
+    return Algo(out.value)
+
+
+def _dtype_code(t, leaf: int) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return MF_F64 | leaf
+    if t.dtype == torch.float32:
+        return MF_F32 | leaf
+    raise TypeError(f"unsupported tensor dtype {t.dtype}")
+
+
+def _check_operands(A, B, C):
+    for name, t in (("A", A), ("B", B), ("C", C)):
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a device tensor")
+        if t.dim() != 2 or t.shape[0] != t.shape[1] or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous square matrix")
+    if not (A.shape == B.shape == C.shape) or not (A.dtype == B.dtype == C.dtype):
+        raise ValueError("A, B, C must have equal shape and dtype")
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def mf_fastmm(algo: Algo, depth: int, cutoff: int, A, B, C, leaf: int = MF_LEAF_NATIVE, stream=None):
+    """C = A B with ``depth`` levels of ``algo`` (torch device tensors)."""
+    _check_operands(A, B, C)
+    _check(lib.mf_fastmm(algo.handle, depth, cutoff, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                         ctypes.c_void_p(C.data_ptr()), A.shape[0], _dtype_code(A, leaf), _stream(stream)))
+    return C
+
+
+def mf_fastmm_ws(algo: Algo, depth: int, cutoff: int, A, B, C, workspace, leaf: int = MF_LEAF_NATIVE,
+                 stream=None):
+    """As mf_fastmm with a caller-owned workspace tensor (any dtype)."""
+    _check_operands(A, B, C)
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib.mf_fastmm_ws(algo.handle, depth, cutoff, ctypes.c_void_p(A.data_ptr()),
+                            ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(C.data_ptr()), A.shape[0],
+                            _dtype_code(A, leaf), ctypes.c_void_p(workspace.data_ptr()), nbytes, _stream(stream)))
+    return C
+
+
+def mf_classical_mm(A, B, C, stream=None):
+    """C = A B with the library's MFMA GEMM."""
+    _check_operands(A, B, C)
+    _check(lib.mf_classical_mm(ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                               ctypes.c_void_p(C.data_ptr()), A.shape[0], _dtype_code(A, 0), _stream(stream)))
+    return C
+
+
+def mf_workspace_bytes(algo: Algo, depth: int, cutoff: int, n: int, dtype_code: int = MF_F64) -> int:
+    out = ctypes.c_size_t()
+    _check(lib.mf_workspace_bytes(algo.handle, depth, cutoff, n, dtype_code, ctypes.byref(out)))
+    return out.value
+
+
+def mf_last_error() -> str:
+    return lib.mf_last_error().decode()

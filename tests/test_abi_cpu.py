@@ -1,0 +1,179 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every declared
+symbol, builds the same algorithms as the oracle (host algebra only) and
+rejects invalid requests before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import mf_inputs as mi
+from oracle import algebra as oa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+mf = pytest.importorskip("paper_2312_12732_amd.mf", reason="libmf.so not built")
+
+
+def declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in os.listdir(inc):
+        if f.endswith(".h"):
+            txt = open(os.path.join(inc, f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(mf_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_symbols()
+    assert "mf_fastmm" in names and "mf_classical_mm" in names and "mf_algo_from_uvw" in names
+    for n in names:
+        assert hasattr(mf.lib, n), n
+    assert set(names) == set(mf.EXPORTED)
+
+
+def oracle_table(t):
+    U, V, W, conv = mi.as_float_tables(t)
+    return oa.canonical(t["n0"], U, V, W, conv)
+
+
+def same(alg_handle, o):
+    U, V, W = alg_handle.uvw()
+    return np.array_equal(U, o.U) and np.array_equal(V, o.V) and np.array_equal(W, o.W)
+
+
+@pytest.mark.parametrize("name,table", [("strassen", mi.STRASSEN_PAPER), ("winograd", mi.WINOGRAD),
+                                        ("strassen1969", mi.STRASSEN_1969)])
+def test_builtins_match_published_tables(name, table):
+    assert same(mf.mf_algo_builtin(name), oracle_table(table))
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_builtin_classical(p):
+    assert same(mf.mf_algo_builtin(f"classical{p}"), oa.classical_algo(p))
+
+
+def test_from_uvw_deepmind_convention():
+    U, V, W, conv = mi.as_float_tables(mi.STRASSEN_PAPER)
+    a = mf.mf_algo_from_uvw(2, U, V, W, conv)
+    assert same(a, oracle_table(mi.STRASSEN_PAPER))
+    assert a.info() == {"n0": 2, "R": 7, "nnz_u": 14, "nnz_v": 14, "nnz_w": 12}
+
+
+def test_from_uvw_rejects_wrong_convention_and_flips():
+    U, V, W, _ = mi.as_float_tables(mi.STRASSEN_PAPER)
+    with pytest.raises(mf.MFError) as e:
+        mf.mf_algo_from_uvw(2, U, V, W, mf.MF_W_ROWMAJOR_C)
+    assert e.value.status == mf.MF_ERR_BRENT
+    U2 = U.copy()
+    U2[1, 3] = -1
+    with pytest.raises(mf.MFError) as e:
+        mf.mf_algo_from_uvw(2, U2, V, W, mf.MF_W_DEEPMIND_CT)
+    assert e.value.status == mf.MF_ERR_BRENT
+
+
+def test_from_uvw_argument_errors():
+    U, V, W, conv = mi.as_float_tables(mi.STRASSEN_PAPER)
+    for bad in (0, 9):
+        with pytest.raises(mf.MFError):
+            mf.mf_algo_from_uvw(bad, U, V, W, conv)
+    with pytest.raises(mf.MFError):
+        mf.mf_algo_from_uvw(2, U, V, W, 7)
+    Un = U.copy()
+    Un[0, 0] = np.nan
+    with pytest.raises(mf.MFError) as e:
+        mf.mf_algo_from_uvw(2, Un, V, W, conv)
+    assert e.value.status == mf.MF_ERR_ARG
+
+
+def test_compose_matches_oracle():
+    s = mf.mf_algo_builtin("winograd")
+    o = oracle_table(mi.WINOGRAD)
+    assert same(mf.mf_algo_compose(s, s), oa.power(o, 2))
+    c3 = mf.mf_algo_builtin("classical3")
+    # split factor 6 > 8 is rejected; 2 x 3 = 6 is allowed
+    assert same(mf.mf_algo_compose(s, c3), oa.compose(o, oa.classical_algo(3)))
+    s2 = mf.mf_algo_compose(s, s)
+    assert same(mf.mf_algo_compose(s2, s), oa.power(o, 3))
+    with pytest.raises(mf.MFError):
+        mf.mf_algo_compose(s2, s2)  # split factor 16
+
+
+@pytest.mark.parametrize("seed", [7, 8, 9])
+def test_rebase_matches_oracle(seed):
+    X, Y, Z = (mi.unimodular(2, seed * 10 + t) for t in range(3))
+    s = mf.mf_algo_builtin("strassen")
+    o = oracle_table(mi.STRASSEN_PAPER)
+    assert same(mf.mf_algo_rebase(s, X, Y, Z), oa.rebase(o, X, Y, Z))
+
+
+def test_rebase_rejects_singular():
+    s = mf.mf_algo_builtin("strassen")
+    I = np.eye(2, dtype=np.int64)
+    with pytest.raises(mf.MFError) as e:
+        mf.mf_algo_rebase(s, 2 * I, I, I)
+    assert e.value.status == mf.MF_ERR_ARG
+
+
+def test_workspace_bytes_closed_form():
+    s = mf.mf_algo_builtin("strassen")
+    # depth 1: 4 materialised T and 4 materialised S of (n/2)^2 doubles
+    assert mf.mf_workspace_bytes(s, 1, 0, 8192) == 8 * 4096 ** 2 * 8
+    # depth 2 (Strassen composed with itself): 40 + 40 blocks of (n/4)^2
+    assert mf.mf_workspace_bytes(s, 2, 0, 8192) == 80 * 2048 ** 2 * 8
+    # depth 3: 316 + 316 blocks of (n/8)^2
+    assert mf.mf_workspace_bytes(s, 3, 0, 8192) == 632 * 1024 ** 2 * 8
+    # ragged: n = 1000, leaf size rounded up to the 128 tile (500 -> 512)
+    assert mf.mf_workspace_bytes(s, 1, 0, 1000) == 8 * 512 ** 2 * 8
+    # classical (depth 0 or cutoff >= n) needs no workspace
+    assert mf.mf_workspace_bytes(s, 0, 0, 8192) == 0
+    assert mf.mf_workspace_bytes(s, 2, 8192, 8192) == 0
+    # classical <3,3,3;27>: every column is a single block, no pre-addition
+    assert mf.mf_workspace_bytes(mf.mf_algo_builtin("classical3"), 1, 0, 8192) == 0
+    w = mf.mf_algo_builtin("winograd")
+    assert mf.mf_workspace_bytes(w, 1, 0, 4096) == 8 * 2048 ** 2 * 8
+
+
+def test_workspace_bytes_paper_size_24012():
+    # The paper's largest size (Section 3.2): 24012^2 doubles ~ 4.6 GB per
+    # matrix.  This executor materialises 4 + 4 blocks at depth 1.
+    s = mf.mf_algo_builtin("strassen")
+    m = 128 * -(-12006 // 128)
+    assert mf.mf_workspace_bytes(s, 1, 0, 24012) == 8 * m * m * 8
+
+
+def _call_fastmm(algo, depth, cutoff, A, B, C, n, dtype):
+    return mf.lib.mf_fastmm(algo.handle if algo else None, depth, cutoff, ctypes.c_void_p(A), ctypes.c_void_p(B),
+                            ctypes.c_void_p(C), n, dtype, None)
+
+
+def test_fastmm_argument_validation_without_device():
+    s = mf.mf_algo_builtin("strassen")
+    A, B, C = 0x100000, 0x200000, 0x300000
+    n = 16
+    assert _call_fastmm(None, 1, 0, A, B, C, n, mf.MF_F64) == mf.MF_ERR_ARG
+    assert _call_fastmm(s, -1, 0, A, B, C, n, mf.MF_F64) == mf.MF_ERR_ARG
+    assert _call_fastmm(s, 1, -1, A, B, C, n, mf.MF_F64) == mf.MF_ERR_ARG
+    assert _call_fastmm(s, 1, 0, A, B, C, -1, mf.MF_F64) == mf.MF_ERR_ARG
+    assert _call_fastmm(s, 1, 0, A, B, C, n, 7) == mf.MF_ERR_ARG
+    assert _call_fastmm(s, 1, 0, A, B, C, n, mf.MF_F64 | (9 << 8)) == mf.MF_ERR_ARG
+    assert _call_fastmm(s, 1, 0, A, B, C, n, mf.MF_F64 | mf.MF_LEAF_BF16) == mf.MF_ERR_UNSUPPORTED
+    assert _call_fastmm(s, 1, 0, 0, B, C, n, mf.MF_F64) == mf.MF_ERR_ARG
+    assert _call_fastmm(s, 1, 0, A, B, A + 8, n, mf.MF_F64) == mf.MF_ERR_ARG      # C overlaps A
+    assert _call_fastmm(s, 1, 0, A, B, B - 8, n, mf.MF_F64) == mf.MF_ERR_ARG      # C overlaps B
+    assert _call_fastmm(s, 1, 0, A + 4, B, C, n, mf.MF_F64) == mf.MF_ERR_ARG      # misaligned
+    assert _call_fastmm(s, 1, 0, A, B, C, (1 << 20) + 1, mf.MF_F64) == mf.MF_ERR_SHAPE
+    assert "overlap" in mf.mf_last_error() or mf.mf_last_error() != ""
+    # n == 0 is a no-op and needs no pointers
+    assert _call_fastmm(s, 1, 0, 0, 0, 0, 0, mf.MF_F64) == mf.MF_OK
+    assert mf.lib.mf_classical_mm(None, None, None, 0, mf.MF_F64, None) == mf.MF_OK
+
+
+def test_unsupported_fused_factor_is_reported():
+    s = mf.mf_algo_builtin("strassen")
+    with pytest.raises(mf.MFError) as e:
+        mf.mf_workspace_bytes(s, 4, 0, 8192)  # split factor 16
+    assert e.value.status == mf.MF_ERR_UNSUPPORTED

@@ -1,0 +1,198 @@
+"""GPU parity of the FP64 path against the CPU oracle, through the C ABI.
+
+Integer-valued inputs must give bit-exact results (every intermediate is an
+integer below 2^53); uniform[-1,1] inputs must stay within the normwise
+relative error bound 1e-11 (depth <= 3, n <= 8192)."""
+import numpy as np
+import pytest
+
+import mf_inputs as mi
+from oracle import algebra as oa
+from oracle import matmul as om
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mf = pytest.importorskip("paper_2312_12732_amd.mf", reason="libmf.so not built")
+
+FP64_TOL = 1e-11
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to("cuda:0")
+
+
+def run_fast(algo, depth, cutoff, A, B):
+    dA, dB = dev(A), dev(B)
+    dC = torch.full_like(dA, float("nan"))
+    mf.mf_fastmm(algo, depth, cutoff, dA, dB, dC)
+    torch.cuda.synchronize()
+    return dC.cpu().numpy()
+
+
+def run_classical(A, B):
+    dA, dB = dev(A), dev(B)
+    dC = torch.full_like(dA, float("nan"))
+    mf.mf_classical_mm(dA, dB, dC)
+    torch.cuda.synchronize()
+    return dC.cpu().numpy()
+
+
+def oracle_algo(name):
+    table = {"strassen": mi.STRASSEN_PAPER, "winograd": mi.WINOGRAD, "strassen1969": mi.STRASSEN_1969}[name]
+    U, V, W, conv = mi.as_float_tables(table)
+    return oa.canonical(2, U, V, W, conv)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _announce():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    yield
+
+
+# ------------------------------------------------------------------ classical
+
+@pytest.mark.parametrize("n", [1, 2, 64, 127, 128, 129, 256, 300, 1000])
+def test_classical_int_exact(n):
+    A = mi.int_uniform(n, 3)
+    B = mi.int_uniform(n, 4)
+    got = run_classical(A.astype(np.float64), B.astype(np.float64))
+    assert np.array_equal(got, om.classical_mm(A, B).astype(np.float64))
+
+
+@pytest.mark.parametrize("n", [256, 1024, 1536])
+def test_classical_fp64_close(n):
+    A = mi.uniform(n, 1)
+    B = mi.uniform(n, 2)
+    err = om.rel_fro_error(run_classical(A, B), om.classical_mm(A, B))
+    assert err < 1e-14
+
+
+# ------------------------------------------------------- fast, bit-exact ints
+
+@pytest.mark.parametrize("name", ["strassen", "winograd", "strassen1969"])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+@pytest.mark.parametrize("n", [256, 300, 1024])
+def test_fast_int_exact(name, depth, n):
+    A = mi.int_uniform(n, 3)
+    B = mi.int_uniform(n, 4)
+    got = run_fast(mf.mf_algo_builtin(name), depth, 0, A.astype(np.float64), B.astype(np.float64))
+    want = om.classical_mm(A, B)
+    # the oracle's own fast executor reaches the same integers
+    if n <= 300:
+        assert np.array_equal(om.fast_mm(A, B, oracle_algo(name), depth), want)
+    assert np.array_equal(got, want.astype(np.float64))
+
+
+def test_paper_config_n256_depth1():
+    """n = 256, Strassen as printed in the paper, one level."""
+    U, V, W, conv = mi.as_float_tables(mi.STRASSEN_PAPER)
+    algo = mf.mf_algo_from_uvw(2, U, V, W, conv)
+    Ai = mi.int_uniform(256, 3)
+    Bi = mi.int_uniform(256, 4)
+    got = run_fast(algo, 1, 0, Ai.astype(np.float64), Bi.astype(np.float64))
+    assert np.array_equal(got, om.fast_mm(Ai, Bi, oracle_algo("strassen"), 1).astype(np.float64))
+    A = mi.uniform(256, 1)
+    B = mi.uniform(256, 2)
+    err = om.rel_fro_error(run_fast(algo, 1, 0, A, B), om.classical_mm(A, B))
+    assert err < FP64_TOL
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_rebased_int_exact(seed):
+    X, Y, Z = (mi.unimodular(2, seed * 10 + t) for t in range(3))
+    algo = mf.mf_algo_rebase(mf.mf_algo_builtin("strassen"), X, Y, Z)
+    A = mi.int_uniform(512, 5)
+    B = mi.int_uniform(512, 6)
+    for depth in (1, 2):
+        got = run_fast(algo, depth, 0, A.astype(np.float64), B.astype(np.float64))
+        assert np.array_equal(got, (A @ B).astype(np.float64))
+
+
+def test_classical_333_control_exact():
+    algo = mf.mf_algo_builtin("classical3")
+    for n in (384, 500):
+        A = mi.int_uniform(n, 7)
+        B = mi.int_uniform(n, 8)
+        got = run_fast(algo, 1, 0, A.astype(np.float64), B.astype(np.float64))
+        assert np.array_equal(got, (A @ B).astype(np.float64))
+
+
+def test_composed_equals_depth2_bitwise():
+    s = mf.mf_algo_builtin("winograd")
+    s2 = mf.mf_algo_compose(s, s)
+    A = mi.uniform(1024, 11)
+    B = mi.uniform(1024, 12)
+    assert np.array_equal(run_fast(s, 2, 0, A, B), run_fast(s2, 1, 0, A, B))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 129, 255])
+def test_fast_tiny_and_ragged_exact(n):
+    A = mi.int_uniform(n, 13)
+    B = mi.int_uniform(n, 14)
+    for depth in (1, 2, 3):
+        got = run_fast(mf.mf_algo_builtin("strassen"), depth, 0, A.astype(np.float64), B.astype(np.float64))
+        assert np.array_equal(got, (A @ B).astype(np.float64)), (n, depth)
+
+
+def test_cutoff_selects_levels():
+    s = mf.mf_algo_builtin("strassen")
+    A = mi.uniform(512, 1)
+    B = mi.uniform(512, 2)
+    # cutoff >= n: classical; it must equal the library's classical GEMM bitwise
+    assert np.array_equal(run_fast(s, 3, 512, A, B), run_classical(A, B))
+    # cutoff 256 with depth 3: one level only, equal to depth 1
+    assert np.array_equal(run_fast(s, 3, 256, A, B), run_fast(s, 1, 0, A, B))
+
+
+# ------------------------------------------------------------ FP64 accuracy
+
+@pytest.mark.parametrize("name", ["strassen", "winograd"])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_fast_fp64_error_1024(name, depth):
+    A = mi.uniform(1024, 10)
+    B = mi.uniform(1024, 11)
+    err = om.rel_fro_error(run_fast(mf.mf_algo_builtin(name), depth, 0, A, B), om.classical_mm(A, B))
+    assert err < FP64_TOL
+
+
+def test_determinism_and_workspace_variant():
+    s = mf.mf_algo_builtin("strassen")
+    A = dev(mi.uniform(1024, 21))
+    B = dev(mi.uniform(1024, 22))
+    C1 = torch.empty_like(A)
+    C2 = torch.empty_like(A)
+    C3 = torch.empty_like(A)
+    mf.mf_fastmm(s, 2, 0, A, B, C1)
+    mf.mf_fastmm(s, 2, 0, A, B, C2)
+    nbytes = mf.mf_workspace_bytes(s, 2, 0, 1024)
+    ws = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    mf.mf_fastmm_ws(s, 2, 0, A, B, C3, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2) and torch.equal(C1, C3)
+
+
+def test_workspace_too_small_rejected():
+    s = mf.mf_algo_builtin("strassen")
+    A = dev(mi.uniform(256, 1))
+    B = dev(mi.uniform(256, 2))
+    C = torch.empty_like(A)
+    ws = torch.empty(16, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(mf.MFError) as e:
+        mf.mf_fastmm_ws(s, 1, 0, A, B, C, ws)
+    assert e.value.status == mf.MF_ERR_SHAPE
+
+
+# --------------------------------------------- full size, sampled rows
+
+@pytest.mark.parametrize("n,name,depth", [(4096, "winograd", 1), (4096, "winograd", 3), (8192, "strassen", 1),
+                                          (8192, "strassen", 2), (8192, "winograd", 3)])
+def test_full_size_sampled_rows(n, name, depth):
+    A = mi.uniform(n, 10)
+    B = mi.uniform(n, 11)
+    got = run_fast(mf.mf_algo_builtin(name), depth, 0, A, B)
+    rows = np.sort(np.random.default_rng(5).choice(n, size=48, replace=False))
+    ref = om.rows_reference(A, B, rows)
+    err = om.rel_fro_error(got[rows], ref)
+    assert err < FP64_TOL, err
+    assert np.isfinite(got).all()

@@ -24,9 +24,6 @@ namespace {
 
 constexpr int64_t kMaxN = 1 << 20;
 
-// Fused split factors with a compiled pre-addition kernel.
-bool fused_supported(int P) { return P == 1 || P == 2 || P == 3 || P == 4 || P == 6 || P == 8 || P == 9; }
-
 mf_status new_handle(const Algo& a, mf_algo** out) {
   const int64_t bad = brent_violations(a);
   if (bad != 0)
@@ -70,29 +67,19 @@ mf_status check_request(const mf_algo* algo, bool need_algo, int depth, int cuto
 
 mf_status plan_for(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
                    std::shared_ptr<const Plan>* pl) {
-  if (algo && depth > 0) {
-    int P = 1, d = 0;
-    int64_t size = n;
-    while (d < depth && size > cutoff && algo->a.p > 1) {
-      size = (size + algo->a.p - 1) / algo->a.p;
-      P *= algo->a.p;
-      ++d;
-      if (P > 9) break;
-    }
-    if (!fused_supported(P))
-      return fail(MF_ERR_UNSUPPORTED, "fused split factor " + std::to_string(P) + " has no pre-addition kernel");
-  }
   return get_plan(depth > 0 ? algo : nullptr, depth, cutoff, n, dtype, pl);
 }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, hipStream_t s) {
   mf_status st = ensure_device(pl);
   if (st != MF_OK) return st;
-  const bool vec_in = (pl.n % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0;
-  hipError_t e = launch_preadd_f64(pl, A, B, ws, vec_in, s);
-  if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("pre-addition launch: ") + hipGetErrorString(e));
-  e = launch_gemm_f64(pl, A, B, C, ws, vec_in, s);
-  if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("GEMM launch: ") + hipGetErrorString(e));
+  const bool even = pl.n % 2 == 0;
+  const bool vec_in = even && aligned16(A) && aligned16(B);
+  const bool vec_c = even && aligned16(C);
+  const hipError_t e = launch_plan_f64(pl, A, B, C, ws, vec_in, vec_c, s);
+  if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return MF_OK;
 }
 

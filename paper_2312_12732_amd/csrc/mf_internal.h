@@ -51,75 +51,102 @@ namespace mf {
 // Device descriptors
 // ---------------------------------------------------------------------------
 
-// Source of an operand view: the caller's A, B or C, or the workspace.
-enum Src : int32_t { SRC_A = 0, SRC_B = 1, SRC_WS = 2 };
+// Source (or destination) of a view: the caller's A, B or C, or the
+// workspace.
+enum Src : int32_t { SRC_A = 0, SRC_B = 1, SRC_C = 2, SRC_WS = 3 };
 
-// One leaf product P_r = scale * X_r Y_r of size m x m x m, where X_r and Y_r
-// are views (src, offset, ld) of the inputs or of workspace blocks.  Entries
-// of a view at row >= vr or column >= vc are zero (virtual padding).
+// One leaf product P_r = X_r Y_r of size m x m x m, where X_r and Y_r are
+// views (src, offset, ld) of the inputs or of workspace blocks.  Entries of
+// a view at row >= vr or column >= vc are zero (virtual padding).
 struct ProdDesc {
-  int64_t a_off, b_off;   // element offsets of the view origins
-  int32_t a_src, b_src;   // Src
-  int32_t lda, ldb;       // leading dimensions (elements)
-  int32_t a_vr, a_vc;     // valid rows / columns of the A view
-  int32_t b_vr, b_vc;     // valid rows / columns of the B view
+  int64_t a_off, b_off;      // element offsets of the view origins
+  int32_t a_src, b_src;      // Src
+  int32_t lda, ldb;          // leading dimensions (elements)
+  int32_t a_vr, a_vc;        // valid rows / columns of the A view
+  int32_t b_vr, b_vc;        // valid rows / columns of the B view
   int32_t epi_beg, epi_end;  // range in the epilogue list
 };
 
-// One post-addition term: C block c (view of C) gets coef * P_r.  `first`
-// is set for the product that writes the block first (in product order).
+// One post-addition term of the GEMM epilogue: output block (dst, offset,
+// ld) gets coef * P_r.  first = 1: the product writes the block first (in
+// product order) and stores; 0: accumulates; 2: stores zeros (a block that
+// no product feeds, which happens only through padding).
 struct EpiDesc {
   int64_t c_off;
+  int32_t c_src;  // SRC_C or SRC_WS
+  int32_t ldc;
   int32_t c_vr, c_vc;
   int32_t first;
   int32_t pad_;
   double coef;
 };
 
-// One materialised pre-addition output: out = sum_k coef[k] * in_k over the
-// p^2 input block views; written densely (ld = m) at ws offset out_off.
-struct PreOut {
-  int64_t out_off;
-  int32_t coef_off;  // offset into the coefficient array (P2 entries)
-  int32_t nnz;
+// Input view of a linear-combination stage.
+struct CombIn {
+  int64_t off;
+  int32_t src;
+  int32_t ld;
+  int32_t vr, vc;  // zero outside (vr = vc = 0: an all-zero input)
 };
 
-// Input block view k of the pre-addition (same for every output).
-struct PreIn {
+// Output of a linear-combination stage: out = sum_k coef[k] * in_k.
+struct CombOut {
   int64_t off;
-  int32_t vr, vc;
+  int32_t dst;
+  int32_t ld;
+  int32_t vr, vc;  // only this extent is written
+  int32_t coef_off;
+  int32_t pad_;
+};
+
+// A linear-combination stage over m x m blocks: n_sets operand sets (blockIdx.y),
+// each with `nin` input views and outputs [out_beg[y], out_beg[y+1]).
+struct CombineStage {
+  int nin = 0;
+  int n_sets = 0;
+  int out_beg[3] = {0, 0, 0};
+  std::vector<CombIn> ins;
+  std::vector<CombOut> outs;
+  std::vector<double> coef;
+  mutable CombIn* d_ins = nullptr;
+  mutable CombOut* d_outs = nullptr;
+  mutable double* d_coef = nullptr;
 };
 
 // ---------------------------------------------------------------------------
 // Plans
 // ---------------------------------------------------------------------------
 
+// Execution plan of one request.  The `levels` recursion levels run as one
+// fused level of split factor P = p^levels (composition of the algorithm
+// with itself).  Its products are split into groups by the first
+// `levels_outer` levels: group g computes the inner product P_g (size
+// m_outer = P_inner * m) with the post-addition of the inner levels fused
+// into the GEMM epilogue, and a final linear combination applies the outer
+// post-addition C_c = sum_g W_outer[c,g] P_g.  With levels_outer = 0 there is
+// one group and the epilogue writes C directly.
 struct Plan {
-  int64_t n = 0;      // true size
-  int64_t npad = 0;   // padded size = P * m
-  int64_t m = 0;      // leaf size (multiple of the GEMM tile)
-  int levels = 0;     // recursion levels taken
-  int P = 1;          // split factor of the fused level (p^levels)
-  int R = 1;          // number of leaf products
+  int64_t n = 0;        // true size
+  int64_t npad = 0;     // padded size = P * m
+  int64_t m = 0;        // leaf size (multiple of the GEMM tile)
+  int64_t m_outer = 0;  // size of a group's output block (P_inner * m)
+  int levels = 0, levels_outer = 0;
+  int P = 1, P_outer = 1;
+  int R = 1, groups = 1;
   int dtype = MF_F64;
   size_t elem = 8;
   size_t ws_bytes = 0;
-  int n_pre_a = 0, n_pre_b = 0;  // materialised T / S outputs
-  // host copies
-  std::vector<ProdDesc> prods;
+  std::vector<ProdDesc> prods;   // ordered by group
   std::vector<EpiDesc> epis;
-  std::vector<PreOut> pre_out;   // A outputs first, then B outputs
-  std::vector<PreIn> pre_in;     // A inputs (P2), then B inputs (P2)
-  std::vector<double> pre_coef;
+  std::vector<int32_t> group_beg;  // groups + 1 entries
+  CombineStage pre, post;
   // device copy (one allocation, owned by the plan), made on first use
   mutable std::once_flag uploaded;
   mutable mf_status upload_status = MF_OK;
   mutable void* dev = nullptr;
   mutable ProdDesc* d_prods = nullptr;
   mutable EpiDesc* d_epis = nullptr;
-  mutable PreOut* d_pre_out = nullptr;
-  mutable PreIn* d_pre_in = nullptr;
-  mutable double* d_pre_coef = nullptr;
+  mutable int32_t* d_group_beg = nullptr;
   ~Plan();
 };
 
@@ -142,10 +169,12 @@ constexpr int kLeafTile = 128;
 // Launchers (kernels.hip)
 // ---------------------------------------------------------------------------
 
-// vec_in: rows of A and B are 16-byte aligned (vector loads allowed).
-hipError_t launch_preadd_f64(const Plan& pl, const void* A, const void* B, void* ws, bool vec_in, hipStream_t s);
-hipError_t launch_gemm_f64(const Plan& pl, const void* A, const void* B, void* C, void* ws, bool vec_in,
+// Enqueues pre-addition, grouped GEMM and (if any) outer post-addition.
+// vec_in / vec_c: rows of A and B / of C are 16-byte aligned.
+hipError_t launch_plan_f64(const Plan& pl, const void* A, const void* B, void* C, void* ws, bool vec_in, bool vec_c,
                            hipStream_t s);
+// Input counts with a compiled linear-combination kernel.
+bool combine_supported(int nin);
 
 // Thread-local error message.
 mf_status fail(mf_status st, const std::string& msg);

@@ -1,7 +1,8 @@
 // Planner: turns (algorithm, depth, cutoff, n, dtype) into the descriptors of
-// one fused level - the pre-addition outputs, the leaf products and the
-// post-addition terms - plus the workspace size.  Plans are immutable and
-// cached; their descriptors live in one device allocation.
+// one fused level - the pre-addition stage, the grouped leaf products with
+// their epilogue post-additions, and the outer post-addition stage - plus
+// the workspace size.  Plans are immutable and cached; their descriptors live
+// in one device allocation made on first use.
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -31,53 +32,55 @@ int levels_for(int64_t n, int p, int depth, int cutoff) {
 }
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
 
 struct View {
   int64_t off;
   int32_t vr, vc;
 };
 
-// Block k of the P x P partition of the padded n x n input (block size m),
-// clipped to the true size n: entries beyond it are virtual zeros.
+// Block k of the P x P partition of an n x n matrix with block size m (the
+// padded size P*m >= n), clipped to the true size: entries beyond it are
+// virtual zeros.  ld of the view is n.
 View block_view(int k, int P, int64_t m, int64_t n) {
   const int64_t bi = k / P, bj = k % P;
   View v;
   const int64_t r0 = bi * m, c0 = bj * m;
   v.vr = (int32_t)std::max<int64_t>(0, std::min<int64_t>(m, n - r0));
   v.vc = (int32_t)std::max<int64_t>(0, std::min<int64_t>(m, n - c0));
-  v.off = (v.vr > 0 && v.vc > 0) ? r0 * n + c0 : 0;
   if (v.vr == 0 || v.vc == 0) v.vr = v.vc = 0;
+  v.off = (v.vr > 0) ? r0 * n + c0 : 0;
   return v;
 }
 
-mf_status upload(const Plan* pl) {
-  auto align = [](size_t x) { return (x + 255) / 256 * 256; };
-  const size_t sp = align(pl->prods.size() * sizeof(ProdDesc));
-  const size_t se = align(pl->epis.size() * sizeof(EpiDesc));
-  const size_t so = align(pl->pre_out.size() * sizeof(PreOut));
-  const size_t si = align(pl->pre_in.size() * sizeof(PreIn));
-  const size_t sc = align(pl->pre_coef.size() * sizeof(double));
-  const size_t total = sp + se + so + si + sc;
-  if (total == 0) return MF_OK;
-  std::vector<char> host(total, 0);
-  char* h = host.data();
-  memcpy(h, pl->prods.data(), pl->prods.size() * sizeof(ProdDesc));
-  memcpy(h + sp, pl->epis.data(), pl->epis.size() * sizeof(EpiDesc));
-  memcpy(h + sp + se, pl->pre_out.data(), pl->pre_out.size() * sizeof(PreOut));
-  memcpy(h + sp + se + so, pl->pre_in.data(), pl->pre_in.size() * sizeof(PreIn));
-  memcpy(h + sp + se + so + si, pl->pre_coef.data(), pl->pre_coef.size() * sizeof(double));
-  if (hipMalloc(&pl->dev, total) != hipSuccess) {
-    pl->dev = nullptr;
-    return fail(MF_ERR_NOMEM, "hipMalloc of plan descriptors failed");
-  }
-  if (hipMemcpy(pl->dev, host.data(), total, hipMemcpyHostToDevice) != hipSuccess)
-    return fail(MF_ERR_HIP, "copy of plan descriptors failed");
-  char* d = static_cast<char*>(pl->dev);
-  pl->d_prods = reinterpret_cast<ProdDesc*>(d);
-  pl->d_epis = reinterpret_cast<EpiDesc*>(d + sp);
-  pl->d_pre_out = reinterpret_cast<PreOut*>(d + sp + se);
-  pl->d_pre_in = reinterpret_cast<PreIn*>(d + sp + se + so);
-  pl->d_pre_coef = reinterpret_cast<double*>(d + sp + se + so + si);
+// Workgroups wanted in the grouped GEMM before outer levels are split off.
+constexpr int64_t kMinWorkgroups = 1024;
+
+mf_status build_classical(int64_t n, Plan* pl) {
+  pl->P = pl->P_outer = 1;
+  pl->R = pl->groups = 1;
+  pl->m = pl->m_outer = round_up(n, kLeafTile);
+  pl->npad = pl->m;
+  ProdDesc pd{};
+  pd.a_src = SRC_A;
+  pd.b_src = SRC_B;
+  pd.lda = pd.ldb = (int32_t)n;
+  pd.a_vr = pd.a_vc = pd.b_vr = pd.b_vc = (int32_t)n;
+  pd.epi_beg = 0;
+  pd.epi_end = 1;
+  pl->prods.push_back(pd);
+  EpiDesc ed{};
+  ed.c_src = SRC_C;
+  ed.ldc = (int32_t)n;
+  ed.c_vr = ed.c_vc = (int32_t)n;
+  ed.first = 1;
+  ed.coef = 1.0;
+  pl->epis.push_back(ed);
+  pl->group_beg = {0, 1};
   return MF_OK;
 }
 
@@ -85,56 +88,52 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, P
   pl->n = n;
   pl->dtype = dtype;
   pl->elem = (dtype & 0xff) == MF_F64 ? 8 : 4;
-  const int levels = algo ? levels_for(n, algo->p, depth, cutoff) : 0;
-  pl->levels = levels;
+  const int L = algo ? levels_for(n, algo->p, depth, cutoff) : 0;
+  pl->levels = L;
+  if (L == 0) return build_classical(n, pl);
 
-  if (levels == 0) {
-    // Classical product: one leaf of size round_up(n, tile) with virtual padding.
-    pl->P = 1;
-    pl->R = 1;
-    pl->m = round_up(n, kLeafTile);
-    pl->npad = pl->m;
-    ProdDesc pd{};
-    pd.a_off = 0;
-    pd.b_off = 0;
-    pd.a_src = SRC_A;
-    pd.b_src = SRC_B;
-    pd.lda = pd.ldb = (int32_t)n;
-    pd.a_vr = pd.a_vc = pd.b_vr = pd.b_vc = (int32_t)n;
-    pd.epi_beg = 0;
-    pd.epi_end = 1;
-    pl->prods.push_back(pd);
-    EpiDesc ed{};
-    ed.c_off = 0;
-    ed.c_vr = ed.c_vc = (int32_t)n;
-    ed.first = 1;
-    ed.coef = 1.0;
-    pl->epis.push_back(ed);
-    return MF_OK;
-  }
-
-  const Algo F = power(*algo, levels);
-  const int P = F.p, P2 = P * P;
-  pl->P = P;
-  pl->R = F.R;
+  const int p = algo->p;
+  const int64_t P = ipow(p, L);
+  const int64_t P2 = P * P;
+  if (!combine_supported((int)P2))
+    return fail(MF_ERR_UNSUPPORTED, "fused split factor " + std::to_string(P) + " has no pre-addition kernel");
+  pl->P = (int)P;
   pl->m = round_up((n + P - 1) / P, kLeafTile);
   pl->npad = pl->m * P;
-  const int64_t m = pl->m;
-  const int64_t mm = m * m;
+  const int64_t m = pl->m, mm = m * m;
+  const int64_t positions = (m / kLeafTile) * (m / kLeafTile);
 
+  // Outer levels split off as groups until the grid is large enough.
+  int Lo = 0;
+  while (Lo < L && Lo < 2 && positions * ipow(algo->R, Lo) < kMinWorkgroups &&
+         combine_supported((int)ipow(algo->R, Lo + 1)))
+    ++Lo;
+  const int Li = L - Lo;
+  pl->levels_outer = Lo;
+  const Algo Fo = Lo > 0 ? power(*algo, Lo) : Algo{};
+  const Algo Fi = Li > 0 ? power(*algo, Li) : Algo{};
+  const Algo F = power(*algo, L);
+  const int Po = Lo > 0 ? Fo.p : 1, Ro = Lo > 0 ? Fo.R : 1;
+  const int Pi = Li > 0 ? Fi.p : 1, Ri = Li > 0 ? Fi.R : 1;
+  pl->P_outer = Po;
+  pl->R = F.R;
+  pl->groups = Ro;
+  pl->m_outer = (int64_t)Pi * m;
+  const int64_t mo = pl->m_outer;
+
+  // ---- pre-addition stage: inputs are the P^2 blocks of A (set 0) and B (set 1)
   std::vector<View> views(P2);
-  for (int k = 0; k < P2; ++k) views[k] = block_view(k, P, m, n);
-  for (int op = 0; op < 2; ++op)
-    for (int k = 0; k < P2; ++k) pl->pre_in.push_back(PreIn{views[k].off, views[k].vr, views[k].vc});
+  for (int k = 0; k < P2; ++k) views[k] = block_view(k, (int)P, m, n);
+  CombineStage& pre = pl->pre;
+  pre.nin = (int)P2;
+  for (int side = 0; side < 2; ++side)
+    for (int k = 0; k < P2; ++k)
+      pre.ins.push_back(CombIn{views[k].off, side == 0 ? SRC_A : SRC_B, (int32_t)n, views[k].vr, views[k].vc});
 
-  // Operand of product r for one side: a single-coefficient column is a view
-  // (scaled by its coefficient in the epilogue); otherwise a workspace block.
   struct Operand {
-    bool zero = false;
-    bool view = false;
-    int block = -1;
+    bool zero = false, view = false;
+    int block = -1, slot = -1;
     double scale = 1.0;
-    int slot = -1;
   };
   auto classify = [&](const std::vector<double>& X, int r) {
     Operand o;
@@ -153,112 +152,205 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, P
     }
     return o;
   };
-
   std::vector<Operand> opa(F.R), opb(F.R);
+  for (int r = 0; r < F.R; ++r) {
+    opa[r] = classify(F.U, r);
+    opb[r] = classify(F.V, r);
+  }
+  // A product with an all-zero operand (only possible through padding)
+  // contributes nothing; it and its pre-additions are skipped.
   int slots = 0;
   for (int side = 0; side < 2; ++side) {
     const std::vector<double>& X = side == 0 ? F.U : F.V;
     std::vector<Operand>& ops = side == 0 ? opa : opb;
-    for (int r = 0; r < F.R; ++r) ops[r] = classify(X, r);
-  }
-  // A product with an all-zero operand (only possible through padding)
-  // contributes nothing; skip it and its pre-additions.
-  for (int side = 0; side < 2; ++side) {
-    const std::vector<double>& X = side == 0 ? F.U : F.V;
-    std::vector<Operand>& ops = side == 0 ? opa : opb;
+    pre.out_beg[side] = (int)pre.outs.size();
     for (int r = 0; r < F.R; ++r) {
-      if (opa[r].zero || opb[r].zero) continue;
-      Operand& o = ops[r];
-      if (o.view) continue;
-      o.slot = slots++;
-      PreOut po;
-      po.out_off = (int64_t)o.slot * mm;
-      po.coef_off = (int32_t)pl->pre_coef.size();
-      po.nnz = 0;
-      for (int k = 0; k < P2; ++k) {
-        const double c = views[k].vr > 0 ? X[(size_t)k * F.R + r] : 0.0;
-        pl->pre_coef.push_back(c);
-        if (c != 0.0) ++po.nnz;
-      }
-      pl->pre_out.push_back(po);
-      if (side == 0)
-        ++pl->n_pre_a;
-      else
-        ++pl->n_pre_b;
+      if (opa[r].zero || opb[r].zero || ops[r].view) continue;
+      ops[r].slot = slots++;
+      CombOut co{};
+      co.off = (int64_t)ops[r].slot * mm;
+      co.dst = SRC_WS;
+      co.ld = (int32_t)m;
+      co.vr = co.vc = (int32_t)m;
+      co.coef_off = (int32_t)pre.coef.size();
+      for (int k = 0; k < P2; ++k) pre.coef.push_back(views[k].vr > 0 ? X[(size_t)k * F.R + r] : 0.0);
+      pre.outs.push_back(co);
     }
   }
-  pl->ws_bytes = (size_t)slots * (size_t)mm * pl->elem;
+  pre.out_beg[2] = (int)pre.outs.size();
+  pre.n_sets = pre.outs.empty() ? 0 : 2;
+  const int64_t pbuf_base = (int64_t)slots * mm;  // group output buffers follow the T/S slots
 
-  std::vector<View> cviews(P2);
-  for (int c = 0; c < P2; ++c) cviews[c] = block_view(c, P, m, n);
-  std::vector<bool> written(P2, false);
-  for (int r = 0; r < F.R; ++r) {
-    if (opa[r].zero || opb[r].zero) continue;
-    ProdDesc pd{};
-    const Operand& a = opa[r];
-    const Operand& b = opb[r];
-    if (a.view) {
-      pd.a_src = SRC_A;
-      pd.a_off = views[a.block].off;
-      pd.lda = (int32_t)n;
-      pd.a_vr = views[a.block].vr;
-      pd.a_vc = views[a.block].vc;
-    } else {
-      pd.a_src = SRC_WS;
-      pd.a_off = (int64_t)a.slot * mm;
-      pd.lda = (int32_t)m;
-      pd.a_vr = pd.a_vc = (int32_t)m;
+  // ---- grouped leaf products with epilogue post-addition
+  for (int g = 0; g < Ro; ++g) {
+    pl->group_beg.push_back((int32_t)pl->prods.size());
+    const int nout = Pi * Pi;  // output blocks of the group
+    std::vector<char> written(nout, 0);
+    // Output block c (inner index) of this group.
+    auto out_view = [&](int c, EpiDesc* ed) {
+      if (Lo == 0) {
+        const View v = block_view(c, (int)P, m, n);
+        ed->c_src = SRC_C;
+        ed->c_off = v.off;
+        ed->ldc = (int32_t)n;
+        ed->c_vr = v.vr;
+        ed->c_vc = v.vc;
+      } else {
+        ed->c_src = SRC_WS;
+        ed->c_off = pbuf_base + (int64_t)g * mo * mo + (int64_t)(c / Pi) * m * mo + (int64_t)(c % Pi) * m;
+        ed->ldc = (int32_t)mo;
+        ed->c_vr = ed->c_vc = (int32_t)m;
+      }
+    };
+    const int group_first = (int)pl->prods.size();
+    for (int ri = 0; ri < Ri; ++ri) {
+      const int r = g * Ri + ri;
+      if (opa[r].zero || opb[r].zero) continue;
+      ProdDesc pd{};
+      const Operand& a = opa[r];
+      const Operand& b = opb[r];
+      if (a.view) {
+        pd.a_src = SRC_A;
+        pd.a_off = views[a.block].off;
+        pd.lda = (int32_t)n;
+        pd.a_vr = views[a.block].vr;
+        pd.a_vc = views[a.block].vc;
+      } else {
+        pd.a_src = SRC_WS;
+        pd.a_off = (int64_t)a.slot * mm;
+        pd.lda = (int32_t)m;
+        pd.a_vr = pd.a_vc = (int32_t)m;
+      }
+      if (b.view) {
+        pd.b_src = SRC_B;
+        pd.b_off = views[b.block].off;
+        pd.ldb = (int32_t)n;
+        pd.b_vr = views[b.block].vr;
+        pd.b_vc = views[b.block].vc;
+      } else {
+        pd.b_src = SRC_WS;
+        pd.b_off = (int64_t)b.slot * mm;
+        pd.ldb = (int32_t)m;
+        pd.b_vr = pd.b_vc = (int32_t)m;
+      }
+      const double scale = a.scale * b.scale;
+      pd.epi_beg = (int32_t)pl->epis.size();
+      for (int c = 0; c < nout; ++c) {
+        const double w = Li > 0 ? Fi.w(c, ri) : 1.0;
+        if (w == 0.0) continue;
+        EpiDesc ed{};
+        out_view(c, &ed);
+        if (ed.c_vr == 0) continue;
+        ed.first = written[c] ? 0 : 1;
+        ed.coef = w * scale;
+        written[c] = 1;
+        pl->epis.push_back(ed);
+      }
+      pd.epi_end = (int32_t)pl->epis.size();
+      pl->prods.push_back(pd);
     }
-    if (b.view) {
-      pd.b_src = SRC_B;
-      pd.b_off = views[b.block].off;
-      pd.ldb = (int32_t)n;
-      pd.b_vr = views[b.block].vr;
-      pd.b_vc = views[b.block].vc;
-    } else {
-      pd.b_src = SRC_WS;
-      pd.b_off = (int64_t)b.slot * mm;
-      pd.ldb = (int32_t)m;
-      pd.b_vr = pd.b_vc = (int32_t)m;
-    }
-    const double scale = a.scale * b.scale;
-    pd.epi_beg = (int32_t)pl->epis.size();
-    for (int c = 0; c < P2; ++c) {
-      const double w = F.w(c, r);
-      if (w == 0.0 || cviews[c].vr == 0) continue;
+    // Output blocks that no product of the group feeds are zero; the first
+    // product of the group stores zeros there.
+    for (int c = 0; c < nout; ++c) {
+      if (written[c]) continue;
       EpiDesc ed{};
-      ed.c_off = cviews[c].off;
-      ed.c_vr = cviews[c].vr;
-      ed.c_vc = cviews[c].vc;
-      ed.first = written[c] ? 0 : 1;
-      ed.coef = w * scale;
-      written[c] = true;
-      pl->epis.push_back(ed);
+      out_view(c, &ed);
+      if (ed.c_vr == 0) continue;
+      if ((int)pl->prods.size() == group_first) break;  // empty group: the post stage reads it as zero
+      ed.first = 2;
+      ed.coef = 0.0;
+      const int at = pl->prods[group_first].epi_end;
+      pl->epis.insert(pl->epis.begin() + at, ed);
+      pl->prods[group_first].epi_end += 1;
+      for (size_t q = group_first + 1; q < pl->prods.size(); ++q) {
+        pl->prods[q].epi_beg += 1;
+        pl->prods[q].epi_end += 1;
+      }
+      written[c] = 1;
     }
-    pd.epi_end = (int32_t)pl->epis.size();
-    pl->prods.push_back(pd);
   }
-  // A C block that no remaining product feeds is zero (padding only): the
-  // first product stores zeros there.
-  for (int c = 0; c < P2; ++c) {
-    if (written[c] || cviews[c].vr == 0) continue;
-    if (pl->prods.empty()) return fail(MF_ERR_SHAPE, "plan has no products");
-    EpiDesc ed{};
-    ed.c_off = cviews[c].off;
-    ed.c_vr = cviews[c].vr;
-    ed.c_vc = cviews[c].vc;
-    ed.first = 2;
-    ed.coef = 0.0;
-    // Insert at the end of product 0's range, shifting later ranges.
-    const int at = pl->prods[0].epi_end;
-    pl->epis.insert(pl->epis.begin() + at, ed);
-    pl->prods[0].epi_end += 1;
-    for (size_t q = 1; q < pl->prods.size(); ++q) {
-      pl->prods[q].epi_beg += 1;
-      pl->prods[q].epi_end += 1;
+  pl->group_beg.push_back((int32_t)pl->prods.size());
+  if (pl->prods.empty()) return fail(MF_ERR_SHAPE, "plan has no products");
+
+  // ---- outer post-addition: C_c = sum_g W_outer[c, g] P_g
+  size_t ws_elems = (size_t)pbuf_base;
+  if (Lo > 0) {
+    CombineStage& post = pl->post;
+    post.nin = Ro;
+    for (int g = 0; g < Ro; ++g) {
+      const bool empty = pl->group_beg[g] == pl->group_beg[g + 1];
+      post.ins.push_back(CombIn{pbuf_base + (int64_t)g * mo * mo, SRC_WS, (int32_t)mo, empty ? 0 : (int32_t)mo,
+                                empty ? 0 : (int32_t)mo});
     }
-    written[c] = true;
+    post.out_beg[0] = 0;
+    for (int c = 0; c < Po * Po; ++c) {
+      const View v = block_view(c, Po, mo, n);
+      if (v.vr == 0) continue;
+      CombOut co{};
+      co.off = v.off;
+      co.dst = SRC_C;
+      co.ld = (int32_t)n;
+      co.vr = v.vr;
+      co.vc = v.vc;
+      co.coef_off = (int32_t)post.coef.size();
+      for (int g = 0; g < Ro; ++g) post.coef.push_back(Fo.w(c, g));
+      post.outs.push_back(co);
+    }
+    post.out_beg[1] = post.out_beg[2] = (int)post.outs.size();
+    post.n_sets = 1;
+    ws_elems += (size_t)Ro * (size_t)mo * (size_t)mo;
   }
+  pl->ws_bytes = ws_elems * pl->elem;
+  return MF_OK;
+}
+
+template <class T>
+size_t bytes_of(const std::vector<T>& v) {
+  return v.size() * sizeof(T);
+}
+
+mf_status upload(const Plan* pl) {
+  auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+  struct Part {
+    const void* src;
+    size_t bytes;
+    size_t off;
+  };
+  std::vector<Part> parts = {
+      {pl->prods.data(), bytes_of(pl->prods), 0},         {pl->epis.data(), bytes_of(pl->epis), 0},
+      {pl->group_beg.data(), bytes_of(pl->group_beg), 0}, {pl->pre.ins.data(), bytes_of(pl->pre.ins), 0},
+      {pl->pre.outs.data(), bytes_of(pl->pre.outs), 0},   {pl->pre.coef.data(), bytes_of(pl->pre.coef), 0},
+      {pl->post.ins.data(), bytes_of(pl->post.ins), 0},   {pl->post.outs.data(), bytes_of(pl->post.outs), 0},
+      {pl->post.coef.data(), bytes_of(pl->post.coef), 0},
+  };
+  size_t total = 0;
+  for (auto& q : parts) {
+    q.off = total;
+    total += align(q.bytes);
+  }
+  if (total == 0) return MF_OK;
+  std::vector<char> host(total, 0);
+  for (auto& q : parts)
+    if (q.bytes) memcpy(host.data() + q.off, q.src, q.bytes);
+  if (hipMalloc(&pl->dev, total) != hipSuccess) {
+    (void)hipGetLastError();
+    pl->dev = nullptr;
+    return MF_ERR_NOMEM;
+  }
+  if (hipMemcpy(pl->dev, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return MF_ERR_HIP;
+  }
+  char* d = static_cast<char*>(pl->dev);
+  pl->d_prods = reinterpret_cast<ProdDesc*>(d + parts[0].off);
+  pl->d_epis = reinterpret_cast<EpiDesc*>(d + parts[1].off);
+  pl->d_group_beg = reinterpret_cast<int32_t*>(d + parts[2].off);
+  pl->pre.d_ins = reinterpret_cast<CombIn*>(d + parts[3].off);
+  pl->pre.d_outs = reinterpret_cast<CombOut*>(d + parts[4].off);
+  pl->pre.d_coef = reinterpret_cast<double*>(d + parts[5].off);
+  pl->post.d_ins = reinterpret_cast<CombIn*>(d + parts[6].off);
+  pl->post.d_outs = reinterpret_cast<CombOut*>(d + parts[7].off);
+  pl->post.d_coef = reinterpret_cast<double*>(d + parts[8].off);
   return MF_OK;
 }
 

@@ -118,23 +118,42 @@ def test_rebase_rejects_singular():
     assert e.value.status == mf.MF_ERR_ARG
 
 
+def expected_ws(n, depth, mat_u, mat_v, R=7, p=2):
+    """Closed form of the executor's workspace: the materialised T and S
+    blocks of size m^2 (m = n / p^d rounded up to the 128 tile), plus, when
+    the grid of (m/128)^2 tile positions is below 1024 workgroups, one output
+    block of size (m * p^d_inner)^2 per group of the first d_outer levels."""
+    P = p ** depth
+    m = 128 * -(-(-(-n // P)) // 128)
+    pos = (m // 128) ** 2
+    lo = 0
+    while lo < depth and lo < 2 and pos * R ** lo < 1024:
+        lo += 1
+    groups = R ** lo if lo else 0
+    mo = m * p ** (depth - lo)
+    return 8 * ((mat_u + mat_v) * m * m + groups * mo * mo)
+
+
 def test_workspace_bytes_closed_form():
     s = mf.mf_algo_builtin("strassen")
     # depth 1: 4 materialised T and 4 materialised S of (n/2)^2 doubles
-    assert mf.mf_workspace_bytes(s, 1, 0, 8192) == 8 * 4096 ** 2 * 8
-    # depth 2 (Strassen composed with itself): 40 + 40 blocks of (n/4)^2
-    assert mf.mf_workspace_bytes(s, 2, 0, 8192) == 80 * 2048 ** 2 * 8
-    # depth 3: 316 + 316 blocks of (n/8)^2
-    assert mf.mf_workspace_bytes(s, 3, 0, 8192) == 632 * 1024 ** 2 * 8
+    assert mf.mf_workspace_bytes(s, 1, 0, 8192) == 8 * 4096 ** 2 * 8 == expected_ws(8192, 1, 4, 4)
+    # depth 2: 40 + 40 blocks of (n/4)^2, plus 7 group outputs of (n/2)^2
+    assert mf.mf_workspace_bytes(s, 2, 0, 8192) == 80 * 2048 ** 2 * 8 + 7 * 4096 ** 2 * 8
+    assert mf.mf_workspace_bytes(s, 2, 0, 8192) == expected_ws(8192, 2, 40, 40)
+    # depth 3: 316 + 316 blocks of (n/8)^2, plus 49 group outputs of (n/4)^2
+    assert mf.mf_workspace_bytes(s, 3, 0, 8192) == 632 * 1024 ** 2 * 8 + 49 * 2048 ** 2 * 8
     # ragged: n = 1000, leaf size rounded up to the 128 tile (500 -> 512)
-    assert mf.mf_workspace_bytes(s, 1, 0, 1000) == 8 * 512 ** 2 * 8
+    assert mf.mf_workspace_bytes(s, 1, 0, 1000) == expected_ws(1000, 1, 4, 4)
     # classical (depth 0 or cutoff >= n) needs no workspace
     assert mf.mf_workspace_bytes(s, 0, 0, 8192) == 0
     assert mf.mf_workspace_bytes(s, 2, 8192, 8192) == 0
-    # classical <3,3,3;27>: every column is a single block, no pre-addition
-    assert mf.mf_workspace_bytes(mf.mf_algo_builtin("classical3"), 1, 0, 8192) == 0
+    # classical <3,3,3;27>: every column is a single block, no pre-addition;
+    # 484 tile positions < 1024, so each product is its own group
+    c3 = mf.mf_workspace_bytes(mf.mf_algo_builtin("classical3"), 1, 0, 8192)
+    assert c3 == expected_ws(8192, 1, 0, 0, R=27, p=3) == 27 * 2816 ** 2 * 8
     w = mf.mf_algo_builtin("winograd")
-    assert mf.mf_workspace_bytes(w, 1, 0, 4096) == 8 * 2048 ** 2 * 8
+    assert mf.mf_workspace_bytes(w, 1, 0, 4096) == expected_ws(4096, 1, 4, 4)
 
 
 def test_workspace_bytes_paper_size_24012():

@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the fast bilinear matrix product on one MI355X.
+
+Metric: effective GFLOP/s = 2 n^3 / t of the fast FP64 product (Strassen-
+Winograd, Kronecker-fused depth 2 by default) at n = 8192, next to the
+library's own classical FP64 MFMA GEMM, with inputs resident in HBM.  One
+step is one whole product C = A B (pre-additions, grouped leaf GEMM with
+fused post-additions, outer post-addition).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
+                       [--algo winograd] [--depth 2] [--no-cpu-baseline]
+
+Prints one JSON line.  The `roofline` object reports the dominant kernel
+(the grouped FP64 MFMA GEMM) against the MI355X FP64 matrix peak, timed live
+with HIP events recorded by the library on the launch stream.  The
+`cpu_baseline` object times the CPU oracle on the host cores and is the only
+place this script touches the oracle (also for the sampled error check).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "effective GFLOP/s (2n^3/t) fast vs classical MFMA GEMM at stated rel. error"
+FP64_MFMA_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2312_12732_amd", "csrc", "kernels_f64.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_f64.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--algo", default="winograd")
+    ap.add_argument("--depth", type=int, default=2)
+    ap.add_argument("--cutoff", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_for(workload: str):
+    """HBM bytes per GEMM launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source for this workload."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(args, A_host, B_host, C_gpu_host):
+    """Time the CPU oracle's fast product on the same workload (bounded to
+    roughly 10-30 s) and check the GPU result on sampled rows."""
+    import numpy as np
+
+    import mf_inputs as mi
+    from oracle import algebra as oa
+    from oracle import matmul as om
+
+    table = {"winograd": mi.WINOGRAD, "strassen": mi.STRASSEN_PAPER, "strassen1969": mi.STRASSEN_1969}[args.algo]
+    U, V, W, conv = mi.as_float_tables(table)
+    alg = oa.canonical(2, U, V, W, conv)
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((p.get("num_threads", 1) for p in threadpool_info()), default=1)
+    except Exception:  # noqa: BLE001
+        cores = os.cpu_count() or 1
+    n = args.n
+    runs, elapsed = 0, 0.0
+    while runs < 3 and elapsed < 10.0:
+        t0 = time.perf_counter()
+        om.fast_mm(A_host, B_host, alg, args.depth, args.cutoff)
+        elapsed += time.perf_counter() - t0
+        runs += 1
+    gflops = runs * 2.0 * n ** 3 / elapsed / 1e9
+    rows = np.sort(np.random.default_rng(5).choice(n, size=min(n, 64), replace=False))
+    ref = om.rows_reference(A_host, B_host, rows)
+    err = om.rel_fro_error(C_gpu_host[rows], ref)
+    return ({"value": round(gflops, 2), "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
+             "sample": f"{runs} full oracle fast_mm run(s) of the same workload (n={n}, {args.algo}, "
+                       f"depth {args.depth}), numpy/OpenBLAS float64, {elapsed:.1f} s"}, err)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import mf_inputs as mi
+    from paper_2312_12732_amd import mf
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    A_host = mi.uniform(n, 10)
+    B_host = mi.uniform(n, 11)
+    A = torch.from_numpy(A_host).to(dev)
+    B = torch.from_numpy(B_host).to(dev)
+    C = torch.empty_like(A)
+    Cc = torch.empty_like(A)
+    algo = mf.mf_algo_builtin(args.algo)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(steps):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / steps
+
+    # classical MFMA GEMM of the library (context: the method's own baseline)
+    classical_ms = timed(lambda: mf.mf_classical_mm(A, B, Cc), max(3, args.steps // 2), 2)
+
+    # fast product: warm-up, then the timed region with per-phase events
+    for _ in range(args.warmup):
+        mf.mf_fastmm(algo, args.depth, args.cutoff, A, B, C)
+    torch.cuda.synchronize()
+    mf.mf_phase_timing_read()
+    mf.mf_phase_timing(True)
+    ms_per_step = timed(lambda: mf.mf_fastmm(algo, args.depth, args.cutoff, A, B, C), args.steps, 0)
+    mf.mf_phase_timing(False)
+    phase_ms, calls = mf.mf_phase_timing_read()
+    phase_avg = [x / max(1, calls) for x in phase_ms]
+
+    flops = 2.0 * n ** 3
+    value = flops / (ms_per_step * 1e-3) / 1e9
+    # algorithmic work of the dominant kernel: R^d leaf products of size n/2^d
+    R = algo.info()["R"]
+    p = algo.info()["n0"]
+    d = args.depth
+    m_true = n / p ** d
+    gemm_flops = R ** d * 2.0 * m_true ** 3
+    gemm_tflops = gemm_flops / (phase_avg[1] * 1e-3) / 1e12
+    workload = f"fp64 n={n} {args.algo} depth {d}"
+    roofline = {"bound": "mfma", "achieved": round(gemm_tflops, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(gemm_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
+                "traffic": traffic_for(workload), "kernel": "gemm_f64_grouped",
+                "kernel_ms": round(phase_avg[1], 4)}
+
+    # pre-addition phase against HBM: read A and B once, write the materialised blocks
+    mat = mf.mf_workspace_bytes(algo, d, args.cutoff, n)  # includes group outputs when split
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": workload, "n": n, "algo": args.algo, "depth": d, "cutoff": args.cutoff,
+                   "storage": "fp64", "leaf": "fp64 MFMA", "inputs": "uniform[-1,1] seeds 10, 11"},
+        "classical_ms": round(classical_ms, 4),
+        "classical_gflops": round(flops / (classical_ms * 1e-3) / 1e9, 1),
+        "speedup_vs_classical": round(classical_ms / ms_per_step, 4),
+        "phases_ms": {"preadd": round(phase_avg[0], 4), "gemm": round(phase_avg[1], 4),
+                      "postadd": round(phase_avg[2], 4)},
+        "workspace_bytes": mat,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        C_host = C.cpu().numpy()
+        cb, err = cpu_baseline(args, A_host, B_host, C_host)
+        out["cpu_baseline"] = cb
+        out["rel_err"] = float(f"{err:.3e}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

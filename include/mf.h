@@ -137,6 +137,16 @@ mf_status mf_workspace_bytes(const mf_algo* algo, int depth, int cutoff, int64_t
 mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C,
                        int64_t n, int dtype, void* workspace, size_t ws_bytes, mf_stream stream);
 
+/* Phase timing (tracing).  While enabled, every mf_fastmm / mf_fastmm_ws /
+ * mf_classical_mm call records HIP events on its stream around its three
+ * phases: 0 pre-additions, 1 grouped leaf GEMM with the fused epilogue
+ * post-addition, 2 outer post-addition.  mf_phase_timing_read waits for the
+ * recorded calls, writes the summed milliseconds of each phase to ms[0..2]
+ * and the number of calls to *calls (either pointer may be NULL), and
+ * forgets them. */
+mf_status mf_phase_timing(int enable);
+mf_status mf_phase_timing_read(double* ms, int* calls);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char* mf_last_error(void);
 

@@ -1,7 +1,10 @@
 // C ABI of the mf library: argument validation, algorithm handles, plan
 // lookup, workspace and the launch sequence of one fast product.
+#include <array>
 #include <atomic>
 #include <cmath>
+#include <mutex>
+#include <vector>
 #include <cstring>
 #include <string>
 
@@ -72,14 +75,44 @@ mf_status plan_for(const mf_algo* algo, int depth, int cutoff, int64_t n, int dt
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// Phase timing: when enabled, every call records a HIP event on its stream
+// before each phase and after the last; reading sums the elapsed times.
+struct PhaseTiming {
+  std::mutex mu;
+  bool enabled = false;
+  std::vector<std::array<hipEvent_t, kPhases + 1>> calls;
+};
+PhaseTiming& timing() {
+  static auto* t = new PhaseTiming();
+  return *t;
+}
+
 mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, hipStream_t s) {
   mf_status st = ensure_device(pl);
   if (st != MF_OK) return st;
   const bool even = pl.n % 2 == 0;
   const bool vec_in = even && aligned16(A) && aligned16(B);
   const bool vec_c = even && aligned16(C);
-  const hipError_t e = launch_plan_f64(pl, A, B, C, ws, vec_in, vec_c, s);
-  if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  std::array<hipEvent_t, kPhases + 1> ev{};
+  bool timed = false;
+  {
+    std::lock_guard<std::mutex> lk(timing().mu);
+    timed = timing().enabled;
+  }
+  if (timed) {
+    for (auto& x : ev)
+      if (hipEventCreate(&x) != hipSuccess) return fail(MF_ERR_HIP, "hipEventCreate failed");
+  }
+  for (int ph = 0; ph < kPhases; ++ph) {
+    if (timed && hipEventRecord(ev[ph], s) != hipSuccess) return fail(MF_ERR_HIP, "hipEventRecord failed");
+    const hipError_t e = launch_phase_f64(pl, ph, A, B, C, ws, vec_in, vec_c, s);
+    if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  }
+  if (timed) {
+    if (hipEventRecord(ev[kPhases], s) != hipSuccess) return fail(MF_ERR_HIP, "hipEventRecord failed");
+    std::lock_guard<std::mutex> lk(timing().mu);
+    timing().calls.push_back(ev);
+  }
   return MF_OK;
 }
 
@@ -247,6 +280,38 @@ mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int 
   st = get_plan(nullptr, 0, 0, n, dtype, &pl);
   if (st != MF_OK) return st;
   return run(*pl, A, B, C, nullptr, static_cast<hipStream_t>(stream));
+}
+
+mf_status mf_phase_timing(int enable) {
+  clear_error();
+  std::lock_guard<std::mutex> lk(timing().mu);
+  timing().enabled = enable != 0;
+  return MF_OK;
+}
+
+mf_status mf_phase_timing_read(double* ms, int* calls) {
+  clear_error();
+  std::vector<std::array<hipEvent_t, kPhases + 1>> evs;
+  {
+    std::lock_guard<std::mutex> lk(timing().mu);
+    evs.swap(timing().calls);
+  }
+  double acc[kPhases] = {0, 0, 0};
+  mf_status st = MF_OK;
+  for (auto& ev : evs) {
+    if (hipEventSynchronize(ev[kPhases]) != hipSuccess) st = fail(MF_ERR_HIP, "hipEventSynchronize failed");
+    for (int ph = 0; ph < kPhases && st == MF_OK; ++ph) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, ev[ph], ev[ph + 1]) != hipSuccess)
+        st = fail(MF_ERR_HIP, "hipEventElapsedTime failed");
+      acc[ph] += t;
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+  }
+  if (ms)
+    for (int ph = 0; ph < kPhases; ++ph) ms[ph] = acc[ph];
+  if (calls) *calls = (int)evs.size();
+  return st;
 }
 
 }  // extern "C"

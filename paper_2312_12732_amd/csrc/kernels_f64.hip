@@ -361,10 +361,10 @@ bool combine_supported(int nin) {
   }
 }
 
-hipError_t launch_plan_f64(const Plan& pl, const void* A, const void* B, void* C, void* ws, bool vec_in, bool vec_c,
-                           hipStream_t s) {
-  hipError_t e = launch_combine(pl.pre, (int)pl.m, A, B, C, ws, vec_in, vec_c, s);
-  if (e != hipSuccess) return e;
+hipError_t launch_phase_f64(const Plan& pl, int phase, const void* A, const void* B, void* C, void* ws, bool vec_in,
+                            bool vec_c, hipStream_t s) {
+  if (phase == 0) return launch_combine(pl.pre, (int)pl.m, A, B, C, ws, vec_in, vec_c, s);
+  if (phase == 2) return launch_combine(pl.post, (int)pl.m_outer, A, B, C, ws, vec_in, vec_c, s);
   GemmArgs g;
   g.A = static_cast<const double*>(A);
   g.B = static_cast<const double*>(B);
@@ -379,9 +379,7 @@ hipError_t launch_plan_f64(const Plan& pl, const void* A, const void* B, void* C
   g.vec_in = vec_in ? 1 : 0;
   const unsigned grid = (unsigned)g.tiles * (unsigned)g.tiles * (unsigned)g.groups;
   hipLaunchKernelGGL(gemm_f64_grouped, dim3(grid), dim3(NTHREADS), 0, s, g);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_combine(pl.post, (int)pl.m_outer, A, B, C, ws, vec_in, vec_c, s);
+  return hipGetLastError();
 }
 
 }  // namespace mf

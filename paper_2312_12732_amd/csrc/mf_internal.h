@@ -169,10 +169,12 @@ constexpr int kLeafTile = 128;
 // Launchers (kernels.hip)
 // ---------------------------------------------------------------------------
 
-// Enqueues pre-addition, grouped GEMM and (if any) outer post-addition.
-// vec_in / vec_c: rows of A and B / of C are 16-byte aligned.
-hipError_t launch_plan_f64(const Plan& pl, const void* A, const void* B, void* C, void* ws, bool vec_in, bool vec_c,
-                           hipStream_t s);
+// Enqueues one phase of a plan: 0 pre-addition, 1 grouped GEMM with the
+// epilogue post-addition, 2 outer post-addition (phases with no work enqueue
+// nothing).  vec_in / vec_c: rows of A and B / of C are 16-byte aligned.
+constexpr int kPhases = 3;
+hipError_t launch_phase_f64(const Plan& pl, int phase, const void* A, const void* B, void* C, void* ws, bool vec_in,
+                            bool vec_c, hipStream_t s);
 // Input counts with a compiled linear-combination kernel.
 bool combine_supported(int nin);
 

@@ -36,7 +36,7 @@ MF_W_DEEPMIND_CT = 1
 
 EXPORTED = ["mf_algo_from_uvw", "mf_algo_builtin", "mf_algo_compose", "mf_algo_rebase", "mf_algo_info",
             "mf_algo_get_uvw", "mf_algo_free", "mf_fastmm", "mf_classical_mm", "mf_workspace_bytes",
-            "mf_fastmm_ws", "mf_last_error"]
+            "mf_fastmm_ws", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read"]
 
 
 class MFError(RuntimeError):
@@ -68,6 +68,8 @@ def _load():
         "mf_workspace_bytes": ([P, I, I, I64, I, ctypes.POINTER(ctypes.c_size_t)], I),
         "mf_fastmm_ws": ([P, I, I, P, P, P, I64, I, P, ctypes.c_size_t, P], I),
         "mf_last_error": ([], ctypes.c_char_p),
+        "mf_phase_timing": ([I], I),
+        "mf_phase_timing_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -213,3 +215,16 @@ def mf_workspace_bytes(algo: Algo, depth: int, cutoff: int, n: int, dtype_code: 
 
 def mf_last_error() -> str:
     return lib.mf_last_error().decode()
+
+
+def mf_phase_timing(enable: bool):
+    """Enable or disable per-phase HIP-event timing of every call."""
+    _check(lib.mf_phase_timing(1 if enable else 0))
+
+
+def mf_phase_timing_read():
+    """(summed ms of [pre-add, GEMM, post-add], number of calls) since the last read."""
+    ms = (ctypes.c_double * 3)()
+    calls = ctypes.c_int()
+    _check(lib.mf_phase_timing_read(ms, ctypes.byref(calls)))
+    return list(ms), calls.value

@@ -56,7 +56,6 @@ mf_status check_request(const mf_algo* algo, bool need_algo, int depth, int cuto
     return fail(MF_ERR_ARG, "unknown dtype code");
   if (storage == MF_F64 && leaf != 0)
     return fail(MF_ERR_UNSUPPORTED, "reduced-precision leaves need FP32 storage");
-  if (storage == MF_F32) return fail(MF_ERR_UNSUPPORTED, "FP32 storage is not implemented in this build");
   if (n == 0) return MF_OK;
   if (!A || !B || !C) return fail(MF_ERR_ARG, "A, B and C must be non-NULL");
   const size_t elem = storage == MF_F64 ? 8 : 4;
@@ -90,9 +89,12 @@ PhaseTiming& timing() {
 mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, hipStream_t s) {
   mf_status st = ensure_device(pl);
   if (st != MF_OK) return st;
-  const bool even = pl.n % 2 == 0;
-  const bool vec_in = even && aligned16(A) && aligned16(B);
-  const bool vec_c = even && aligned16(C);
+  // Rows start on 16-byte boundaries when the bases do and a row is a whole
+  // number of 16-byte units.
+  const bool rows16 = (pl.n * (int64_t)pl.elem) % 16 == 0;
+  const bool vec_in = rows16 && aligned16(A) && aligned16(B);
+  const bool vec_c = rows16 && aligned16(C);
+  const int leaf = (pl.dtype >> 8) & 0xff;
   std::array<hipEvent_t, kPhases + 1> ev{};
   bool timed = false;
   {
@@ -105,7 +107,17 @@ mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, h
   }
   for (int ph = 0; ph < kPhases; ++ph) {
     if (timed && hipEventRecord(ev[ph], s) != hipSuccess) return fail(MF_ERR_HIP, "hipEventRecord failed");
-    const hipError_t e = launch_phase_f64(pl, ph, A, B, C, ws, vec_in, vec_c, s);
+    hipError_t e;
+    if (ph == 0)
+      e = launch_combine(pl.pre, (int)pl.elem, (int)pl.m, A, B, C, ws, vec_in, vec_c, s);
+    else if (ph == 2)
+      e = launch_combine(pl.post, (int)pl.elem, (int)pl.m_outer, A, B, C, ws, vec_in, vec_c, s);
+    else if (pl.elem == 8)
+      e = launch_gemm_f64(pl, A, B, C, ws, vec_in, s);
+    else if (leaf == 2 || leaf == 3)
+      e = launch_gemm_bf16(pl, leaf == 3, A, B, C, ws, vec_in, s);
+    else
+      e = launch_gemm_f32(pl, A, B, C, ws, vec_in, s);
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   }
   if (timed) {

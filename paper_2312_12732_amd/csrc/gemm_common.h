@@ -1,0 +1,80 @@
+// Device-side pieces shared by the grouped GEMM kernels (FP64 / FP32 MFMA
+// leaves and BF16 MFMA leaves): kernel arguments, the workgroup -> (group,
+// tile) map, and the epilogue post-addition of one output element.
+#pragma once
+
+#include "mf_internal.h"
+
+namespace mf {
+
+// Output tile of every grouped GEMM kernel; leaf sizes are multiples of it.
+constexpr int GEMM_BM = 128, GEMM_BN = 128;
+static_assert(GEMM_BM == kLeafTile && GEMM_BN == kLeafTile, "leaf tile and GEMM tile must agree");
+
+template <class T>
+struct GemmArgs {
+  const T* A;
+  const T* B;
+  T* C;
+  T* ws;
+  const ProdDesc* prods;
+  const EpiDesc* epis;
+  const int32_t* group_beg;  // products of group g: [group_beg[g], group_beg[g+1])
+  int groups;
+  int m;       // M = N = K of every leaf product
+  int tiles;   // tiles per side (m / 128)
+  int vec_in;  // A and B rows are 16-byte aligned
+};
+
+template <class T>
+__device__ __forceinline__ const T* src_ptr(const GemmArgs<T>& g, int src) {
+  const T* p = g.ws;
+  p = src == SRC_A ? g.A : p;
+  p = src == SRC_B ? g.B : p;
+  p = src == SRC_C ? g.C : p;
+  return p;
+}
+
+template <class T>
+__device__ __forceinline__ T* dst_ptr(const GemmArgs<T>& g, int dst) {
+  return dst == SRC_C ? g.C : g.ws;
+}
+
+// Map a workgroup id to (group, tile position).  Workgroups are dealt
+// round-robin to the 8 XCDs; regroup so that each XCD works on a contiguous
+// range of (group, position) pairs, and walk positions in bands of 8 tile
+// rows so that concurrently running tiles share operand panels in the XCD's
+// L2.
+__device__ __forceinline__ void work_of(int b, int tiles, int groups, int* grp, int* ti, int* tj) {
+  const int G = tiles * tiles;
+  const int total = G * groups;
+  int L = b;
+  if ((total & 7) == 0) L = (b & 7) * (total >> 3) + (b >> 3);
+  *grp = L / G;
+  L -= *grp * G;
+  constexpr int BAND = 8;
+  const int per_band = BAND * tiles;
+  const int band = L / per_band;
+  const int first = band * BAND;
+  const int rows = min(BAND, tiles - first);
+  const int in = L - band * per_band;
+  *ti = first + in % rows;
+  *tj = in / rows;
+}
+
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Post-addition of one output element: first == 1 stores coef * v, 0 adds
+// coef * v (fused multiply-add), 2 stores zero.
+template <class T>
+__device__ __forceinline__ void epi_apply(T* p, int first, T coef, T v) {
+  if (first == 1)
+    *p = coef * v;
+  else if (first == 2)
+    *p = T(0);
+  else
+    *p = fma_t(coef, v, *p);
+}
+
+}  // namespace mf

@@ -1,0 +1,173 @@
+// Linear combination of matrix blocks (GEMA) for gfx950, in FP64 or FP32:
+// the pre-additions T_r = sum_k U[k,r] A_k, S_r = sum_l V[l,r] B_l of a fused
+// level and its outer post-addition C_c = sum_g W_outer[c,g] P_g (equation
+// "strassen", Section 2 of the paper).  HBM-bound: every input element is
+// read once and every output element written once.
+#include "gemm_common.h"
+
+namespace mf {
+
+template <class T>
+struct CombArgs {
+  const T* A;
+  const T* B;
+  T* C;
+  T* ws;
+  const CombIn* ins;     // NIN per operand set
+  const CombOut* outs;
+  const double* coef;    // NIN per output
+  int out_beg[3];        // outputs of set y: [out_beg[y], out_beg[y+1])
+  int m;
+  int vec_in;            // input views with src A/B/C have 16-byte aligned rows
+  int vec_out;           // output views with dst C have 16-byte aligned rows
+  int full[2];           // set y: every view has full extent and aligned rows
+};
+
+template <class T>
+__device__ __forceinline__ const T* comb_src(const CombArgs<T>& g, int src) {
+  const T* p = g.ws;
+  p = src == SRC_A ? g.A : p;
+  p = src == SRC_B ? g.B : p;
+  p = src == SRC_C ? g.C : p;
+  return p;
+}
+
+template <class T>
+__device__ __forceinline__ T* comb_dst(const CombArgs<T>& g, int dst) {
+  return dst == SRC_C ? g.C : g.ws;
+}
+
+template <class T, int NIN, int VEC, bool FULL>
+__device__ __forceinline__ void combine_body(const CombArgs<T>& g, int op, int i, int j) {
+  typedef T tv __attribute__((ext_vector_type(VEC)));
+  const CombIn* ins = g.ins + op * NIN;
+  tv in[NIN];
+#pragma unroll
+  for (int k = 0; k < NIN; ++k) {
+    const CombIn v = ins[k];
+    const T* p = comb_src(g, v.src) + v.off + (int64_t)i * v.ld + j;
+    if (FULL) {
+      in[k] = *reinterpret_cast<const tv*>(p);
+    } else {
+      const bool vec = v.src == SRC_WS || g.vec_in;
+      if (vec && i < v.vr && j + VEC <= v.vc) {
+        in[k] = *reinterpret_cast<const tv*>(p);
+      } else {
+        tv x;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) x[q] = (i < v.vr && j + q < v.vc) ? p[q] : T(0);
+        in[k] = x;
+      }
+    }
+  }
+  for (int o = g.out_beg[op]; o < g.out_beg[op + 1]; ++o) {
+    const CombOut po = g.outs[o];
+    const double* c = g.coef + po.coef_off;
+    tv acc;
+    bool started = false;
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      const T ck = (T)c[k];
+      if (ck != T(0)) {
+        if (!started) {
+          acc = ck == T(1) ? in[k] : ck * in[k];
+          started = true;
+        } else {
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) acc[q] = fma_t(ck, in[k][q], acc[q]);
+        }
+      }
+    }
+    if (!started) acc = (tv)(T(0));
+    T* p = comb_dst(g, po.dst) + po.off + (int64_t)i * po.ld + j;
+    if (FULL) {
+      *reinterpret_cast<tv*>(p) = acc;
+    } else {
+      if (i >= po.vr) continue;
+      const bool vec = po.dst == SRC_WS || g.vec_out;
+      if (vec && j + VEC <= po.vc) {
+        *reinterpret_cast<tv*>(p) = acc;
+      } else {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q)
+          if (j + q < po.vc) p[q] = acc[q];
+      }
+    }
+  }
+}
+
+// Every thread owns VEC consecutive elements at one position (i, j) of the
+// m x m blocks, reads that position of all NIN input views once and writes it
+// to every output of its operand set (blockIdx.y selects the set).  Inputs
+// outside a view's valid extent are zero; outputs outside a view's valid
+// extent are not written.  Sets whose views all have full extent and aligned
+// rows take a branch-free path.
+template <class T, int NIN, int VEC>
+__global__ void __launch_bounds__(256) combine(CombArgs<T> g) {
+  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  const int64_t mm = (int64_t)g.m * g.m;
+  if (e >= mm) return;
+  const int i = (int)(e / g.m), j = (int)(e % g.m);
+  const int op = blockIdx.y;
+  if (g.full[op])
+    combine_body<T, NIN, VEC, true>(g, op, i, j);
+  else
+    combine_body<T, NIN, VEC, false>(g, op, i, j);
+}
+
+#ifndef MF_COMB_VEC_SMALL
+#define MF_COMB_VEC_SMALL 2
+#endif
+
+template <class T>
+static hipError_t launch_combine_t(const CombineStage& cs, int m, const void* A, const void* B, void* C, void* ws,
+                                   bool vec_in, bool vec_out, hipStream_t s) {
+  if (cs.n_sets == 0) return hipSuccess;
+  CombArgs<T> g;
+  g.A = static_cast<const T*>(A);
+  g.B = static_cast<const T*>(B);
+  g.C = static_cast<T*>(C);
+  g.ws = static_cast<T*>(ws);
+  g.ins = cs.d_ins;
+  g.outs = cs.d_outs;
+  g.coef = cs.d_coef;
+  for (int y = 0; y < 3; ++y) g.out_beg[y] = cs.out_beg[y];
+  g.m = m;
+  g.vec_in = vec_in ? 1 : 0;
+  g.vec_out = vec_out ? 1 : 0;
+  for (int y = 0; y < 2; ++y) g.full[y] = cs.full[y] && vec_in && vec_out ? 1 : 0;
+  const int64_t mm = (int64_t)m * m;
+  auto grid = [&](int vec) { return dim3((unsigned)((mm / vec + 255) / 256), (unsigned)cs.n_sets, 1); };
+  switch (cs.nin) {
+#define MF_COMB_CASE(N, V) \
+  case N: hipLaunchKernelGGL((combine<T, N, V>), grid(V), dim3(256), 0, s, g); break;
+    MF_COMB_CASE(4, MF_COMB_VEC_SMALL)
+    MF_COMB_CASE(7, MF_COMB_VEC_SMALL)
+    MF_COMB_CASE(9, MF_COMB_VEC_SMALL)
+    MF_COMB_CASE(16, MF_COMB_VEC_SMALL)
+    MF_COMB_CASE(27, 1)
+    MF_COMB_CASE(36, 1)
+    MF_COMB_CASE(49, 1)
+    MF_COMB_CASE(64, 1)
+    MF_COMB_CASE(81, 1)
+#undef MF_COMB_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+bool combine_supported(int nin) {
+  switch (nin) {
+    case 4: case 7: case 9: case 16: case 27: case 36: case 49: case 64: case 81: return true;
+    default: return false;
+  }
+}
+
+hipError_t launch_combine(const CombineStage& cs, int elem, int m, const void* A, const void* B, void* C, void* ws,
+                          bool vec_in, bool vec_out, hipStream_t s) {
+  return elem == 8 ? launch_combine_t<double>(cs, m, A, B, C, ws, vec_in, vec_out, s)
+                   : launch_combine_t<float>(cs, m, A, B, C, ws, vec_in, vec_out, s);
+}
+
+}  // namespace mf

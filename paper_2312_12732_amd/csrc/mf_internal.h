@@ -105,6 +105,7 @@ struct CombineStage {
   int nin = 0;
   int n_sets = 0;
   int out_beg[3] = {0, 0, 0};
+  int full[2] = {0, 0};  // set y: all input and output views have full extent m x m
   std::vector<CombIn> ins;
   std::vector<CombOut> outs;
   std::vector<double> coef;
@@ -169,12 +170,17 @@ constexpr int kLeafTile = 128;
 // Launchers (kernels.hip)
 // ---------------------------------------------------------------------------
 
-// Enqueues one phase of a plan: 0 pre-addition, 1 grouped GEMM with the
-// epilogue post-addition, 2 outer post-addition (phases with no work enqueue
-// nothing).  vec_in / vec_c: rows of A and B / of C are 16-byte aligned.
-constexpr int kPhases = 3;
-hipError_t launch_phase_f64(const Plan& pl, int phase, const void* A, const void* B, void* C, void* ws, bool vec_in,
-                            bool vec_c, hipStream_t s);
+// Kernel launchers.  vec_in / vec_out: rows of A and B / of C start on
+// 16-byte boundaries.
+constexpr int kPhases = 3;  // pre-addition, grouped GEMM, outer post-addition
+hipError_t launch_combine(const CombineStage& cs, int elem, int m, const void* A, const void* B, void* C, void* ws,
+                          bool vec_in, bool vec_out, hipStream_t s);
+hipError_t launch_gemm_f64(const Plan& pl, const void* A, const void* B, void* C, void* ws, bool vec_in,
+                           hipStream_t s);
+hipError_t launch_gemm_f32(const Plan& pl, const void* A, const void* B, void* C, void* ws, bool vec_in,
+                           hipStream_t s);
+hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
+                            hipStream_t s);
 // Input counts with a compiled linear-combination kernel.
 bool combine_supported(int nin);
 

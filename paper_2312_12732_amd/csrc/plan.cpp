@@ -57,6 +57,20 @@ View block_view(int k, int P, int64_t m, int64_t n) {
   return v;
 }
 
+// Marks the operand sets of a stage whose views all cover a full m x m block
+// (no virtual padding), which run on the kernel's branch-free path.
+void set_full(CombineStage* cs, int64_t m) {
+  for (int y = 0; y < cs->n_sets; ++y) {
+    bool full = true;
+    for (int k = 0; k < cs->nin; ++k) {
+      const CombIn& v = cs->ins[(size_t)y * cs->nin + k];
+      full = full && v.vr == m && v.vc == m;
+    }
+    for (int o = cs->out_beg[y]; o < cs->out_beg[y + 1]; ++o) full = full && cs->outs[o].vr == m && cs->outs[o].vc == m;
+    cs->full[y] = full ? 1 : 0;
+  }
+}
+
 // Workgroups wanted in the grouped GEMM before outer levels are split off.
 constexpr int64_t kMinWorkgroups = 1024;
 
@@ -179,6 +193,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, P
   }
   pre.out_beg[2] = (int)pre.outs.size();
   pre.n_sets = pre.outs.empty() ? 0 : 2;
+  set_full(&pre, m);
   const int64_t pbuf_base = (int64_t)slots * mm;  // group output buffers follow the T/S slots
 
   // ---- grouped leaf products with epilogue post-addition
@@ -298,6 +313,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, P
     }
     post.out_beg[1] = post.out_beg[2] = (int)post.outs.size();
     post.n_sets = 1;
+    set_full(&post, mo);
     ws_elems += (size_t)Ro * (size_t)mo * (size_t)mo;
   }
   pl->ws_bytes = ws_elems * pl->elem;

@@ -1,0 +1,131 @@
+"""GPU parity of the precision form: FP32 storage and additions, leaves in
+FP32, BF16 (FP32 accumulation) or split-BF16x3, through the C ABI.
+
+Reference: the FP64 CPU oracle applied to the FP32-rounded inputs, so input
+rounding is excluded from the measured error.
+
+Exactness pin: on integer inputs in [-8, 8] every intermediate of the
+algorithm is an integer small enough to be exact in the leaf precision
+(|T|, |S| <= 16 * 8 = 128 <= 256 at depth <= 2 is exact in BF16's 8-bit
+significand; products and sums stay below 2^24, exact in FP32), so every mode
+must match the integer product bit for bit.  At depth 3 |T| reaches 512,
+which BF16 rounds but the split form represents exactly (hi + lo).
+
+Tolerances (normwise, ||C_hat - C||_F / ||C||_F, uniform[-1,1], n <= 1024,
+depth <= 3): FP32 leaves 2e-5, BF16 leaves 1e-1, BF16x3 leaves 5e-4.  They are
+a factor of about 10 above the unit roundoff of the leaf format times the
+growth of Strassen's normwise error bound over three levels (FP32 u = 6e-8,
+BF16 u = 3.9e-3; BF16x3 products carry about 16 significant bits, FP32
+accumulation dominates)."""
+import numpy as np
+import pytest
+
+import mf_inputs as mi
+from oracle import algebra as oa
+from oracle import matmul as om
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mf = pytest.importorskip("paper_2312_12732_amd.mf", reason="libmf.so not built")
+
+LEAVES = {"f32": mf.MF_LEAF_F32, "bf16": mf.MF_LEAF_BF16, "bf16x3": mf.MF_LEAF_BF16X3}
+TOL = {"f32": 2e-5, "bf16": 1e-1, "bf16x3": 5e-4}
+
+
+def dev32(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to("cuda:0")
+
+
+def run(algo, depth, A, B, leaf):
+    dA, dB = dev32(A), dev32(B)
+    dC = torch.full_like(dA, float("nan"))
+    if algo is None:
+        mf.mf_classical_mm(dA, dB, dC) if leaf == mf.MF_LEAF_NATIVE else mf.mf_fastmm(
+            mf.mf_algo_builtin("strassen"), 0, 0, dA, dB, dC, leaf=leaf)
+    else:
+        mf.mf_fastmm(algo, depth, 0, dA, dB, dC, leaf=leaf)
+    torch.cuda.synchronize()
+    return dC.cpu().numpy().astype(np.float64)
+
+
+def ref64(A, B):
+    return om.classical_mm(A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("leaf", list(LEAVES))
+@pytest.mark.parametrize("depth", [0, 1, 2])
+@pytest.mark.parametrize("n", [256, 300])
+def test_int_exact(leaf, depth, n):
+    A = mi.int_uniform(n, 3).astype(np.float64)
+    B = mi.int_uniform(n, 4).astype(np.float64)
+    got = run(mf.mf_algo_builtin("strassen"), depth, A, B, LEAVES[leaf])
+    assert np.array_equal(got, A @ B)
+
+
+@pytest.mark.parametrize("leaf", ["f32", "bf16x3"])
+def test_int_exact_depth3(leaf):
+    A = mi.int_uniform(512, 5).astype(np.float64)
+    B = mi.int_uniform(512, 6).astype(np.float64)
+    got = run(mf.mf_algo_builtin("winograd"), 3, A, B, LEAVES[leaf])
+    assert np.array_equal(got, A @ B)
+
+
+def test_native_fp32_storage_is_f32_leaf():
+    A = mi.uniform(512, 1)
+    B = mi.uniform(512, 2)
+    s = mf.mf_algo_builtin("strassen")
+    assert np.array_equal(run(s, 1, A, B, mf.MF_LEAF_NATIVE), run(s, 1, A, B, mf.MF_LEAF_F32))
+
+
+def test_fp32_classical():
+    A = mi.uniform(1024, 1)
+    B = mi.uniform(1024, 2)
+    err = om.rel_fro_error(run(None, 0, A, B, mf.MF_LEAF_NATIVE), ref64(A, B))
+    assert err < 2e-6
+
+
+@pytest.mark.parametrize("leaf", list(LEAVES))
+@pytest.mark.parametrize("depth", [0, 1, 2, 3])
+def test_uniform_error(leaf, depth):
+    n = 1024
+    A = mi.uniform(n, 20)
+    B = mi.uniform(n, 21)
+    err = om.rel_fro_error(run(mf.mf_algo_builtin("winograd"), depth, A, B, LEAVES[leaf]), ref64(A, B))
+    assert err < TOL[leaf], err
+
+
+def test_bf16x3_recovers_accuracy():
+    n = 1024
+    A = mi.uniform(n, 20)
+    B = mi.uniform(n, 21)
+    s = mf.mf_algo_builtin("strassen")
+    e1 = om.rel_fro_error(run(s, 1, A, B, LEAVES["bf16"]), ref64(A, B))
+    e3 = om.rel_fro_error(run(s, 1, A, B, LEAVES["bf16x3"]), ref64(A, B))
+    assert e3 < e1 / 50
+
+
+@pytest.mark.parametrize("leaf", list(LEAVES))
+def test_scaled_inputs_normwise(leaf):
+    # rows and columns scaled by log-uniform factors in [1e-4, 1e4]; the
+    # normwise bound relative to ||A|| ||B|| holds, with the same tolerance.
+    n = 512
+    A = mi.scaled(n, 22, 23, 24).astype(np.float32).astype(np.float64)
+    B = mi.scaled(n, 25, 26, 27).astype(np.float32).astype(np.float64)
+    ref = ref64(A, B)
+    got = run(mf.mf_algo_builtin("strassen"), 2, A, B, LEAVES[leaf])
+    err = np.linalg.norm(got - ref) / (np.linalg.norm(A) * np.linalg.norm(B))
+    assert err < TOL[leaf]
+
+
+def test_precision_determinism():
+    A = dev32(mi.uniform(512, 1))
+    B = dev32(mi.uniform(512, 2))
+    s = mf.mf_algo_builtin("winograd")
+    for leaf in LEAVES.values():
+        C1 = torch.empty_like(A)
+        C2 = torch.empty_like(A)
+        mf.mf_fastmm(s, 2, 0, A, B, C1, leaf=leaf)
+        mf.mf_fastmm(s, 2, 0, A, B, C2, leaf=leaf)
+        torch.cuda.synchronize()
+        assert torch.equal(C1, C2)

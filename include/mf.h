@@ -113,9 +113,10 @@ mf_status mf_algo_get_uvw(const mf_algo* a, double* U, double* V, double* W);
 /* Release an algorithm (NULL is ignored). */
 void mf_algo_free(mf_algo* a);
 
-/* C = A B with `depth` levels of `algo`.  A level is taken while levels
- * remain and the current size exceeds `cutoff`; depth 0 (or cutoff >= n) is
- * the classical product.  Sizes that the split factor does not divide are
+/* C = A B with up to `depth` levels of `algo`.  A level is taken while
+ * levels remain, the current size exceeds `cutoff` and the 128 leaf tile, and
+ * the number of leaf products stays within 2^16 (sizes are rounded up at each
+ * split); depth 0 (or cutoff >= n) is the classical product.  Sizes that the split factor does not divide are
  * handled by virtual zero padding (no copy of A, B or C).  Temporaries come
  * from a stream-ordered pool owned by the library.  A, B, C: device
  * pointers to n x n matrices of the storage type of `dtype`. */

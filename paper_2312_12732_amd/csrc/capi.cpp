@@ -107,12 +107,14 @@ mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, h
   }
   for (int ph = 0; ph < kPhases; ++ph) {
     if (timed && hipEventRecord(ev[ph], s) != hipSuccess) return fail(MF_ERR_HIP, "hipEventRecord failed");
-    hipError_t e;
-    if (ph == 0)
-      e = launch_combine(pl.pre, (int)pl.elem, (int)pl.m, A, B, C, ws, vec_in, vec_c, s);
-    else if (ph == 2)
-      e = launch_combine(pl.post, (int)pl.elem, (int)pl.m_outer, A, B, C, ws, vec_in, vec_c, s);
-    else if (pl.elem == 8)
+    hipError_t e = hipSuccess;
+    if (ph == 0) {
+      for (const CombineStage& st : pl.pre)
+        if (e == hipSuccess) e = launch_combine(st, (int)pl.elem, A, B, C, ws, vec_in, vec_c, s);
+    } else if (ph == 2) {
+      for (const CombineStage& st : pl.post)
+        if (e == hipSuccess) e = launch_combine(st, (int)pl.elem, A, B, C, ws, vec_in, vec_c, s);
+    } else if (pl.elem == 8)
       e = launch_gemm_f64(pl, A, B, C, ws, vec_in, s);
     else if (leaf == 2 || leaf == 3)
       e = launch_gemm_bf16(pl, leaf == 3, A, B, C, ws, vec_in, s);

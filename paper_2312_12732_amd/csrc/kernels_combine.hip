@@ -13,14 +13,13 @@ struct CombArgs {
   const T* B;
   T* C;
   T* ws;
-  const CombIn* ins;     // NIN per operand set
+  const CombSet* sets;   // one per blockIdx.y
+  const CombIn* ins;     // NIN per set
   const CombOut* outs;
   const double* coef;    // NIN per output
-  int out_beg[3];        // outputs of set y: [out_beg[y], out_beg[y+1])
   int m;
   int vec_in;            // input views with src A/B/C have 16-byte aligned rows
   int vec_out;           // output views with dst C have 16-byte aligned rows
-  int full[2];           // set y: every view has full extent and aligned rows
 };
 
 template <class T>
@@ -38,9 +37,9 @@ __device__ __forceinline__ T* comb_dst(const CombArgs<T>& g, int dst) {
 }
 
 template <class T, int NIN, int VEC, bool FULL>
-__device__ __forceinline__ void combine_body(const CombArgs<T>& g, int op, int i, int j) {
+__device__ __forceinline__ void combine_body(const CombArgs<T>& g, const CombSet& set, int i, int j) {
   typedef T tv __attribute__((ext_vector_type(VEC)));
-  const CombIn* ins = g.ins + op * NIN;
+  const CombIn* ins = g.ins + set.in_beg;
   tv in[NIN];
 #pragma unroll
   for (int k = 0; k < NIN; ++k) {
@@ -60,7 +59,7 @@ __device__ __forceinline__ void combine_body(const CombArgs<T>& g, int op, int i
       }
     }
   }
-  for (int o = g.out_beg[op]; o < g.out_beg[op + 1]; ++o) {
+  for (int o = set.out_beg; o < set.out_end; ++o) {
     const CombOut po = g.outs[o];
     const double* c = g.coef + po.coef_off;
     tv acc;
@@ -97,8 +96,8 @@ __device__ __forceinline__ void combine_body(const CombArgs<T>& g, int op, int i
 }
 
 // Every thread owns VEC consecutive elements at one position (i, j) of the
-// m x m blocks, reads that position of all NIN input views once and writes it
-// to every output of its operand set (blockIdx.y selects the set).  Inputs
+// m x m blocks, reads that position of all NIN input views of its set
+// (blockIdx.y) once and writes it to every output of the set.  Inputs
 // outside a view's valid extent are zero; outputs outside a view's valid
 // extent are not written.  Sets whose views all have full extent and aligned
 // rows take a branch-free path.
@@ -108,41 +107,41 @@ __global__ void __launch_bounds__(256) combine(CombArgs<T> g) {
   const int64_t mm = (int64_t)g.m * g.m;
   if (e >= mm) return;
   const int i = (int)(e / g.m), j = (int)(e % g.m);
-  const int op = blockIdx.y;
-  if (g.full[op])
-    combine_body<T, NIN, VEC, true>(g, op, i, j);
+  const CombSet set = g.sets[blockIdx.y];
+  if (set.full && g.vec_in && g.vec_out)
+    combine_body<T, NIN, VEC, true>(g, set, i, j);
   else
-    combine_body<T, NIN, VEC, false>(g, op, i, j);
+    combine_body<T, NIN, VEC, false>(g, set, i, j);
 }
 
 #ifndef MF_COMB_VEC_SMALL
-#define MF_COMB_VEC_SMALL 2
+#define MF_COMB_VEC_SMALL 4
 #endif
 
 template <class T>
-static hipError_t launch_combine_t(const CombineStage& cs, int m, const void* A, const void* B, void* C, void* ws,
+static hipError_t launch_combine_t(const CombineStage& cs, const void* A, const void* B, void* C, void* ws,
                                    bool vec_in, bool vec_out, hipStream_t s) {
-  if (cs.n_sets == 0) return hipSuccess;
+  if (cs.sets.empty()) return hipSuccess;
   CombArgs<T> g;
   g.A = static_cast<const T*>(A);
   g.B = static_cast<const T*>(B);
   g.C = static_cast<T*>(C);
   g.ws = static_cast<T*>(ws);
+  g.sets = cs.d_sets;
   g.ins = cs.d_ins;
   g.outs = cs.d_outs;
   g.coef = cs.d_coef;
-  for (int y = 0; y < 3; ++y) g.out_beg[y] = cs.out_beg[y];
-  g.m = m;
+  g.m = (int)cs.m;
   g.vec_in = vec_in ? 1 : 0;
   g.vec_out = vec_out ? 1 : 0;
-  for (int y = 0; y < 2; ++y) g.full[y] = cs.full[y] && vec_in && vec_out ? 1 : 0;
-  const int64_t mm = (int64_t)m * m;
-  auto grid = [&](int vec) { return dim3((unsigned)((mm / vec + 255) / 256), (unsigned)cs.n_sets, 1); };
+  const int64_t mm = cs.m * cs.m;
+  auto grid = [&](int vec) { return dim3((unsigned)((mm / vec + 255) / 256), (unsigned)cs.sets.size(), 1); };
   switch (cs.nin) {
 #define MF_COMB_CASE(N, V) \
   case N: hipLaunchKernelGGL((combine<T, N, V>), grid(V), dim3(256), 0, s, g); break;
     MF_COMB_CASE(4, MF_COMB_VEC_SMALL)
     MF_COMB_CASE(7, MF_COMB_VEC_SMALL)
+    MF_COMB_CASE(8, MF_COMB_VEC_SMALL)
     MF_COMB_CASE(9, MF_COMB_VEC_SMALL)
     MF_COMB_CASE(16, MF_COMB_VEC_SMALL)
     MF_COMB_CASE(27, 1)
@@ -159,15 +158,15 @@ static hipError_t launch_combine_t(const CombineStage& cs, int m, const void* A,
 
 bool combine_supported(int nin) {
   switch (nin) {
-    case 4: case 7: case 9: case 16: case 27: case 36: case 49: case 64: case 81: return true;
+    case 4: case 7: case 8: case 9: case 16: case 27: case 36: case 49: case 64: case 81: return true;
     default: return false;
   }
 }
 
-hipError_t launch_combine(const CombineStage& cs, int elem, int m, const void* A, const void* B, void* C, void* ws,
+hipError_t launch_combine(const CombineStage& cs, int elem, const void* A, const void* B, void* C, void* ws,
                           bool vec_in, bool vec_out, hipStream_t s) {
-  return elem == 8 ? launch_combine_t<double>(cs, m, A, B, C, ws, vec_in, vec_out, s)
-                   : launch_combine_t<float>(cs, m, A, B, C, ws, vec_in, vec_out, s);
+  return elem == 8 ? launch_combine_t<double>(cs, A, B, C, ws, vec_in, vec_out, s)
+                   : launch_combine_t<float>(cs, A, B, C, ws, vec_in, vec_out, s);
 }
 
 }  // namespace mf

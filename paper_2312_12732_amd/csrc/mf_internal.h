@@ -99,16 +99,25 @@ struct CombOut {
   int32_t pad_;
 };
 
-// A linear-combination stage over m x m blocks: n_sets operand sets (blockIdx.y),
-// each with `nin` input views and outputs [out_beg[y], out_beg[y+1]).
+// One operand set of a linear-combination stage: `nin` input views starting
+// at ins[in_beg] and the outputs [out_beg, out_end).  full: every view covers
+// its whole m x m block (no virtual padding).
+struct CombSet {
+  int32_t in_beg;
+  int32_t out_beg, out_end;
+  int32_t full;
+};
+
+// A linear-combination launch over m x m blocks: one operand set per
+// blockIdx.y.
 struct CombineStage {
   int nin = 0;
-  int n_sets = 0;
-  int out_beg[3] = {0, 0, 0};
-  int full[2] = {0, 0};  // set y: all input and output views have full extent m x m
+  int64_t m = 0;
+  std::vector<CombSet> sets;
   std::vector<CombIn> ins;
   std::vector<CombOut> outs;
   std::vector<double> coef;
+  mutable CombSet* d_sets = nullptr;
   mutable CombIn* d_ins = nullptr;
   mutable CombOut* d_outs = nullptr;
   mutable double* d_coef = nullptr;
@@ -118,14 +127,18 @@ struct CombineStage {
 // Plans
 // ---------------------------------------------------------------------------
 
-// Execution plan of one request.  The `levels` recursion levels run as one
-// fused level of split factor P = p^levels (composition of the algorithm
-// with itself).  Its products are split into groups by the first
-// `levels_outer` levels: group g computes the inner product P_g (size
-// m_outer = P_inner * m) with the post-addition of the inner levels fused
-// into the GEMM epilogue, and a final linear combination applies the outer
-// post-addition C_c = sum_g W_outer[c,g] P_g.  With levels_outer = 0 there is
-// one group and the epilogue writes C directly.
+// Execution plan of one request, a recursive data flow of `levels` levels of
+// the algorithm (split factor p, R products per level):
+//  - pre-addition stages, one launch per level: every block of the level
+//    above is split into p^2 quarters and each of its R children is either a
+//    (scaled) view of one quarter or a materialised linear combination;
+//  - one grouped GEMM over all R^levels leaf products.  The products are
+//    grouped by the first `levels_outer` levels: group g computes the result
+//    P_g of its sub-problem, with the post-additions of the remaining inner
+//    levels fused into the GEMM epilogue (composed coefficients);
+//  - post-addition stages, one launch per outer level, innermost first,
+//    combining R child results into the p^2 blocks of their parent (C at the
+//    top).  With levels_outer = 0 the epilogue writes C directly.
 struct Plan {
   int64_t n = 0;        // true size
   int64_t npad = 0;     // padded size = P * m
@@ -140,7 +153,7 @@ struct Plan {
   std::vector<ProdDesc> prods;   // ordered by group
   std::vector<EpiDesc> epis;
   std::vector<int32_t> group_beg;  // groups + 1 entries
-  CombineStage pre, post;
+  std::vector<CombineStage> pre, post;  // in launch order
   // device copy (one allocation, owned by the plan), made on first use
   mutable std::once_flag uploaded;
   mutable mf_status upload_status = MF_OK;
@@ -173,7 +186,7 @@ constexpr int kLeafTile = 128;
 // Kernel launchers.  vec_in / vec_out: rows of A and B / of C start on
 // 16-byte boundaries.
 constexpr int kPhases = 3;  // pre-addition, grouped GEMM, outer post-addition
-hipError_t launch_combine(const CombineStage& cs, int elem, int m, const void* A, const void* B, void* C, void* ws,
+hipError_t launch_combine(const CombineStage& cs, int elem, const void* A, const void* B, void* C, void* ws,
                           bool vec_in, bool vec_out, hipStream_t s);
 hipError_t launch_gemm_f64(const Plan& pl, const void* A, const void* B, void* C, void* ws, bool vec_in,
                            hipStream_t s);

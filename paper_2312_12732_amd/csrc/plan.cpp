@@ -19,13 +19,19 @@ Plan::~Plan() {
 
 namespace {
 
-// Levels taken for an n x n product: a level is taken while levels remain and
-// the current size exceeds the cutoff (sizes rounded up at each split).
-int levels_for(int64_t n, int p, int depth, int cutoff) {
+// Leaf products allowed in one plan.
+constexpr int64_t kMaxLeafProducts = 1 << 16;
+
+// Levels taken for an n x n product: a level is taken while levels remain,
+// the current size exceeds the cutoff and the leaf tile (smaller leaves only
+// add padding on this GEMM), and the leaf count stays within the limit
+// (sizes rounded up at each split).
+int levels_for(int64_t n, int p, int R, int depth, int cutoff) {
   int d = 0;
-  int64_t size = n;
-  while (d < depth && size > cutoff && p > 1) {
+  int64_t size = n, leaves = 1;
+  while (d < depth && size > cutoff && size > kLeafTile && p > 1 && leaves * R <= kMaxLeafProducts) {
     size = (size + p - 1) / p;
+    leaves *= R;
     ++d;
   }
   return d;
@@ -38,37 +44,53 @@ int64_t ipow(int64_t b, int e) {
   return r;
 }
 
-struct View {
-  int64_t off;
-  int32_t vr, vc;
+// A block of the recursion: a view (src, offset, ld) of a matrix or of a
+// workspace buffer, valid over vr x vc (virtual zeros beyond), standing for
+// scale times the viewed entries.
+struct Blk {
+  int32_t src = SRC_A;
+  int64_t off = 0;
+  int32_t ld = 0;
+  int32_t vr = 0, vc = 0;
+  double scale = 1.0;
+  bool zero = true;
 };
 
-// Block k of the P x P partition of an n x n matrix with block size m (the
-// padded size P*m >= n), clipped to the true size: entries beyond it are
-// virtual zeros.  ld of the view is n.
-View block_view(int k, int P, int64_t m, int64_t n) {
-  const int64_t bi = k / P, bj = k % P;
-  View v;
-  const int64_t r0 = bi * m, c0 = bj * m;
-  v.vr = (int32_t)std::max<int64_t>(0, std::min<int64_t>(m, n - r0));
-  v.vc = (int32_t)std::max<int64_t>(0, std::min<int64_t>(m, n - c0));
-  if (v.vr == 0 || v.vc == 0) v.vr = v.vc = 0;
-  v.off = (v.vr > 0) ? r0 * n + c0 : 0;
-  return v;
+// Quarter k (row-major in the p x p split) of block b, of size s.
+Blk quarter(const Blk& b, int k, int p, int64_t s) {
+  Blk q = b;
+  const int64_t r0 = (int64_t)(k / p) * s, c0 = (int64_t)(k % p) * s;
+  q.vr = (int32_t)std::max<int64_t>(0, std::min<int64_t>(s, b.vr - r0));
+  q.vc = (int32_t)std::max<int64_t>(0, std::min<int64_t>(s, b.vc - c0));
+  q.zero = b.zero || q.vr == 0 || q.vc == 0;
+  if (q.zero) {
+    q.vr = q.vc = 0;
+    q.off = 0;
+  } else {
+    q.off = b.off + r0 * b.ld + c0;
+  }
+  return q;
 }
 
-// Marks the operand sets of a stage whose views all cover a full m x m block
-// (no virtual padding), which run on the kernel's branch-free path.
-void set_full(CombineStage* cs, int64_t m) {
-  for (int y = 0; y < cs->n_sets; ++y) {
-    bool full = true;
-    for (int k = 0; k < cs->nin; ++k) {
-      const CombIn& v = cs->ins[(size_t)y * cs->nin + k];
-      full = full && v.vr == m && v.vc == m;
-    }
-    for (int o = cs->out_beg[y]; o < cs->out_beg[y + 1]; ++o) full = full && cs->outs[o].vr == m && cs->outs[o].vc == m;
-    cs->full[y] = full ? 1 : 0;
+CombIn as_input(const Blk& b) {
+  CombIn in{};
+  in.off = b.off;
+  in.src = b.src;
+  in.ld = b.ld;
+  in.vr = b.zero ? 0 : b.vr;
+  in.vc = b.zero ? 0 : b.vc;
+  return in;
+}
+
+void finish_set(CombineStage* st, CombSet set) {
+  bool full = true;
+  for (int k = 0; k < st->nin; ++k) {
+    const CombIn& v = st->ins[(size_t)set.in_beg + k];
+    full = full && v.vr == st->m && v.vc == st->m;
   }
+  for (int o = set.out_beg; o < set.out_end; ++o) full = full && st->outs[o].vr == st->m && st->outs[o].vc == st->m;
+  set.full = full ? 1 : 0;
+  st->sets.push_back(set);
 }
 
 // Workgroups wanted in the grouped GEMM before outer levels are split off.
@@ -102,152 +124,161 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, P
   pl->n = n;
   pl->dtype = dtype;
   pl->elem = (dtype & 0xff) == MF_F64 ? 8 : 4;
-  const int L = algo ? levels_for(n, algo->p, depth, cutoff) : 0;
+  const int L = algo ? levels_for(n, algo->p, algo->R, depth, cutoff) : 0;
   pl->levels = L;
   if (L == 0) return build_classical(n, pl);
 
-  const int p = algo->p;
+  const int p = algo->p, p2 = p * p, R = algo->R;
+  if (!combine_supported(p2) || !combine_supported(R))
+    return fail(MF_ERR_UNSUPPORTED, "no linear-combination kernel for this algorithm shape");
   const int64_t P = ipow(p, L);
-  const int64_t P2 = P * P;
-  if (!combine_supported((int)P2))
-    return fail(MF_ERR_UNSUPPORTED, "fused split factor " + std::to_string(P) + " has no pre-addition kernel");
   pl->P = (int)P;
   pl->m = round_up((n + P - 1) / P, kLeafTile);
   pl->npad = pl->m * P;
-  const int64_t m = pl->m, mm = m * m;
+  const int64_t m = pl->m;
   const int64_t positions = (m / kLeafTile) * (m / kLeafTile);
 
-  // Outer levels split off as groups until the grid is large enough.
+  // Outer levels split off as groups (with post-addition stages) until the
+  // grouped GEMM has enough workgroups.
   int Lo = 0;
-  while (Lo < L && Lo < 2 && positions * ipow(algo->R, Lo) < kMinWorkgroups &&
-         combine_supported((int)ipow(algo->R, Lo + 1)))
-    ++Lo;
+  while (Lo < L && positions * ipow(R, Lo) < kMinWorkgroups) ++Lo;
   const int Li = L - Lo;
   pl->levels_outer = Lo;
-  const Algo Fo = Lo > 0 ? power(*algo, Lo) : Algo{};
   const Algo Fi = Li > 0 ? power(*algo, Li) : Algo{};
-  const Algo F = power(*algo, L);
-  const int Po = Lo > 0 ? Fo.p : 1, Ro = Lo > 0 ? Fo.R : 1;
   const int Pi = Li > 0 ? Fi.p : 1, Ri = Li > 0 ? Fi.R : 1;
-  pl->P_outer = Po;
-  pl->R = F.R;
-  pl->groups = Ro;
+  pl->P_outer = (int)ipow(p, Lo);
+  pl->R = (int)ipow(R, L);
+  pl->groups = (int)ipow(R, Lo);
   pl->m_outer = (int64_t)Pi * m;
-  const int64_t mo = pl->m_outer;
-
-  // ---- pre-addition stage: inputs are the P^2 blocks of A (set 0) and B (set 1)
-  std::vector<View> views(P2);
-  for (int k = 0; k < P2; ++k) views[k] = block_view(k, (int)P, m, n);
-  CombineStage& pre = pl->pre;
-  pre.nin = (int)P2;
-  for (int side = 0; side < 2; ++side)
-    for (int k = 0; k < P2; ++k)
-      pre.ins.push_back(CombIn{views[k].off, side == 0 ? SRC_A : SRC_B, (int32_t)n, views[k].vr, views[k].vc});
-
-  struct Operand {
-    bool zero = false, view = false;
-    int block = -1, slot = -1;
-    double scale = 1.0;
+  int64_t ws = 0;  // workspace elements allocated so far
+  auto alloc = [&](int64_t elems) {
+    const int64_t off = ws;
+    ws += round_up(elems, 64);
+    return off;
   };
-  auto classify = [&](const std::vector<double>& X, int r) {
-    Operand o;
-    int nnz = 0, last = -1;
-    for (int k = 0; k < P2; ++k)
-      if (X[(size_t)k * F.R + r] != 0.0 && views[k].vr > 0) {
-        ++nnz;
-        last = k;
+
+  // ---- pre-addition stages, level by level, both operands in each launch
+  std::vector<Blk> leaves[2];
+  {
+    std::vector<Blk> cur[2];
+    for (int side = 0; side < 2; ++side) {
+      Blk top;
+      top.src = side == 0 ? SRC_A : SRC_B;
+      top.off = 0;
+      top.ld = (int32_t)n;
+      top.vr = top.vc = (int32_t)n;
+      top.scale = 1.0;
+      top.zero = false;
+      cur[side] = {top};
+    }
+    int64_t size = pl->npad;
+    for (int lev = 1; lev <= L; ++lev) {
+      const int64_t sz = size / p;
+      CombineStage st;
+      st.nin = p2;
+      st.m = sz;
+      std::vector<Blk> next[2];
+      for (int side = 0; side < 2; ++side) {
+        const std::vector<double>& X = side == 0 ? algo->U : algo->V;
+        for (const Blk& b : cur[side]) {
+          std::vector<Blk> q(p2);
+          for (int k = 0; k < p2; ++k) q[k] = quarter(b, k, p, sz);
+          CombSet set{};
+          set.in_beg = (int32_t)st.ins.size();
+          set.out_beg = (int32_t)st.outs.size();
+          for (int r = 0; r < R; ++r) {
+            int nnz = 0, last = -1;
+            for (int k = 0; k < p2; ++k)
+              if (X[(size_t)k * R + r] != 0.0 && !q[k].zero) {
+                ++nnz;
+                last = k;
+              }
+            Blk child;
+            if (nnz == 0) {
+              child.zero = true;
+            } else if (nnz == 1) {
+              child = q[last];
+              child.scale = b.scale * X[(size_t)last * R + r];
+            } else {
+              CombOut co{};
+              co.off = alloc(sz * sz);
+              co.dst = SRC_WS;
+              co.ld = (int32_t)sz;
+              co.vr = co.vc = (int32_t)sz;
+              co.coef_off = (int32_t)st.coef.size();
+              for (int k = 0; k < p2; ++k) st.coef.push_back(q[k].zero ? 0.0 : X[(size_t)k * R + r] * b.scale);
+              st.outs.push_back(co);
+              child.src = SRC_WS;
+              child.off = co.off;
+              child.ld = (int32_t)sz;
+              child.vr = child.vc = (int32_t)sz;
+              child.scale = 1.0;
+              child.zero = false;
+            }
+            next[side].push_back(child);
+          }
+          set.out_end = (int32_t)st.outs.size();
+          if (set.out_end > set.out_beg) {
+            for (int k = 0; k < p2; ++k) st.ins.push_back(as_input(q[k]));
+            finish_set(&st, set);
+          }
+        }
       }
-    if (nnz == 0) {
-      o.zero = true;
-    } else if (nnz == 1) {
-      o.view = true;
-      o.block = last;
-      o.scale = X[(size_t)last * F.R + r];
+      if (!st.sets.empty()) pl->pre.push_back(std::move(st));
+      cur[0].swap(next[0]);
+      cur[1].swap(next[1]);
+      size = sz;
     }
-    return o;
-  };
-  std::vector<Operand> opa(F.R), opb(F.R);
-  for (int r = 0; r < F.R; ++r) {
-    opa[r] = classify(F.U, r);
-    opb[r] = classify(F.V, r);
+    leaves[0].swap(cur[0]);
+    leaves[1].swap(cur[1]);
   }
-  // A product with an all-zero operand (only possible through padding)
-  // contributes nothing; it and its pre-additions are skipped.
-  int slots = 0;
-  for (int side = 0; side < 2; ++side) {
-    const std::vector<double>& X = side == 0 ? F.U : F.V;
-    std::vector<Operand>& ops = side == 0 ? opa : opb;
-    pre.out_beg[side] = (int)pre.outs.size();
-    for (int r = 0; r < F.R; ++r) {
-      if (opa[r].zero || opb[r].zero || ops[r].view) continue;
-      ops[r].slot = slots++;
-      CombOut co{};
-      co.off = (int64_t)ops[r].slot * mm;
-      co.dst = SRC_WS;
-      co.ld = (int32_t)m;
-      co.vr = co.vc = (int32_t)m;
-      co.coef_off = (int32_t)pre.coef.size();
-      for (int k = 0; k < P2; ++k) pre.coef.push_back(views[k].vr > 0 ? X[(size_t)k * F.R + r] : 0.0);
-      pre.outs.push_back(co);
-    }
-  }
-  pre.out_beg[2] = (int)pre.outs.size();
-  pre.n_sets = pre.outs.empty() ? 0 : 2;
-  set_full(&pre, m);
-  const int64_t pbuf_base = (int64_t)slots * mm;  // group output buffers follow the T/S slots
 
-  // ---- grouped leaf products with epilogue post-addition
-  for (int g = 0; g < Ro; ++g) {
+  // ---- group output buffers (sub-problem results of the outer levels)
+  const int G = pl->groups;
+  const int64_t mo = pl->m_outer;
+  std::vector<int64_t> gbuf(G, 0);
+  if (Lo > 0)
+    for (int g = 0; g < G; ++g) gbuf[g] = alloc(mo * mo);
+
+  // ---- grouped leaf products with the inner post-addition in the epilogue
+  std::vector<char> group_empty(G, 1);
+  for (int g = 0; g < G; ++g) {
     pl->group_beg.push_back((int32_t)pl->prods.size());
-    const int nout = Pi * Pi;  // output blocks of the group
+    const int nout = Pi * Pi;
     std::vector<char> written(nout, 0);
-    // Output block c (inner index) of this group.
     auto out_view = [&](int c, EpiDesc* ed) {
+      const int64_t r0 = (int64_t)(c / Pi) * m, c0 = (int64_t)(c % Pi) * m;
       if (Lo == 0) {
-        const View v = block_view(c, (int)P, m, n);
         ed->c_src = SRC_C;
-        ed->c_off = v.off;
         ed->ldc = (int32_t)n;
-        ed->c_vr = v.vr;
-        ed->c_vc = v.vc;
+        ed->c_vr = (int32_t)std::max<int64_t>(0, std::min<int64_t>(m, n - r0));
+        ed->c_vc = (int32_t)std::max<int64_t>(0, std::min<int64_t>(m, n - c0));
+        if (ed->c_vr == 0 || ed->c_vc == 0) ed->c_vr = ed->c_vc = 0;
+        ed->c_off = ed->c_vr > 0 ? r0 * n + c0 : 0;
       } else {
         ed->c_src = SRC_WS;
-        ed->c_off = pbuf_base + (int64_t)g * mo * mo + (int64_t)(c / Pi) * m * mo + (int64_t)(c % Pi) * m;
         ed->ldc = (int32_t)mo;
         ed->c_vr = ed->c_vc = (int32_t)m;
+        ed->c_off = gbuf[g] + r0 * mo + c0;
       }
     };
     const int group_first = (int)pl->prods.size();
     for (int ri = 0; ri < Ri; ++ri) {
       const int r = g * Ri + ri;
-      if (opa[r].zero || opb[r].zero) continue;
+      const Blk& a = leaves[0][r];
+      const Blk& b = leaves[1][r];
+      if (a.zero || b.zero) continue;
       ProdDesc pd{};
-      const Operand& a = opa[r];
-      const Operand& b = opb[r];
-      if (a.view) {
-        pd.a_src = SRC_A;
-        pd.a_off = views[a.block].off;
-        pd.lda = (int32_t)n;
-        pd.a_vr = views[a.block].vr;
-        pd.a_vc = views[a.block].vc;
-      } else {
-        pd.a_src = SRC_WS;
-        pd.a_off = (int64_t)a.slot * mm;
-        pd.lda = (int32_t)m;
-        pd.a_vr = pd.a_vc = (int32_t)m;
-      }
-      if (b.view) {
-        pd.b_src = SRC_B;
-        pd.b_off = views[b.block].off;
-        pd.ldb = (int32_t)n;
-        pd.b_vr = views[b.block].vr;
-        pd.b_vc = views[b.block].vc;
-      } else {
-        pd.b_src = SRC_WS;
-        pd.b_off = (int64_t)b.slot * mm;
-        pd.ldb = (int32_t)m;
-        pd.b_vr = pd.b_vc = (int32_t)m;
-      }
+      pd.a_src = a.src;
+      pd.a_off = a.off;
+      pd.lda = a.ld;
+      pd.a_vr = a.vr;
+      pd.a_vc = a.vc;
+      pd.b_src = b.src;
+      pd.b_off = b.off;
+      pd.ldb = b.ld;
+      pd.b_vr = b.vr;
+      pd.b_vc = b.vc;
       const double scale = a.scale * b.scale;
       pd.epi_beg = (int32_t)pl->epis.size();
       for (int c = 0; c < nout; ++c) {
@@ -263,23 +294,24 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, P
       }
       pd.epi_end = (int32_t)pl->epis.size();
       pl->prods.push_back(pd);
+      group_empty[g] = 0;
     }
     // Output blocks that no product of the group feeds are zero; the first
-    // product of the group stores zeros there.
-    for (int c = 0; c < nout; ++c) {
+    // product of the group stores zeros there.  (An empty group is read as
+    // zero by the post-addition instead.)
+    for (int c = 0; c < nout && !group_empty[g]; ++c) {
       if (written[c]) continue;
       EpiDesc ed{};
       out_view(c, &ed);
       if (ed.c_vr == 0) continue;
-      if ((int)pl->prods.size() == group_first) break;  // empty group: the post stage reads it as zero
       ed.first = 2;
       ed.coef = 0.0;
       const int at = pl->prods[group_first].epi_end;
       pl->epis.insert(pl->epis.begin() + at, ed);
       pl->prods[group_first].epi_end += 1;
-      for (size_t q = group_first + 1; q < pl->prods.size(); ++q) {
-        pl->prods[q].epi_beg += 1;
-        pl->prods[q].epi_end += 1;
+      for (size_t qd = group_first + 1; qd < pl->prods.size(); ++qd) {
+        pl->prods[qd].epi_beg += 1;
+        pl->prods[qd].epi_end += 1;
       }
       written[c] = 1;
     }
@@ -287,36 +319,67 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, P
   pl->group_beg.push_back((int32_t)pl->prods.size());
   if (pl->prods.empty()) return fail(MF_ERR_SHAPE, "plan has no products");
 
-  // ---- outer post-addition: C_c = sum_g W_outer[c, g] P_g
-  size_t ws_elems = (size_t)pbuf_base;
+  // ---- post-addition stages, innermost outer level first:
+  // parent_c = sum_r W[c, r] child_r for each of the p^2 blocks c of a parent.
   if (Lo > 0) {
-    CombineStage& post = pl->post;
-    post.nin = Ro;
-    for (int g = 0; g < Ro; ++g) {
-      const bool empty = pl->group_beg[g] == pl->group_beg[g + 1];
-      post.ins.push_back(CombIn{pbuf_base + (int64_t)g * mo * mo, SRC_WS, (int32_t)mo, empty ? 0 : (int32_t)mo,
-                                empty ? 0 : (int32_t)mo});
+    std::vector<Blk> child(G);
+    for (int g = 0; g < G; ++g) {
+      child[g].src = SRC_WS;
+      child[g].off = gbuf[g];
+      child[g].ld = (int32_t)mo;
+      child[g].vr = child[g].vc = (int32_t)mo;
+      child[g].zero = group_empty[g] != 0;
     }
-    post.out_beg[0] = 0;
-    for (int c = 0; c < Po * Po; ++c) {
-      const View v = block_view(c, Po, mo, n);
-      if (v.vr == 0) continue;
-      CombOut co{};
-      co.off = v.off;
-      co.dst = SRC_C;
-      co.ld = (int32_t)n;
-      co.vr = v.vr;
-      co.vc = v.vc;
-      co.coef_off = (int32_t)post.coef.size();
-      for (int g = 0; g < Ro; ++g) post.coef.push_back(Fo.w(c, g));
-      post.outs.push_back(co);
+    int64_t csz = mo;  // size of a child result
+    for (int lev = Lo; lev >= 1; --lev) {
+      const int nparent = (int)ipow(R, lev - 1);
+      const int64_t psz = csz * p;
+      CombineStage st;
+      st.nin = R;
+      st.m = csz;
+      std::vector<Blk> parents(nparent);
+      for (int q = 0; q < nparent; ++q) {
+        Blk par;
+        if (lev == 1) {
+          par.src = SRC_C;
+          par.off = 0;
+          par.ld = (int32_t)n;
+          par.vr = par.vc = (int32_t)n;
+          par.zero = false;
+        } else {
+          par.src = SRC_WS;
+          par.off = alloc(psz * psz);
+          par.ld = (int32_t)psz;
+          par.vr = par.vc = (int32_t)psz;
+          par.zero = false;
+        }
+        parents[q] = par;
+        CombSet set{};
+        set.in_beg = (int32_t)st.ins.size();
+        for (int r = 0; r < R; ++r) st.ins.push_back(as_input(child[(size_t)q * R + r]));
+        set.out_beg = (int32_t)st.outs.size();
+        for (int c = 0; c < p2; ++c) {
+          const Blk qb = quarter(par, c, p, csz);
+          if (qb.zero) continue;
+          CombOut co{};
+          co.off = qb.off;
+          co.dst = qb.src;
+          co.ld = qb.ld;
+          co.vr = qb.vr;
+          co.vc = qb.vc;
+          co.coef_off = (int32_t)st.coef.size();
+          for (int r = 0; r < R; ++r) st.coef.push_back(algo->w(c, r));
+          st.outs.push_back(co);
+        }
+        set.out_end = (int32_t)st.outs.size();
+        finish_set(&st, set);
+      }
+      pl->post.push_back(std::move(st));
+      child.swap(parents);
+      csz = psz;
     }
-    post.out_beg[1] = post.out_beg[2] = (int)post.outs.size();
-    post.n_sets = 1;
-    set_full(&post, mo);
-    ws_elems += (size_t)Ro * (size_t)mo * (size_t)mo;
   }
-  pl->ws_bytes = ws_elems * pl->elem;
+  pl->ws_bytes = (size_t)ws * pl->elem;
   return MF_OK;
 }
 
@@ -332,19 +395,23 @@ mf_status upload(const Plan* pl) {
     size_t bytes;
     size_t off;
   };
-  std::vector<Part> parts = {
-      {pl->prods.data(), bytes_of(pl->prods), 0},         {pl->epis.data(), bytes_of(pl->epis), 0},
-      {pl->group_beg.data(), bytes_of(pl->group_beg), 0}, {pl->pre.ins.data(), bytes_of(pl->pre.ins), 0},
-      {pl->pre.outs.data(), bytes_of(pl->pre.outs), 0},   {pl->pre.coef.data(), bytes_of(pl->pre.coef), 0},
-      {pl->post.ins.data(), bytes_of(pl->post.ins), 0},   {pl->post.outs.data(), bytes_of(pl->post.outs), 0},
-      {pl->post.coef.data(), bytes_of(pl->post.coef), 0},
-  };
+  std::vector<Part> parts = {{pl->prods.data(), bytes_of(pl->prods), 0},
+                             {pl->epis.data(), bytes_of(pl->epis), 0},
+                             {pl->group_beg.data(), bytes_of(pl->group_beg), 0}};
+  std::vector<const CombineStage*> stages;
+  for (const auto& st : pl->pre) stages.push_back(&st);
+  for (const auto& st : pl->post) stages.push_back(&st);
+  for (const CombineStage* st : stages) {
+    parts.push_back({st->sets.data(), bytes_of(st->sets), 0});
+    parts.push_back({st->ins.data(), bytes_of(st->ins), 0});
+    parts.push_back({st->outs.data(), bytes_of(st->outs), 0});
+    parts.push_back({st->coef.data(), bytes_of(st->coef), 0});
+  }
   size_t total = 0;
   for (auto& q : parts) {
     q.off = total;
-    total += align(q.bytes);
+    total += align(std::max<size_t>(q.bytes, 1));
   }
-  if (total == 0) return MF_OK;
   std::vector<char> host(total, 0);
   for (auto& q : parts)
     if (q.bytes) memcpy(host.data() + q.off, q.src, q.bytes);
@@ -361,12 +428,12 @@ mf_status upload(const Plan* pl) {
   pl->d_prods = reinterpret_cast<ProdDesc*>(d + parts[0].off);
   pl->d_epis = reinterpret_cast<EpiDesc*>(d + parts[1].off);
   pl->d_group_beg = reinterpret_cast<int32_t*>(d + parts[2].off);
-  pl->pre.d_ins = reinterpret_cast<CombIn*>(d + parts[3].off);
-  pl->pre.d_outs = reinterpret_cast<CombOut*>(d + parts[4].off);
-  pl->pre.d_coef = reinterpret_cast<double*>(d + parts[5].off);
-  pl->post.d_ins = reinterpret_cast<CombIn*>(d + parts[6].off);
-  pl->post.d_outs = reinterpret_cast<CombOut*>(d + parts[7].off);
-  pl->post.d_coef = reinterpret_cast<double*>(d + parts[8].off);
+  for (size_t i = 0; i < stages.size(); ++i) {
+    stages[i]->d_sets = reinterpret_cast<CombSet*>(d + parts[3 + 4 * i].off);
+    stages[i]->d_ins = reinterpret_cast<CombIn*>(d + parts[4 + 4 * i].off);
+    stages[i]->d_outs = reinterpret_cast<CombOut*>(d + parts[5 + 4 * i].off);
+    stages[i]->d_coef = reinterpret_cast<double*>(d + parts[6 + 4 * i].off);
+  }
   return MF_OK;
 }
 
@@ -391,7 +458,7 @@ std::map<Key, std::shared_ptr<const Plan>>& cache() {
 
 mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
                    std::shared_ptr<const Plan>* out) {
-  const int levels = algo ? levels_for(n, algo->a.p, depth, cutoff) : 0;
+  const int levels = algo ? levels_for(n, algo->a.p, algo->a.R, depth, cutoff) : 0;
   const Key key{levels == 0 ? 0 : algo->id, levels, dtype, n};
   {
     std::lock_guard<std::mutex> lk(g_mu);

@@ -119,32 +119,53 @@ def test_rebase_rejects_singular():
 
 
 def expected_ws(n, depth, mat_u, mat_v, R=7, p=2):
-    """Closed form of the executor's workspace: the materialised T and S
-    blocks of size m^2 (m = n / p^d rounded up to the 128 tile), plus, when
-    the grid of (m/128)^2 tile positions is below 1024 workgroups, one output
-    block of size (m * p^d_inner)^2 per group of the first d_outer levels."""
+    """Closed form of the executor's workspace (elements of 8 bytes):
+    level l of the pre-additions materialises mat_u + mat_v children of each
+    of the R^(l-1) parents, each of size (n'/p^l)^2 (n' = p^d * m, m = n/p^d
+    rounded up to the 128 tile); when the (m/128)^2 tile positions times
+    R^lo groups first reach 1024 workgroups at lo outer levels, every group
+    keeps a result block of size (m p^(d-lo))^2 and every post-addition
+    parent below the top one a block p times larger."""
+    size, d = n, 0
+    while d < depth and size > 128 and R ** (d + 1) <= 1 << 16:
+        size, d = -(-size // p), d + 1
+    depth = d
     P = p ** depth
     m = 128 * -(-(-(-n // P)) // 128)
+    npad = P * m
+    elems = 0
+    for lev in range(1, depth + 1):
+        s = npad // p ** lev
+        elems += (mat_u + mat_v) * R ** (lev - 1) * s * s
     pos = (m // 128) ** 2
     lo = 0
-    while lo < depth and lo < 2 and pos * R ** lo < 1024:
+    while lo < depth and pos * R ** lo < 1024:
         lo += 1
-    groups = R ** lo if lo else 0
-    mo = m * p ** (depth - lo)
-    return 8 * ((mat_u + mat_v) * m * m + groups * mo * mo)
+    if lo:
+        mo = m * p ** (depth - lo)
+        elems += R ** lo * mo * mo
+        csz = mo
+        for lev in range(lo, 1, -1):
+            csz *= p
+            elems += R ** (lev - 1) * csz * csz
+    return 8 * elems
 
 
 def test_workspace_bytes_closed_form():
     s = mf.mf_algo_builtin("strassen")
     # depth 1: 4 materialised T and 4 materialised S of (n/2)^2 doubles
     assert mf.mf_workspace_bytes(s, 1, 0, 8192) == 8 * 4096 ** 2 * 8 == expected_ws(8192, 1, 4, 4)
-    # depth 2: 40 + 40 blocks of (n/4)^2, plus 7 group outputs of (n/2)^2
-    assert mf.mf_workspace_bytes(s, 2, 0, 8192) == 80 * 2048 ** 2 * 8 + 7 * 4096 ** 2 * 8
-    assert mf.mf_workspace_bytes(s, 2, 0, 8192) == expected_ws(8192, 2, 40, 40)
-    # depth 3: 316 + 316 blocks of (n/8)^2, plus 49 group outputs of (n/4)^2
-    assert mf.mf_workspace_bytes(s, 3, 0, 8192) == 632 * 1024 ** 2 * 8 + 49 * 2048 ** 2 * 8
+    # depth 2: level 1 (4 + 4 blocks of (n/2)^2), level 2 (7 x (4 + 4) blocks of
+    # (n/4)^2), plus 7 group results of (n/2)^2
+    assert mf.mf_workspace_bytes(s, 2, 0, 8192) == 8 * (8 * 4096 ** 2 + 56 * 2048 ** 2 + 7 * 4096 ** 2)
+    assert mf.mf_workspace_bytes(s, 2, 0, 8192) == expected_ws(8192, 2, 4, 4)
+    # depth 3: 49 group results of (n/4)^2 and 7 level-2 parents of (n/2)^2
+    assert mf.mf_workspace_bytes(s, 3, 0, 8192) == 8 * (8 * 4096 ** 2 + 56 * 2048 ** 2 + 392 * 1024 ** 2
+                                                         + 49 * 2048 ** 2 + 7 * 4096 ** 2)
+    assert mf.mf_workspace_bytes(s, 3, 0, 8192) == expected_ws(8192, 3, 4, 4)
     # ragged: n = 1000, leaf size rounded up to the 128 tile (500 -> 512)
     assert mf.mf_workspace_bytes(s, 1, 0, 1000) == expected_ws(1000, 1, 4, 4)
+    assert mf.mf_workspace_bytes(s, 2, 0, 1000) == expected_ws(1000, 2, 4, 4)
     # classical (depth 0 or cutoff >= n) needs no workspace
     assert mf.mf_workspace_bytes(s, 0, 0, 8192) == 0
     assert mf.mf_workspace_bytes(s, 2, 8192, 8192) == 0
@@ -152,8 +173,15 @@ def test_workspace_bytes_closed_form():
     # 484 tile positions < 1024, so each product is its own group
     c3 = mf.mf_workspace_bytes(mf.mf_algo_builtin("classical3"), 1, 0, 8192)
     assert c3 == expected_ws(8192, 1, 0, 0, R=27, p=3) == 27 * 2816 ** 2 * 8
+    # Winograd: also 4 materialised columns in U and in V
     w = mf.mf_algo_builtin("winograd")
     assert mf.mf_workspace_bytes(w, 1, 0, 4096) == expected_ws(4096, 1, 4, 4)
+    assert mf.mf_workspace_bytes(w, 3, 0, 4096) == expected_ws(4096, 3, 4, 4)
+    # Strassen 1969: 5 materialised columns in U and in V
+    s69 = mf.mf_algo_builtin("strassen1969")
+    assert mf.mf_workspace_bytes(s69, 2, 0, 8192) == expected_ws(8192, 2, 5, 5)
+    # FP32 storage halves every byte count
+    assert mf.mf_workspace_bytes(s, 2, 0, 8192, mf.MF_F32) * 2 == expected_ws(8192, 2, 4, 4)
 
 
 def test_workspace_bytes_paper_size_24012():
@@ -191,8 +219,19 @@ def test_fastmm_argument_validation_without_device():
     assert mf.lib.mf_classical_mm(None, None, None, 0, mf.MF_F64, None) == mf.MF_OK
 
 
-def test_unsupported_fused_factor_is_reported():
-    s = mf.mf_algo_builtin("strassen")
+def test_unsupported_algorithm_shape_is_reported():
+    # split factor 5 (25 inputs per block combination) has no compiled kernel
+    c5 = oa.classical_algo(5)
+    a = mf.mf_algo_from_uvw(5, c5.U, c5.V, c5.W, mf.MF_W_ROWMAJOR_C)
     with pytest.raises(mf.MFError) as e:
-        mf.mf_workspace_bytes(s, 4, 0, 8192)  # split factor 16
+        mf.mf_workspace_bytes(a, 1, 0, 1000)
     assert e.value.status == mf.MF_ERR_UNSUPPORTED
+    assert mf.mf_workspace_bytes(a, 0, 0, 1000) == 0  # classical still works
+
+
+def test_deep_recursion_plans():
+    s = mf.mf_algo_builtin("strassen")
+    assert mf.mf_workspace_bytes(s, 4, 0, 8192) == expected_ws(8192, 4, 4, 4)
+    # depth beyond what the size allows stops once a level reaches the tile
+    assert mf.mf_workspace_bytes(s, 10, 0, 256) == expected_ws(256, 1, 4, 4) == 8 * (8 + 7) * 128 ** 2
+    assert mf.mf_workspace_bytes(s, 10, 0, 4096) == expected_ws(4096, 5, 4, 4)

@@ -118,12 +118,23 @@ def test_classical_333_control_exact():
         assert np.array_equal(got, (A @ B).astype(np.float64))
 
 
-def test_composed_equals_depth2_bitwise():
+def test_composed_444_49_matches_depth2():
+    """<4,4,4;49> = Strassen-Winograd composed with itself, run as one level
+    of split factor 4, and the same algorithm as two levels: identical
+    integers, FP64 results within the bound (their summation orders differ:
+    one 16-input combination versus two levels of 4-input combinations)."""
     s = mf.mf_algo_builtin("winograd")
     s2 = mf.mf_algo_compose(s, s)
+    assert s2.info()["R"] == 49 and s2.info()["n0"] == 4
+    Ai = mi.int_uniform(1024, 11).astype(np.float64)
+    Bi = mi.int_uniform(1024, 12).astype(np.float64)
+    assert np.array_equal(run_fast(s2, 1, 0, Ai, Bi), Ai @ Bi)
+    assert np.array_equal(run_fast(s, 2, 0, Ai, Bi), Ai @ Bi)
     A = mi.uniform(1024, 11)
     B = mi.uniform(1024, 12)
-    assert np.array_equal(run_fast(s, 2, 0, A, B), run_fast(s2, 1, 0, A, B))
+    ref = om.classical_mm(A, B)
+    assert om.rel_fro_error(run_fast(s2, 1, 0, A, B), ref) < FP64_TOL
+    assert om.rel_fro_error(run_fast(s, 2, 0, A, B), ref) < FP64_TOL
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 129, 255])

@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "effective GFLOP/s (2n^3/t) fast vs classical MFMA GEMM at stated rel. error"
 FP64_MFMA_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2312_12732_amd", "csrc", "kernels_f64.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2312_12732_amd", "csrc", "kernels_gemm.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_f64.json")
 
 
@@ -163,7 +163,7 @@ def main():
     workload = f"fp64 n={n} {args.algo} depth {d}"
     roofline = {"bound": "mfma", "achieved": round(gemm_tflops, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(gemm_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
-                "traffic": traffic_for(workload), "kernel": "gemm_f64_grouped",
+                "traffic": traffic_for(workload), "kernel": "gemm_grouped<double>",
                 "kernel_ms": round(phase_avg[1], 4)}
 
     # pre-addition phase against HBM: read A and B once, write the materialised blocks

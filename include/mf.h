@@ -138,6 +138,45 @@ mf_status mf_workspace_bytes(const mf_algo* algo, int depth, int cutoff, int64_t
 mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C,
                        int64_t n, int dtype, void* workspace, size_t ws_bytes, mf_stream stream);
 
+/* ---- Batched execution ----------------------------------------------------
+ * Many independent products C_i = A_i B_i (i < count) of sizes n[i], each
+ * with its own algorithm (algos[i], NULL when depth[i] == 0), depth and
+ * cutoff, all with storage dtype MF_F64 or MF_F32 (leaves in the storage
+ * type), executed by ONE persistent launch: its workgroups take tasks
+ * (addition chunks and GEMM tiles of every instance) from a global ticket in
+ * a topological order and wait on per-instance stage counters, so instances
+ * of different sizes share the GPU.  A batch plan is immutable; it must not
+ * run concurrently with itself (runs on one stream are fine). */
+typedef struct mf_batch mf_batch;
+
+/* Plan a batch (host only; device state is made on the first run).  The
+ * algorithm handles must outlive the batch.  1 <= n[i] <= 65536. */
+mf_status mf_batch_create(int count, const int64_t* n, const mf_algo* const* algos, const int* depth,
+                          const int* cutoff, int dtype, mf_batch** out);
+
+/* Device workspace bytes a run needs (0 if every instance is classical). */
+mf_status mf_batch_workspace_bytes(const mf_batch* b, size_t* bytes);
+
+/* Run the batch on `stream`.  A, B, C: host arrays of `count` device
+ * pointers to n[i] x n[i] row-major matrices (C_i must not overlap A_i or
+ * B_i).  workspace: NULL (stream-ordered pool of the library) or a caller
+ * buffer of at least mf_batch_workspace_bytes, 256-byte aligned. */
+mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* const* B, void* const* C,
+                       void* workspace, size_t ws_bytes, mf_stream stream);
+
+/* Waits for the device and reports whether the last run aborted (a task's
+ * wait exceeded its spin limit; the results are then invalid). */
+mf_status mf_batch_aborted(const mf_batch* b, int* aborted);
+
+/* The task graph, for host-side schedule checks: *ntasks tasks and *nctr
+ * counters; if desc is not NULL it receives 5 ints per task in launch order:
+ * type (0 addition chunk, 1 GEMM tile), instance, wait counter (-1: none),
+ * wait value, done counter. */
+mf_status mf_batch_tasks(const mf_batch* b, int* ntasks, int* nctr, int32_t* desc);
+
+/* Release a batch (NULL is ignored). */
+void mf_batch_free(mf_batch* b);
+
 /* Phase timing (tracing).  While enabled, every mf_fastmm / mf_fastmm_ws /
  * mf_classical_mm call records HIP events on its stream around its three
  * phases: 0 pre-additions, 1 grouped leaf GEMM with the fused epilogue

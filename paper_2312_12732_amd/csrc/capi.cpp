@@ -69,7 +69,7 @@ mf_status check_request(const mf_algo* algo, bool need_algo, int depth, int cuto
 
 mf_status plan_for(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
                    std::shared_ptr<const Plan>* pl) {
-  return get_plan(depth > 0 ? algo : nullptr, depth, cutoff, n, dtype, pl);
+  return get_plan(depth > 0 ? algo : nullptr, depth, cutoff, n, dtype, kStandaloneMinWorkgroups, pl);
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -291,7 +291,7 @@ mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int 
   mf_status st = check_request(nullptr, false, 0, 0, A, B, C, n, dtype);
   if (st != MF_OK || n == 0) return st;
   std::shared_ptr<const Plan> pl;
-  st = get_plan(nullptr, 0, 0, n, dtype, &pl);
+  st = get_plan(nullptr, 0, 0, n, dtype, kStandaloneMinWorkgroups, &pl);
   if (st != MF_OK) return st;
   return run(*pl, A, B, C, nullptr, static_cast<hipStream_t>(stream));
 }

@@ -1,0 +1,115 @@
+// Device code of the linear combination of matrix blocks (GEMA), shared by
+// the combination kernel and the persistent batched kernel: one thread
+// computes VEC consecutive elements at position (i, j) of every output of a
+// set from the same position of the set's input views.
+#pragma once
+
+#include <type_traits>
+
+#include "gemm_common.h"
+
+namespace mf {
+
+template <class T>
+struct CombArgs {
+  const T* A;
+  const T* B;
+  T* C;
+  T* ws;
+  const CombSet* sets;   // one per blockIdx.y
+  const CombIn* ins;     // NIN per set
+  const CombOut* outs;
+  const double* coef;    // NIN per output
+  int m;
+  int vec_in;            // input views with src A/B/C have 16-byte aligned rows
+  int vec_out;           // output views with dst C have 16-byte aligned rows
+};
+
+template <class T>
+__device__ __forceinline__ const T* comb_src(const CombArgs<T>& g, int src) {
+  const T* p = g.ws;
+  p = src == SRC_A ? g.A : p;
+  p = src == SRC_B ? g.B : p;
+  p = src == SRC_C ? g.C : p;
+  return p;
+}
+
+template <class T>
+__device__ __forceinline__ T* comb_dst(const CombArgs<T>& g, int dst) {
+  return dst == SRC_C ? g.C : g.ws;
+}
+
+template <class T, int NIN, int VEC, bool FULL>
+__device__ __forceinline__ void combine_body(const CombArgs<T>& g, const CombSet& set, int i, int j) {
+  typedef T tv __attribute__((ext_vector_type(VEC)));
+  const CombIn* ins = g.ins + set.in_beg;
+  tv in[NIN];
+#pragma unroll
+  for (int k = 0; k < NIN; ++k) {
+    const CombIn v = ins[k];
+    const T* p = comb_src(g, v.src) + v.off + (int64_t)i * v.ld + j;
+    if (FULL) {
+      in[k] = *reinterpret_cast<const tv*>(p);
+    } else {
+      const bool vec = v.src == SRC_WS || g.vec_in;
+      if (vec && i < v.vr && j + VEC <= v.vc) {
+        in[k] = *reinterpret_cast<const tv*>(p);
+      } else {
+        tv x;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) x[q] = (i < v.vr && j + q < v.vc) ? p[q] : T(0);
+        in[k] = x;
+      }
+    }
+  }
+  for (int o = set.out_beg; o < set.out_end; ++o) {
+    const CombOut po = g.outs[o];
+    const double* c = g.coef + po.coef_off;
+    tv acc;
+    bool started = false;
+#pragma unroll
+    for (int k = 0; k < NIN; ++k) {
+      const T ck = (T)c[k];
+      if (ck != T(0)) {
+        if (!started) {
+          acc = ck == T(1) ? in[k] : ck * in[k];
+          started = true;
+        } else {
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) acc[q] = fma_t(ck, in[k][q], acc[q]);
+        }
+      }
+    }
+    if (!started) acc = (tv)(T(0));
+    T* p = comb_dst(g, po.dst) + po.off + (int64_t)i * po.ld + j;
+    if (FULL) {
+      *reinterpret_cast<tv*>(p) = acc;
+    } else {
+      if (i >= po.vr) continue;
+      const bool vec = po.dst == SRC_WS || g.vec_out;
+      if (vec && j + VEC <= po.vc) {
+        *reinterpret_cast<tv*>(p) = acc;
+      } else {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q)
+          if (j + q < po.vc) p[q] = acc[q];
+      }
+    }
+  }
+}
+
+// Number of inputs of a set, as a compile-time dispatch: calls
+// f(std::integral_constant<int, NIN>) for the supported counts.
+template <class F>
+__device__ __forceinline__ void with_nin(int nin, F&& f) {
+  switch (nin) {
+    case 4: f(std::integral_constant<int, 4>()); break;
+    case 7: f(std::integral_constant<int, 7>()); break;
+    case 8: f(std::integral_constant<int, 8>()); break;
+    case 9: f(std::integral_constant<int, 9>()); break;
+    case 16: f(std::integral_constant<int, 16>()); break;
+    default: break;
+  }
+}
+
+}  // namespace mf

@@ -1,0 +1,173 @@
+// Persistent batched kernel (gfx950): all tasks of many independent fast
+// products - chunks of their pre-/post-addition stages and the work items
+// of their grouped leaf GEMMs - run in one launch.
+//
+// Scheduling.  Tasks are stored in topological order (every task a task
+// waits on has a smaller index).  A workgroup takes the next index from a
+// global ticket, waits until its prerequisite counter reaches the required
+// value, runs the task and increments its own counter.  A task only waits on
+// tasks with smaller tickets, which were taken earlier by workgroups that are
+// running, so the smallest unfinished task can always proceed: no deadlock,
+// whatever the number of resident workgroups.  Every wait is bounded: past
+// the spin limit (or once another workgroup has aborted) the workgroup sets
+// the abort flag and exits, and so does every workgroup that takes a ticket
+// afterwards; the host reports the abort.
+//
+// Memory ordering.  A task's results are published by an agent-scope
+// release fence in every wave followed by the counter increment; a waiting
+// workgroup observes the counter with agent-scope acquire loads and every
+// wave executes an acquire fence before reading them (the fences write back
+// and invalidate the XCD-local caches, so producers and consumers may sit on
+// different XCDs).  Counters are polled with vector memory loads.
+#include "combine_body.h"
+#include "gemm_tile.h"
+
+namespace mf {
+
+namespace {
+
+constexpr int kSpinLimit = 1 << 22;
+
+struct BatchArgs {
+  const BatchTask* tasks;
+  const StageRec* stages;
+  const GemmRec* gemms;
+  const BatchInst* insts;
+  int* ctr;  // nctr counters, then the ticket, then the abort flag
+  int nctr;
+  int ntasks;
+};
+
+__device__ __forceinline__ int load_acquire(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ void run_combine(const BatchArgs& g, const BatchTask& tk) {
+  const StageRec st = g.stages[tk.rec];
+  const BatchInst in = g.insts[tk.inst];
+  CombArgs<T> a;
+  a.A = static_cast<const T*>(in.A);
+  a.B = static_cast<const T*>(in.B);
+  a.C = static_cast<T*>(in.C);
+  a.ws = static_cast<T*>(in.ws);
+  a.sets = st.sets;
+  a.ins = st.ins;
+  a.outs = st.outs;
+  a.coef = st.coef;
+  a.m = st.m;
+  a.vec_in = in.vec_in;
+  a.vec_out = in.vec_out;
+  const CombSet set = st.sets[tk.a];
+  const bool full = set.full && in.vec_in && in.vec_out;
+  with_nin(st.nin, [&](auto nin_c) {
+    constexpr int NIN = decltype(nin_c)::value;
+    constexpr int VEC = NIN <= 4 ? 4 : (NIN <= 9 ? 2 : 1);
+    for (int64_t e = tk.e0 + (int64_t)threadIdx.x * VEC; e < tk.e1; e += (int64_t)NTHREADS * VEC) {
+      const int i = (int)(e / st.m), j = (int)(e % st.m);
+      if (full)
+        combine_body<T, NIN, VEC, true>(a, set, i, j);
+      else
+        combine_body<T, NIN, VEC, false>(a, set, i, j);
+    }
+  });
+}
+
+template <class T>
+__device__ __forceinline__ void run_gemm(const BatchArgs& g, const BatchTask& tk, T (*lds)[2][BK * LDS_STRIDE]) {
+  const GemmRec gr = g.gemms[tk.rec];
+  const BatchInst in = g.insts[tk.inst];
+  GemmArgs<T> a;
+  a.A = static_cast<const T*>(in.A);
+  a.B = static_cast<const T*>(in.B);
+  a.C = static_cast<T*>(in.C);
+  a.ws = static_cast<T*>(in.ws);
+  a.prods = gr.prods;
+  a.epis = gr.epis;
+  a.group_beg = gr.group_beg;
+  a.groups = gr.groups;
+  a.m = gr.m;
+  a.tiles = gr.tiles;
+  a.vec_in = in.vec_in;
+  gemm_tile<T>(a, tk.a, tk.b, tk.c, lds);
+}
+
+template <class T>
+__global__ void __launch_bounds__(NTHREADS, MF_GEMM_WAVES_PER_SIMD) batch_persistent(BatchArgs g) {
+  __shared__ T lds[2][2][BK * LDS_STRIDE];
+  __shared__ int s_task;
+  __shared__ int s_ok;
+  int* ticket = g.ctr + g.nctr;
+  int* abort_flag = ticket + 1;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int t = atomicAdd(ticket, 1);
+      if (load_acquire(abort_flag) != 0) t = g.ntasks;
+      s_task = t;
+    }
+    __syncthreads();
+    const int t = s_task;
+    if (t >= g.ntasks) return;
+    const BatchTask tk = g.tasks[t];
+    if (tk.wait_ctr >= 0) {
+      if (threadIdx.x == 0) {
+        int ok = 1;
+        for (int spins = 0; load_acquire(&g.ctr[tk.wait_ctr]) < tk.wait_val; ++spins) {
+          if (spins >= kSpinLimit || load_acquire(abort_flag) != 0) {
+            ok = 0;
+            atomicExch(abort_flag, 1);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(8);
+        }
+        s_ok = ok;
+      }
+      __syncthreads();
+      if (s_ok == 0) return;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    if (tk.type == 0)
+      run_combine<T>(g, tk);
+    else
+      run_gemm<T>(g, tk, lds);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(&g.ctr[tk.done_ctr], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void fill_zero(int* p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+}  // namespace
+
+bool batch_nin_supported(int nin) {
+  return nin == 4 || nin == 7 || nin == 8 || nin == 9 || nin == 16;
+}
+
+hipError_t launch_fill_zero(int* p, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(int elem, const BatchTask* tasks, int ntasks, const StageRec* stages, const GemmRec* gemms,
+                        const BatchInst* insts, int* ctr, int nctr, int grid, hipStream_t s) {
+  BatchArgs g;
+  g.tasks = tasks;
+  g.stages = stages;
+  g.gemms = gemms;
+  g.insts = insts;
+  g.ctr = ctr;
+  g.nctr = nctr;
+  g.ntasks = ntasks;
+  if (elem == 8)
+    hipLaunchKernelGGL(batch_persistent<double>, dim3(grid), dim3(NTHREADS), 0, s, g);
+  else
+    hipLaunchKernelGGL(batch_persistent<float>, dim3(grid), dim3(NTHREADS), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace mf

@@ -1,246 +1,23 @@
-// Grouped leaf GEMM on FP64 or FP32 MFMA for gfx950, with the inner
+// Grouped leaf GEMM kernel on FP64 or FP32 MFMA for gfx950, with the inner
 // post-addition fused into its epilogue.
 //
-// One launch covers all leaf products of a fused level (equation "strassen",
+// One launch covers all leaf products of a plan (equation "strassen",
 // Section 2 of the paper).  Workgroup (group g, tile position): for each
 // product r of group g in order, acc = T_r S_r (MFMA), then
 // Out_c (tile) = / += W[c,r] * acc for each output block c it feeds.  With one
 // group Out is C itself; otherwise Out is the group's workspace block P_g (the
-// inner product result) and a linear-combination launch applies the outer
-// post-addition.  A workgroup owns its tile position of every block it
-// writes, so the read-modify-write is race-free and its summation order is
-// fixed (bitwise reproducible).
-#include "gemm_common.h"
+// inner product result) and linear-combination launches apply the outer
+// post-additions.
+#include "gemm_tile.h"
 
 namespace mf {
-
-// ---------------------------------------------------------------------------
-// Tile geometry: 128 x 128 output tile per workgroup of 8 waves (2 x 4), each
-// wave 64 x 32 = 4 x 2 MFMA tiles of 16 x 16, K step 16 (4 MFMA k-steps of
-// 4), LDS double-buffered, 2 workgroups per CU (4 waves per SIMD).  Both MFMAs
-// used (v_mfma_f64_16x16x4_f64, v_mfma_f32_16x16x4_f32) take
-//   A operand: lane l holds A[l % 16][l / 16]   (16 x 4)
-//   B operand: lane l holds B[l / 16][l % 16]   (4 x 16)
-// and return 4 values per lane:
-//   f64: element v of lane l is D[l / 16 + 4 v][l % 16]
-//   f32: element v of lane l is D[4 (l / 16) + v][l % 16].
-// Both LDS tiles are stored k-major (A transposed on the way in) so that the
-// 16 lanes of a fragment row read 16 consecutive elements.
-// ---------------------------------------------------------------------------
-#ifndef MF_GEMM_BK
-#define MF_GEMM_BK 16
-#endif
-#ifndef MF_GEMM_WAVES_PER_SIMD
-#define MF_GEMM_WAVES_PER_SIMD 4
-#endif
-#ifndef MF_GEMM_FRAG_DB
-#define MF_GEMM_FRAG_DB 1
-#endif
-#ifndef MF_GEMM_WN_TILES
-#define MF_GEMM_WN_TILES 2
-#endif
-constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = MF_GEMM_BK;
-constexpr int LDS_STRIDE = BM + 16;  // elements per LDS row
-constexpr int WM_T = 4, WN_T = MF_GEMM_WN_TILES;  // 16 x 16 MFMA tiles per wave (M, N)
-constexpr int WAVES_N = BN / (16 * WN_T), WAVES_M = BM / (16 * WM_T);
-constexpr int NTHREADS = 64 * WAVES_M * WAVES_N;
-constexpr int LPT = BM * BK / 2 / NTHREADS;  // pair loads per thread per operand and K step
-static_assert(LPT >= 1 && BM * BK / 2 % NTHREADS == 0, "tile loads must divide evenly");
-
-template <class T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-  typedef double v2 __attribute__((ext_vector_type(2)));
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
-};
-template <>
-struct Mfma<float> {
-  typedef float v2 __attribute__((ext_vector_type(2)));
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
-};
-
-// Global -> register prefetch of one BM x BK tile of the A view and one
-// BK x BN tile of the B view, two consecutive elements per load.  MASKED:
-// entries outside the view's valid rows/columns are zero and only valid
-// elements are read.
-template <class T, bool MASKED>
-__device__ __forceinline__ void load_tiles(const T* __restrict__ pa, int lda, int a_vr, int a_vc,
-                                           const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0, int j0,
-                                           int k0, int t, typename Mfma<T>::v2 (&ra)[LPT],
-                                           typename Mfma<T>::v2 (&rb)[LPT]) {
-  typedef typename Mfma<T>::v2 v2;
-#pragma unroll
-  for (int q = 0; q < LPT; ++q) {
-    const int idx = t + NTHREADS * q;
-    const int row = idx / (BK / 2), kp = (idx % (BK / 2)) * 2;
-    const int gi = i0 + row, gk = k0 + kp;
-    if (!MASKED) {
-      ra[q] = *reinterpret_cast<const v2*>(pa + (size_t)gi * lda + gk);
-    } else {
-      v2 v = {T(0), T(0)};
-      if (gi < a_vr) {
-        if (gk < a_vc) v.x = pa[(size_t)gi * lda + gk];
-        if (gk + 1 < a_vc) v.y = pa[(size_t)gi * lda + gk + 1];
-      }
-      ra[q] = v;
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < LPT; ++q) {
-    const int idx = t + NTHREADS * q;
-    const int kr = idx / (BN / 2), cp = (idx % (BN / 2)) * 2;
-    const int gk = k0 + kr, gj = j0 + cp;
-    if (!MASKED) {
-      rb[q] = *reinterpret_cast<const v2*>(pb + (size_t)gk * ldb + gj);
-    } else {
-      v2 v = {T(0), T(0)};
-      if (gk < b_vr) {
-        if (gj < b_vc) v.x = pb[(size_t)gk * ldb + gj];
-        if (gj + 1 < b_vc) v.y = pb[(size_t)gk * ldb + gj + 1];
-      }
-      rb[q] = v;
-    }
-  }
-}
-
-template <class T>
-__device__ __forceinline__ void store_tiles(T* As, T* Bs, int t, const typename Mfma<T>::v2 (&ra)[LPT],
-                                            const typename Mfma<T>::v2 (&rb)[LPT]) {
-  typedef typename Mfma<T>::v2 v2;
-#pragma unroll
-  for (int q = 0; q < LPT; ++q) {
-    const int idx = t + NTHREADS * q;
-    const int row = idx / (BK / 2), kp = (idx % (BK / 2)) * 2;
-    As[kp * LDS_STRIDE + row] = ra[q].x;
-    As[(kp + 1) * LDS_STRIDE + row] = ra[q].y;
-  }
-#pragma unroll
-  for (int q = 0; q < LPT; ++q) {
-    const int idx = t + NTHREADS * q;
-    const int kr = idx / (BN / 2), cp = (idx % (BN / 2)) * 2;
-    *reinterpret_cast<v2*>(Bs + kr * LDS_STRIDE + cp) = rb[q];
-  }
-}
-
-template <class T>
-__device__ __forceinline__ void load_frags(const T* As, const T* Bs, int s, int wm, int wn, int lr, int lk,
-                                           T (&fa)[WM_T], T (&fb)[WN_T]) {
-#pragma unroll
-  for (int mi = 0; mi < WM_T; ++mi) fa[mi] = As[(4 * s + lk) * LDS_STRIDE + wm + 16 * mi + lr];
-#pragma unroll
-  for (int ni = 0; ni < WN_T; ++ni) fb[ni] = Bs[(4 * s + lk) * LDS_STRIDE + wn + 16 * ni + lr];
-}
-
-template <class T>
-__device__ __forceinline__ void mfma_step(const T (&fa)[WM_T], const T (&fb)[WN_T],
-                                          typename Mfma<T>::v4 (&acc)[WM_T][WN_T]) {
-#pragma unroll
-  for (int mi = 0; mi < WM_T; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < WN_T; ++ni) acc[mi][ni] = Mfma<T>::op(fa[mi], fb[ni], acc[mi][ni]);
-}
-
-// acc = A_view(i0.., :) * B_view(:, j0..) over K = KT * BK.
-template <class T, bool MASKED>
-__device__ __forceinline__ void k_loop(T (*lds)[2][BK * LDS_STRIDE], const T* __restrict__ pa, int lda, int a_vr,
-                                       int a_vc, const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0,
-                                       int j0, int KT, int t, int wm, int wn, int lr, int lk,
-                                       typename Mfma<T>::v4 (&acc)[WM_T][WN_T]) {
-  typename Mfma<T>::v2 ra[LPT], rb[LPT];
-  load_tiles<T, MASKED>(pa, lda, a_vr, a_vc, pb, ldb, b_vr, b_vc, i0, j0, 0, t, ra, rb);
-  store_tiles<T>(lds[0][0], lds[0][1], t, ra, rb);
-  __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    const bool more = kt + 1 < KT;
-    if (more) load_tiles<T, MASKED>(pa, lda, a_vr, a_vc, pb, ldb, b_vr, b_vc, i0, j0, (kt + 1) * BK, t, ra, rb);
-    const T* As = lds[cur][0];
-    const T* Bs = lds[cur][1];
-#if MF_GEMM_FRAG_DB
-    T fa[2][WM_T], fb[2][WN_T];
-    load_frags<T>(As, Bs, 0, wm, wn, lr, lk, fa[0], fb[0]);
-#pragma unroll
-    for (int s = 0; s < BK / 4; ++s) {
-      if (s + 1 < BK / 4) load_frags<T>(As, Bs, s + 1, wm, wn, lr, lk, fa[(s + 1) & 1], fb[(s + 1) & 1]);
-      mfma_step<T>(fa[s & 1], fb[s & 1], acc);
-    }
-#else
-#pragma unroll
-    for (int s = 0; s < BK / 4; ++s) {
-      T fa[WM_T], fb[WN_T];
-      load_frags<T>(As, Bs, s, wm, wn, lr, lk, fa, fb);
-      mfma_step<T>(fa, fb, acc);
-    }
-#endif
-    if (more) store_tiles<T>(lds[cur ^ 1][0], lds[cur ^ 1][1], t, ra, rb);
-    __syncthreads();
-  }
-}
 
 template <class T>
 __global__ void __launch_bounds__(NTHREADS, MF_GEMM_WAVES_PER_SIMD) gemm_grouped(GemmArgs<T> g) {
   __shared__ T lds[2][2][BK * LDS_STRIDE];  // [buffer][A|B][k][col]
-  typedef typename Mfma<T>::v4 v4;
-  const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  const int wm = (wave / WAVES_N) * (16 * WM_T), wn = (wave % WAVES_N) * (16 * WN_T);
-  const int lr = lane & 15, lk = lane >> 4;
   int grp, ti, tj;
   work_of(blockIdx.x, g.tiles, g.groups, &grp, &ti, &tj);
-  const int i0 = ti * BM, j0 = tj * BN;
-  const int KT = g.m / BK;
-  const int r_beg = g.group_beg[grp], r_end = g.group_beg[grp + 1];
-
-  for (int r = r_beg; r < r_end; ++r) {
-    const ProdDesc pd = g.prods[r];
-    const T* pa = src_ptr(g, pd.a_src) + pd.a_off;
-    const T* pb = src_ptr(g, pd.b_src) + pd.b_off;
-    const bool vec_a = pd.a_src == SRC_WS || g.vec_in;
-    const bool vec_b = pd.b_src == SRC_WS || g.vec_in;
-
-    v4 acc[WM_T][WN_T];
-#pragma unroll
-    for (int mi = 0; mi < WM_T; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < WN_T; ++ni) acc[mi][ni] = v4{T(0), T(0), T(0), T(0)};
-
-    const bool interior = vec_a && vec_b && i0 + BM <= pd.a_vr && pd.a_vc >= g.m && pd.b_vr >= g.m &&
-                          j0 + BN <= pd.b_vc;
-    if (interior)
-      k_loop<T, false>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
-                       lk, acc);
-    else
-      k_loop<T, true>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
-                      lk, acc);
-
-    // Epilogue: post-addition into every output block this product feeds.
-    for (int e = pd.epi_beg; e < pd.epi_end; ++e) {
-      const EpiDesc ed = g.epis[e];
-      T* pc = dst_ptr(g, ed.c_src) + ed.c_off;
-      const bool full = (i0 + BM <= ed.c_vr) && (j0 + BN <= ed.c_vc);
-      const T coef = (T)ed.coef;
-#pragma unroll
-      for (int mi = 0; mi < WM_T; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < WN_T; ++ni)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = i0 + wm + 16 * mi + Mfma<T>::row(lk, v);
-            const int col = j0 + wn + 16 * ni + lr;
-            if (full || (row < ed.c_vr && col < ed.c_vc))
-              epi_apply<T>(pc + (size_t)row * ed.ldc + col, ed.first, coef, acc[mi][ni][v]);
-          }
-    }
-  }
+  gemm_tile<T>(g, grp, ti, tj, lds);
 }
 
 template <class T>

@@ -164,9 +164,62 @@ struct Plan {
   ~Plan();
 };
 
-// Builds (or fetches from the cache) the plan for a request.  Returns an
-// mf_status and sets the thread's error message on failure.
-mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
+// ---------------------------------------------------------------------------
+// Batched execution: many independent products in one persistent launch
+// ---------------------------------------------------------------------------
+
+// Device record of one combination stage of a plan (pointers into the plan's
+// device descriptors).
+struct StageRec {
+  const CombSet* sets;
+  const CombIn* ins;
+  const CombOut* outs;
+  const double* coef;
+  int32_t nin;
+  int32_t m;
+};
+
+// Device record of the grouped GEMM of a plan.
+struct GemmRec {
+  const ProdDesc* prods;
+  const EpiDesc* epis;
+  const int32_t* group_beg;
+  int32_t groups;
+  int32_t m;
+  int32_t tiles;
+  int32_t pad_;
+};
+
+// Per-run pointers of one instance.
+struct BatchInst {
+  const void* A;
+  const void* B;
+  void* C;
+  void* ws;
+  int32_t vec_in, vec_out;
+};
+
+// One task of the persistent kernel, in topological order: a chunk
+// [e0, e1) of one set of a combination stage (type 0) or one (group, tile)
+// work item of a grouped GEMM (type 1).  The task waits until counter
+// wait_ctr reaches wait_val (no wait if wait_ctr < 0) and increments done_ctr
+// when it has finished.
+struct BatchTask {
+  int32_t type;
+  int32_t inst;
+  int32_t rec;  // StageRec or GemmRec index
+  int32_t wait_ctr, wait_val, done_ctr;
+  int32_t a, b, c;  // combination: set; GEMM: group, ti, tj
+  int32_t pad_;
+  int64_t e0, e1;
+};
+
+// Builds (or fetches from the cache) the plan for a request.  Outer levels
+// are split into groups while the grouped GEMM has fewer than min_wg
+// workgroups (a standalone launch wants to fill the GPU; a batch does not).
+// Returns an mf_status and sets the thread's error message on failure.
+constexpr int64_t kStandaloneMinWorkgroups = 1024;
+mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg,
                    std::shared_ptr<const Plan>* out);
 
 // Copies the plan's descriptors to the device once (host-only queries such as
@@ -196,6 +249,14 @@ hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* 
                             hipStream_t s);
 // Input counts with a compiled linear-combination kernel.
 bool combine_supported(int nin);
+
+// Persistent batched kernel: runs `ntasks` tasks with `grid` workgroups.
+// ctr holds nctr counters, then the ticket, then the abort flag (all must be
+// zero at launch); abort is set if a wait exceeds its spin limit.
+hipError_t launch_batch(int elem, const BatchTask* tasks, int ntasks, const StageRec* stages, const GemmRec* gemms,
+                        const BatchInst* insts, int* ctr, int nctr, int grid, hipStream_t s);
+hipError_t launch_fill_zero(int* p, int count, hipStream_t s);
+bool batch_nin_supported(int nin);
 
 // Thread-local error message.
 mf_status fail(mf_status st, const std::string& msg);

@@ -93,9 +93,6 @@ void finish_set(CombineStage* st, CombSet set) {
   st->sets.push_back(set);
 }
 
-// Workgroups wanted in the grouped GEMM before outer levels are split off.
-constexpr int64_t kMinWorkgroups = 1024;
-
 mf_status build_classical(int64_t n, Plan* pl) {
   pl->P = pl->P_outer = 1;
   pl->R = pl->groups = 1;
@@ -120,7 +117,7 @@ mf_status build_classical(int64_t n, Plan* pl) {
   return MF_OK;
 }
 
-mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, Plan* pl) {
+mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg, Plan* pl) {
   pl->n = n;
   pl->dtype = dtype;
   pl->elem = (dtype & 0xff) == MF_F64 ? 8 : 4;
@@ -141,7 +138,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, P
   // Outer levels split off as groups (with post-addition stages) until the
   // grouped GEMM has enough workgroups.
   int Lo = 0;
-  while (Lo < L && positions * ipow(R, Lo) < kMinWorkgroups) ++Lo;
+  while (Lo < L && positions * ipow(R, Lo) < min_wg) ++Lo;
   const int Li = L - Lo;
   pl->levels_outer = Lo;
   const Algo Fi = Li > 0 ? power(*algo, Li) : Algo{};
@@ -440,9 +437,9 @@ mf_status upload(const Plan* pl) {
 struct Key {
   uint64_t algo;
   int levels, dtype;
-  int64_t n;
+  int64_t n, min_wg;
   bool operator<(const Key& o) const {
-    return std::tie(algo, levels, dtype, n) < std::tie(o.algo, o.levels, o.dtype, o.n);
+    return std::tie(algo, levels, dtype, n, min_wg) < std::tie(o.algo, o.levels, o.dtype, o.n, o.min_wg);
   }
 };
 
@@ -456,10 +453,10 @@ std::map<Key, std::shared_ptr<const Plan>>& cache() {
 
 }  // namespace
 
-mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
+mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg,
                    std::shared_ptr<const Plan>* out) {
   const int levels = algo ? levels_for(n, algo->a.p, algo->a.R, depth, cutoff) : 0;
-  const Key key{levels == 0 ? 0 : algo->id, levels, dtype, n};
+  const Key key{levels == 0 ? 0 : algo->id, levels, dtype, n, levels == 0 ? 0 : min_wg};
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = cache().find(key);
@@ -469,7 +466,7 @@ mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dt
     }
   }
   auto pl = std::make_shared<Plan>();
-  const mf_status st = build(levels == 0 ? nullptr : &algo->a, depth, cutoff, n, dtype, pl.get());
+  const mf_status st = build(levels == 0 ? nullptr : &algo->a, depth, cutoff, n, dtype, min_wg, pl.get());
   if (st != MF_OK) return st;
   std::lock_guard<std::mutex> lk(g_mu);
   auto ins = cache().emplace(key, pl);

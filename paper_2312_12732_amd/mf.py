@@ -36,7 +36,8 @@ MF_W_DEEPMIND_CT = 1
 
 EXPORTED = ["mf_algo_from_uvw", "mf_algo_builtin", "mf_algo_compose", "mf_algo_rebase", "mf_algo_info",
             "mf_algo_get_uvw", "mf_algo_free", "mf_fastmm", "mf_classical_mm", "mf_workspace_bytes",
-            "mf_fastmm_ws", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read"]
+            "mf_fastmm_ws", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read", "mf_batch_create",
+            "mf_batch_workspace_bytes", "mf_batch_run", "mf_batch_aborted", "mf_batch_tasks", "mf_batch_free"]
 
 
 class MFError(RuntimeError):
@@ -69,6 +70,12 @@ def _load():
         "mf_fastmm_ws": ([P, I, I, P, P, P, I64, I, P, ctypes.c_size_t, P], I),
         "mf_last_error": ([], ctypes.c_char_p),
         "mf_phase_timing": ([I], I),
+        "mf_batch_create": ([I, LP, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(I), I, AP], I),
+        "mf_batch_workspace_bytes": ([P, ctypes.POINTER(ctypes.c_size_t)], I),
+        "mf_batch_run": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P, ctypes.c_size_t, P], I),
+        "mf_batch_aborted": ([P, ctypes.POINTER(I)], I),
+        "mf_batch_tasks": ([P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_int32)], I),
+        "mf_batch_free": ([P], None),
         "mf_phase_timing_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
@@ -228,3 +235,73 @@ def mf_phase_timing_read():
     calls = ctypes.c_int()
     _check(lib.mf_phase_timing_read(ms, ctypes.byref(calls)))
     return list(ms), calls.value
+
+
+class Batch:
+    """Owning wrapper of an mf_batch handle (keeps its algorithms alive)."""
+
+    def __init__(self, handle: int, algos, sizes, dtype_code):
+        self._h = ctypes.c_void_p(handle)
+        self._algos = algos
+        self.sizes = list(sizes)
+        self.dtype_code = dtype_code
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        free = getattr(lib, "mf_batch_free", None) if lib is not None else None
+        if h is not None and h.value and free is not None:
+            free(h)
+            self._h = ctypes.c_void_p(0)
+
+    def workspace_bytes(self) -> int:
+        out = ctypes.c_size_t()
+        _check(lib.mf_batch_workspace_bytes(self._h, ctypes.byref(out)))
+        return out.value
+
+    def tasks(self):
+        """(ntasks, nctr, int32 array [ntasks, 5]: type, instance, wait counter, wait value, done counter)."""
+        nt, nc = ctypes.c_int(), ctypes.c_int()
+        _check(lib.mf_batch_tasks(self._h, ctypes.byref(nt), ctypes.byref(nc), None))
+        desc = np.zeros((nt.value, 5), dtype=np.int32)
+        _check(lib.mf_batch_tasks(self._h, None, None, desc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return nt.value, nc.value, desc
+
+    def aborted(self) -> bool:
+        flag = ctypes.c_int()
+        _check(lib.mf_batch_aborted(self._h, ctypes.byref(flag)))
+        return bool(flag.value)
+
+
+def mf_batch_create(sizes, algos, depths, cutoffs, dtype_code: int = MF_F64) -> Batch:
+    """Plan a batch: algos[i] may be None where depths[i] == 0."""
+    count = len(sizes)
+    n_arr = (ctypes.c_int64 * count)(*sizes)
+    a_arr = (ctypes.c_void_p * count)(*[(a.handle.value if a is not None else None) for a in algos])
+    d_arr = (ctypes.c_int * count)(*depths)
+    c_arr = (ctypes.c_int * count)(*cutoffs)
+    out = ctypes.c_void_p()
+    _check(lib.mf_batch_create(count, n_arr, a_arr, d_arr, c_arr, dtype_code, ctypes.byref(out)))
+    return Batch(out.value, [a for a in algos if a is not None], sizes, dtype_code)
+
+
+def mf_batch_run(batch: Batch, As, Bs, Cs, workspace=None, stream=None):
+    """Run a planned batch over lists of torch device tensors."""
+    count = len(batch.sizes)
+    if not (len(As) == len(Bs) == len(Cs) == count):
+        raise ValueError("one A, B, C per instance")
+    for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        _check_operands(A, B, C)
+        if A.shape[0] != batch.sizes[i]:
+            raise ValueError(f"instance {i}: size {A.shape[0]} != planned {batch.sizes[i]}")
+        if (_dtype_code(A, 0) & 0xff) != (batch.dtype_code & 0xff):
+            raise TypeError(f"instance {i}: dtype does not match the batch")
+    pa = (ctypes.c_void_p * count)(*[t.data_ptr() for t in As])
+    pb = (ctypes.c_void_p * count)(*[t.data_ptr() for t in Bs])
+    pc = (ctypes.c_void_p * count)(*[t.data_ptr() for t in Cs])
+    ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
+    nbytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib.mf_batch_run(batch.handle, pa, pb, pc, ws, nbytes, _stream(stream)))

@@ -177,6 +177,64 @@ mf_status mf_batch_tasks(const mf_batch* b, int* ntasks, int* nctr, int32_t* des
 /* Release a batch (NULL is ignored). */
 void mf_batch_free(mf_batch* b);
 
+/* ---- Serving -----------------------------------------------------------------
+ * A request loop for fast-multiply requests of different sizes.  Requests
+ * wait in a FIFO queue; the head request is admitted when one of max_slots
+ * slots (HIP streams) is free and the HBM it needs (A, B, C and the
+ * temporaries of its plan) fits in what remains of hbm_budget
+ * (allow_overtake lets later requests that fit pass a blocked head).  An
+ * admitted request allocates its memory from the stream-ordered pool,
+ * generates A and B on the device from its seed (mf_fill_uniform with seeds
+ * 2*seed and 2*seed+1), runs its product and releases its memory, all on its
+ * slot's stream, so requests on different slots overlap.  The plan is a pure
+ * function of (n, dtype): depth k+1 is used when n >= depth_min_n_*[k]
+ * (0 disables a level; algo NULL means classical only); results are
+ * therefore identical alone and among other requests. */
+typedef struct {
+  int max_slots;                /* 1..64 concurrent requests */
+  size_t hbm_budget;            /* bytes for all admitted requests together */
+  int allow_overtake;           /* 0: strict FIFO admission */
+  int64_t depth_min_n_f64[4];   /* depth policy for MF_F64 requests */
+  int64_t depth_min_n_f32[4];   /* depth policy for MF_F32 requests */
+} mf_server_config;
+typedef struct mf_server mf_server;
+
+/* Start a server (a worker thread and max_slots streams on the current
+ * device).  algo (may be NULL) must outlive the server. */
+mf_status mf_server_create(const mf_server_config* cfg, const mf_algo* algo, mf_server** out);
+/* HBM bytes a request of this size and dtype is admitted against. */
+mf_status mf_server_need_bytes(const mf_server* s, int64_t n, int dtype, size_t* bytes);
+/* Enqueue a request (dtype MF_F64 or MF_F32).  host_out: NULL, or pinned
+ * host memory of n*n elements that receives C.  MF_ERR_NOMEM if the request
+ * alone exceeds the budget.  *id: request index (may be NULL). */
+mf_status mf_server_submit(mf_server* s, int64_t n, int dtype, uint64_t seed, void* host_out, int64_t* id);
+/* Submit `count` requests from a replay thread at arrival times t_arrive[k]
+ * seconds after the call (host arrays are copied). */
+mf_status mf_server_replay(mf_server* s, int count, const double* t_arrive, const int64_t* n, const int* dtype,
+                           const uint64_t* seed);
+/* Wait until every submitted request has completed (including a replay). */
+mf_status mf_server_drain(mf_server* s);
+/* Per request (in id order; any pointer may be NULL): arrival, admission and
+ * completion times in seconds since the server started (-1 if not done),
+ * size and depth used; *count = number of requests. */
+mf_status mf_server_stats(mf_server* s, int64_t* count, double* t_arrive, double* t_admit, double* t_done, int64_t* n,
+                          int* depth);
+/* Stop the worker after the queue drains and release the server. */
+void mf_server_free(mf_server* s);
+
+/* Host-only simulation of the admission controller with given arrival
+ * times, service times and HBM needs (for tests and capacity planning):
+ * fills admission and completion times and the peak budget in use. */
+mf_status mf_admission_simulate(int count, const double* t_arrive, const double* service, const size_t* need,
+                                int slots, size_t budget, int allow_overtake, double* t_admit, double* t_done,
+                                size_t* peak_used);
+
+/* Fill count elements of device memory p (dtype MF_F64 or MF_F32) with the
+ * counter-based generator of the serving runtime: element i is 2u - 1 where
+ * u is the top 53 bits of the SplitMix64 output function applied to
+ * seed + (i + 1) * 0x9e3779b97f4a7c15, times 2^-53. */
+mf_status mf_fill_uniform(void* p, int64_t count, int dtype, uint64_t seed, mf_stream stream);
+
 /* Phase timing (tracing).  While enabled, every mf_fastmm / mf_fastmm_ws /
  * mf_classical_mm call records HIP events on its stream around its three
  * phases: 0 pre-additions, 1 grouped leaf GEMM with the fused epilogue

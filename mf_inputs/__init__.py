@@ -204,3 +204,20 @@ def unimodular(p: int, seed: int, shears: int = 3) -> np.ndarray:
         i, j = g.choice(p, size=2, replace=False)
         m[[i, j]] = m[[j, i]]
     return m
+
+
+# SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014), used as a
+# counter-based generator: element i = 2u - 1, u = top 53 bits of
+# mix(seed + (i + 1) * GAMMA) times 2^-53.
+_SPLITMIX_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def counter_uniform(count: int, seed: int, dtype=np.float64) -> np.ndarray:
+    """Counter-based uniform[-1, 1) values (the serving runtime's operands)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.arange(1, count + 1, dtype=np.uint64) * _SPLITMIX_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    u = (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    return (2.0 * u - 1.0).astype(dtype)

@@ -1,0 +1,413 @@
+// Serving runtime: a request loop that runs fast-multiply requests of
+// different sizes as they arrive.  Requests wait in a FIFO queue; the
+// admission controller admits the head request when a slot (a HIP stream) is
+// free and the HBM it needs - operands, output and temporaries - fits in the
+// remaining budget.  An admitted request allocates its memory from the
+// stream-ordered pool, generates its operands on the device from its seed,
+// runs mf_fastmm_ws with the plan chosen by a pure function of (n, dtype) and
+// releases its memory, all on its slot's stream; requests on different slots
+// overlap on the device.  A worker thread admits and polls completions; an
+// optional replay thread submits requests at given arrival times.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+
+#include "mf_internal.h"
+
+namespace mf {
+
+hipError_t launch_fill_uniform(void* p, int64_t count, int elem, uint64_t seed, hipStream_t s);
+
+// FIFO admission by free slots and HBM budget (host only).
+class Admission {
+ public:
+  Admission(int slots, size_t budget, bool overtake) : slots_(slots), budget_(budget), overtake_(overtake) {}
+  void arrive(int64_t id, size_t need) { queue_.push_back({id, need}); }
+  // Admits what fits now, in arrival order; returns the admitted ids.
+  std::vector<int64_t> admit() {
+    std::vector<int64_t> out;
+    for (auto it = queue_.begin(); it != queue_.end();) {
+      if (busy_ >= slots_) break;
+      if (used_ + it->need <= budget_) {
+        used_ += it->need;
+        ++busy_;
+        held_.push_back(*it);
+        out.push_back(it->id);
+        it = queue_.erase(it);
+      } else if (overtake_) {
+        ++it;
+      } else {
+        break;
+      }
+    }
+    return out;
+  }
+  void release(int64_t id) {
+    for (auto it = held_.begin(); it != held_.end(); ++it)
+      if (it->id == id) {
+        used_ -= it->need;
+        --busy_;
+        held_.erase(it);
+        return;
+      }
+  }
+  size_t used() const { return used_; }
+  int busy() const { return busy_; }
+  size_t waiting() const { return queue_.size(); }
+
+ private:
+  struct Item {
+    int64_t id;
+    size_t need;
+  };
+  int slots_;
+  size_t budget_;
+  bool overtake_;
+  size_t used_ = 0;
+  int busy_ = 0;
+  std::deque<Item> queue_;
+  std::vector<Item> held_;
+};
+
+}  // namespace mf
+
+using namespace mf;
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+  int64_t id;
+  int64_t n;
+  int dtype;
+  uint64_t seed;
+  void* host_out;  // pinned host buffer for C, or NULL
+  size_t need = 0;
+  int depth = 0;
+  double t_arrive = 0, t_admit = 0, t_done = 0;
+  int slot = -1;
+  mf_status status = MF_OK;
+  bool done = false;
+};
+
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+struct mf_server {
+  mf_server_config cfg;
+  const mf_algo* algo = nullptr;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  std::vector<int64_t> slot_req;  // request id per slot, -1 if free
+  std::mutex mu;
+  std::condition_variable cv;
+  std::vector<Req> reqs;  // by id
+  Admission adm;
+  std::thread worker;
+  std::thread replayer;
+  std::atomic<bool> stop{false};
+  int device = 0;
+  double t0 = 0;
+  int64_t completed = 0;
+  explicit mf_server(const mf_server_config& c)
+      : cfg(c), adm(c.max_slots, c.hbm_budget, c.allow_overtake != 0) {}
+};
+
+namespace {
+
+// Depth policy: a pure function of (n, dtype), so a request's result is the
+// same alone and among others.
+int depth_for(const mf_server* s, int64_t n, int dtype) {
+  if (!s->algo) return 0;
+  const bool f64 = (dtype & 0xff) == MF_F64;
+  const int64_t* th = f64 ? s->cfg.depth_min_n_f64 : s->cfg.depth_min_n_f32;
+  int d = 0;
+  for (int k = 0; k < 4; ++k)
+    if (th[k] > 0 && n >= th[k]) d = k + 1;
+  return d;
+}
+
+mf_status need_bytes(const mf_server* s, int64_t n, int dtype, int depth, size_t* bytes) {
+  size_t ws = 0;
+  if (depth > 0) {
+    mf_status st = mf_workspace_bytes(s->algo, depth, 0, n, dtype, &ws);
+    if (st != MF_OK) return st;
+  }
+  const size_t elem = (dtype & 0xff) == MF_F64 ? 8 : 4;
+  *bytes = 3 * round256((size_t)n * (size_t)n * elem) + round256(ws);
+  return MF_OK;
+}
+
+// Enqueues the whole request on its slot's stream.
+mf_status launch_request(mf_server* s, Req& r) {
+  hipStream_t st = s->streams[r.slot];
+  const size_t elem = (r.dtype & 0xff) == MF_F64 ? 8 : 4;
+  const size_t mat = round256((size_t)r.n * (size_t)r.n * elem);
+  char* mem = nullptr;
+  if (hipMallocAsync(reinterpret_cast<void**>(&mem), r.need, st) != hipSuccess || !mem) {
+    (void)hipGetLastError();
+    return fail(MF_ERR_NOMEM, "request allocation failed");
+  }
+  void* A = mem;
+  void* B = mem + mat;
+  void* C = mem + 2 * mat;
+  void* ws = mem + 3 * mat;
+  const int64_t cnt = r.n * r.n;
+  mf_status res = MF_OK;
+  if (launch_fill_uniform(A, cnt, (int)elem, r.seed * 2 + 0, st) != hipSuccess ||
+      launch_fill_uniform(B, cnt, (int)elem, r.seed * 2 + 1, st) != hipSuccess)
+    res = fail(MF_ERR_HIP, "operand generation launch failed");
+  if (res == MF_OK) {
+    if (r.depth > 0)
+      res = mf_fastmm_ws(s->algo, r.depth, 0, A, B, C, r.n, r.dtype, ws, r.need - 3 * mat, st);
+    else
+      res = mf_classical_mm(A, B, C, r.n, r.dtype, st);
+  }
+  if (res == MF_OK && r.host_out &&
+      hipMemcpyAsync(r.host_out, C, (size_t)cnt * elem, hipMemcpyDeviceToHost, st) != hipSuccess)
+    res = fail(MF_ERR_HIP, "result copy failed");
+  if (hipFreeAsync(mem, st) != hipSuccess && res == MF_OK) res = fail(MF_ERR_HIP, "request release failed");
+  if (hipEventRecord(s->events[r.slot], st) != hipSuccess && res == MF_OK)
+    res = fail(MF_ERR_HIP, "completion event failed");
+  return res;
+}
+
+void worker_loop(mf_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (true) {
+    // completions
+    bool any_busy = false;
+    for (size_t k = 0; k < s->slot_req.size(); ++k) {
+      const int64_t id = s->slot_req[k];
+      if (id < 0) continue;
+      any_busy = true;
+      const hipError_t q = hipEventQuery(s->events[k]);
+      if (q == hipErrorNotReady) continue;
+      Req& r = s->reqs[id];
+      r.t_done = now_s() - s->t0;
+      if (q != hipSuccess && r.status == MF_OK) r.status = MF_ERR_HIP;
+      r.done = true;
+      s->adm.release(id);
+      s->slot_req[k] = -1;
+      ++s->completed;
+      s->cv.notify_all();
+    }
+    // admissions
+    for (int64_t id : s->adm.admit()) {
+      Req& r = s->reqs[id];
+      int slot = -1;
+      for (size_t k = 0; k < s->slot_req.size(); ++k)
+        if (s->slot_req[k] < 0) {
+          slot = (int)k;
+          break;
+        }
+      r.slot = slot;
+      r.t_admit = now_s() - s->t0;
+      s->slot_req[slot] = id;
+      r.status = launch_request(s, r);
+      any_busy = true;
+    }
+    if (s->stop && !any_busy && s->adm.waiting() == 0) break;
+    if (any_busy) {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+    } else {
+      s->cv.wait_for(lk, std::chrono::milliseconds(1));
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_server_create(const mf_server_config* cfg, const mf_algo* algo, mf_server** out) {
+  clear_error();
+  if (!cfg || !out) return fail(MF_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  if (cfg->max_slots < 1 || cfg->max_slots > 64) return fail(MF_ERR_ARG, "max_slots must be in [1, 64]");
+  if (cfg->hbm_budget == 0) return fail(MF_ERR_ARG, "hbm_budget must be > 0");
+  mf_server* s = new (std::nothrow) mf_server(*cfg);
+  if (!s) return fail(MF_ERR_NOMEM, "host allocation failed");
+  s->algo = algo;
+  (void)hipGetDevice(&s->device);
+  for (int k = 0; k < cfg->max_slots; ++k) {
+    hipStream_t st;
+    hipEvent_t ev;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      mf_server_free(s);
+      return fail(MF_ERR_HIP, "stream creation failed");
+    }
+    s->streams.push_back(st);
+    s->events.push_back(ev);
+    s->slot_req.push_back(-1);
+  }
+  s->t0 = now_s();
+  s->worker = std::thread(worker_loop, s);
+  *out = s;
+  return MF_OK;
+}
+
+mf_status mf_server_need_bytes(const mf_server* s, int64_t n, int dtype, size_t* bytes) {
+  clear_error();
+  if (!s || !bytes || n < 1) return fail(MF_ERR_ARG, "invalid argument");
+  if ((dtype & 0xff) != MF_F64 && (dtype & 0xff) != MF_F32) return fail(MF_ERR_ARG, "unknown dtype");
+  return need_bytes(s, n, dtype, depth_for(s, n, dtype), bytes);
+}
+
+mf_status mf_server_submit(mf_server* s, int64_t n, int dtype, uint64_t seed, void* host_out, int64_t* id) {
+  clear_error();
+  if (!s || n < 1 || n > (1 << 16)) return fail(MF_ERR_ARG, "invalid argument");
+  if ((dtype & ~0xff) != 0 || ((dtype & 0xff) != MF_F64 && (dtype & 0xff) != MF_F32))
+    return fail(MF_ERR_ARG, "serving takes MF_F64 or MF_F32 (native leaves)");
+  Req r{};
+  r.n = n;
+  r.dtype = dtype;
+  r.seed = seed;
+  r.host_out = host_out;
+  r.depth = depth_for(s, n, dtype);
+  mf_status st = need_bytes(s, n, dtype, r.depth, &r.need);
+  if (st != MF_OK) return st;
+  if (r.need > s->cfg.hbm_budget) return fail(MF_ERR_NOMEM, "request needs more HBM than the whole budget");
+  std::lock_guard<std::mutex> lk(s->mu);
+  r.id = (int64_t)s->reqs.size();
+  r.t_arrive = now_s() - s->t0;
+  s->reqs.push_back(r);
+  s->adm.arrive(r.id, r.need);
+  s->cv.notify_all();
+  if (id) *id = r.id;
+  return MF_OK;
+}
+
+mf_status mf_server_replay(mf_server* s, int count, const double* t_arrive, const int64_t* n, const int* dtype,
+                           const uint64_t* seed) {
+  clear_error();
+  if (!s || count < 0 || (count > 0 && (!t_arrive || !n || !dtype || !seed))) return fail(MF_ERR_ARG, "invalid argument");
+  if (s->replayer.joinable()) s->replayer.join();
+  std::vector<double> t(t_arrive, t_arrive + count);
+  std::vector<int64_t> nn(n, n + count);
+  std::vector<int> dt(dtype, dtype + count);
+  std::vector<uint64_t> sd(seed, seed + count);
+  s->replayer = std::thread([s, t, nn, dt, sd]() {
+    (void)hipSetDevice(s->device);
+    const double base = now_s();
+    for (size_t k = 0; k < t.size(); ++k) {
+      const double wait = base + t[k] - now_s();
+      if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+      (void)mf_server_submit(s, nn[k], dt[k], sd[k], nullptr, nullptr);
+    }
+  });
+  return MF_OK;
+}
+
+mf_status mf_server_drain(mf_server* s) {
+  clear_error();
+  if (!s) return fail(MF_ERR_ARG, "server is NULL");
+  if (s->replayer.joinable()) s->replayer.join();
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv.wait(lk, [&]() { return s->completed == (int64_t)s->reqs.size(); });
+  for (const Req& r : s->reqs)
+    if (r.status != MF_OK) return fail(r.status, "a request failed");
+  return MF_OK;
+}
+
+mf_status mf_server_stats(mf_server* s, int64_t* count, double* t_arrive, double* t_admit, double* t_done,
+                          int64_t* n, int* depth) {
+  clear_error();
+  if (!s) return fail(MF_ERR_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (count) *count = (int64_t)s->reqs.size();
+  for (size_t k = 0; k < s->reqs.size(); ++k) {
+    const Req& r = s->reqs[k];
+    if (t_arrive) t_arrive[k] = r.t_arrive;
+    if (t_admit) t_admit[k] = r.t_admit;
+    if (t_done) t_done[k] = r.done ? r.t_done : -1.0;
+    if (n) n[k] = r.n;
+    if (depth) depth[k] = r.depth;
+  }
+  return MF_OK;
+}
+
+void mf_server_free(mf_server* s) {
+  if (!s) return;
+  if (s->replayer.joinable()) s->replayer.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  for (auto& e : s->events) (void)hipEventDestroy(e);
+  for (auto& st : s->streams) (void)hipStreamDestroy(st);
+  delete s;
+}
+
+mf_status mf_fill_uniform(void* p, int64_t count, int dtype, uint64_t seed, mf_stream stream) {
+  clear_error();
+  if (count < 0 || (count > 0 && !p)) return fail(MF_ERR_ARG, "invalid argument");
+  if (dtype != MF_F64 && dtype != MF_F32) return fail(MF_ERR_ARG, "dtype must be MF_F64 or MF_F32");
+  const int elem = dtype == MF_F64 ? 8 : 4;
+  if (reinterpret_cast<uintptr_t>(p) & (elem - 1)) return fail(MF_ERR_ARG, "misaligned pointer");
+  if (launch_fill_uniform(p, count, elem, seed, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return fail(MF_ERR_HIP, "fill launch failed");
+  return MF_OK;
+}
+
+mf_status mf_admission_simulate(int count, const double* t_arrive, const double* service, const size_t* need,
+                                int slots, size_t budget, int allow_overtake, double* t_admit, double* t_done,
+                                size_t* peak_used) {
+  clear_error();
+  if (count < 0 || slots < 1 || (count > 0 && (!t_arrive || !service || !need || !t_admit || !t_done)))
+    return fail(MF_ERR_ARG, "invalid argument");
+  for (int k = 0; k < count; ++k)
+    if (need[k] > budget) return fail(MF_ERR_NOMEM, "a request needs more than the whole budget");
+  Admission adm(slots, budget, allow_overtake != 0);
+  std::vector<std::pair<double, int>> running;  // (finish time, id)
+  int next = 0, finished = 0;
+  double now = 0;
+  size_t peak = 0;
+  while (finished < count) {
+    // next event: an arrival or a completion
+    double t_arr = next < count ? t_arrive[next] : 1e300;
+    double t_fin = 1e300;
+    for (auto& rf : running) t_fin = std::min(t_fin, rf.first);
+    if (t_arr <= t_fin) {
+      now = t_arr;
+      adm.arrive(next, need[next]);
+      ++next;
+    } else {
+      now = t_fin;
+      for (auto it = running.begin(); it != running.end();) {
+        if (it->first <= now) {
+          t_done[it->second] = it->first;
+          adm.release(it->second);
+          ++finished;
+          it = running.erase(it);
+        } else {
+          ++it;
+        }
+      }
+    }
+    for (int64_t id : adm.admit()) {
+      t_admit[id] = now;
+      running.push_back({now + service[id], (int)id});
+    }
+    peak = std::max(peak, adm.used());
+  }
+  if (peak_used) *peak_used = peak;
+  return MF_OK;
+}
+
+}  // extern "C"

@@ -37,7 +37,14 @@ MF_W_DEEPMIND_CT = 1
 EXPORTED = ["mf_algo_from_uvw", "mf_algo_builtin", "mf_algo_compose", "mf_algo_rebase", "mf_algo_info",
             "mf_algo_get_uvw", "mf_algo_free", "mf_fastmm", "mf_classical_mm", "mf_workspace_bytes",
             "mf_fastmm_ws", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read", "mf_batch_create",
-            "mf_batch_workspace_bytes", "mf_batch_run", "mf_batch_aborted", "mf_batch_tasks", "mf_batch_free"]
+            "mf_batch_workspace_bytes", "mf_batch_run", "mf_batch_aborted", "mf_batch_tasks", "mf_batch_free",
+            "mf_server_create", "mf_server_need_bytes", "mf_server_submit", "mf_server_replay", "mf_server_drain",
+            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform"]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int), ("hbm_budget", ctypes.c_size_t), ("allow_overtake", ctypes.c_int),
+                ("depth_min_n_f64", ctypes.c_int64 * 4), ("depth_min_n_f32", ctypes.c_int64 * 4)]
 
 
 class MFError(RuntimeError):
@@ -76,6 +83,16 @@ def _load():
         "mf_batch_aborted": ([P, ctypes.POINTER(I)], I),
         "mf_batch_tasks": ([P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_int32)], I),
         "mf_batch_free": ([P], None),
+        "mf_server_create": ([ctypes.POINTER(ServerConfig), P, AP], I),
+        "mf_server_need_bytes": ([P, I64, I, ctypes.POINTER(ctypes.c_size_t)], I),
+        "mf_server_submit": ([P, I64, I, ctypes.c_uint64, P, LP], I),
+        "mf_server_replay": ([P, I, DP, LP, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_uint64)], I),
+        "mf_server_drain": ([P], I),
+        "mf_server_stats": ([P, LP, DP, DP, DP, LP, ctypes.POINTER(I)], I),
+        "mf_server_free": ([P], None),
+        "mf_admission_simulate": ([I, DP, DP, ctypes.POINTER(ctypes.c_size_t), I, ctypes.c_size_t, I, DP, DP,
+                                   ctypes.POINTER(ctypes.c_size_t)], I),
+        "mf_fill_uniform": ([P, I64, I, ctypes.c_uint64, P], I),
         "mf_phase_timing_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
@@ -305,3 +322,87 @@ def mf_batch_run(batch: Batch, As, Bs, Cs, workspace=None, stream=None):
     ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
     nbytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
     _check(lib.mf_batch_run(batch.handle, pa, pb, pc, ws, nbytes, _stream(stream)))
+
+
+class Server:
+    """Owning wrapper of an mf_server (keeps its algorithm alive)."""
+
+    def __init__(self, max_slots, hbm_budget, algo=None, depth_min_n_f64=(0, 0, 0, 0), depth_min_n_f32=(0, 0, 0, 0),
+                 allow_overtake=False):
+        cfg = ServerConfig()
+        cfg.max_slots = max_slots
+        cfg.hbm_budget = int(hbm_budget)
+        cfg.allow_overtake = 1 if allow_overtake else 0
+        for k in range(4):
+            cfg.depth_min_n_f64[k] = int(depth_min_n_f64[k])
+            cfg.depth_min_n_f32[k] = int(depth_min_n_f32[k])
+        self._algo = algo
+        out = ctypes.c_void_p()
+        _check(lib.mf_server_create(ctypes.byref(cfg), algo.handle if algo is not None else None, ctypes.byref(out)))
+        self._h = out
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        free = getattr(lib, "mf_server_free", None) if lib is not None else None
+        if h is not None and h.value and free is not None:
+            free(h)
+            self._h = ctypes.c_void_p(0)
+
+    __del__ = close
+
+    def need_bytes(self, n, dtype_code):
+        out = ctypes.c_size_t()
+        _check(lib.mf_server_need_bytes(self._h, n, dtype_code, ctypes.byref(out)))
+        return out.value
+
+    def submit(self, n, dtype_code, seed, host_out=None):
+        """host_out: pinned torch CPU tensor of n*n elements (or None)."""
+        rid = ctypes.c_int64()
+        ptr = ctypes.c_void_p(host_out.data_ptr()) if host_out is not None else None
+        _check(lib.mf_server_submit(self._h, n, dtype_code, seed, ptr, ctypes.byref(rid)))
+        return rid.value
+
+    def replay(self, t_arrive, ns, dtype_codes, seeds):
+        k = len(ns)
+        t = np.ascontiguousarray(t_arrive, dtype=np.float64)
+        nn = np.ascontiguousarray(ns, dtype=np.int64)
+        dd = np.ascontiguousarray(dtype_codes, dtype=np.int32)
+        ss = np.ascontiguousarray(seeds, dtype=np.uint64)
+        _check(lib.mf_server_replay(self._h, k, _dptr(t), nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    dd.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                    ss.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+
+    def drain(self):
+        _check(lib.mf_server_drain(self._h))
+
+    def stats(self):
+        cnt = ctypes.c_int64()
+        _check(lib.mf_server_stats(self._h, ctypes.byref(cnt), None, None, None, None, None))
+        c = cnt.value
+        ta, tm, td = (np.zeros(c) for _ in range(3))
+        nn = np.zeros(c, dtype=np.int64)
+        dp = np.zeros(c, dtype=np.int32)
+        _check(lib.mf_server_stats(self._h, ctypes.byref(cnt), _dptr(ta), _dptr(tm), _dptr(td),
+                                   nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   dp.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+        return {"t_arrive": ta, "t_admit": tm, "t_done": td, "n": nn, "depth": dp}
+
+
+def mf_admission_simulate(t_arrive, service, need, slots, budget, allow_overtake=False):
+    k = len(t_arrive)
+    t = np.ascontiguousarray(t_arrive, dtype=np.float64)
+    sv = np.ascontiguousarray(service, dtype=np.float64)
+    nd = (ctypes.c_size_t * k)(*[int(x) for x in need])
+    ta = np.zeros(k)
+    td = np.zeros(k)
+    peak = ctypes.c_size_t()
+    _check(lib.mf_admission_simulate(k, _dptr(t), _dptr(sv), nd, slots, int(budget), 1 if allow_overtake else 0,
+                                     _dptr(ta), _dptr(td), ctypes.byref(peak)))
+    return ta, td, peak.value
+
+
+def mf_fill_uniform(t, seed, stream=None):
+    """Fill a device tensor (float64 or float32) with the serving generator."""
+    code = _dtype_code(t, 0)
+    _check(lib.mf_fill_uniform(ctypes.c_void_p(t.data_ptr()), t.numel(), code, seed, _stream(stream)))
+    return t

@@ -1,0 +1,88 @@
+"""GPU checks of the serving runtime: requests of mixed sizes and dtypes
+served concurrently give the same results as each request served alone
+(bitwise: the plan is a pure function of (n, dtype) and the kernels are
+deterministic), match the CPU oracle on independently generated operands,
+and overlap on the device."""
+import numpy as np
+import pytest
+
+import mf_inputs as mi
+from oracle import matmul as om
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mf = pytest.importorskip("paper_2312_12732_amd.mf", reason="libmf.so not built")
+
+REQS = [(300, "f32", 1), (1000, "f64", 2), (128, "f32", 3), (2048, "f32", 4), (700, "f64", 5), (1536, "f64", 6),
+        (256, "f32", 7), (1200, "f32", 8), (2500, "f64", 9), (64, "f64", 10)]
+POLICY = dict(depth_min_n_f64=(512, 1500, 0, 0), depth_min_n_f32=(1024, 2000, 0, 0))
+
+
+def code(dt):
+    return mf.MF_F64 if dt == "f64" else mf.MF_F32
+
+
+def tdtype(dt):
+    return torch.float64 if dt == "f64" else torch.float32
+
+
+def serve(reqs, slots):
+    srv = mf.Server(slots, 16 << 30, mf.mf_algo_builtin("winograd"), **POLICY)
+    outs = []
+    for n, dt, seed in reqs:
+        out = torch.empty(n, n, dtype=tdtype(dt)).pin_memory()
+        srv.submit(n, code(dt), seed, out)
+        outs.append(out)
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    return [o.numpy().astype(np.float64) for o in outs], st
+
+
+def test_generator_matches_host():
+    for dt, npdt in (("f64", np.float64), ("f32", np.float32)):
+        t = torch.empty(12345, dtype=tdtype(dt), device="cuda:0")
+        mf.mf_fill_uniform(t, 777)
+        torch.cuda.synchronize()
+        assert np.array_equal(t.cpu().numpy(), mi.counter_uniform(12345, 777, npdt))
+
+
+def test_mix_equals_alone_and_oracle():
+    mixed, st = serve(REQS, slots=4)
+    for k, (n, dt, seed) in enumerate(REQS):
+        alone, _ = serve([(n, dt, seed)], slots=1)
+        assert np.array_equal(mixed[k], alone[0]), (n, dt)
+        npdt = np.float64 if dt == "f64" else np.float32
+        A = mi.counter_uniform(n * n, 2 * seed, npdt).astype(np.float64).reshape(n, n)
+        B = mi.counter_uniform(n * n, 2 * seed + 1, npdt).astype(np.float64).reshape(n, n)
+        err = om.rel_fro_error(mixed[k], om.classical_mm(A, B))
+        assert err < (1e-11 if dt == "f64" else 2e-5), (n, dt, err)
+    assert (st["t_admit"] >= st["t_arrive"]).all() and (st["t_done"] >= st["t_admit"]).all()
+    # requests submitted together overlap on the device
+    first_done = st["t_done"].min()
+    assert (st["t_admit"] < first_done).sum() >= 2
+    assert set(st["depth"].tolist()) >= {0, 1, 2}
+
+
+def test_budget_limits_concurrency():
+    # a budget that fits one 2048 fp64 request at a time serialises them
+    srv = mf.Server(4, 1, None)
+    need = srv.need_bytes(2048, mf.MF_F64)
+    srv.close()
+    srv = mf.Server(4, need, None)
+    for s in range(3):
+        srv.submit(2048, mf.MF_F64, 100 + s)
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    order = np.argsort(st["t_admit"])
+    ta, td = st["t_admit"][order], st["t_done"][order]
+    assert (ta[1:] >= td[:-1]).all()
+    with pytest.raises(mf.MFError) as e:
+        srv2 = mf.Server(2, need - 1, None)
+        try:
+            srv2.submit(2048, mf.MF_F64, 1)
+        finally:
+            srv2.close()
+    assert e.value.status == mf.MF_ERR_NOMEM

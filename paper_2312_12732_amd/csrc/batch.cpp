@@ -36,7 +36,12 @@ struct mf_batch {
   mutable void* run_dev = nullptr;
   mutable mf::BatchInst* d_insts = nullptr;
   mutable int* d_ctr = nullptr;
+  mutable mf::BatchInst* h_insts = nullptr;  // pinned staging of the instance table
+  mutable hipEvent_t copied = nullptr;        // the last run's table copy has executed
   ~mf_batch() {
+    if (copied) (void)hipEventSynchronize(copied);
+    if (copied) (void)hipEventDestroy(copied);
+    if (h_insts) (void)hipHostFree(h_insts);
     if (dev) (void)hipFree(dev);
     if (run_dev) (void)hipFree(run_dev);
   }
@@ -205,6 +210,12 @@ mf_status upload_batch(const mf_batch* b) {
     return fail(MF_ERR_NOMEM, "device allocation of the batch run state failed");
   }
   b->d_insts = static_cast<BatchInst*>(b->run_dev);
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_insts), (size_t)b->count * sizeof(BatchInst), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MF_ERR_NOMEM, "pinned staging allocation of the batch failed");
+  }
   b->d_ctr = reinterpret_cast<int*>(static_cast<char*>(b->run_dev) + align((size_t)b->count * sizeof(BatchInst)));
   int dev_id = 0, cus = 256;
   if (hipGetDevice(&dev_id) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
@@ -316,7 +327,12 @@ mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* cons
   }
   for (int i = 0; i < b->count; ++i) insts[i].ws = static_cast<char*>(ws) + b->ws_off[i];
   mf_status st = MF_OK;
-  hipError_t e = hipMemcpyAsync(b->d_insts, insts.data(), insts.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s);
+  // The pinned staging buffer is reused: wait until the previous run's copy
+  // out of it has executed.
+  if (hipEventSynchronize(b->copied) != hipSuccess) return fail(MF_ERR_HIP, "waiting for the previous run failed");
+  memcpy(b->h_insts, insts.data(), insts.size() * sizeof(BatchInst));
+  hipError_t e = hipMemcpyAsync(b->d_insts, b->h_insts, insts.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(b->copied, s);
   if (e == hipSuccess) e = launch_fill_zero(b->d_ctr, b->nctr + 2, s);
   if (e == hipSuccess)
     e = launch_batch((int)b->elem, b->d_tasks, (int)b->tasks.size(), b->d_stages, b->d_gemms, b->d_insts, b->d_ctr,

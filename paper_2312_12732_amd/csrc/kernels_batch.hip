@@ -15,10 +15,13 @@
 //
 // Memory ordering.  A task's results are published by an agent-scope
 // release fence in every wave followed by the counter increment; a waiting
-// workgroup observes the counter with agent-scope acquire loads and every
-// wave executes an acquire fence before reading them (the fences write back
-// and invalidate the XCD-local caches, so producers and consumers may sit on
-// different XCDs).  Counters are polled with vector memory loads.
+// workgroup polls the counter with relaxed agent-scope loads (vector loads
+// that bypass the non-coherent caches without invalidating anything), sleeping
+// between polls, and once it has seen the value every wave executes one
+// agent-scope acquire fence (which invalidates the XCD-local caches) before
+// reading the results, so producers and consumers may sit on different XCDs.
+// Polling with acquire loads would invalidate the L2 on every poll and, with
+// hundreds of waiting workgroups, starve the producers.
 #include "combine_body.h"
 #include "gemm_tile.h"
 
@@ -26,7 +29,9 @@ namespace mf {
 
 namespace {
 
-constexpr int kSpinLimit = 1 << 22;
+// Polls (each after a sleep of about 2000 cycles) before a wait gives up:
+// a few seconds, far beyond any legitimate wait.
+constexpr int kSpinLimit = 1 << 21;
 
 struct BatchArgs {
   const BatchTask* tasks;
@@ -38,8 +43,8 @@ struct BatchArgs {
   int ntasks;
 };
 
-__device__ __forceinline__ int load_acquire(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int load_relaxed(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <class T>
@@ -102,7 +107,7 @@ __global__ void __launch_bounds__(NTHREADS, MF_GEMM_WAVES_PER_SIMD) batch_persis
   for (;;) {
     if (threadIdx.x == 0) {
       int t = atomicAdd(ticket, 1);
-      if (load_acquire(abort_flag) != 0) t = g.ntasks;
+      if (load_relaxed(abort_flag) != 0) t = g.ntasks;
       s_task = t;
     }
     __syncthreads();
@@ -112,13 +117,13 @@ __global__ void __launch_bounds__(NTHREADS, MF_GEMM_WAVES_PER_SIMD) batch_persis
     if (tk.wait_ctr >= 0) {
       if (threadIdx.x == 0) {
         int ok = 1;
-        for (int spins = 0; load_acquire(&g.ctr[tk.wait_ctr]) < tk.wait_val; ++spins) {
-          if (spins >= kSpinLimit || load_acquire(abort_flag) != 0) {
+        for (int spins = 0; load_relaxed(&g.ctr[tk.wait_ctr]) < tk.wait_val; ++spins) {
+          if (spins >= kSpinLimit || load_relaxed(abort_flag) != 0) {
             ok = 0;
             atomicExch(abort_flag, 1);
             break;
           }
-          __builtin_amdgcn_s_sleep(8);
+          __builtin_amdgcn_s_sleep(32);
         }
         s_ok = ok;
       }

@@ -38,6 +38,32 @@ def run(batch, As, Bs, tdtype, workspace=None):
 SIZES = mi.batch_sizes(20, 30) + [100, 300, 513, 64, 1]
 
 
+def test_batch_matches_standalone_for_classical():
+    sizes = [256, 640, 1024]
+    b = mf.mf_batch_create(sizes, [None] * 3, [0] * 3, [0] * 3, mf.MF_F64)
+    As = [mi.uniform(n, 1 + i) for i, n in enumerate(sizes)]
+    Bs = [mi.uniform(n, 11 + i) for i, n in enumerate(sizes)]
+    Cs = run(b, As, Bs, torch.float64)
+    for A, B, C in zip(As, Bs, Cs):
+        dA = torch.from_numpy(A).cuda()
+        dB = torch.from_numpy(B).cuda()
+        dC = torch.empty_like(dA)
+        mf.mf_classical_mm(dA, dB, dC)
+        torch.cuda.synchronize()
+        assert np.array_equal(C, dC.cpu().numpy())
+
+
+def test_tiny_fast_batch():
+    """Two instances with dependencies (pre-additions, then GEMM tiles)."""
+    s = mf.mf_algo_builtin("winograd")
+    sizes = [256, 384]
+    b = mf.mf_batch_create(sizes, [s, s], [1, 1], [0, 0], mf.MF_F64)
+    As = [mi.int_uniform(n, 900 + i).astype(np.float64) for i, n in enumerate(sizes)]
+    Bs = [mi.int_uniform(n, 950 + i).astype(np.float64) for i, n in enumerate(sizes)]
+    for A, B, C in zip(As, Bs, run(b, As, Bs, torch.float64)):
+        assert np.array_equal(C, A @ B)
+
+
 def test_batch_fp64_int_exact():
     b = plan(SIZES, mf.MF_F64)
     As = [mi.int_uniform(n, 100 + i).astype(np.float64) for i, n in enumerate(SIZES)]
@@ -57,21 +83,6 @@ def test_batch_fp64_uniform_and_deterministic():
     for A, B, c1, c2 in zip(As, Bs, C1, C2):
         assert np.array_equal(c1, c2)
         assert om.rel_fro_error(c1, om.classical_mm(A, B)) < 1e-11
-
-
-def test_batch_matches_standalone_for_classical():
-    sizes = [256, 640, 1024]
-    b = mf.mf_batch_create(sizes, [None] * 3, [0] * 3, [0] * 3, mf.MF_F64)
-    As = [mi.uniform(n, 1 + i) for i, n in enumerate(sizes)]
-    Bs = [mi.uniform(n, 11 + i) for i, n in enumerate(sizes)]
-    Cs = run(b, As, Bs, torch.float64)
-    for A, B, C in zip(As, Bs, Cs):
-        dA = torch.from_numpy(A).cuda()
-        dB = torch.from_numpy(B).cuda()
-        dC = torch.empty_like(dA)
-        mf.mf_classical_mm(dA, dB, dC)
-        torch.cuda.synchronize()
-        assert np.array_equal(C, dC.cpu().numpy())
 
 
 def test_batch_fp32():

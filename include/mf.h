@@ -177,6 +177,27 @@ mf_status mf_batch_tasks(const mf_batch* b, int* ntasks, int* nctr, int32_t* des
 /* Release a batch (NULL is ignored). */
 void mf_batch_free(mf_batch* b);
 
+/* ---- Autotuner of the batched form ------------------------------------------
+ * For each of nsizes sizes n[i], measures every candidate plan where it will
+ * run, in a persistent batch of many products of that size, and picks the
+ * one with the least device time per product.  Candidates, ncand =
+ * 1 + nalgos * max_depth of them: index 0 is the classical GEMM; index
+ * 1 + j * max_depth + (d - 1) is algos[j] at depth d (1 <= d <= max_depth).
+ * A depth whose levels the plan would not take for that size (see
+ * mf_fastmm) repeats a shallower plan and is skipped (time -1).  Each
+ * measurement plans a batch of copies = ceil(work_flops / (2 n^3)) products
+ * (at most max_copies, and at most 8 GiB of operands), fills distinct
+ * operands on the device with the counter-based generator, runs it once
+ * untimed and then `reps` times between two HIP events on `stream`.
+ * Outputs: out_choice[i] = index of the fastest candidate for n[i];
+ * out_ms[i * ncand + c] = device ms per product of candidate c (or -1).
+ * Allocates and frees its own device memory and synchronises before it
+ * returns.  Errors: MF_ERR_ARG / MF_ERR_SHAPE / MF_ERR_UNSUPPORTED for bad
+ * arguments, MF_ERR_NOMEM, MF_ERR_HIP (including an aborted batch). */
+mf_status mf_autotune_batch(int nsizes, const int64_t* n, int dtype, const mf_algo* const* algos, int nalgos,
+                            int max_depth, double work_flops, int max_copies, int reps, mf_stream stream,
+                            int* out_choice, double* out_ms);
+
 /* ---- Serving -----------------------------------------------------------------
  * A request loop for fast-multiply requests of different sizes.  Requests
  * wait in a FIFO queue; the head request is admitted when one of max_slots

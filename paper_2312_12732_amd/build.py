@@ -33,11 +33,9 @@ def sources():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *COMMON]
-    if src.endswith(".hip"):
-        cmd += ["-x", "hip", *DEVICE]
-    else:
-        cmd += ["-D__HIP_PLATFORM_AMD__"]
+    # hipcc treats .cpp files as HIP too; give every file the gfx950 target so
+    # that no device pass runs for the compiler's default architecture.
+    cmd = [HIPCC, *COMMON, "-x", "hip", *DEVICE]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

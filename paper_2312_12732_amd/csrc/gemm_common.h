@@ -26,6 +26,21 @@ struct GemmArgs {
   int vec_in;  // A and B rows are 16-byte aligned
 };
 
+// Load a descriptor that every lane of the wave reads at the same address and
+// mark each word as wave-uniform, so address arithmetic on it runs on the
+// scalar unit and buffer descriptors built from it stay in scalar registers.
+template <class S>
+__device__ __forceinline__ S load_uniform(const S* p) {
+  static_assert(sizeof(S) % 4 == 0, "descriptor must be a whole number of words");
+  S v = *p;
+  int w[sizeof(S) / 4];
+  __builtin_memcpy(w, &v, sizeof(S));
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(S) / 4; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  __builtin_memcpy(&v, w, sizeof(S));
+  return v;
+}
+
 template <class T>
 __device__ __forceinline__ const T* src_ptr(const GemmArgs<T>& g, int src) {
   const T* p = g.ws;

@@ -11,7 +11,10 @@
 //   f64: element v of lane l is D[l / 16 + 4 v][l % 16]
 //   f32: element v of lane l is D[4 (l / 16) + v][l % 16].
 // Both LDS tiles are stored k-major (A transposed on the way in) so that the
-// 16 lanes of a fragment row read 16 consecutive elements.
+// 16 lanes of a fragment row read 16 consecutive elements.  The A tile is
+// loaded so that the lanes one LDS cycle serves write consecutive rows of one
+// k-row pair (a_slot), which keeps the transposing stores free of bank
+// conflicts.
 //
 // A work item owns one tile position of every output block of its group and
 // runs the group's products in order: the first product feeding a block
@@ -42,6 +45,20 @@ constexpr int NTHREADS = 64 * WAVES_M * WAVES_N;
 constexpr int LPT = BM * BK / 2 / NTHREADS;  // pair loads per thread per operand and K step
 static_assert(LPT >= 1 && BM * BK / 2 % NTHREADS == 0, "tile loads must divide evenly");
 
+// Element pair idx of the A tile -> (row, kp): the pair A[row][kp..kp+1].
+// LDS has 32 four-byte banks and serves 128 bytes per cycle (16 lanes of a
+// 64-bit store, 32 lanes of a 32-bit one); RUN consecutive lanes take RUN
+// consecutive rows of the same k-row pair, so the transposed stores of those
+// lanes cover every bank once.  Mapping consecutive lanes along k instead
+// would put all k-row pairs of a row in the same banks.
+template <class T>
+__device__ __forceinline__ void a_slot(int idx, int& row, int& kp) {
+  constexpr int RUN = 128 / sizeof(T);
+  static_assert(BM % RUN == 0, "A tile rows must split into runs");
+  row = idx % RUN + RUN * (idx / (RUN * (BK / 2)));
+  kp = 2 * ((idx / RUN) % (BK / 2));
+}
+
 template <class T>
 struct Mfma;
 template <>
@@ -64,46 +81,103 @@ struct Mfma<float> {
 };
 
 // Global -> register prefetch of one BM x BK tile of the A view and one
-// BK x BN tile of the B view, two consecutive elements per load.  MASKED:
-// entries outside the view's valid rows/columns are zero and only valid
-// elements are read.
-template <class T, bool MASKED>
-__device__ __forceinline__ void load_tiles(const T* __restrict__ pa, int lda, int a_vr, int a_vc,
-                                           const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0, int j0,
-                                           int k0, int t, typename Mfma<T>::v2 (&ra)[LPT],
-                                           typename Mfma<T>::v2 (&rb)[LPT]) {
+// BK x BN tile of the B view, two consecutive elements per load.
+//
+// Interior tiles (every element valid, rows 16-byte aligned): raw buffer loads
+// whose descriptors (tile origin at the current k0) live in scalar registers,
+// so each lane keeps only two 32-bit byte offsets per operand across the K loop
+// (row * ld + column, fixed for the whole loop).  Edge tiles: plain loads with
+// per-element masks; entries outside the view's valid rows/columns are zero
+// and only valid elements are read.
+struct LaneOffsets {
+  int a[LPT], b[LPT];
+};
+
+template <class T>
+__device__ __forceinline__ void b_slot(int idx, int& kr, int& cp) {
+  kr = idx / (BN / 2);
+  cp = (idx % (BN / 2)) * 2;
+}
+
+template <class T>
+__device__ __forceinline__ LaneOffsets lane_offsets(int lda, int ldb, int t) {
+  LaneOffsets o;
+#pragma unroll
+  for (int q = 0; q < LPT; ++q) {
+    int row, kp, kr, cp;
+    a_slot<T>(t + NTHREADS * q, row, kp);
+    b_slot<T>(t + NTHREADS * q, kr, cp);
+    // row < BM and kr < BK, ld <= 2^21: every offset is below 2^31 bytes.
+    o.a[q] = (row * lda + kp) * (int)sizeof(T);
+    o.b[q] = (kr * ldb + cp) * (int)sizeof(T);
+  }
+  return o;
+}
+
+// Descriptor word 3 for raw (untyped) buffer access on gfx9-family parts:
+// 32-bit data format, no swizzle, no index stride.  The record count only
+// bounds offsets, which are below 2^31 here.  The base is the same in every
+// lane (a tile origin); taking it from the first lane tells the compiler so,
+// which keeps the descriptor in scalar registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(lo | hi << 32), (short)0, 0x7fffffff,
+                                           0x00020000);
+}
+
+template <class T>
+__device__ __forceinline__ typename Mfma<T>::v2 buffer_pair(__amdgpu_buffer_rsrc_t r, int off) {
+  typedef typename Mfma<T>::v2 v2;
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  else
+    return __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+template <class T>
+__device__ __forceinline__ void load_tiles_interior(const T* __restrict__ pa, int lda, const T* __restrict__ pb,
+                                                    int ldb, int i0, int j0, int k0, const LaneOffsets& o,
+                                                    typename Mfma<T>::v2 (&ra)[LPT],
+                                                    typename Mfma<T>::v2 (&rb)[LPT]) {
+  const __amdgpu_buffer_rsrc_t sa = raw_rsrc(pa + (size_t)i0 * lda + k0);
+  const __amdgpu_buffer_rsrc_t sb = raw_rsrc(pb + (size_t)k0 * ldb + j0);
+#pragma unroll
+  for (int q = 0; q < LPT; ++q) ra[q] = buffer_pair<T>(sa, o.a[q]);
+#pragma unroll
+  for (int q = 0; q < LPT; ++q) rb[q] = buffer_pair<T>(sb, o.b[q]);
+}
+
+template <class T>
+__device__ __forceinline__ void load_tiles_masked(const T* __restrict__ pa, int lda, int a_vr, int a_vc,
+                                                  const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0,
+                                                  int j0, int k0, int t, typename Mfma<T>::v2 (&ra)[LPT],
+                                                  typename Mfma<T>::v2 (&rb)[LPT]) {
   typedef typename Mfma<T>::v2 v2;
 #pragma unroll
   for (int q = 0; q < LPT; ++q) {
-    const int idx = t + NTHREADS * q;
-    const int row = idx / (BK / 2), kp = (idx % (BK / 2)) * 2;
+    int row, kp;
+    a_slot<T>(t + NTHREADS * q, row, kp);
     const int gi = i0 + row, gk = k0 + kp;
-    if (!MASKED) {
-      ra[q] = *reinterpret_cast<const v2*>(pa + (size_t)gi * lda + gk);
-    } else {
-      v2 v = {T(0), T(0)};
-      if (gi < a_vr) {
-        if (gk < a_vc) v.x = pa[(size_t)gi * lda + gk];
-        if (gk + 1 < a_vc) v.y = pa[(size_t)gi * lda + gk + 1];
-      }
-      ra[q] = v;
+    v2 v = {T(0), T(0)};
+    if (gi < a_vr) {
+      if (gk < a_vc) v.x = pa[(size_t)gi * lda + gk];
+      if (gk + 1 < a_vc) v.y = pa[(size_t)gi * lda + gk + 1];
     }
+    ra[q] = v;
   }
 #pragma unroll
   for (int q = 0; q < LPT; ++q) {
-    const int idx = t + NTHREADS * q;
-    const int kr = idx / (BN / 2), cp = (idx % (BN / 2)) * 2;
+    int kr, cp;
+    b_slot<T>(t + NTHREADS * q, kr, cp);
     const int gk = k0 + kr, gj = j0 + cp;
-    if (!MASKED) {
-      rb[q] = *reinterpret_cast<const v2*>(pb + (size_t)gk * ldb + gj);
-    } else {
-      v2 v = {T(0), T(0)};
-      if (gk < b_vr) {
-        if (gj < b_vc) v.x = pb[(size_t)gk * ldb + gj];
-        if (gj + 1 < b_vc) v.y = pb[(size_t)gk * ldb + gj + 1];
-      }
-      rb[q] = v;
+    v2 v = {T(0), T(0)};
+    if (gk < b_vr) {
+      if (gj < b_vc) v.x = pb[(size_t)gk * ldb + gj];
+      if (gj + 1 < b_vc) v.y = pb[(size_t)gk * ldb + gj + 1];
     }
+    rb[q] = v;
   }
 }
 
@@ -113,15 +187,15 @@ __device__ __forceinline__ void store_tiles(T* As, T* Bs, int t, const typename 
   typedef typename Mfma<T>::v2 v2;
 #pragma unroll
   for (int q = 0; q < LPT; ++q) {
-    const int idx = t + NTHREADS * q;
-    const int row = idx / (BK / 2), kp = (idx % (BK / 2)) * 2;
+    int row, kp;
+    a_slot<T>(t + NTHREADS * q, row, kp);
     As[kp * LDS_STRIDE + row] = ra[q].x;
     As[(kp + 1) * LDS_STRIDE + row] = ra[q].y;
   }
 #pragma unroll
   for (int q = 0; q < LPT; ++q) {
-    const int idx = t + NTHREADS * q;
-    const int kr = idx / (BN / 2), cp = (idx % (BN / 2)) * 2;
+    int kr, cp;
+    b_slot<T>(t + NTHREADS * q, kr, cp);
     *reinterpret_cast<v2*>(Bs + kr * LDS_STRIDE + cp) = rb[q];
   }
 }
@@ -151,13 +225,21 @@ __device__ __forceinline__ void k_loop(T (*lds)[2][BK * LDS_STRIDE], const T* __
                                        int j0, int KT, int t, int wm, int wn, int lr, int lk,
                                        typename Mfma<T>::v4 (&acc)[WM_T][WN_T]) {
   typename Mfma<T>::v2 ra[LPT], rb[LPT];
-  load_tiles<T, MASKED>(pa, lda, a_vr, a_vc, pb, ldb, b_vr, b_vc, i0, j0, 0, t, ra, rb);
+  LaneOffsets o;
+  if constexpr (!MASKED) o = lane_offsets<T>(lda, ldb, t);
+  auto load = [&](int k0) {
+    if constexpr (MASKED)
+      load_tiles_masked<T>(pa, lda, a_vr, a_vc, pb, ldb, b_vr, b_vc, i0, j0, k0, t, ra, rb);
+    else
+      load_tiles_interior<T>(pa, lda, pb, ldb, i0, j0, k0, o, ra, rb);
+  };
+  load(0);
   store_tiles<T>(lds[0][0], lds[0][1], t, ra, rb);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < KT;
-    if (more) load_tiles<T, MASKED>(pa, lda, a_vr, a_vc, pb, ldb, b_vr, b_vc, i0, j0, (kt + 1) * BK, t, ra, rb);
+    if (more) load((kt + 1) * BK);
     const T* As = lds[cur][0];
     const T* Bs = lds[cur][1];
 #if MF_GEMM_FRAG_DB
@@ -193,10 +275,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
   const int lr = lane & 15, lk = lane >> 4;
   const int i0 = ti * BM, j0 = tj * BN;
   const int KT = g.m / BK;
-  const int r_beg = g.group_beg[grp], r_end = g.group_beg[grp + 1];
+  const int r_beg = load_uniform(g.group_beg + grp), r_end = load_uniform(g.group_beg + grp + 1);
 
   for (int r = r_beg; r < r_end; ++r) {
-    const ProdDesc pd = g.prods[r];
+    const ProdDesc pd = load_uniform(g.prods + r);
     const T* pa = src_ptr(g, pd.a_src) + pd.a_off;
     const T* pb = src_ptr(g, pd.b_src) + pd.b_off;
     const bool vec_a = pd.a_src == SRC_WS || g.vec_in;
@@ -219,7 +301,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
 
     // Epilogue: post-addition into every output block this product feeds.
     for (int e = pd.epi_beg; e < pd.epi_end; ++e) {
-      const EpiDesc ed = g.epis[e];
+      const EpiDesc ed = load_uniform(g.epis + e);
       T* pc = dst_ptr(g, ed.c_src) + ed.c_off;
       const bool full = (i0 + BM <= ed.c_vr) && (j0 + BN <= ed.c_vc);
       const T coef = (T)ed.coef;

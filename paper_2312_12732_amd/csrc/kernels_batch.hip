@@ -49,8 +49,8 @@ __device__ __forceinline__ int load_relaxed(const int* p) {
 
 template <class T>
 __device__ __forceinline__ void run_combine(const BatchArgs& g, const BatchTask& tk) {
-  const StageRec st = g.stages[tk.rec];
-  const BatchInst in = g.insts[tk.inst];
+  const StageRec st = load_uniform(g.stages + tk.rec);
+  const BatchInst in = load_uniform(g.insts + tk.inst);
   CombArgs<T> a;
   a.A = static_cast<const T*>(in.A);
   a.B = static_cast<const T*>(in.B);
@@ -63,7 +63,7 @@ __device__ __forceinline__ void run_combine(const BatchArgs& g, const BatchTask&
   a.m = st.m;
   a.vec_in = in.vec_in;
   a.vec_out = in.vec_out;
-  const CombSet set = st.sets[tk.a];
+  const CombSet set = load_uniform(st.sets + tk.a);
   const bool full = set.full && in.vec_in && in.vec_out;
   with_nin(st.nin, [&](auto nin_c) {
     constexpr int NIN = decltype(nin_c)::value;
@@ -80,8 +80,8 @@ __device__ __forceinline__ void run_combine(const BatchArgs& g, const BatchTask&
 
 template <class T>
 __device__ __forceinline__ void run_gemm(const BatchArgs& g, const BatchTask& tk, T (*lds)[2][BK * LDS_STRIDE]) {
-  const GemmRec gr = g.gemms[tk.rec];
-  const BatchInst in = g.insts[tk.inst];
+  const GemmRec gr = load_uniform(g.gemms + tk.rec);
+  const BatchInst in = load_uniform(g.insts + tk.inst);
   GemmArgs<T> a;
   a.A = static_cast<const T*>(in.A);
   a.B = static_cast<const T*>(in.B);
@@ -111,9 +111,9 @@ __global__ void __launch_bounds__(NTHREADS, MF_GEMM_WAVES_PER_SIMD) batch_persis
       s_task = t;
     }
     __syncthreads();
-    const int t = s_task;
+    const int t = __builtin_amdgcn_readfirstlane(s_task);
     if (t >= g.ntasks) return;
-    const BatchTask tk = g.tasks[t];
+    const BatchTask tk = load_uniform(g.tasks + t);
     if (tk.wait_ctr >= 0) {
       if (threadIdx.x == 0) {
         int ok = 1;

@@ -232,6 +232,10 @@ void drop_plans(uint64_t algo_id);
 // Leaf tile granularity: every leaf size is a multiple of this.
 constexpr int kLeafTile = 128;
 
+// Number of recursion levels the plan of an n x n product takes for an
+// algorithm of block size p and rank R at the requested depth and cutoff.
+int levels_for(int64_t n, int p, int R, int depth, int cutoff);
+
 // ---------------------------------------------------------------------------
 // Launchers (kernels.hip)
 // ---------------------------------------------------------------------------

@@ -22,21 +22,6 @@ namespace {
 // Leaf products allowed in one plan.
 constexpr int64_t kMaxLeafProducts = 1 << 16;
 
-// Levels taken for an n x n product: a level is taken while levels remain,
-// the current size exceeds the cutoff and the leaf tile (smaller leaves only
-// add padding on this GEMM), and the leaf count stays within the limit
-// (sizes rounded up at each split).
-int levels_for(int64_t n, int p, int R, int depth, int cutoff) {
-  int d = 0;
-  int64_t size = n, leaves = 1;
-  while (d < depth && size > cutoff && size > kLeafTile && p > 1 && leaves * R <= kMaxLeafProducts) {
-    size = (size + p - 1) / p;
-    leaves *= R;
-    ++d;
-  }
-  return d;
-}
-
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 int64_t ipow(int64_t b, int e) {
   int64_t r = 1;
@@ -452,6 +437,21 @@ std::map<Key, std::shared_ptr<const Plan>>& cache() {
 }
 
 }  // namespace
+
+// Levels taken for an n x n product: a level is taken while levels remain,
+// the current size exceeds the cutoff and the leaf tile (smaller leaves only
+// add padding on this GEMM), and the leaf count stays within the limit
+// (sizes rounded up at each split).
+int levels_for(int64_t n, int p, int R, int depth, int cutoff) {
+  int d = 0;
+  int64_t size = n, leaves = 1;
+  while (d < depth && size > cutoff && size > kLeafTile && p > 1 && leaves * R <= kMaxLeafProducts) {
+    size = (size + p - 1) / p;
+    leaves *= R;
+    ++d;
+  }
+  return d;
+}
 
 mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg,
                    std::shared_ptr<const Plan>* out) {

@@ -39,7 +39,7 @@ EXPORTED = ["mf_algo_from_uvw", "mf_algo_builtin", "mf_algo_compose", "mf_algo_r
             "mf_fastmm_ws", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read", "mf_batch_create",
             "mf_batch_workspace_bytes", "mf_batch_run", "mf_batch_aborted", "mf_batch_tasks", "mf_batch_free",
             "mf_server_create", "mf_server_need_bytes", "mf_server_submit", "mf_server_replay", "mf_server_drain",
-            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform"]
+            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform", "mf_autotune_batch"]
 
 
 class ServerConfig(ctypes.Structure):
@@ -94,6 +94,8 @@ def _load():
                                    ctypes.POINTER(ctypes.c_size_t)], I),
         "mf_fill_uniform": ([P, I64, I, ctypes.c_uint64, P], I),
         "mf_phase_timing_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I)], I),
+        "mf_autotune_batch": ([I, LP, I, ctypes.POINTER(P), I, I, ctypes.c_double, I, I, P, ctypes.POINTER(I), DP],
+                              I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -303,6 +305,28 @@ def mf_batch_create(sizes, algos, depths, cutoffs, dtype_code: int = MF_F64) -> 
     out = ctypes.c_void_p()
     _check(lib.mf_batch_create(count, n_arr, a_arr, d_arr, c_arr, dtype_code, ctypes.byref(out)))
     return Batch(out.value, [a for a in algos if a is not None], sizes, dtype_code)
+
+
+def mf_autotune_batch(sizes, dtype_code, algos, max_depth, work_flops=2e11, max_copies=4096, reps=3, stream=None):
+    """Tune (algorithm, depth) per size for the batched form.
+
+    Returns (choices, ms): choices[i] is a (algo or None, depth) pair for
+    sizes[i]; ms[i][c] is the device time per product of candidate c
+    (classical first, then algos[j] at depths 1..max_depth), -1 if skipped.
+    """
+    k = len(sizes)
+    ncand = 1 + len(algos) * max_depth
+    n_arr = (ctypes.c_int64 * k)(*sizes)
+    a_arr = (ctypes.c_void_p * max(1, len(algos)))(*[a.handle.value for a in algos])
+    choice = (ctypes.c_int * k)()
+    ms = (ctypes.c_double * (k * ncand))()
+    _check(lib.mf_autotune_batch(k, n_arr, dtype_code, a_arr, len(algos), max_depth, float(work_flops), max_copies,
+                                 reps, _stream(stream), choice, ms))
+    out = []
+    for i in range(k):
+        c = choice[i]
+        out.append((None, 0) if c == 0 else (algos[(c - 1) // max_depth], 1 + (c - 1) % max_depth))
+    return out, [[ms[i * ncand + c] for c in range(ncand)] for i in range(k)]
 
 
 def mf_batch_run(batch: Batch, As, Bs, Cs, workspace=None, stream=None):

@@ -235,3 +235,28 @@ def test_deep_recursion_plans():
     # depth beyond what the size allows stops once a level reaches the tile
     assert mf.mf_workspace_bytes(s, 10, 0, 256) == expected_ws(256, 1, 4, 4) == 8 * (8 + 7) * 128 ** 2
     assert mf.mf_workspace_bytes(s, 10, 0, 4096) == expected_ws(4096, 5, 4, 4)
+
+
+def _tune(nsizes, n, dtype, algos, max_depth, work=1e9, copies=4, reps=1):
+    k = max(1, nsizes)
+    n_arr = (ctypes.c_int64 * k)(*(list(n) + [1] * (k - len(n))))
+    a_arr = (ctypes.c_void_p * max(1, len(algos)))(*[a.handle.value if a else None for a in algos])
+    choice = (ctypes.c_int * k)()
+    ms = (ctypes.c_double * (k * (1 + len(algos) * max(0, max_depth)) + 1))()
+    return mf.lib.mf_autotune_batch(nsizes, n_arr, dtype, a_arr, len(algos), max_depth, work, copies, reps, None,
+                                    choice, ms)
+
+
+def test_autotune_argument_validation_without_device():
+    s = mf.mf_algo_builtin("winograd")
+    assert _tune(0, [256], mf.MF_F64, [s], 2) == mf.MF_ERR_ARG
+    assert _tune(1, [256], mf.MF_F64 | mf.MF_LEAF_BF16, [s], 2) == mf.MF_ERR_UNSUPPORTED
+    assert _tune(1, [256], 7, [s], 2) == mf.MF_ERR_UNSUPPORTED
+    assert _tune(1, [0], mf.MF_F64, [s], 2) == mf.MF_ERR_SHAPE
+    assert _tune(1, [(1 << 16) + 1], mf.MF_F64, [s], 2) == mf.MF_ERR_SHAPE
+    assert _tune(1, [256], mf.MF_F64, [s], -1) == mf.MF_ERR_ARG
+    assert _tune(1, [256], mf.MF_F64, [s], 9) == mf.MF_ERR_ARG
+    assert _tune(1, [256], mf.MF_F64, [None], 2) == mf.MF_ERR_ARG
+    assert _tune(1, [256], mf.MF_F64, [s], 2, work=0.0) == mf.MF_ERR_ARG
+    assert _tune(1, [256], mf.MF_F64, [s], 2, copies=0) == mf.MF_ERR_ARG
+    assert _tune(1, [256], mf.MF_F64, [s], 2, reps=0) == mf.MF_ERR_ARG

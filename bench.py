@@ -14,6 +14,13 @@ Other workloads, each printing one JSON line of the same shape:
   --workload serving    1000 requests, n log-uniform in [256, 8192], 70 % FP32,
                         Poisson arrivals at 0.5, 0.9 and 1.5 x the serial
                         service rate; p50/p99 latency and throughput
+  --workload precision  FP32 storage, leaves FP32 / BF16 / split-BF16x3,
+                        n = 8192 and 16384, depth 0..3, uniform and scaled
+                        inputs: time, effective GFLOP/s and error vs the oracle
+  --workload algorithms FP64 at n = 4096 and 8192: Strassen (paper form) and
+                        Strassen-Winograd at depth 1..3, <4,4,4;49>, a re-based
+                        Strassen and the classical <3,3,3;27> control: time,
+                        phase rooflines and error vs the oracle
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload square]
                        [--n N] [--algo winograd] [--depth 2] [--no-cpu-baseline]
@@ -53,7 +60,8 @@ def parse():
     ap.add_argument("--depth", type=int, default=2)
     ap.add_argument("--cutoff", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("square", "batched", "serving"), default="square")
+    ap.add_argument("--workload", choices=("square", "batched", "serving", "precision", "algorithms"),
+                    default="square")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per arrival rate")
     return ap.parse_args()
 
@@ -465,6 +473,165 @@ def serving_cpu_baseline(reqs, seeds):
                       f"(float64) with the same depth policy, {elapsed:.1f} s"}
 
 
+# ---------------------------------------------------------------------------
+# Precision form and the algorithm sweep.
+# ---------------------------------------------------------------------------
+
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def sampled_rows(n, seed, count=64):
+    import numpy as np
+    return np.sort(np.random.default_rng(seed).choice(n, size=min(n, count), replace=False))
+
+
+def phase_run(mf, timed, fn, steps, warmup):
+    """Time fn (one whole product per call) and return (ms per call, phase ms list)."""
+    for _ in range(warmup):
+        fn()
+    mf.mf_phase_timing_read()
+    mf.mf_phase_timing(True)
+    ms = timed(fn, steps, 0)
+    mf.mf_phase_timing(False)
+    ph, calls = mf.mf_phase_timing_read()
+    return ms, [x / max(1, calls) for x in ph]
+
+
+def run_precision(args):
+    import numpy as np
+    import torch
+
+    import mf_inputs as mi
+    from oracle import matmul as om
+    from paper_2312_12732_amd import mf
+
+    dev = torch.device("cuda:0")
+    timed = timer(torch, torch.cuda.current_stream())
+    wino = mf.mf_algo_builtin("winograd")
+    leaves = (("f32", mf.MF_LEAF_F32, FP32_MFMA_PEAK_TFLOPS, 1), ("bf16", mf.MF_LEAF_BF16, BF16_MFMA_PEAK_TFLOPS, 1),
+              ("bf16x3", mf.MF_LEAF_BF16X3, BF16_MFMA_PEAK_TFLOPS, 3))
+    results = []
+    for n in (8192, 16384):
+        sets = {"uniform": (mi.uniform(n, 20), mi.uniform(n, 21)),
+                "scaled": (mi.scaled(n, 22, 24, 25), mi.scaled(n, 23, 26, 27))}
+        rows = sampled_rows(n, 3)
+        refs, dev_in = {}, {}
+        for name, (A, B) in sets.items():
+            A32, B32 = A.astype(np.float32), B.astype(np.float32)
+            refs[name] = om.rows_reference(A32.astype(np.float64), B32.astype(np.float64), rows)
+            dev_in[name] = (torch.from_numpy(A32).to(dev), torch.from_numpy(B32).to(dev))
+        del sets
+        C = torch.empty(n, n, dtype=torch.float32, device=dev)
+        for lname, leaf, peak, mfma_mult in leaves:
+            for d in range(4):
+                A, B = dev_in["uniform"]
+                ms, ph = phase_run(mf, timed, lambda: mf.mf_fastmm(wino, d, 0, A, B, C, leaf=leaf),
+                                   max(2, args.steps // 3), 1)
+                q = mf.mf_plan_query(wino if d else None, d, 0, n, mf.MF_F32 | leaf)
+                mfma_tf = q["gemm_flops"] * mfma_mult / (ph[1] * 1e-3) / 1e12
+                rec = {"n": n, "leaf": lname, "depth": d, "ms": round(ms, 4),
+                       "gflops": round(2.0 * n ** 3 / (ms * 1e-3) / 1e9, 1),
+                       "gemm_ms": round(ph[1], 4), "mfma_tflops": round(mfma_tf, 1),
+                       "mfma_frac": round(mfma_tf / peak, 4)}
+                for name in ("uniform", "scaled"):
+                    A, B = dev_in[name]
+                    mf.mf_fastmm(wino, d, 0, A, B, C, leaf=leaf)
+                    torch.cuda.synchronize()
+                    Cr = C[torch.from_numpy(rows).to(dev)].cpu().numpy().astype(np.float64)
+                    rec[f"err_{name}"] = float(f"{om.rel_fro_error(Cr, refs[name]):.3e}")
+                results.append(rec)
+                print(json.dumps({"progress": rec}), file=sys.stderr, flush=True)
+        del dev_in, C
+        torch.cuda.empty_cache()
+    head = next(r for r in results if r["n"] == 16384 and r["leaf"] == "bf16x3" and r["depth"] == 2)
+    out = {
+        "metric": "effective GFLOP/s (2n^3/t) of the precision form at stated error vs the FP64 oracle",
+        "value": head["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": max(2, args.steps // 3), "warmup": 1,
+        "ms_per_step": head["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 storage, bf16x3 leaves", "data": "synthetic",
+        "config": {"workload": "precision: n 8192 and 16384, winograd depth 0-3, FP32 storage and additions, leaves "
+                               "FP32 / BF16 / split-BF16x3; uniform[-1,1] (seeds 20, 21) and scaled D1 A0 D2 "
+                               "(A: seeds 22, 24, 25; B: 23, 26, 27); error on 64 sampled rows vs the FP64 oracle "
+                               "on the FP32-rounded inputs", "headline": "n=16384 bf16x3 depth 2"},
+        "results": results,
+        "roofline": {"bound": "mfma", "achieved": head["mfma_tflops"], "peak": BF16_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": head["mfma_frac"], "traffic": None,
+                     "kernel": "gemm_bf16_grouped<true>", "kernel_ms": head["gemm_ms"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_algorithms(args):
+    import numpy as np
+    import torch
+
+    import mf_inputs as mi
+    from oracle import matmul as om
+    from paper_2312_12732_amd import mf
+
+    dev = torch.device("cuda:0")
+    timed = timer(torch, torch.cuda.current_stream())
+    wino = mf.mf_algo_builtin("winograd")
+    stras = mf.mf_algo_builtin("strassen")
+    c444 = mf.mf_algo_compose(wino, wino)
+    X = mi.unimodular(2, 7)
+    Y = mi.unimodular(2, 8)
+    Z = mi.unimodular(2, 9)
+    rebased = mf.mf_algo_rebase(stras, X, Y, Z)
+    c3 = mf.mf_algo_builtin("classical3")
+    cases = [("classical", None, 0)]
+    cases += [(f"strassen d{d}", stras, d) for d in (1, 2, 3)]
+    cases += [(f"winograd d{d}", wino, d) for d in (1, 2, 3)]
+    cases += [("<4,4,4;49> d1", c444, 1), ("rebased strassen d1", rebased, 1), ("rebased strassen d2", rebased, 2),
+              ("<3,3,3;27> d1 (control)", c3, 1)]
+    results = []
+    for n in (4096, 8192):
+        Ah, Bh = mi.uniform(n, 10), mi.uniform(n, 11)
+        A, B = torch.from_numpy(Ah).to(dev), torch.from_numpy(Bh).to(dev)
+        C = torch.empty_like(A)
+        rows = sampled_rows(n, 4)
+        ref = om.rows_reference(Ah, Bh, rows)
+        for name, al, d in cases:
+            if al is None:
+                ms, ph = phase_run(mf, timed, lambda: mf.mf_classical_mm(A, B, C), args.steps, 2)
+            else:
+                ms, ph = phase_run(mf, timed, lambda: mf.mf_fastmm(al, d, 0, A, B, C), args.steps, 2)
+            q = mf.mf_plan_query(al, d, 0, n)
+            Cr = C[torch.from_numpy(rows).to(dev)].cpu().numpy()
+            gemm_tf = q["gemm_flops"] / (ph[1] * 1e-3) / 1e12
+            rec = {"n": n, "case": name, "ms": round(ms, 4), "gflops": round(2.0 * n ** 3 / (ms * 1e-3) / 1e9, 1),
+                   "rel_err": float(f"{om.rel_fro_error(Cr, ref):.3e}"), "leaf_m": q["leaf_m"],
+                   "products": q["products"],
+                   "phases_ms": [round(x, 4) for x in ph],
+                   "gemm_tflops": round(gemm_tf, 2), "gemm_frac": round(gemm_tf / FP64_MFMA_PEAK_TFLOPS, 4),
+                   "pre_gbs": round(q["pre_bytes"] / (ph[0] * 1e-3) / 1e9, 1) if ph[0] > 0 else None,
+                   "post_gbs": round(q["post_bytes"] / (ph[2] * 1e-3) / 1e9, 1) if ph[2] > 0 else None}
+            results.append(rec)
+            print(json.dumps({"progress": rec}), file=sys.stderr, flush=True)
+        tms = timed(lambda: torch.matmul(A, B, out=C), args.steps, 2)
+        results.append({"n": n, "case": "torch.matmul (context)", "ms": round(tms, 4),
+                        "gflops": round(2.0 * n ** 3 / (tms * 1e-3) / 1e9, 1)})
+        del A, B, C
+        torch.cuda.empty_cache()
+    best = min((r for r in results if r["n"] == 8192 and "rel_err" in r and r["case"] != "classical"),
+               key=lambda r: r["ms"])
+    out = {
+        "metric": "effective GFLOP/s (2n^3/t) per algorithm and depth, FP64, at stated rel. error",
+        "value": best["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": 2,
+        "ms_per_step": best["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "algorithms: FP64 n 4096 and 8192, uniform[-1,1] (seeds 10, 11); Strassen (paper "
+                               "form), Strassen-Winograd d1-3, <4,4,4;49> = Winograd composed with itself, Strassen "
+                               "re-based by unimodular X, Y, Z (seeds 7, 8, 9), classical <3,3,3;27> control; error "
+                               "on 64 sampled rows vs the oracle", "best_at_8192": best["case"]},
+        "results": results,
+        "roofline": {"bound": "mfma", "achieved": best["gemm_tflops"], "peak": FP64_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": best["gemm_frac"], "traffic": None,
+                     "kernel": "gemm_grouped<double>", "kernel_ms": best["phases_ms"][1]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -476,8 +643,12 @@ def main():
         run_square(args)
     elif args.workload == "batched":
         run_batched(args)
-    else:
+    elif args.workload == "serving":
         run_serving(args)
+    elif args.workload == "precision":
+        run_precision(args)
+    else:
+        run_algorithms(args)
 
 
 if __name__ == "__main__":

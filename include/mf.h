@@ -131,6 +131,26 @@ mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int 
 mf_status mf_workspace_bytes(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
                              size_t* bytes);
 
+/* Shape and algorithmic cost of the plan mf_fastmm uses for a request (host
+ * only).  Byte counts are what the addition stages must move at least: every
+ * valid element of every input view read once and every element of every
+ * output written once.  Input views exclude virtual padding; an output that
+ * is a workspace block is written whole (zeros in its padding), since the
+ * leaf GEMM reads whole blocks. */
+typedef struct {
+  int levels;          /* recursion levels taken (0: classical) */
+  int levels_outer;    /* levels whose post-additions run as separate stages */
+  int groups;          /* products are grouped by the outer levels */
+  int pre_stages, post_stages;
+  int64_t leaf_m;      /* leaf size, a multiple of the 128 GEMM tile */
+  int64_t products;    /* R^levels leaf products */
+  double gemm_flops;   /* products * 2 leaf_m^3, as executed (padded) */
+  double pre_bytes;    /* algorithmic bytes of all pre-addition stages */
+  double post_bytes;   /* algorithmic bytes of all post-addition stages */
+  size_t ws_bytes;     /* as mf_workspace_bytes */
+} mf_plan_info;
+mf_status mf_plan_query(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, mf_plan_info* out);
+
 /* As mf_fastmm, with caller-owned device workspace of ws_bytes bytes
  * (256-byte aligned; MF_ERR_SHAPE if smaller than mf_workspace_bytes).  The
  * workspace must not be used by other work until the call has completed on

@@ -31,11 +31,11 @@ def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def _compile(src: str) -> str:
+def _compile(src: str, defines=()) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     # hipcc treats .cpp files as HIP too; give every file the gfx950 target so
     # that no device pass runs for the compiler's default architecture.
-    cmd = [HIPCC, *COMMON, "-x", "hip", *DEVICE]
+    cmd = [HIPCC, *COMMON, *defines, "-x", "hip", *DEVICE]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -43,11 +43,12 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libmf.so; returns its path."""
+def build(verbose: bool = False, defines=()) -> str:
+    """Compile every source and link libmf.so; returns its path.  defines:
+    extra -D options (tuning experiments)."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, sources()))
+        objs = list(ex.map(lambda f: _compile(f, tuple(defines)), sources()))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", *DEVICE, "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -60,5 +61,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, defines=[a for a in sys.argv[1:] if a.startswith("-D")])
     sys.exit(0)

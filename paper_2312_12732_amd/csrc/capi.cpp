@@ -245,6 +245,41 @@ mf_status mf_workspace_bytes(const mf_algo* algo, int depth, int cutoff, int64_t
   return MF_OK;
 }
 
+mf_status mf_plan_query(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, mf_plan_info* out) {
+  clear_error();
+  if (!out) return fail(MF_ERR_ARG, "out is NULL");
+  *out = mf_plan_info{};
+  static const double dummy[3] = {0, 0, 0};
+  mf_status st = check_request(algo, depth > 0, depth, cutoff, &dummy[0], &dummy[1], (void*)&dummy[2], 0, dtype);
+  if (st != MF_OK) return st;
+  if (n < 1) return fail(MF_ERR_ARG, "n must be >= 1");
+  if (n > kMaxN) return fail(MF_ERR_SHAPE, "n exceeds the supported maximum (2^20)");
+  std::shared_ptr<const Plan> pl;
+  st = plan_for(algo, depth, cutoff, n, dtype, &pl);
+  if (st != MF_OK) return st;
+  auto stage_bytes = [&](const std::vector<CombineStage>& stages) {
+    double b = 0;
+    for (const CombineStage& cs : stages)
+      for (const CombSet& set : cs.sets) {
+        for (int k = 0; k < cs.nin; ++k) b += (double)cs.ins[set.in_beg + k].vr * cs.ins[set.in_beg + k].vc;
+        for (int o = set.out_beg; o < set.out_end; ++o) b += (double)cs.outs[o].vr * cs.outs[o].vc;
+      }
+    return b * (double)pl->elem;
+  };
+  out->levels = pl->levels;
+  out->levels_outer = pl->levels_outer;
+  out->groups = pl->groups;
+  out->pre_stages = (int)pl->pre.size();
+  out->post_stages = (int)pl->post.size();
+  out->leaf_m = pl->m;
+  out->products = (int64_t)pl->prods.size();
+  out->gemm_flops = (double)pl->prods.size() * 2.0 * (double)pl->m * (double)pl->m * (double)pl->m;
+  out->pre_bytes = stage_bytes(pl->pre);
+  out->post_bytes = stage_bytes(pl->post);
+  out->ws_bytes = pl->ws_bytes;
+  return MF_OK;
+}
+
 mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C,
                        int64_t n, int dtype, void* workspace, size_t ws_bytes, mf_stream stream) {
   clear_error();

@@ -7,9 +7,6 @@
 
 namespace mf {
 
-// Output tile of every grouped GEMM kernel; leaf sizes are multiples of it.
-constexpr int GEMM_BM = 128, GEMM_BN = 128;
-static_assert(GEMM_BM == kLeafTile && GEMM_BN == kLeafTile, "leaf tile and GEMM tile must agree");
 
 template <class T>
 struct GemmArgs {
@@ -21,9 +18,10 @@ struct GemmArgs {
   const EpiDesc* epis;
   const int32_t* group_beg;  // products of group g: [group_beg[g], group_beg[g+1])
   int groups;
-  int m;       // M = N = K of every leaf product
-  int tiles;   // tiles per side (m / 128)
-  int vec_in;  // A and B rows are 16-byte aligned
+  int m;        // M = N = K of every leaf product
+  int tiles_m;  // output tiles along rows (m / BM) and columns (m / BN)
+  int tiles_n;
+  int vec_in;   // A and B rows are 16-byte aligned
 };
 
 // Load a descriptor that every lane of the wave reads at the same address and
@@ -60,18 +58,18 @@ __device__ __forceinline__ T* dst_ptr(const GemmArgs<T>& g, int dst) {
 // range of (group, position) pairs, and walk positions in bands of 8 tile
 // rows so that concurrently running tiles share operand panels in the XCD's
 // L2.
-__device__ __forceinline__ void work_of(int b, int tiles, int groups, int* grp, int* ti, int* tj) {
-  const int G = tiles * tiles;
+__device__ __forceinline__ void work_of(int b, int tiles_m, int tiles_n, int groups, int* grp, int* ti, int* tj) {
+  const int G = tiles_m * tiles_n;
   const int total = G * groups;
   int L = b;
   if ((total & 7) == 0) L = (b & 7) * (total >> 3) + (b >> 3);
   *grp = L / G;
   L -= *grp * G;
   constexpr int BAND = 8;
-  const int per_band = BAND * tiles;
+  const int per_band = BAND * tiles_n;
   const int band = L / per_band;
   const int first = band * BAND;
-  const int rows = min(BAND, tiles - first);
+  const int rows = min(BAND, tiles_m - first);
   const int in = L - band * per_band;
   *ti = first + in % rows;
   *tj = in / rows;

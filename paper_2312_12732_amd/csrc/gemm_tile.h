@@ -1,10 +1,12 @@
 // Device code of the grouped leaf GEMM on FP64 / FP32 MFMA (gfx950), shared
 // by the grouped-GEMM kernel and the persistent batched kernel.
 //
-// Tile geometry: 128 x 128 output tile per workgroup of 8 waves (2 x 4), each
-// wave 64 x 32 = 4 x 2 MFMA tiles of 16 x 16, K step 16 (4 MFMA k-steps of
-// 4), LDS double-buffered, 2 workgroups per CU (4 waves per SIMD).  Both
-// MFMAs used (v_mfma_f64_16x16x4_f64, v_mfma_f32_16x16x4_f32) take
+// Tile geometry (TileCfg): a BM x BN output tile per workgroup of
+// WAVES_M x WAVES_N waves, each wave (BM / WAVES_M) x (BN / WAVES_N) made of
+// 16 x 16 MFMA tiles, K step 16 (4 MFMA k-steps of 4), LDS double-buffered.
+// Tile128: 128 x 128, 8 waves of 64 x 32, two workgroups per CU (4 waves per
+// SIMD).  Tile256: 256 x 128, 8 waves of 128 x 32, one workgroup per CU (2
+// waves per SIMD, accumulators in 128 of each wave's 256 registers).  Both MFMAs used (v_mfma_f64_16x16x4_f64, v_mfma_f32_16x16x4_f32) take
 //   A operand: lane l holds A[l % 16][l / 16]   (16 x 4)
 //   B operand: lane l holds B[l / 16][l % 16]   (4 x 16)
 // and return 4 values per lane:
@@ -25,25 +27,28 @@
 
 namespace mf {
 
-#ifndef MF_GEMM_BK
-#define MF_GEMM_BK 16
-#endif
-#ifndef MF_GEMM_WAVES_PER_SIMD
-#define MF_GEMM_WAVES_PER_SIMD 4
-#endif
 #ifndef MF_GEMM_FRAG_DB
 #define MF_GEMM_FRAG_DB 1
 #endif
-#ifndef MF_GEMM_WN_TILES
-#define MF_GEMM_WN_TILES 2
-#endif
-constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = MF_GEMM_BK;
-constexpr int LDS_STRIDE = BM + 16;  // elements per LDS row
-constexpr int WM_T = 4, WN_T = MF_GEMM_WN_TILES;  // 16 x 16 MFMA tiles per wave (M, N)
-constexpr int WAVES_N = BN / (16 * WN_T), WAVES_M = BM / (16 * WM_T);
-constexpr int NTHREADS = 64 * WAVES_M * WAVES_N;
-constexpr int LPT = BM * BK / 2 / NTHREADS;  // pair loads per thread per operand and K step
-static_assert(LPT >= 1 && BM * BK / 2 % NTHREADS == 0, "tile loads must divide evenly");
+
+template <int BM_, int BN_, int WAVES_M_, int WAVES_N_, int WAVES_PER_SIMD_>
+struct TileCfg {
+  static constexpr int BM = BM_, BN = BN_, BK = 16;
+  static constexpr int WAVES_M = WAVES_M_, WAVES_N = WAVES_N_;
+  static constexpr int NTHREADS = 64 * WAVES_M * WAVES_N;
+  static constexpr int WAVES_PER_SIMD = WAVES_PER_SIMD_;  // occupancy the register budget is sized for
+  static constexpr int WM_T = BM / (16 * WAVES_M), WN_T = BN / (16 * WAVES_N);  // MFMA tiles per wave
+  static constexpr int SA = BM + 16, SB = BN + 16;  // LDS row strides (elements)
+  static constexpr int LPT_A = BM * BK / 2 / NTHREADS;  // element-pair loads per thread and K step
+  static constexpr int LPT_B = BK * BN / 2 / NTHREADS;
+  static constexpr int LDS_A = BK * SA, LDS_B = BK * SB;
+  static constexpr int LDS_ELEMS = 2 * (LDS_A + LDS_B);  // two buffers of A and B
+  static_assert(LPT_A >= 1 && LPT_B >= 1 && BM * BK / 2 % NTHREADS == 0 && BK * BN / 2 % NTHREADS == 0,
+                "tile loads must divide evenly");
+  static_assert(BM % kLeafTile == 0 && BN % kLeafTile == 0, "tiles are multiples of the leaf granularity");
+};
+using Tile128 = TileCfg<128, 128, 2, 4, 4>;
+using Tile256 = TileCfg<256, 128, 2, 4, 2>;
 
 // Element pair idx of the A tile -> (row, kp): the pair A[row][kp..kp+1].
 // LDS has 32 four-byte banks and serves 128 bytes per cycle (16 lanes of a
@@ -51,12 +56,19 @@ static_assert(LPT >= 1 && BM * BK / 2 % NTHREADS == 0, "tile loads must divide e
 // consecutive rows of the same k-row pair, so the transposed stores of those
 // lanes cover every bank once.  Mapping consecutive lanes along k instead
 // would put all k-row pairs of a row in the same banks.
-template <class T>
+template <class T, class Cfg>
 __device__ __forceinline__ void a_slot(int idx, int& row, int& kp) {
-  constexpr int RUN = 128 / sizeof(T);
-  static_assert(BM % RUN == 0, "A tile rows must split into runs");
+  constexpr int RUN = 128 / sizeof(T), BK = Cfg::BK;
+  static_assert(Cfg::BM % RUN == 0, "A tile rows must split into runs");
   row = idx % RUN + RUN * (idx / (RUN * (BK / 2)));
   kp = 2 * ((idx / RUN) % (BK / 2));
+}
+
+// Element pair idx of the B tile -> (k row, column pair).
+template <class T, class Cfg>
+__device__ __forceinline__ void b_slot(int idx, int& kr, int& cp) {
+  kr = idx / (Cfg::BN / 2);
+  cp = (idx % (Cfg::BN / 2)) * 2;
 }
 
 template <class T>
@@ -89,26 +101,25 @@ struct Mfma<float> {
 // (row * ld + column, fixed for the whole loop).  Edge tiles: plain loads with
 // per-element masks; entries outside the view's valid rows/columns are zero
 // and only valid elements are read.
+template <class Cfg>
 struct LaneOffsets {
-  int a[LPT], b[LPT];
+  int a[Cfg::LPT_A], b[Cfg::LPT_B];
 };
 
-template <class T>
-__device__ __forceinline__ void b_slot(int idx, int& kr, int& cp) {
-  kr = idx / (BN / 2);
-  cp = (idx % (BN / 2)) * 2;
-}
-
-template <class T>
-__device__ __forceinline__ LaneOffsets lane_offsets(int lda, int ldb, int t) {
-  LaneOffsets o;
+template <class T, class Cfg>
+__device__ __forceinline__ LaneOffsets<Cfg> lane_offsets(int lda, int ldb, int t) {
+  LaneOffsets<Cfg> o;
 #pragma unroll
-  for (int q = 0; q < LPT; ++q) {
-    int row, kp, kr, cp;
-    a_slot<T>(t + NTHREADS * q, row, kp);
-    b_slot<T>(t + NTHREADS * q, kr, cp);
-    // row < BM and kr < BK, ld <= 2^21: every offset is below 2^31 bytes.
+  for (int q = 0; q < Cfg::LPT_A; ++q) {
+    int row, kp;
+    a_slot<T, Cfg>(t + Cfg::NTHREADS * q, row, kp);
+    // row < 256 and ld <= 2^21: every offset is below 2^31 bytes.
     o.a[q] = (row * lda + kp) * (int)sizeof(T);
+  }
+#pragma unroll
+  for (int q = 0; q < Cfg::LPT_B; ++q) {
+    int kr, cp;
+    b_slot<T, Cfg>(t + Cfg::NTHREADS * q, kr, cp);
     o.b[q] = (kr * ldb + cp) * (int)sizeof(T);
   }
   return o;
@@ -136,29 +147,29 @@ __device__ __forceinline__ typename Mfma<T>::v2 buffer_pair(__amdgpu_buffer_rsrc
     return __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
-template <class T>
+template <class T, class Cfg>
 __device__ __forceinline__ void load_tiles_interior(const T* __restrict__ pa, int lda, const T* __restrict__ pb,
-                                                    int ldb, int i0, int j0, int k0, const LaneOffsets& o,
-                                                    typename Mfma<T>::v2 (&ra)[LPT],
-                                                    typename Mfma<T>::v2 (&rb)[LPT]) {
+                                                    int ldb, int i0, int j0, int k0, const LaneOffsets<Cfg>& o,
+                                                    typename Mfma<T>::v2 (&ra)[Cfg::LPT_A],
+                                                    typename Mfma<T>::v2 (&rb)[Cfg::LPT_B]) {
   const __amdgpu_buffer_rsrc_t sa = raw_rsrc(pa + (size_t)i0 * lda + k0);
   const __amdgpu_buffer_rsrc_t sb = raw_rsrc(pb + (size_t)k0 * ldb + j0);
 #pragma unroll
-  for (int q = 0; q < LPT; ++q) ra[q] = buffer_pair<T>(sa, o.a[q]);
+  for (int q = 0; q < Cfg::LPT_A; ++q) ra[q] = buffer_pair<T>(sa, o.a[q]);
 #pragma unroll
-  for (int q = 0; q < LPT; ++q) rb[q] = buffer_pair<T>(sb, o.b[q]);
+  for (int q = 0; q < Cfg::LPT_B; ++q) rb[q] = buffer_pair<T>(sb, o.b[q]);
 }
 
-template <class T>
+template <class T, class Cfg>
 __device__ __forceinline__ void load_tiles_masked(const T* __restrict__ pa, int lda, int a_vr, int a_vc,
                                                   const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0,
-                                                  int j0, int k0, int t, typename Mfma<T>::v2 (&ra)[LPT],
-                                                  typename Mfma<T>::v2 (&rb)[LPT]) {
+                                                  int j0, int k0, int t, typename Mfma<T>::v2 (&ra)[Cfg::LPT_A],
+                                                  typename Mfma<T>::v2 (&rb)[Cfg::LPT_B]) {
   typedef typename Mfma<T>::v2 v2;
 #pragma unroll
-  for (int q = 0; q < LPT; ++q) {
+  for (int q = 0; q < Cfg::LPT_A; ++q) {
     int row, kp;
-    a_slot<T>(t + NTHREADS * q, row, kp);
+    a_slot<T, Cfg>(t + Cfg::NTHREADS * q, row, kp);
     const int gi = i0 + row, gk = k0 + kp;
     v2 v = {T(0), T(0)};
     if (gi < a_vr) {
@@ -168,9 +179,9 @@ __device__ __forceinline__ void load_tiles_masked(const T* __restrict__ pa, int 
     ra[q] = v;
   }
 #pragma unroll
-  for (int q = 0; q < LPT; ++q) {
+  for (int q = 0; q < Cfg::LPT_B; ++q) {
     int kr, cp;
-    b_slot<T>(t + NTHREADS * q, kr, cp);
+    b_slot<T, Cfg>(t + Cfg::NTHREADS * q, kr, cp);
     const int gk = k0 + kr, gj = j0 + cp;
     v2 v = {T(0), T(0)};
     if (gk < b_vr) {
@@ -181,100 +192,104 @@ __device__ __forceinline__ void load_tiles_masked(const T* __restrict__ pa, int 
   }
 }
 
-template <class T>
-__device__ __forceinline__ void store_tiles(T* As, T* Bs, int t, const typename Mfma<T>::v2 (&ra)[LPT],
-                                            const typename Mfma<T>::v2 (&rb)[LPT]) {
+template <class T, class Cfg>
+__device__ __forceinline__ void store_tiles(T* As, T* Bs, int t, const typename Mfma<T>::v2 (&ra)[Cfg::LPT_A],
+                                            const typename Mfma<T>::v2 (&rb)[Cfg::LPT_B]) {
   typedef typename Mfma<T>::v2 v2;
 #pragma unroll
-  for (int q = 0; q < LPT; ++q) {
+  for (int q = 0; q < Cfg::LPT_A; ++q) {
     int row, kp;
-    a_slot<T>(t + NTHREADS * q, row, kp);
-    As[kp * LDS_STRIDE + row] = ra[q].x;
-    As[(kp + 1) * LDS_STRIDE + row] = ra[q].y;
+    a_slot<T, Cfg>(t + Cfg::NTHREADS * q, row, kp);
+    As[kp * Cfg::SA + row] = ra[q].x;
+    As[(kp + 1) * Cfg::SA + row] = ra[q].y;
   }
 #pragma unroll
-  for (int q = 0; q < LPT; ++q) {
+  for (int q = 0; q < Cfg::LPT_B; ++q) {
     int kr, cp;
-    b_slot<T>(t + NTHREADS * q, kr, cp);
-    *reinterpret_cast<v2*>(Bs + kr * LDS_STRIDE + cp) = rb[q];
+    b_slot<T, Cfg>(t + Cfg::NTHREADS * q, kr, cp);
+    *reinterpret_cast<v2*>(Bs + kr * Cfg::SB + cp) = rb[q];
   }
 }
 
-template <class T>
+template <class T, class Cfg>
 __device__ __forceinline__ void load_frags(const T* As, const T* Bs, int s, int wm, int wn, int lr, int lk,
-                                           T (&fa)[WM_T], T (&fb)[WN_T]) {
+                                           T (&fa)[Cfg::WM_T], T (&fb)[Cfg::WN_T]) {
 #pragma unroll
-  for (int mi = 0; mi < WM_T; ++mi) fa[mi] = As[(4 * s + lk) * LDS_STRIDE + wm + 16 * mi + lr];
+  for (int mi = 0; mi < Cfg::WM_T; ++mi) fa[mi] = As[(4 * s + lk) * Cfg::SA + wm + 16 * mi + lr];
 #pragma unroll
-  for (int ni = 0; ni < WN_T; ++ni) fb[ni] = Bs[(4 * s + lk) * LDS_STRIDE + wn + 16 * ni + lr];
+  for (int ni = 0; ni < Cfg::WN_T; ++ni) fb[ni] = Bs[(4 * s + lk) * Cfg::SB + wn + 16 * ni + lr];
 }
 
-template <class T>
-__device__ __forceinline__ void mfma_step(const T (&fa)[WM_T], const T (&fb)[WN_T],
-                                          typename Mfma<T>::v4 (&acc)[WM_T][WN_T]) {
+template <class T, class Cfg>
+__device__ __forceinline__ void mfma_step(const T (&fa)[Cfg::WM_T], const T (&fb)[Cfg::WN_T],
+                                          typename Mfma<T>::v4 (&acc)[Cfg::WM_T][Cfg::WN_T]) {
 #pragma unroll
-  for (int mi = 0; mi < WM_T; ++mi)
+  for (int mi = 0; mi < Cfg::WM_T; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < WN_T; ++ni) acc[mi][ni] = Mfma<T>::op(fa[mi], fb[ni], acc[mi][ni]);
+    for (int ni = 0; ni < Cfg::WN_T; ++ni) acc[mi][ni] = Mfma<T>::op(fa[mi], fb[ni], acc[mi][ni]);
 }
 
-// acc = A_view(i0.., :) * B_view(:, j0..) over K = KT * BK.
-template <class T, bool MASKED>
-__device__ __forceinline__ void k_loop(T (*lds)[2][BK * LDS_STRIDE], const T* __restrict__ pa, int lda, int a_vr,
-                                       int a_vc, const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0,
-                                       int j0, int KT, int t, int wm, int wn, int lr, int lk,
-                                       typename Mfma<T>::v4 (&acc)[WM_T][WN_T]) {
-  typename Mfma<T>::v2 ra[LPT], rb[LPT];
-  LaneOffsets o;
-  if constexpr (!MASKED) o = lane_offsets<T>(lda, ldb, t);
+// acc = A_view(i0.., :) * B_view(:, j0..) over K = KT * BK.  lds holds the
+// two A buffers, then the two B buffers.
+template <class T, class Cfg, bool MASKED>
+__device__ __forceinline__ void k_loop(T* lds, const T* __restrict__ pa, int lda, int a_vr, int a_vc,
+                                       const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0, int j0, int KT,
+                                       int t, int wm, int wn, int lr, int lk,
+                                       typename Mfma<T>::v4 (&acc)[Cfg::WM_T][Cfg::WN_T]) {
+  constexpr int WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, BK = Cfg::BK;
+  typename Mfma<T>::v2 ra[Cfg::LPT_A], rb[Cfg::LPT_B];
+  LaneOffsets<Cfg> o;
+  if constexpr (!MASKED) o = lane_offsets<T, Cfg>(lda, ldb, t);
   auto load = [&](int k0) {
     if constexpr (MASKED)
-      load_tiles_masked<T>(pa, lda, a_vr, a_vc, pb, ldb, b_vr, b_vc, i0, j0, k0, t, ra, rb);
+      load_tiles_masked<T, Cfg>(pa, lda, a_vr, a_vc, pb, ldb, b_vr, b_vc, i0, j0, k0, t, ra, rb);
     else
-      load_tiles_interior<T>(pa, lda, pb, ldb, i0, j0, k0, o, ra, rb);
+      load_tiles_interior<T, Cfg>(pa, lda, pb, ldb, i0, j0, k0, o, ra, rb);
   };
+  auto a_buf = [&](int b) { return lds + b * Cfg::LDS_A; };
+  auto b_buf = [&](int b) { return lds + 2 * Cfg::LDS_A + b * Cfg::LDS_B; };
   load(0);
-  store_tiles<T>(lds[0][0], lds[0][1], t, ra, rb);
+  store_tiles<T, Cfg>(a_buf(0), b_buf(0), t, ra, rb);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < KT;
     if (more) load((kt + 1) * BK);
-    const T* As = lds[cur][0];
-    const T* Bs = lds[cur][1];
+    const T* As = a_buf(cur);
+    const T* Bs = b_buf(cur);
 #if MF_GEMM_FRAG_DB
     T fa[2][WM_T], fb[2][WN_T];
-    load_frags<T>(As, Bs, 0, wm, wn, lr, lk, fa[0], fb[0]);
+    load_frags<T, Cfg>(As, Bs, 0, wm, wn, lr, lk, fa[0], fb[0]);
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
-      if (s + 1 < BK / 4) load_frags<T>(As, Bs, s + 1, wm, wn, lr, lk, fa[(s + 1) & 1], fb[(s + 1) & 1]);
-      mfma_step<T>(fa[s & 1], fb[s & 1], acc);
+      if (s + 1 < BK / 4) load_frags<T, Cfg>(As, Bs, s + 1, wm, wn, lr, lk, fa[(s + 1) & 1], fb[(s + 1) & 1]);
+      mfma_step<T, Cfg>(fa[s & 1], fb[s & 1], acc);
     }
 #else
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       T fa[WM_T], fb[WN_T];
-      load_frags<T>(As, Bs, s, wm, wn, lr, lk, fa, fb);
-      mfma_step<T>(fa, fb, acc);
+      load_frags<T, Cfg>(As, Bs, s, wm, wn, lr, lk, fa, fb);
+      mfma_step<T, Cfg>(fa, fb, acc);
     }
 #endif
-    if (more) store_tiles<T>(lds[cur ^ 1][0], lds[cur ^ 1][1], t, ra, rb);
+    if (more) store_tiles<T, Cfg>(a_buf(cur ^ 1), b_buf(cur ^ 1), t, ra, rb);
     __syncthreads();
   }
 }
 
 // One work item of the grouped GEMM: tile (ti, tj) of every product of group
 // grp, in product order, each followed by its epilogue post-additions.
-template <class T>
-__device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti, int tj,
-                                          T (*lds)[2][BK * LDS_STRIDE]) {
+template <class T, class Cfg>
+__device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti, int tj, T* lds) {
   typedef typename Mfma<T>::v4 v4;
+  constexpr int BM = Cfg::BM, BN = Cfg::BN, WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, WAVES_N = Cfg::WAVES_N;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = (wave / WAVES_N) * (16 * WM_T), wn = (wave % WAVES_N) * (16 * WN_T);
   const int lr = lane & 15, lk = lane >> 4;
   const int i0 = ti * BM, j0 = tj * BN;
-  const int KT = g.m / BK;
+  const int KT = g.m / Cfg::BK;
   const int r_beg = load_uniform(g.group_beg + grp), r_end = load_uniform(g.group_beg + grp + 1);
 
   for (int r = r_beg; r < r_end; ++r) {
@@ -293,10 +308,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
     const bool interior = vec_a && vec_b && i0 + BM <= pd.a_vr && pd.a_vc >= g.m && pd.b_vr >= g.m &&
                           j0 + BN <= pd.b_vc;
     if (interior)
-      k_loop<T, false>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
+      k_loop<T, Cfg, false>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
                        lk, acc);
     else
-      k_loop<T, true>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
+      k_loop<T, Cfg, true>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
                       lk, acc);
 
     // Epilogue: post-addition into every output block this product feeds.

@@ -68,7 +68,7 @@ __device__ __forceinline__ void run_combine(const BatchArgs& g, const BatchTask&
   with_nin(st.nin, [&](auto nin_c) {
     constexpr int NIN = decltype(nin_c)::value;
     constexpr int VEC = NIN <= 4 ? 4 : (NIN <= 9 ? 2 : 1);
-    for (int64_t e = tk.e0 + (int64_t)threadIdx.x * VEC; e < tk.e1; e += (int64_t)NTHREADS * VEC) {
+    for (int64_t e = tk.e0 + (int64_t)threadIdx.x * VEC; e < tk.e1; e += (int64_t)Tile128::NTHREADS * VEC) {
       const int i = (int)(e / st.m), j = (int)(e % st.m);
       if (full)
         combine_body<T, NIN, VEC, true>(a, set, i, j);
@@ -79,7 +79,7 @@ __device__ __forceinline__ void run_combine(const BatchArgs& g, const BatchTask&
 }
 
 template <class T>
-__device__ __forceinline__ void run_gemm(const BatchArgs& g, const BatchTask& tk, T (*lds)[2][BK * LDS_STRIDE]) {
+__device__ __forceinline__ void run_gemm(const BatchArgs& g, const BatchTask& tk, T* lds) {
   const GemmRec gr = load_uniform(g.gemms + tk.rec);
   const BatchInst in = load_uniform(g.insts + tk.inst);
   GemmArgs<T> a;
@@ -92,14 +92,15 @@ __device__ __forceinline__ void run_gemm(const BatchArgs& g, const BatchTask& tk
   a.group_beg = gr.group_beg;
   a.groups = gr.groups;
   a.m = gr.m;
-  a.tiles = gr.tiles;
+  a.tiles_m = gr.tiles;
+  a.tiles_n = gr.tiles;
   a.vec_in = in.vec_in;
-  gemm_tile<T>(a, tk.a, tk.b, tk.c, lds);
+  gemm_tile<T, Tile128>(a, tk.a, tk.b, tk.c, lds);
 }
 
 template <class T>
-__global__ void __launch_bounds__(NTHREADS, MF_GEMM_WAVES_PER_SIMD) batch_persistent(BatchArgs g) {
-  __shared__ T lds[2][2][BK * LDS_STRIDE];
+__global__ void __launch_bounds__(Tile128::NTHREADS, Tile128::WAVES_PER_SIMD) batch_persistent(BatchArgs g) {
+  __shared__ T lds[Tile128::LDS_ELEMS];
   __shared__ int s_task;
   __shared__ int s_ok;
   int* ticket = g.ctr + g.nctr;
@@ -169,9 +170,9 @@ hipError_t launch_batch(int elem, const BatchTask* tasks, int ntasks, const Stag
   g.nctr = nctr;
   g.ntasks = ntasks;
   if (elem == 8)
-    hipLaunchKernelGGL(batch_persistent<double>, dim3(grid), dim3(NTHREADS), 0, s, g);
+    hipLaunchKernelGGL(batch_persistent<double>, dim3(grid), dim3(Tile128::NTHREADS), 0, s, g);
   else
-    hipLaunchKernelGGL(batch_persistent<float>, dim3(grid), dim3(NTHREADS), 0, s, g);
+    hipLaunchKernelGGL(batch_persistent<float>, dim3(grid), dim3(Tile128::NTHREADS), 0, s, g);
   return hipGetLastError();
 }
 

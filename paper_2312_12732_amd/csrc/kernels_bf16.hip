@@ -24,7 +24,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = GEMM_BM, BN = GEMM_BN, BK = 32;
+constexpr int BM = kLeafTile, BN = kLeafTile, BK = 32;
 constexpr int KS = BK + 8;           // bf16 elements per LDS row (16-byte aligned, conflict-free reads)
 constexpr int NTHREADS = 256;        // 4 waves, 2 x 2, each 64 x 64
 constexpr int WT = 4;                // 16 x 16 tiles per wave side
@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_grouped(GemmArgs<float>
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int lr = lane & 15, lk = lane >> 4;
   int grp, ti, tj;
-  work_of(blockIdx.x, g.tiles, g.groups, &grp, &ti, &tj);
+  work_of(blockIdx.x, g.tiles_m, g.tiles_n, g.groups, &grp, &ti, &tj);
   const int i0 = ti * BM, j0 = tj * BN;
   const int KT = g.m / BK;
   const int r_beg = g.group_beg[grp], r_end = g.group_beg[grp + 1];
@@ -230,9 +230,10 @@ hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* 
   g.group_beg = pl.d_group_beg;
   g.groups = pl.groups;
   g.m = (int)pl.m;
-  g.tiles = (int)(pl.m / bf::BM);
+  g.tiles_m = (int)(pl.m / bf::BM);
+  g.tiles_n = (int)(pl.m / bf::BN);
   g.vec_in = vec_in ? 1 : 0;
-  const unsigned grid = (unsigned)g.tiles * (unsigned)g.tiles * (unsigned)g.groups;
+  const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n * (unsigned)g.groups;
   if (x3)
     hipLaunchKernelGGL(bf::gemm_bf16_grouped<true>, dim3(grid), dim3(bf::NTHREADS), 0, s, g);
   else

@@ -10,14 +10,34 @@
 // post-additions.
 #include "gemm_tile.h"
 
+// Tile choice.  Tile256: 256 x 128 tiles, one workgroup of eight 128 x 32
+// waves per CU (a quarter less operand traffic per flop than Tile128).
+// Tile128: 128 x 128 tiles, two workgroups of eight 64 x 32 waves per CU.
+// With one workgroup per CU a partly filled last round of workgroups leaves
+// CUs idle, so Tile256 is taken only when its work items fill whole rounds
+// or are many (MF_GEMM_BIG_TILES = 1); 0 never takes it, 2 whenever the leaf
+// size allows.
+#ifndef MF_GEMM_BIG_TILES
+#define MF_GEMM_BIG_TILES 1
+#endif
+
 namespace mf {
 
-template <class T>
-__global__ void __launch_bounds__(NTHREADS, MF_GEMM_WAVES_PER_SIMD) gemm_grouped(GemmArgs<T> g) {
-  __shared__ T lds[2][2][BK * LDS_STRIDE];  // [buffer][A|B][k][col]
+template <class T, class Cfg>
+__global__ void __launch_bounds__(Cfg::NTHREADS, Cfg::WAVES_PER_SIMD) gemm_grouped(GemmArgs<T> g) {
+  __shared__ T lds[Cfg::LDS_ELEMS];  // [A buffer 0 | A buffer 1 | B buffer 0 | B buffer 1], k-major
   int grp, ti, tj;
-  work_of(blockIdx.x, g.tiles, g.groups, &grp, &ti, &tj);
-  gemm_tile<T>(g, grp, ti, tj, lds);
+  work_of(blockIdx.x, g.tiles_m, g.tiles_n, g.groups, &grp, &ti, &tj);
+  gemm_tile<T, Cfg>(g, grp, ti, tj, lds);
+}
+
+template <class T, class Cfg>
+static hipError_t launch_cfg(GemmArgs<T> g, int64_t m, hipStream_t s) {
+  g.tiles_m = (int)(m / Cfg::BM);
+  g.tiles_n = (int)(m / Cfg::BN);
+  const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n * (unsigned)g.groups;
+  hipLaunchKernelGGL((gemm_grouped<T, Cfg>), dim3(grid), dim3(Cfg::NTHREADS), 0, s, g);
+  return hipGetLastError();
 }
 
 template <class T>
@@ -33,11 +53,16 @@ static hipError_t launch_gemm_t(const Plan& pl, const void* A, const void* B, vo
   g.group_beg = pl.d_group_beg;
   g.groups = pl.groups;
   g.m = (int)pl.m;
-  g.tiles = (int)(pl.m / BM);
   g.vec_in = vec_in ? 1 : 0;
-  const unsigned grid = (unsigned)g.tiles * (unsigned)g.tiles * (unsigned)g.groups;
-  hipLaunchKernelGGL(gemm_grouped<T>, dim3(grid), dim3(NTHREADS), 0, s, g);
-  return hipGetLastError();
+  int cus = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t big_items = (pl.m / Tile256::BM) * (pl.m / Tile256::BN) * (int64_t)pl.groups;
+  const bool big_ok = pl.m % Tile256::BM == 0 && big_items >= cus;
+  const bool big_fills = big_items % cus == 0 || big_items >= 8 * (int64_t)cus;
+  if (big_ok && (MF_GEMM_BIG_TILES == 2 || (MF_GEMM_BIG_TILES == 1 && big_fills)))
+    return launch_cfg<T, Tile256>(g, pl.m, s);
+  return launch_cfg<T, Tile128>(g, pl.m, s);
 }
 
 hipError_t launch_gemm_f64(const Plan& pl, const void* A, const void* B, void* C, void* ws, bool vec_in,

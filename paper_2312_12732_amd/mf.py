@@ -39,12 +39,19 @@ EXPORTED = ["mf_algo_from_uvw", "mf_algo_builtin", "mf_algo_compose", "mf_algo_r
             "mf_fastmm_ws", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read", "mf_batch_create",
             "mf_batch_workspace_bytes", "mf_batch_run", "mf_batch_aborted", "mf_batch_tasks", "mf_batch_free",
             "mf_server_create", "mf_server_need_bytes", "mf_server_submit", "mf_server_replay", "mf_server_drain",
-            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform", "mf_autotune_batch"]
+            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform", "mf_autotune_batch", "mf_plan_query"]
 
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int), ("hbm_budget", ctypes.c_size_t), ("allow_overtake", ctypes.c_int),
                 ("depth_min_n_f64", ctypes.c_int64 * 4), ("depth_min_n_f32", ctypes.c_int64 * 4)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("levels_outer", ctypes.c_int), ("groups", ctypes.c_int),
+                ("pre_stages", ctypes.c_int), ("post_stages", ctypes.c_int), ("leaf_m", ctypes.c_int64),
+                ("products", ctypes.c_int64), ("gemm_flops", ctypes.c_double), ("pre_bytes", ctypes.c_double),
+                ("post_bytes", ctypes.c_double), ("ws_bytes", ctypes.c_size_t)]
 
 
 class MFError(RuntimeError):
@@ -94,6 +101,7 @@ def _load():
                                    ctypes.POINTER(ctypes.c_size_t)], I),
         "mf_fill_uniform": ([P, I64, I, ctypes.c_uint64, P], I),
         "mf_phase_timing_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I)], I),
+        "mf_plan_query": ([P, I, I, I64, I, ctypes.POINTER(PlanInfo)], I),
         "mf_autotune_batch": ([I, LP, I, ctypes.POINTER(P), I, I, ctypes.c_double, I, I, P, ctypes.POINTER(I), DP],
                               I),
     }
@@ -305,6 +313,14 @@ def mf_batch_create(sizes, algos, depths, cutoffs, dtype_code: int = MF_F64) -> 
     out = ctypes.c_void_p()
     _check(lib.mf_batch_create(count, n_arr, a_arr, d_arr, c_arr, dtype_code, ctypes.byref(out)))
     return Batch(out.value, [a for a in algos if a is not None], sizes, dtype_code)
+
+
+def mf_plan_query(algo, depth, cutoff, n, dtype_code=MF_F64) -> dict:
+    """Shape and algorithmic cost of the plan of a request (host only)."""
+    info = PlanInfo()
+    _check(lib.mf_plan_query(algo.handle if algo is not None else None, depth, cutoff, n, dtype_code,
+                             ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in PlanInfo._fields_}
 
 
 def mf_autotune_batch(sizes, dtype_code, algos, max_depth, work_flops=2e11, max_copies=4096, reps=3, stream=None):

@@ -260,3 +260,29 @@ def test_autotune_argument_validation_without_device():
     assert _tune(1, [256], mf.MF_F64, [s], 2, work=0.0) == mf.MF_ERR_ARG
     assert _tune(1, [256], mf.MF_F64, [s], 2, copies=0) == mf.MF_ERR_ARG
     assert _tune(1, [256], mf.MF_F64, [s], 2, reps=0) == mf.MF_ERR_ARG
+
+
+def test_plan_query_closed_forms():
+    """Algorithmic bytes and flops of the plan against closed forms (Winograd
+    form: 4 materialised T and 4 materialised S per level)."""
+    w = mf.mf_algo_builtin("winograd")
+    n = 8192
+    for d in (1, 2, 3):
+        q = mf.mf_plan_query(w, d, 0, n)
+        assert q["levels"] == d and q["products"] == 7 ** d and q["leaf_m"] == n >> d
+        assert q["gemm_flops"] == 7 ** d * 2.0 * (n >> d) ** 3
+        # level l, per operand: its 7^l blocks of size n / 2^l are read once and
+        # the 4 materialised children of each are written
+        pre = sum(2 * 8 * 7 ** lv * ((n >> lv) ** 2 + 4 * (n >> (lv + 1)) ** 2) for lv in range(d))
+        assert q["pre_bytes"] == pre
+        assert q["ws_bytes"] == mf.mf_workspace_bytes(w, d, 0, n)
+        # outer post-additions: level l reads R children and writes p^2 quarters of 7^l parents
+        lo = q["levels_outer"]
+        post = sum(8 * 7 ** lv * (7 + 4) * (n >> (lv + 1)) ** 2 for lv in range(lo))
+        assert q["post_bytes"] == post
+    c = mf.mf_plan_query(None, 0, 0, 1000)
+    assert c["levels"] == 0 and c["products"] == 1 and c["leaf_m"] == 1024 and c["pre_bytes"] == 0
+    # virtual padding: the inputs count only their valid elements (n = 1000: quarters of 500 x 500), while a
+    # materialised child is a whole 512 x 512 workspace block, zeros included, as the leaf GEMM reads it
+    q = mf.mf_plan_query(w, 1, 0, 1000)
+    assert q["leaf_m"] == 512 and q["pre_bytes"] == 2 * 8 * (1000 * 1000 + 4 * 512 * 512)

@@ -207,3 +207,29 @@ def test_full_size_sampled_rows(n, name, depth):
     err = om.rel_fro_error(got[rows], ref)
     assert err < FP64_TOL, err
     assert np.isfinite(got).all()
+
+
+# ------------------------------------------------- large-tile GEMM (256 x 128)
+# The 256 x 128 tile kernel runs where its work items fill whole rounds of the
+# CUs: classical n = 4000, 4001 (masked edge tiles: valid extent 4000 / 4001
+# inside a 4096 leaf) and 4096 (interior), and the depth-1 product at 8192.
+# n = 6144 (classical and depth 1) takes the 128 x 128 kernel at the same sizes.
+@pytest.mark.parametrize("n", [4000, 4001, 4096, 6144])
+def test_large_tile_classical_int_exact_rows(n):
+    A = mi.int_uniform(n, 60).astype(np.float64)
+    B = mi.int_uniform(n, 61).astype(np.float64)
+    got = run_classical(A, B)
+    rows = np.sort(np.random.default_rng(n).choice(n, size=40, replace=False))
+    rows = np.unique(np.concatenate([rows, [0, n - 1]]))
+    assert np.array_equal(got[rows], om.rows_reference(A, B, rows))
+    cols = np.unique(np.concatenate([np.random.default_rng(n + 1).choice(n, size=40, replace=False), [0, n - 1]]))
+    assert np.array_equal(got[:, cols], A @ B[:, cols])
+
+
+@pytest.mark.parametrize("n", [6144, 8192])
+def test_large_tile_fast_depth1_int_exact_rows(n):
+    A = mi.int_uniform(n, 62).astype(np.float64)
+    B = mi.int_uniform(n, 63).astype(np.float64)
+    got = run_fast(mf.mf_algo_builtin("winograd"), 1, 0, A, B)
+    rows = np.unique(np.concatenate([np.random.default_rng(n).choice(n, size=32, replace=False), [0, n - 1]]))
+    assert np.array_equal(got[rows], om.rows_reference(A, B, rows))

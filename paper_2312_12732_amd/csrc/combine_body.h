@@ -46,7 +46,7 @@ __device__ __forceinline__ void combine_body(const CombArgs<T>& g, const CombSet
   tv in[NIN];
 #pragma unroll
   for (int k = 0; k < NIN; ++k) {
-    const CombIn v = ins[k];
+    const CombIn v = load_uniform(ins + k);
     const T* p = comb_src(g, v.src) + v.off + (int64_t)i * v.ld + j;
     if (FULL) {
       in[k] = *reinterpret_cast<const tv*>(p);
@@ -63,13 +63,13 @@ __device__ __forceinline__ void combine_body(const CombArgs<T>& g, const CombSet
     }
   }
   for (int o = set.out_beg; o < set.out_end; ++o) {
-    const CombOut po = g.outs[o];
+    const CombOut po = load_uniform(g.outs + o);
     const double* c = g.coef + po.coef_off;
     tv acc;
     bool started = false;
 #pragma unroll
     for (int k = 0; k < NIN; ++k) {
-      const T ck = (T)c[k];
+      const T ck = (T)load_uniform(c + k);
       if (ck != T(0)) {
         if (!started) {
           acc = ck == T(1) ? in[k] : ck * in[k];

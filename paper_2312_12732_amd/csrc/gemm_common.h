@@ -27,14 +27,22 @@ struct GemmArgs {
 // Load a descriptor that every lane of the wave reads at the same address and
 // mark each word as wave-uniform, so address arithmetic on it runs on the
 // scalar unit and buffer descriptors built from it stay in scalar registers.
+// Descriptors are written before the kernel starts and never during it, so
+// they are read through the constant address space: with a wave-uniform
+// address that is one scalar load instead of a vector load in every lane.
 template <class S>
 __device__ __forceinline__ S load_uniform(const S* p) {
   static_assert(sizeof(S) % 4 == 0, "descriptor must be a whole number of words");
-  S v = *p;
   int w[sizeof(S) / 4];
-  __builtin_memcpy(w, &v, sizeof(S));
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef const __attribute__((address_space(4))) int cint;
+  cint* q = (cint*)p;
 #pragma unroll
-  for (unsigned i = 0; i < sizeof(S) / 4; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  for (unsigned i = 0; i < sizeof(S) / 4; ++i) w[i] = __builtin_amdgcn_readfirstlane(q[i]);
+#else
+  __builtin_memcpy(w, p, sizeof(S));
+#endif
+  S v;
   __builtin_memcpy(&v, w, sizeof(S));
   return v;
 }

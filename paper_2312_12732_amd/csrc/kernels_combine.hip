@@ -19,7 +19,7 @@ __global__ void __launch_bounds__(256) combine(CombArgs<T> g) {
   const int64_t mm = (int64_t)g.m * g.m;
   if (e >= mm) return;
   const int i = (int)(e / g.m), j = (int)(e % g.m);
-  const CombSet set = g.sets[blockIdx.y];
+  const CombSet set = load_uniform(g.sets + blockIdx.y);
   if (set.full && g.vec_in && g.vec_out)
     combine_body<T, NIN, VEC, true>(g, set, i, j);
   else

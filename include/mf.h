@@ -162,11 +162,13 @@ mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A
  * Many independent products C_i = A_i B_i (i < count) of sizes n[i], each
  * with its own algorithm (algos[i], NULL when depth[i] == 0), depth and
  * cutoff, all with storage dtype MF_F64 or MF_F32 (leaves in the storage
- * type), executed by ONE persistent launch: its workgroups take tasks
- * (addition chunks and GEMM tiles of every instance) from a global ticket in
- * a topological order and wait on per-instance stage counters, so instances
- * of different sizes share the GPU.  A batch plan is immutable; it must not
- * run concurrently with itself (runs on one stream are fine). */
+ * type).  The plan is a task list (addition chunks and GEMM tiles of every
+ * instance) in topological order, split into phases: pre-addition level 0 of
+ * every instance, level 1, ..., all GEMM tiles (largest leaves first), then
+ * the post-addition levels.  A run launches each phase once over all
+ * instances (one workgroup per task), so instances of different sizes share
+ * the GPU within every launch.  A batch plan is immutable; it must not run
+ * concurrently with itself (runs on one stream are fine). */
 typedef struct mf_batch mf_batch;
 
 /* Plan a batch (host only; device state is made on the first run).  The
@@ -184,8 +186,8 @@ mf_status mf_batch_workspace_bytes(const mf_batch* b, size_t* bytes);
 mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* const* B, void* const* C,
                        void* workspace, size_t ws_bytes, mf_stream stream);
 
-/* Waits for the device and reports whether the last run aborted (a task's
- * wait exceeded its spin limit; the results are then invalid). */
+/* Waits for the device and reports whether the last run aborted; a run of
+ * the phase form never aborts (it has no waits), so *aborted is 0. */
 mf_status mf_batch_aborted(const mf_batch* b, int* aborted);
 
 /* The task graph, for host-side schedule checks: *ntasks tasks and *nctr
@@ -194,12 +196,17 @@ mf_status mf_batch_aborted(const mf_batch* b, int* aborted);
  * wait value, done counter. */
 mf_status mf_batch_tasks(const mf_batch* b, int* ntasks, int* nctr, int32_t* desc);
 
+/* The phases of the task list: *nphases phases; if desc is not NULL it
+ * receives 3 ints per phase: first task, end task (exclusive), 1 if the phase
+ * holds GEMM tiles (else addition chunks).  The phases partition the list. */
+mf_status mf_batch_phases(const mf_batch* b, int* nphases, int32_t* desc);
+
 /* Release a batch (NULL is ignored). */
 void mf_batch_free(mf_batch* b);
 
 /* ---- Autotuner of the batched form ------------------------------------------
  * For each of nsizes sizes n[i], measures every candidate plan where it will
- * run, in a persistent batch of many products of that size, and picks the
+ * run, in a batch of many products of that size, and picks the
  * one with the least device time per product.  Candidates, ncand =
  * 1 + nalgos * max_depth of them: index 0 is the classical GEMM; index
  * 1 + j * max_depth + (d - 1) is algos[j] at depth d (1 <= d <= max_depth).

@@ -18,6 +18,9 @@ struct mf_batch {
   std::vector<size_t> ws_off;  // bytes, per instance
   size_t ws_bytes = 0;
   std::vector<mf::BatchTask> tasks;
+  // phases of the task list, in order: [begin, end) and whether GEMM tiles
+  std::vector<std::pair<int, int>> phase_range;
+  std::vector<bool> phase_gemm;
   int nctr = 0;
   // record tables: stage records (plan, pre stage s >= 0 or post stage -1-q)
   // and GEMM records (plan), in the index order the tasks use
@@ -49,6 +52,12 @@ struct mf_batch {
 
 namespace mf {
 namespace {
+
+// Execution form of a batch run.  true: the persistent kernel (one launch,
+// ticket and stage counters).  false: one launch per phase.  The persistent
+// form stays off until its restructured task loop has been validated on the
+// device; the phase form needs no cross-workgroup waits.
+constexpr bool kPersistentBatch = false;
 
 constexpr int64_t kChunk = 32768;  // elements per combination task
 
@@ -160,9 +169,19 @@ mf_status build_batch(mf_batch* b, const std::vector<const mf_algo*>& algos, con
   }
   std::stable_sort(gemm_phase.begin(), gemm_phase.end(),
                    [](const auto& x, const auto& y) { return x.first > y.first; });
-  for (auto& v : pre_phase) b->tasks.insert(b->tasks.end(), v.begin(), v.end());
-  for (auto& v : gemm_phase) b->tasks.insert(b->tasks.end(), v.second.begin(), v.second.end());
-  for (auto& v : post_phase) b->tasks.insert(b->tasks.end(), v.begin(), v.end());
+  auto add_phase = [&](const std::vector<BatchTask>& v, bool gemm) {
+    const int beg = (int)b->tasks.size();
+    b->tasks.insert(b->tasks.end(), v.begin(), v.end());
+    if ((int)b->tasks.size() > beg) {
+      b->phase_range.push_back({beg, (int)b->tasks.size()});
+      b->phase_gemm.push_back(gemm);
+    }
+  };
+  for (auto& v : pre_phase) add_phase(v, false);
+  std::vector<BatchTask> all_gemm;
+  for (auto& v : gemm_phase) all_gemm.insert(all_gemm.end(), v.second.begin(), v.second.end());
+  add_phase(all_gemm, true);
+  for (auto& v : post_phase) add_phase(v, false);
 
   return MF_OK;
 }
@@ -333,10 +352,17 @@ mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* cons
   memcpy(b->h_insts, insts.data(), insts.size() * sizeof(BatchInst));
   hipError_t e = hipMemcpyAsync(b->d_insts, b->h_insts, insts.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(b->copied, s);
-  if (e == hipSuccess) e = launch_fill_zero(b->d_ctr, b->nctr + 2, s);
-  if (e == hipSuccess)
-    e = launch_batch((int)b->elem, b->d_tasks, (int)b->tasks.size(), b->d_stages, b->d_gemms, b->d_insts, b->d_ctr,
-                     b->nctr, b->grid, s);
+  if (kPersistentBatch) {
+    if (e == hipSuccess) e = launch_fill_zero(b->d_ctr, b->nctr + 2, s);
+    if (e == hipSuccess)
+      e = launch_batch((int)b->elem, b->d_tasks, (int)b->tasks.size(), b->d_stages, b->d_gemms, b->d_insts,
+                       b->d_ctr, b->nctr, b->grid, s);
+  } else {
+    for (size_t p = 0; p < b->phase_range.size() && e == hipSuccess; ++p)
+      e = launch_batch_phase((int)b->elem, b->phase_gemm[p], b->d_tasks, b->phase_range[p].first,
+                             b->phase_range[p].second - b->phase_range[p].first, b->d_stages, b->d_gemms,
+                             b->d_insts, s);
+  }
   if (e != hipSuccess) st = fail(MF_ERR_HIP, std::string("batch launch failed: ") + hipGetErrorString(e));
   if (own && hipFreeAsync(ws, s) != hipSuccess && st == MF_OK) st = fail(MF_ERR_HIP, "workspace release failed");
   return st;
@@ -346,14 +372,27 @@ mf_status mf_batch_aborted(const mf_batch* b, int* aborted) {
   clear_error();
   if (!b || !aborted) return fail(MF_ERR_ARG, "NULL argument");
   int flag = 0;
-  if (!b->d_ctr) {
+  if (hipDeviceSynchronize() != hipSuccess) return fail(MF_ERR_HIP, "synchronisation failed");
+  if (!b->d_ctr || !kPersistentBatch) {  // the phase form has no waits to abort
     *aborted = 0;
     return MF_OK;
   }
-  if (hipDeviceSynchronize() != hipSuccess) return fail(MF_ERR_HIP, "synchronisation failed");
   if (hipMemcpy(&flag, b->d_ctr + b->nctr + 1, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(MF_ERR_HIP, "reading the abort flag failed");
   *aborted = flag;
+  return MF_OK;
+}
+
+mf_status mf_batch_phases(const mf_batch* b, int* nphases, int32_t* desc) {
+  clear_error();
+  if (!b || !nphases) return fail(MF_ERR_ARG, "NULL argument");
+  *nphases = (int)b->phase_range.size();
+  if (desc)
+    for (size_t p = 0; p < b->phase_range.size(); ++p) {
+      desc[3 * p] = b->phase_range[p].first;
+      desc[3 * p + 1] = b->phase_range[p].second;
+      desc[3 * p + 2] = b->phase_gemm[p] ? 1 : 0;
+    }
   return MF_OK;
 }
 

@@ -98,6 +98,14 @@ __device__ __forceinline__ void run_gemm(const BatchArgs& g, const BatchTask& tk
   gemm_tile<T, Tile128>(a, tk.a, tk.b, tk.c, lds);
 }
 
+// Persistent form: one launch, workgroups take tasks from a global ticket and
+// wait on per-instance stage counters.  Thread 0 does all the atomics, in ONE
+// region per iteration placed before the barrier: it publishes the previous
+// task's completion, then takes the next ticket.  (With the completion add at
+// the end of the body and the ticket fetch at the top, the compiler merged the
+// two thread-0 regions across the back-edge into a nested loop in which the
+// other lanes re-ran the barrier and the same task while lane 0 stayed masked
+// off: the launch never finished.)
 template <class T>
 __global__ void __launch_bounds__(Tile128::NTHREADS, Tile128::WAVES_PER_SIMD) batch_persistent(BatchArgs g) {
   __shared__ T lds[Tile128::LDS_ELEMS];
@@ -105,15 +113,17 @@ __global__ void __launch_bounds__(Tile128::NTHREADS, Tile128::WAVES_PER_SIMD) ba
   __shared__ int s_ok;
   int* ticket = g.ctr + g.nctr;
   int* abort_flag = ticket + 1;
+  int prev_done = -1;  // wave-uniform
   for (;;) {
     if (threadIdx.x == 0) {
+      if (prev_done >= 0) __hip_atomic_fetch_add(&g.ctr[prev_done], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       int t = atomicAdd(ticket, 1);
       if (load_relaxed(abort_flag) != 0) t = g.ntasks;
       s_task = t;
     }
     __syncthreads();
     const int t = __builtin_amdgcn_readfirstlane(s_task);
-    if (t >= g.ntasks) return;
+    if (t >= g.ntasks) break;
     const BatchTask tk = load_uniform(g.tasks + t);
     if (tk.wait_ctr >= 0) {
       if (threadIdx.x == 0) {
@@ -129,7 +139,7 @@ __global__ void __launch_bounds__(Tile128::NTHREADS, Tile128::WAVES_PER_SIMD) ba
         s_ok = ok;
       }
       __syncthreads();
-      if (s_ok == 0) return;
+      if (__builtin_amdgcn_readfirstlane(s_ok) == 0) break;
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     if (tk.type == 0)
@@ -138,8 +148,25 @@ __global__ void __launch_bounds__(Tile128::NTHREADS, Tile128::WAVES_PER_SIMD) ba
       run_gemm<T>(g, tk, lds);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(&g.ctr[tk.done_ctr], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    prev_done = tk.done_ctr;
   }
+}
+
+// Phase form: one launch per phase (a pre-addition level of every instance,
+// all GEMM tiles, a post-addition level of every instance); workgroup b runs
+// task task0 + b.  No counters and no waits: launch order on the stream
+// orders the phases.
+template <class T>
+__global__ void __launch_bounds__(Tile128::NTHREADS) batch_combine_phase(BatchArgs g, int task0) {
+  const BatchTask tk = load_uniform(g.tasks + task0 + blockIdx.x);
+  run_combine<T>(g, tk);
+}
+
+template <class T>
+__global__ void __launch_bounds__(Tile128::NTHREADS, Tile128::WAVES_PER_SIMD) batch_gemm_phase(BatchArgs g, int task0) {
+  __shared__ T lds[Tile128::LDS_ELEMS];
+  const BatchTask tk = load_uniform(g.tasks + task0 + blockIdx.x);
+  run_gemm<T>(g, tk, lds);
 }
 
 __global__ void fill_zero(int* p, int count) {
@@ -173,6 +200,30 @@ hipError_t launch_batch(int elem, const BatchTask* tasks, int ntasks, const Stag
     hipLaunchKernelGGL(batch_persistent<double>, dim3(grid), dim3(Tile128::NTHREADS), 0, s, g);
   else
     hipLaunchKernelGGL(batch_persistent<float>, dim3(grid), dim3(Tile128::NTHREADS), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_phase(int elem, bool gemm, const BatchTask* tasks, int task0, int count,
+                              const StageRec* stages, const GemmRec* gemms, const BatchInst* insts, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  BatchArgs g{};
+  g.tasks = tasks;
+  g.stages = stages;
+  g.gemms = gemms;
+  g.insts = insts;
+  g.ntasks = task0 + count;
+  const dim3 grid((unsigned)count), block(Tile128::NTHREADS);
+  if (elem == 8) {
+    if (gemm)
+      hipLaunchKernelGGL(batch_gemm_phase<double>, grid, block, 0, s, g, task0);
+    else
+      hipLaunchKernelGGL(batch_combine_phase<double>, grid, block, 0, s, g, task0);
+  } else {
+    if (gemm)
+      hipLaunchKernelGGL(batch_gemm_phase<float>, grid, block, 0, s, g, task0);
+    else
+      hipLaunchKernelGGL(batch_combine_phase<float>, grid, block, 0, s, g, task0);
+  }
   return hipGetLastError();
 }
 

@@ -10,15 +10,17 @@
 // post-additions.
 #include "gemm_tile.h"
 
-// Tile choice.  Tile256: 256 x 128 tiles, one workgroup of eight 128 x 32
-// waves per CU (a quarter less operand traffic per flop than Tile128).
-// Tile128: 128 x 128 tiles, two workgroups of eight 64 x 32 waves per CU.
-// With one workgroup per CU a partly filled last round of workgroups leaves
-// CUs idle, so Tile256 is taken only when its work items fill whole rounds
-// or are many (MF_GEMM_BIG_TILES = 1); 0 never takes it, 2 whenever the leaf
-// size allows.
+// Tile choice.  Tile128: 128 x 128 tiles, two workgroups of eight 64 x 32
+// waves per CU.  Tile256: 256 x 128 tiles, one workgroup of eight 128 x 32
+// waves per CU (a quarter less operand traffic per flop).  Measured on
+// MI355X at n = 8192 (FP64 classical / Winograd depth 1 / depth 2), Tile256
+// is slower (16.9 / 16.1 / 18.1 ms against 16.0 / 15.1 / 14.9 ms): with two
+// waves per SIMD the barrier of each K step stalls the MFMA pipes.  It is
+// kept as an option: MF_GEMM_BIG_TILES = 1 takes it where its work items
+// fill whole rounds of the CUs, 2 wherever the leaf size allows, 0 (default)
+// never.
 #ifndef MF_GEMM_BIG_TILES
-#define MF_GEMM_BIG_TILES 1
+#define MF_GEMM_BIG_TILES 0
 #endif
 
 namespace mf {

@@ -260,6 +260,10 @@ bool combine_supported(int nin);
 hipError_t launch_batch(int elem, const BatchTask* tasks, int ntasks, const StageRec* stages, const GemmRec* gemms,
                         const BatchInst* insts, int* ctr, int nctr, int grid, hipStream_t s);
 hipError_t launch_fill_zero(int* p, int count, hipStream_t s);
+// One phase of a batch (tasks [task0, task0 + count), all of one type) as
+// its own launch, one workgroup per task.
+hipError_t launch_batch_phase(int elem, bool gemm, const BatchTask* tasks, int task0, int count,
+                              const StageRec* stages, const GemmRec* gemms, const BatchInst* insts, hipStream_t s);
 bool batch_nin_supported(int nin);
 
 // Thread-local error message.

@@ -39,7 +39,7 @@ EXPORTED = ["mf_algo_from_uvw", "mf_algo_builtin", "mf_algo_compose", "mf_algo_r
             "mf_fastmm_ws", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read", "mf_batch_create",
             "mf_batch_workspace_bytes", "mf_batch_run", "mf_batch_aborted", "mf_batch_tasks", "mf_batch_free",
             "mf_server_create", "mf_server_need_bytes", "mf_server_submit", "mf_server_replay", "mf_server_drain",
-            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform", "mf_autotune_batch", "mf_plan_query"]
+            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform", "mf_autotune_batch", "mf_plan_query", "mf_batch_phases"]
 
 
 class ServerConfig(ctypes.Structure):
@@ -89,6 +89,7 @@ def _load():
         "mf_batch_run": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P, ctypes.c_size_t, P], I),
         "mf_batch_aborted": ([P, ctypes.POINTER(I)], I),
         "mf_batch_tasks": ([P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_int32)], I),
+        "mf_batch_phases": ([P, ctypes.POINTER(I), ctypes.POINTER(ctypes.c_int32)], I),
         "mf_batch_free": ([P], None),
         "mf_server_create": ([ctypes.POINTER(ServerConfig), P, AP], I),
         "mf_server_need_bytes": ([P, I64, I, ctypes.POINTER(ctypes.c_size_t)], I),
@@ -296,6 +297,14 @@ class Batch:
         desc = np.zeros((nt.value, 5), dtype=np.int32)
         _check(lib.mf_batch_tasks(self._h, None, None, desc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return nt.value, nc.value, desc
+
+    def phases(self):
+        """int32 array [nphases, 3]: first task, end task, 1 for a GEMM phase."""
+        npz = ctypes.c_int()
+        _check(lib.mf_batch_phases(self._h, ctypes.byref(npz), None))
+        desc = np.zeros((npz.value, 3), dtype=np.int32)
+        _check(lib.mf_batch_phases(self._h, ctypes.byref(npz), desc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return desc
 
     def aborted(self) -> bool:
         flag = ctypes.c_int()

@@ -1,4 +1,4 @@
-"""Host-side checks of the batched persistent launch's task graph.
+"""Host-side checks of the batched form's task graph.
 
 The library exports the task list (type, instance, wait counter, wait value,
 done counter) in launch order.  These tests check, on the CPU, that the order
@@ -132,3 +132,62 @@ def test_batch_workspace_and_validation():
     with pytest.raises(mf.MFError) as e:
         mf.mf_batch_create([256], [None], [0], [0], mf.MF_F32 | mf.MF_LEAF_BF16)
     assert e.value.status == mf.MF_ERR_UNSUPPORTED
+
+
+def check_phases(desc, phases):
+    """The phases partition the task list, each holds one task type, and every
+    task's input stage is produced entirely by earlier phases (launch order
+    on the stream is then enough: no waits inside a launch)."""
+    assert len(phases) >= 1 and phases[0][0] == 0 and phases[-1][1] == len(desc)
+    phase_of = np.empty(len(desc), dtype=np.int64)
+    for p, (beg, end, gemm) in enumerate(phases):
+        assert beg < end
+        if p:
+            assert beg == phases[p - 1][1]
+        assert set(desc[beg:end, 0].tolist()) == {1 if gemm else 0}
+        phase_of[beg:end] = p
+    last_phase_of_ctr = {}
+    for t, (typ, inst, wc, wv, dc) in enumerate(desc):
+        last_phase_of_ctr[dc] = max(last_phase_of_ctr.get(dc, -1), phase_of[t])
+    for t, (typ, inst, wc, wv, dc) in enumerate(desc):
+        if wc >= 0:
+            assert last_phase_of_ctr[wc] < phase_of[t], (t, wc)
+    return phase_of
+
+
+@pytest.mark.parametrize("seed", [30, 31, 32])
+def test_phases_order_dependencies(seed):
+    b, sizes = make_batch(seed=seed, count=24)
+    nt, nctr, desc = b.tasks()
+    phases = b.phases()
+    check_phases(desc, phases)
+    # exactly one GEMM phase, after every pre-addition phase and before every post-addition phase
+    gemm = [p for p, ph in enumerate(phases) if ph[2] == 1]
+    assert len(gemm) == 1
+
+
+def test_phase_check_catches_a_misplaced_task():
+    b, _ = make_batch(seed=33, count=12)
+    nt, nctr, desc = b.tasks()
+    phases = b.phases().copy()
+    # plant: move the GEMM phase boundary one task earlier, so a pre-addition task is
+    # taken as GEMM work (type mismatch) -- the check must reject it
+    g = int(np.flatnonzero(phases[:, 2] == 1)[0])
+    if g > 0:
+        phases[g - 1, 1] -= 1
+        phases[g, 0] -= 1
+        with pytest.raises(AssertionError):
+            check_phases(desc, phases)
+    # plant: the last addition task (a post-addition chunk) waits on its own stage
+    # counter, which tasks of its own phase produce -- the check must reject it
+    bad = desc.copy()
+    post = int(np.flatnonzero(bad[:, 0] == 0)[-1])
+    bad[post, 2] = bad[post, 4]
+    with pytest.raises(AssertionError):
+        check_phases(bad, b.phases())
+
+
+def test_classical_only_batch_is_one_gemm_phase():
+    b = mf.mf_batch_create([256, 640, 1024], [None] * 3, [0] * 3, [0] * 3, mf.MF_F64)
+    phases = b.phases()
+    assert phases.tolist() == [[0, 4 + 25 + 64, 1]]

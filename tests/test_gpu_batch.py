@@ -1,5 +1,6 @@
-"""GPU parity of the batched persistent launch: many products of different
-sizes, algorithms and depths in one launch, against the CPU oracle."""
+"""GPU parity of the batched form: many products of different sizes,
+algorithms and depths, run as one launch per phase over all instances,
+against the CPU oracle and against standalone products."""
 import numpy as np
 import pytest
 

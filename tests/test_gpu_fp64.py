@@ -209,11 +209,11 @@ def test_full_size_sampled_rows(n, name, depth):
     assert np.isfinite(got).all()
 
 
-# ------------------------------------------------- large-tile GEMM (256 x 128)
-# The 256 x 128 tile kernel runs where its work items fill whole rounds of the
-# CUs: classical n = 4000, 4001 (masked edge tiles: valid extent 4000 / 4001
-# inside a 4096 leaf) and 4096 (interior), and the depth-1 product at 8192.
-# n = 6144 (classical and depth 1) takes the 128 x 128 kernel at the same sizes.
+# ------------------------------------------------------------- large leaves
+# Full-size exactness of the GEMM on large leaves: classical n = 4000, 4001
+# (masked edge tiles: valid extent 4000 / 4001 inside a 4096 leaf), 4096 and
+# 6144 (interior), and depth-1 products at 6144 and 8192; every sampled row and
+# column, including the first and the last, is compared exactly.
 @pytest.mark.parametrize("n", [4000, 4001, 4096, 6144])
 def test_large_tile_classical_int_exact_rows(n):
     A = mi.int_uniform(n, 60).astype(np.float64)

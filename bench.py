@@ -414,6 +414,7 @@ def run_serving(args):
     mu = count / t_serial
     plain = replay(1, None, {}, zeros)
     t_plain = plain["t_done"].max() - plain["t_admit"].min()
+    big = np.asarray(ns) >= SERVE_POLICY["depth_min_n_f64"][0]
 
     def summary(st, arrivals_start):
         lat = (st["t_done"] - st["t_arrive"]) * 1e3
@@ -440,6 +441,10 @@ def run_serving(args):
                                f"(seeds {SERVE_ARRIVAL_SEED}+k), {SERVE_SLOTS} slots, budget {SERVE_BUDGET >> 30} GiB",
                    "policy": SERVE_POLICY},
         "serial_fast_s": round(t_serial, 4), "serial_classical_s": round(t_plain, 4),
+        "serial_device_s": {"fast": round(float(ser["device_ms"].sum()) / 1e3, 4),
+                            "classical": round(float(plain["device_ms"].sum()) / 1e3, 4),
+                            "fast_on_fast_plans": round(float(ser["device_ms"][big].sum()) / 1e3, 4),
+                            "classical_on_same_requests": round(float(plain["device_ms"][big].sum()) / 1e3, 4)},
         "mu_serial_rps": round(mu, 2), "rates": rates,
     }
     if not args.no_cpu_baseline:

@@ -231,7 +231,8 @@ mf_status mf_autotune_batch(int nsizes, const int64_t* n, int dtype, const mf_al
  * slots (HIP streams) is free and the HBM it needs (A, B, C and the
  * temporaries of its plan) fits in what remains of hbm_budget
  * (allow_overtake lets later requests that fit pass a blocked head).  An
- * admitted request allocates its memory from the stream-ordered pool,
+ * admitted request allocates its memory from the server's own stream-ordered
+ * pool (which keeps freed memory reserved for later requests),
  * generates A and B on the device from its seed (mf_fill_uniform with seeds
  * 2*seed and 2*seed+1), runs its product and releases its memory, all on its
  * slot's stream, so requests on different slots overlap.  The plan is a pure
@@ -267,6 +268,10 @@ mf_status mf_server_drain(mf_server* s);
  * size and depth used; *count = number of requests. */
 mf_status mf_server_stats(mf_server* s, int64_t* count, double* t_arrive, double* t_admit, double* t_done, int64_t* n,
                           int* depth);
+/* Per request (in id order): device time in ms from the start of its first
+ * operation on its slot's stream to its completion, -1 if not done; ms must
+ * hold as many entries as mf_server_stats reports requests. */
+mf_status mf_server_device_ms(mf_server* s, double* ms);
 /* Stop the worker after the queue drains and release the server. */
 void mf_server_free(mf_server* s);
 

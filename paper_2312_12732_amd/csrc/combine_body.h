@@ -98,6 +98,73 @@ __device__ __forceinline__ void combine_body(const CombArgs<T>& g, const CombSet
   }
 }
 
+// The same combination with the outputs held in registers and the inputs
+// streamed through them, for sets with many inputs and few outputs (the
+// post-addition of a composed algorithm: 49 inputs, 16 outputs).  Each output
+// is formed exactly as above: its first nonzero term c_k * in_k, then
+// fused multiply-adds in ascending k, so both bodies give identical bits.
+template <class T, int NIN, int NOUT, int VEC, bool FULL>
+__device__ __forceinline__ void combine_acc_body(const CombArgs<T>& g, const CombSet& set, int i, int j) {
+  typedef T tv __attribute__((ext_vector_type(VEC)));
+  const CombIn* ins = g.ins + set.in_beg;
+  const int nout = set.out_end - set.out_beg;
+  int coef_off[NOUT];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) coef_off[o] = o < nout ? load_uniform(g.outs + set.out_beg + o).coef_off : 0;
+  tv acc[NOUT];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) acc[o] = (tv)(T(0));
+  uint32_t started = 0;  // bit o: output o has its first term (wave-uniform)
+  for (int k = 0; k < NIN; ++k) {
+    const CombIn v = load_uniform(ins + k);
+    const T* p = comb_src(g, v.src) + v.off + (int64_t)i * v.ld + j;
+    tv x;
+    if (FULL) {
+      x = *reinterpret_cast<const tv*>(p);
+    } else {
+      const bool vec = v.src == SRC_WS || g.vec_in;
+      if (vec && i < v.vr && j + VEC <= v.vc) {
+        x = *reinterpret_cast<const tv*>(p);
+      } else {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) x[q] = (i < v.vr && j + q < v.vc) ? p[q] : T(0);
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      const T ck = o < nout ? (T)load_uniform(g.coef + coef_off[o] + k) : T(0);
+      if (ck != T(0)) {
+        if (!(started >> o & 1u)) {
+          acc[o] = ck == T(1) ? x : ck * x;
+          started |= 1u << o;
+        } else {
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) acc[o][q] = fma_t(ck, x[q], acc[o][q]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    if (o >= nout) continue;
+    const CombOut po = load_uniform(g.outs + set.out_beg + o);
+    T* p = comb_dst(g, po.dst) + po.off + (int64_t)i * po.ld + j;
+    if (FULL) {
+      *reinterpret_cast<tv*>(p) = acc[o];
+    } else {
+      if (i >= po.vr) continue;
+      const bool vec = po.dst == SRC_WS || g.vec_out;
+      if (vec && j + VEC <= po.vc) {
+        *reinterpret_cast<tv*>(p) = acc[o];
+      } else {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q)
+          if (j + q < po.vc) p[q] = acc[o][q];
+      }
+    }
+  }
+}
+
 // Number of inputs of a set, as a compile-time dispatch: calls
 // f(std::integral_constant<int, NIN>) for the supported counts.
 template <class F>

@@ -26,6 +26,21 @@ __global__ void __launch_bounds__(256) combine(CombArgs<T> g) {
     combine_body<T, NIN, VEC, false>(g, set, i, j);
 }
 
+// Outputs in registers, inputs streamed (many inputs, at most NOUT outputs
+// per set).
+template <class T, int NIN, int NOUT, int VEC>
+__global__ void __launch_bounds__(256) combine_acc(CombArgs<T> g) {
+  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  const int64_t mm = (int64_t)g.m * g.m;
+  if (e >= mm) return;
+  const int i = (int)(e / g.m), j = (int)(e % g.m);
+  const CombSet set = load_uniform(g.sets + blockIdx.y);
+  if (set.full && g.vec_in && g.vec_out)
+    combine_acc_body<T, NIN, NOUT, VEC, true>(g, set, i, j);
+  else
+    combine_acc_body<T, NIN, NOUT, VEC, false>(g, set, i, j);
+}
+
 #ifndef MF_COMB_VEC_SMALL
 #define MF_COMB_VEC_SMALL 4
 #endif
@@ -48,6 +63,26 @@ static hipError_t launch_combine_t(const CombineStage& cs, const void* A, const 
   g.vec_out = vec_out ? 1 : 0;
   const int64_t mm = cs.m * cs.m;
   auto grid = [&](int vec) { return dim3((unsigned)((mm / vec + 255) / 256), (unsigned)cs.sets.size(), 1); };
+  // many inputs, few outputs: outputs in registers, inputs streamed with wide loads
+  if (cs.nin >= 27 && cs.nout_max <= 16) {
+    switch (cs.nin) {
+#define MF_COMB_ACC_CASE(N, NO)                                                                   \
+  case N:                                                                                         \
+    if (cs.nout_max <= NO) {                                                                      \
+      hipLaunchKernelGGL((combine_acc<T, N, NO, 4>), grid(4), dim3(256), 0, s, g);                \
+      return hipGetLastError();                                                                   \
+    }                                                                                             \
+    break;
+      MF_COMB_ACC_CASE(27, 9)
+      MF_COMB_ACC_CASE(36, 9)
+      MF_COMB_ACC_CASE(49, 16)
+      MF_COMB_ACC_CASE(64, 16)
+      MF_COMB_ACC_CASE(81, 9)
+#undef MF_COMB_ACC_CASE
+      default:
+        break;
+    }
+  }
   switch (cs.nin) {
 #define MF_COMB_CASE(N, V) \
   case N: hipLaunchKernelGGL((combine<T, N, V>), grid(V), dim3(256), 0, s, g); break;

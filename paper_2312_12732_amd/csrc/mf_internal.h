@@ -112,6 +112,7 @@ struct CombSet {
 // blockIdx.y.
 struct CombineStage {
   int nin = 0;
+  int nout_max = 0;  // most outputs of any set
   int64_t m = 0;
   std::vector<CombSet> sets;
   std::vector<CombIn> ins;
@@ -216,9 +217,19 @@ struct BatchTask {
 
 // Builds (or fetches from the cache) the plan for a request.  Outer levels
 // are split into groups while the grouped GEMM has fewer than min_wg
-// workgroups (a standalone launch wants to fill the GPU; a batch does not).
+// workgroups.  A standalone product takes every level as an outer level:
+// each leaf product is stored once and the post-additions run as separate
+// HBM-bound launches.  Fusing inner post-additions into the GEMM epilogue
+// moves fewer bytes but its read-modify-writes stall the MFMA pipes; on
+// MI355X at n = 8192 (FP64 Winograd) storing every product is faster at
+// depth 1 / 2 / 3: 14.82 / 14.30 / 15.05 ms against 15.13 / 14.86 / 16.23 ms
+// with outer levels only until 1024 workgroups.  A batch (min_wg 0) fuses
+// every level into the epilogue.
 // Returns an mf_status and sets the thread's error message on failure.
-constexpr int64_t kStandaloneMinWorkgroups = 1024;
+#ifndef MF_STANDALONE_MIN_WG
+#define MF_STANDALONE_MIN_WG (int64_t(1) << 62)
+#endif
+constexpr int64_t kStandaloneMinWorkgroups = MF_STANDALONE_MIN_WG;
 mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg,
                    std::shared_ptr<const Plan>* out);
 

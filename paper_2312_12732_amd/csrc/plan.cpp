@@ -9,6 +9,8 @@
 #include <mutex>
 #include <tuple>
 
+#include <algorithm>
+
 #include "mf_internal.h"
 
 namespace mf {
@@ -75,6 +77,7 @@ void finish_set(CombineStage* st, CombSet set) {
   }
   for (int o = set.out_beg; o < set.out_end; ++o) full = full && st->outs[o].vr == st->m && st->outs[o].vc == st->m;
   set.full = full ? 1 : 0;
+  st->nout_max = std::max(st->nout_max, set.out_end - set.out_beg);
   st->sets.push_back(set);
 }
 

@@ -95,6 +95,7 @@ struct Req {
   int slot = -1;
   mf_status status = MF_OK;
   bool done = false;
+  double device_ms = -1;  // from the request's first launch to its completion, on its stream
 };
 
 size_t round256(size_t x) { return (x + 255) / 256 * 256; }
@@ -105,7 +106,9 @@ struct mf_server {
   mf_server_config cfg;
   const mf_algo* algo = nullptr;
   std::vector<hipStream_t> streams;
-  std::vector<hipEvent_t> events;
+  std::vector<hipEvent_t> events;        // completion, per slot
+  std::vector<hipEvent_t> start_events;  // start of the request's device work, per slot
+  hipMemPool_t pool = nullptr;           // request memory; keeps what it has reserved
   std::vector<int64_t> slot_req;  // request id per slot, -1 if free
   std::mutex mu;
   std::condition_variable cv;
@@ -152,7 +155,8 @@ mf_status launch_request(mf_server* s, Req& r) {
   const size_t elem = (r.dtype & 0xff) == MF_F64 ? 8 : 4;
   const size_t mat = round256((size_t)r.n * (size_t)r.n * elem);
   char* mem = nullptr;
-  if (hipMallocAsync(reinterpret_cast<void**>(&mem), r.need, st) != hipSuccess || !mem) {
+  if (hipEventRecord(s->start_events[r.slot], st) != hipSuccess) return fail(MF_ERR_HIP, "start event failed");
+  if (hipMallocFromPoolAsync(reinterpret_cast<void**>(&mem), r.need, s->pool, st) != hipSuccess || !mem) {
     (void)hipGetLastError();
     return fail(MF_ERR_NOMEM, "request allocation failed");
   }
@@ -195,6 +199,9 @@ void worker_loop(mf_server* s) {
       Req& r = s->reqs[id];
       r.t_done = now_s() - s->t0;
       if (q != hipSuccess && r.status == MF_OK) r.status = MF_ERR_HIP;
+      float ms = 0.f;
+      if (q == hipSuccess && hipEventElapsedTime(&ms, s->start_events[k], s->events[k]) == hipSuccess)
+        r.device_ms = ms;
       r.done = true;
       s->adm.release(id);
       s->slot_req[k] = -1;
@@ -241,17 +248,34 @@ mf_status mf_server_create(const mf_server_config* cfg, const mf_algo* algo, mf_
   if (!s) return fail(MF_ERR_NOMEM, "host allocation failed");
   s->algo = algo;
   (void)hipGetDevice(&s->device);
+  // A pool of its own for request memory: with the release threshold at its
+  // maximum, memory freed by finished requests stays reserved for the next
+  // ones instead of being returned to the driver and mapped again.
+  hipMemPoolProps props{};
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = s->device;
+  uint64_t keep = UINT64_MAX;
+  if (hipMemPoolCreate(&s->pool, &props) != hipSuccess ||
+      hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+    (void)hipGetLastError();
+    s->pool = nullptr;
+    mf_server_free(s);
+    return fail(MF_ERR_HIP, "memory pool creation failed");
+  }
   for (int k = 0; k < cfg->max_slots; ++k) {
     hipStream_t st;
-    hipEvent_t ev;
+    hipEvent_t ev, ev0;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreate(&ev) != hipSuccess || hipEventCreate(&ev0) != hipSuccess) {
       (void)hipGetLastError();
       mf_server_free(s);
       return fail(MF_ERR_HIP, "stream creation failed");
     }
     s->streams.push_back(st);
     s->events.push_back(ev);
+    s->start_events.push_back(ev0);
     s->slot_req.push_back(-1);
   }
   s->t0 = now_s();
@@ -349,9 +373,20 @@ void mf_server_free(mf_server* s) {
     s->cv.notify_all();
   }
   if (s->worker.joinable()) s->worker.join();
+  for (auto& st : s->streams) (void)hipStreamSynchronize(st);
   for (auto& e : s->events) (void)hipEventDestroy(e);
+  for (auto& e : s->start_events) (void)hipEventDestroy(e);
   for (auto& st : s->streams) (void)hipStreamDestroy(st);
+  if (s->pool) (void)hipMemPoolDestroy(s->pool);
   delete s;
+}
+
+mf_status mf_server_device_ms(mf_server* s, double* ms) {
+  clear_error();
+  if (!s || !ms) return fail(MF_ERR_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (size_t k = 0; k < s->reqs.size(); ++k) ms[k] = s->reqs[k].device_ms;
+  return MF_OK;
 }
 
 mf_status mf_fill_uniform(void* p, int64_t count, int dtype, uint64_t seed, mf_stream stream) {

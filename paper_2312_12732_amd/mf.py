@@ -39,7 +39,7 @@ EXPORTED = ["mf_algo_from_uvw", "mf_algo_builtin", "mf_algo_compose", "mf_algo_r
             "mf_fastmm_ws", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read", "mf_batch_create",
             "mf_batch_workspace_bytes", "mf_batch_run", "mf_batch_aborted", "mf_batch_tasks", "mf_batch_free",
             "mf_server_create", "mf_server_need_bytes", "mf_server_submit", "mf_server_replay", "mf_server_drain",
-            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform", "mf_autotune_batch", "mf_plan_query", "mf_batch_phases"]
+            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform", "mf_autotune_batch", "mf_plan_query", "mf_batch_phases", "mf_server_device_ms"]
 
 
 class ServerConfig(ctypes.Structure):
@@ -98,6 +98,7 @@ def _load():
         "mf_server_drain": ([P], I),
         "mf_server_stats": ([P, LP, DP, DP, DP, LP, ctypes.POINTER(I)], I),
         "mf_server_free": ([P], None),
+        "mf_server_device_ms": ([P, DP], I),
         "mf_admission_simulate": ([I, DP, DP, ctypes.POINTER(ctypes.c_size_t), I, ctypes.c_size_t, I, DP, DP,
                                    ctypes.POINTER(ctypes.c_size_t)], I),
         "mf_fill_uniform": ([P, I64, I, ctypes.c_uint64, P], I),
@@ -434,7 +435,9 @@ class Server:
         _check(lib.mf_server_stats(self._h, ctypes.byref(cnt), _dptr(ta), _dptr(tm), _dptr(td),
                                    nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                    dp.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
-        return {"t_arrive": ta, "t_admit": tm, "t_done": td, "n": nn, "depth": dp}
+        dev = np.zeros(c)
+        _check(lib.mf_server_device_ms(self._h, _dptr(dev)))
+        return {"t_arrive": ta, "t_admit": tm, "t_done": td, "n": nn, "depth": dp, "device_ms": dev}
 
 
 def mf_admission_simulate(t_arrive, service, need, slots, budget, allow_overtake=False):

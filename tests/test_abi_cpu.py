@@ -118,14 +118,15 @@ def test_rebase_rejects_singular():
     assert e.value.status == mf.MF_ERR_ARG
 
 
-def expected_ws(n, depth, mat_u, mat_v, R=7, p=2):
+def expected_ws(n, depth, mat_u, mat_v, R=7, p=2, min_wg=1 << 62):
     """Closed form of the executor's workspace (elements of 8 bytes):
     level l of the pre-additions materialises mat_u + mat_v children of each
     of the R^(l-1) parents, each of size (n'/p^l)^2 (n' = p^d * m, m = n/p^d
     rounded up to the 128 tile); when the (m/128)^2 tile positions times
-    R^lo groups first reach 1024 workgroups at lo outer levels, every group
-    keeps a result block of size (m p^(d-lo))^2 and every post-addition
-    parent below the top one a block p times larger."""
+    R^lo groups first reach min_wg workgroups at lo outer levels (a
+    standalone product takes every level: lo = d), every group keeps a result
+    block of size (m p^(d-lo))^2 and every post-addition parent below the
+    top one a block p times larger."""
     size, d = n, 0
     while d < depth and size > 128 and R ** (d + 1) <= 1 << 16:
         size, d = -(-size // p), d + 1
@@ -139,7 +140,7 @@ def expected_ws(n, depth, mat_u, mat_v, R=7, p=2):
         elems += (mat_u + mat_v) * R ** (lev - 1) * s * s
     pos = (m // 128) ** 2
     lo = 0
-    while lo < depth and pos * R ** lo < 1024:
+    while lo < depth and pos * R ** lo < min_wg:
         lo += 1
     if lo:
         mo = m * p ** (depth - lo)
@@ -153,15 +154,17 @@ def expected_ws(n, depth, mat_u, mat_v, R=7, p=2):
 
 def test_workspace_bytes_closed_form():
     s = mf.mf_algo_builtin("strassen")
-    # depth 1: 4 materialised T and 4 materialised S of (n/2)^2 doubles
-    assert mf.mf_workspace_bytes(s, 1, 0, 8192) == 8 * 4096 ** 2 * 8 == expected_ws(8192, 1, 4, 4)
+    # depth 1: 4 materialised T and 4 materialised S of (n/2)^2 doubles, and the
+    # 7 stored products of (n/2)^2
+    assert mf.mf_workspace_bytes(s, 1, 0, 8192) == 8 * (8 + 7) * 4096 ** 2 == expected_ws(8192, 1, 4, 4)
     # depth 2: level 1 (4 + 4 blocks of (n/2)^2), level 2 (7 x (4 + 4) blocks of
-    # (n/4)^2), plus 7 group results of (n/2)^2
-    assert mf.mf_workspace_bytes(s, 2, 0, 8192) == 8 * (8 * 4096 ** 2 + 56 * 2048 ** 2 + 7 * 4096 ** 2)
+    # (n/4)^2), the 49 products of (n/4)^2 and 7 level-1 parents of (n/2)^2
+    assert mf.mf_workspace_bytes(s, 2, 0, 8192) == 8 * (8 * 4096 ** 2 + 56 * 2048 ** 2 + 49 * 2048 ** 2
+                                                         + 7 * 4096 ** 2)
     assert mf.mf_workspace_bytes(s, 2, 0, 8192) == expected_ws(8192, 2, 4, 4)
-    # depth 3: 49 group results of (n/4)^2 and 7 level-2 parents of (n/2)^2
+    # depth 3: 343 products of (n/8)^2, 49 level-2 parents of (n/4)^2 and 7 level-1 parents of (n/2)^2
     assert mf.mf_workspace_bytes(s, 3, 0, 8192) == 8 * (8 * 4096 ** 2 + 56 * 2048 ** 2 + 392 * 1024 ** 2
-                                                         + 49 * 2048 ** 2 + 7 * 4096 ** 2)
+                                                         + 343 * 1024 ** 2 + 49 * 2048 ** 2 + 7 * 4096 ** 2)
     assert mf.mf_workspace_bytes(s, 3, 0, 8192) == expected_ws(8192, 3, 4, 4)
     # ragged: n = 1000, leaf size rounded up to the 128 tile (500 -> 512)
     assert mf.mf_workspace_bytes(s, 1, 0, 1000) == expected_ws(1000, 1, 4, 4)
@@ -186,10 +189,11 @@ def test_workspace_bytes_closed_form():
 
 def test_workspace_bytes_paper_size_24012():
     # The paper's largest size (Section 3.2): 24012^2 doubles ~ 4.6 GB per
-    # matrix.  This executor materialises 4 + 4 blocks at depth 1.
+    # matrix.  This executor materialises 4 + 4 blocks and stores the 7
+    # products at depth 1.
     s = mf.mf_algo_builtin("strassen")
     m = 128 * -(-12006 // 128)
-    assert mf.mf_workspace_bytes(s, 1, 0, 24012) == 8 * m * m * 8
+    assert mf.mf_workspace_bytes(s, 1, 0, 24012) == 8 * (8 + 7) * m * m
 
 
 def _call_fastmm(algo, depth, cutoff, A, B, C, n, dtype):

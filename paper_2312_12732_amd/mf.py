@@ -11,6 +11,11 @@ import ctypes
 import os
 
 import numpy as np
+# PyTorch for ROCm ships its own copy of the HIP runtime.  Loading torch before
+# libmf.so makes the library bind to that copy, so the process holds ONE HIP
+# runtime; loaded the other way round, the library would bring up a second
+# runtime next to torch's, whose streams and events it cannot use.
+import torch  # noqa: F401  (must precede the CDLL load below)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmf.so")

@@ -226,19 +226,19 @@ mf_status mf_autotune_batch(int nsizes, const int64_t* n, int dtype, const mf_al
                             int* out_choice, double* out_ms);
 
 /* ---- Serving -----------------------------------------------------------------
- * A request loop for fast-multiply requests of different sizes.  Requests
- * wait in a FIFO queue; the head request is admitted when one of max_slots
- * slots (HIP streams) is free and the HBM it needs (A, B, C and the
- * temporaries of its plan) fits in what remains of hbm_budget
- * (allow_overtake lets later requests that fit pass a blocked head).  An
- * admitted request allocates its memory from the server's own stream-ordered
- * pool (which keeps freed memory reserved for later requests),
- * generates A and B on the device from its seed (mf_fill_uniform with seeds
- * 2*seed and 2*seed+1), runs its product and releases its memory, all on its
- * slot's stream, so requests on different slots overlap.  The plan is a pure
- * function of (n, dtype): depth k+1 is used when n >= depth_min_n_*[k]
- * (0 disables a level; algo NULL means classical only); results are
- * therefore identical alone and among other requests. */
+ * A request loop for fast-multiply requests of different sizes.  The server
+ * owns one device arena of hbm_budget bytes.  Requests wait in a FIFO queue;
+ * the head request is admitted when one of max_slots slots (HIP streams) is
+ * free and the HBM it needs (A, B, C and the temporaries of its plan) fits in
+ * the arena as one block, first fit (allow_overtake lets later requests that
+ * fit pass a blocked head).  An admitted request generates A and B in its
+ * block on the device from its seed (mf_fill_uniform with seeds 2*seed and
+ * 2*seed+1), runs its product and copies C out if asked, all on its slot's
+ * stream, so requests on different slots overlap; its block is released when
+ * its completion is observed.  The plan is a pure function of (n, dtype):
+ * depth k+1 is used when n >= depth_min_n_*[k] (0 disables a level; algo
+ * NULL means classical only); results are therefore identical alone and among
+ * other requests. */
 typedef struct {
   int max_slots;                /* 1..64 concurrent requests */
   size_t hbm_budget;            /* bytes for all admitted requests together */
@@ -248,8 +248,9 @@ typedef struct {
 } mf_server_config;
 typedef struct mf_server mf_server;
 
-/* Start a server (a worker thread and max_slots streams on the current
- * device).  algo (may be NULL) must outlive the server. */
+/* Start a server (a worker thread, max_slots streams and the arena on the
+ * current device; MF_ERR_NOMEM if the arena cannot be allocated).  algo (may
+ * be NULL) must outlive the server. */
 mf_status mf_server_create(const mf_server_config* cfg, const mf_algo* algo, mf_server** out);
 /* HBM bytes a request of this size and dtype is admitted against. */
 mf_status mf_server_need_bytes(const mf_server* s, int64_t n, int dtype, size_t* bytes);
@@ -275,9 +276,10 @@ mf_status mf_server_device_ms(mf_server* s, double* ms);
 /* Stop the worker after the queue drains and release the server. */
 void mf_server_free(mf_server* s);
 
-/* Host-only simulation of the admission controller with given arrival
- * times, service times and HBM needs (for tests and capacity planning):
- * fills admission and completion times and the peak budget in use. */
+/* Host-only simulation of the admission controller (the same policy and
+ * first-fit arena as the server) with given arrival times, service times and
+ * HBM needs (for tests and capacity planning): fills admission and
+ * completion times and the peak arena bytes in use. */
 mf_status mf_admission_simulate(int count, const double* t_arrive, const double* service, const size_t* need,
                                 int slots, size_t budget, int allow_overtake, double* t_admit, double* t_done,
                                 size_t* peak_used);

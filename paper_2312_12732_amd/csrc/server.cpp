@@ -1,18 +1,21 @@
 // Serving runtime: a request loop that runs fast-multiply requests of
 // different sizes as they arrive.  Requests wait in a FIFO queue; the
 // admission controller admits the head request when a slot (a HIP stream) is
-// free and the HBM it needs - operands, output and temporaries - fits in the
-// remaining budget.  An admitted request allocates its memory from the
-// stream-ordered pool, generates its operands on the device from its seed,
-// runs mf_fastmm_ws with the plan chosen by a pure function of (n, dtype) and
-// releases its memory, all on its slot's stream; requests on different slots
-// overlap on the device.  A worker thread admits and polls completions; an
-// optional replay thread submits requests at given arrival times.
+// free and the HBM it needs - operands, output and temporaries - fits as one
+// block in the server's device arena (first fit).  An admitted request
+// generates its operands in its block on the device from its seed, runs
+// mf_fastmm_ws with the plan chosen by a pure function of (n, dtype), all on
+// its slot's stream; requests on different slots overlap on the device, and a
+// block is released when its request's completion is observed.  A worker
+// thread admits and polls completions; an optional replay thread submits
+// requests at given arrival times.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <iterator>
+#include <map>
 #include <mutex>
 #include <thread>
 
@@ -22,21 +25,70 @@ namespace mf {
 
 hipError_t launch_fill_uniform(void* p, int64_t count, int elem, uint64_t seed, hipStream_t s);
 
-// FIFO admission by free slots and HBM budget (host only).
+// Host-side bookkeeping of a device arena [0, size): first-fit allocation of
+// 256-byte aligned blocks, coalescing on release.
+class Arena {
+ public:
+  explicit Arena(size_t size) : size_(size) {
+    if (size_ > 0) free_[0] = size_;
+  }
+  bool alloc(size_t need, size_t* off) {
+    need = (need + 255) / 256 * 256;
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= need) {
+        *off = it->first;
+        const size_t rest = it->second - need, at = it->first + need;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        used_ += need;
+        return true;
+      }
+    return false;
+  }
+  void release(size_t off, size_t need) {
+    need = (need + 255) / 256 * 256;
+    used_ -= need;
+    auto it = free_.emplace(off, need).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+
+ private:
+  size_t size_;
+  size_t used_ = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+};
+
+// FIFO admission by free slots and HBM (host only).  A request is admitted
+// when a slot is free and its memory fits, as one block, in the arena of
+// budget bytes; the same policy drives the server and the simulation.
 class Admission {
  public:
-  Admission(int slots, size_t budget, bool overtake) : slots_(slots), budget_(budget), overtake_(overtake) {}
-  void arrive(int64_t id, size_t need) { queue_.push_back({id, need}); }
-  // Admits what fits now, in arrival order; returns the admitted ids.
-  std::vector<int64_t> admit() {
-    std::vector<int64_t> out;
+  Admission(int slots, size_t budget, bool overtake) : slots_(slots), arena_(budget), overtake_(overtake) {}
+  void arrive(int64_t id, size_t need) { queue_.push_back({id, need, 0}); }
+  // Admits what fits now, in arrival order; returns (id, arena offset) pairs.
+  std::vector<std::pair<int64_t, size_t>> admit() {
+    std::vector<std::pair<int64_t, size_t>> out;
     for (auto it = queue_.begin(); it != queue_.end();) {
       if (busy_ >= slots_) break;
-      if (used_ + it->need <= budget_) {
-        used_ += it->need;
+      size_t off = 0;
+      if (arena_.alloc(it->need, &off)) {
         ++busy_;
+        it->off = off;
         held_.push_back(*it);
-        out.push_back(it->id);
+        out.push_back({it->id, off});
         it = queue_.erase(it);
       } else if (overtake_) {
         ++it;
@@ -49,13 +101,13 @@ class Admission {
   void release(int64_t id) {
     for (auto it = held_.begin(); it != held_.end(); ++it)
       if (it->id == id) {
-        used_ -= it->need;
+        arena_.release(it->off, it->need);
         --busy_;
         held_.erase(it);
         return;
       }
   }
-  size_t used() const { return used_; }
+  size_t used() const { return arena_.used(); }
   int busy() const { return busy_; }
   size_t waiting() const { return queue_.size(); }
 
@@ -63,11 +115,11 @@ class Admission {
   struct Item {
     int64_t id;
     size_t need;
+    size_t off;
   };
   int slots_;
-  size_t budget_;
+  Arena arena_;
   bool overtake_;
-  size_t used_ = 0;
   int busy_ = 0;
   std::deque<Item> queue_;
   std::vector<Item> held_;
@@ -93,6 +145,7 @@ struct Req {
   int depth = 0;
   double t_arrive = 0, t_admit = 0, t_done = 0;
   int slot = -1;
+  size_t off = 0;  // of its memory in the arena
   mf_status status = MF_OK;
   bool done = false;
   double device_ms = -1;  // from the request's first launch to its completion, on its stream
@@ -108,7 +161,7 @@ struct mf_server {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;        // completion, per slot
   std::vector<hipEvent_t> start_events;  // start of the request's device work, per slot
-  hipMemPool_t pool = nullptr;           // request memory; keeps what it has reserved
+  char* arena = nullptr;                 // hbm_budget bytes of device memory for admitted requests
   std::vector<int64_t> slot_req;  // request id per slot, -1 if free
   std::mutex mu;
   std::condition_variable cv;
@@ -154,12 +207,8 @@ mf_status launch_request(mf_server* s, Req& r) {
   hipStream_t st = s->streams[r.slot];
   const size_t elem = (r.dtype & 0xff) == MF_F64 ? 8 : 4;
   const size_t mat = round256((size_t)r.n * (size_t)r.n * elem);
-  char* mem = nullptr;
   if (hipEventRecord(s->start_events[r.slot], st) != hipSuccess) return fail(MF_ERR_HIP, "start event failed");
-  if (hipMallocFromPoolAsync(reinterpret_cast<void**>(&mem), r.need, s->pool, st) != hipSuccess || !mem) {
-    (void)hipGetLastError();
-    return fail(MF_ERR_NOMEM, "request allocation failed");
-  }
+  char* mem = s->arena + r.off;  // reserved by admission until the completion is observed
   void* A = mem;
   void* B = mem + mat;
   void* C = mem + 2 * mat;
@@ -178,7 +227,6 @@ mf_status launch_request(mf_server* s, Req& r) {
   if (res == MF_OK && r.host_out &&
       hipMemcpyAsync(r.host_out, C, (size_t)cnt * elem, hipMemcpyDeviceToHost, st) != hipSuccess)
     res = fail(MF_ERR_HIP, "result copy failed");
-  if (hipFreeAsync(mem, st) != hipSuccess && res == MF_OK) res = fail(MF_ERR_HIP, "request release failed");
   if (hipEventRecord(s->events[r.slot], st) != hipSuccess && res == MF_OK)
     res = fail(MF_ERR_HIP, "completion event failed");
   return res;
@@ -209,8 +257,10 @@ void worker_loop(mf_server* s) {
       s->cv.notify_all();
     }
     // admissions
-    for (int64_t id : s->adm.admit()) {
+    for (const auto& adm : s->adm.admit()) {
+      const int64_t id = adm.first;
       Req& r = s->reqs[id];
+      r.off = adm.second;
       int slot = -1;
       for (size_t k = 0; k < s->slot_req.size(); ++k)
         if (s->slot_req[k] < 0) {
@@ -248,21 +298,14 @@ mf_status mf_server_create(const mf_server_config* cfg, const mf_algo* algo, mf_
   if (!s) return fail(MF_ERR_NOMEM, "host allocation failed");
   s->algo = algo;
   (void)hipGetDevice(&s->device);
-  // A pool of its own for request memory: with the release threshold at its
-  // maximum, memory freed by finished requests stays reserved for the next
-  // ones instead of being returned to the driver and mapped again.
-  hipMemPoolProps props{};
-  props.allocType = hipMemAllocationTypePinned;
-  props.handleTypes = hipMemHandleTypeNone;
-  props.location.type = hipMemLocationTypeDevice;
-  props.location.id = s->device;
-  uint64_t keep = UINT64_MAX;
-  if (hipMemPoolCreate(&s->pool, &props) != hipSuccess ||
-      hipMemPoolSetAttribute(s->pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+  // One device arena of hbm_budget bytes holds every admitted request's
+  // memory; admission places a request in it (first fit), so requests never
+  // allocate or map device memory while the server runs.
+  if (hipMalloc(reinterpret_cast<void**>(&s->arena), cfg->hbm_budget) != hipSuccess) {
     (void)hipGetLastError();
-    s->pool = nullptr;
+    s->arena = nullptr;
     mf_server_free(s);
-    return fail(MF_ERR_HIP, "memory pool creation failed");
+    return fail(MF_ERR_NOMEM, "the HBM budget cannot be allocated on the device");
   }
   for (int k = 0; k < cfg->max_slots; ++k) {
     hipStream_t st;
@@ -377,7 +420,7 @@ void mf_server_free(mf_server* s) {
   for (auto& e : s->events) (void)hipEventDestroy(e);
   for (auto& e : s->start_events) (void)hipEventDestroy(e);
   for (auto& st : s->streams) (void)hipStreamDestroy(st);
-  if (s->pool) (void)hipMemPoolDestroy(s->pool);
+  if (s->arena) (void)hipFree(s->arena);
   delete s;
 }
 
@@ -435,9 +478,9 @@ mf_status mf_admission_simulate(int count, const double* t_arrive, const double*
         }
       }
     }
-    for (int64_t id : adm.admit()) {
-      t_admit[id] = now;
-      running.push_back({now + service[id], (int)id});
+    for (const auto& a : adm.admit()) {
+      t_admit[a.first] = now;
+      running.push_back({now + service[a.first], (int)a.first});
     }
     peak = std::max(peak, adm.used());
   }

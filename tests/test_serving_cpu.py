@@ -91,3 +91,28 @@ def test_counter_generator_matches_published_splitmix():
     assert v.min() >= -1.0 and v.max() < 1.0
     f = mi.counter_uniform(1000, 12345, np.float32)
     assert np.array_equal(f, v.astype(np.float32))
+
+
+def test_arena_fragmentation_blocks_fifo_head_until_space_coalesces():
+    # budget 3 MiB: A (offset 0), B (1 MiB) and C (2 MiB) fill it.  When B ends at t=1
+    # only its 1 MiB hole is free, so the 2 MiB request D waits; when A ends at t=5
+    # its block coalesces with B's hole into 2 MiB at offset 0 and D is admitted
+    mib = 1 << 20
+    t = [0.0, 0.0, 0.0, 0.1]
+    service = [5.0, 1.0, 9.0, 1.0]
+    need = [mib, mib, mib, 2 * mib]
+    ta, td, peak = mf.mf_admission_simulate(t, service, need, 4, 3 * mib)
+    assert ta[:3].tolist() == [0.0, 0.0, 0.0]
+    assert ta[3] == 5.0  # A's block (offset 0) and B's (offset 1 MiB) coalesce into 2 MiB
+    assert peak == 3 * mib
+
+
+def test_arena_first_fit_needs_contiguous_space():
+    # budget 4 MiB: A(1) B(1) C(1) D(1) fill it; B and D end, leaving two 1 MiB holes
+    # (2 MiB free, not contiguous); a 2 MiB request waits until C ends
+    mib = 1 << 20
+    t = [0.0, 0.0, 0.0, 0.0, 0.5]
+    service = [10.0, 1.0, 3.0, 1.0, 1.0]
+    need = [mib, mib, mib, mib, 2 * mib]
+    ta, td, _ = mf.mf_admission_simulate(t, service, need, 8, 4 * mib)
+    assert ta[4] == 3.0

@@ -18,6 +18,9 @@ Other workloads, each printing one JSON line of the same shape:
   --workload precision  FP32 storage, leaves FP32 / BF16 / split-BF16x3,
                         n = 8192 and 16384, depth 0..3, uniform and scaled
                         inputs: time, effective GFLOP/s and error vs the oracle
+  --workload copy       a plain 1 GiB device-to-device copy (the HBM reference
+                        that calibrates the rocprofv3 FETCH_SIZE / WRITE_SIZE
+                        counters)
   --workload algorithms FP64 at n = 4096 and 8192: Strassen (paper form) and
                         Strassen-Winograd at depth 1..3, <4,4,4;49>, a re-based
                         Strassen and the classical <3,3,3;27> control: time,
@@ -61,7 +64,7 @@ def parse():
     ap.add_argument("--depth", type=int, default=2)
     ap.add_argument("--cutoff", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("square", "batched", "serving", "precision", "algorithms"),
+    ap.add_argument("--workload", choices=("square", "batched", "serving", "precision", "algorithms", "copy"),
                     default="square")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per arrival rate")
     return ap.parse_args()
@@ -639,6 +642,25 @@ def run_algorithms(args):
     print(json.dumps(out), flush=True)
 
 
+def run_copy(args):
+    """A plain device copy of 1 GiB: achieved GB/s (read + write) and the
+    known byte counts the HBM counters are calibrated against."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    timed = timer(torch, torch.cuda.current_stream())
+    ms = timed(lambda: dst.copy_(src), max(1, args.steps), args.warmup)
+    gbs = 2 * nbytes / (ms * 1e-3) / 1e9
+    print(json.dumps({"metric": "device copy bandwidth (read + write)", "value": round(gbs, 1), "unit": "GB/s",
+                      "n_gpus": 1, "steps": max(1, args.steps), "warmup": args.warmup, "ms_per_step": round(ms, 4),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                      "data": "synthetic", "config": {"workload": "copy: 1 GiB device to device"},
+                      "bytes_read": nbytes, "bytes_written": nbytes}), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -654,6 +676,8 @@ def main():
         run_serving(args)
     elif args.workload == "precision":
         run_precision(args)
+    elif args.workload == "copy":
+        run_copy(args)
     else:
         run_algorithms(args)
 

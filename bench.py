@@ -4,8 +4,10 @@
 Default workload (``--workload square``): effective GFLOP/s = 2 n^3 / t of
 the fast FP64 product (Strassen-Winograd, depth 2) at n = 8192, next to the
 library's own classical FP64 MFMA GEMM, with inputs resident in HBM.  One
-step is one whole product C = A B (pre-additions, grouped leaf GEMM with
-fused post-additions, outer post-addition).
+step is one whole product C = A B: pre-additions, the grouped GEMM of the 49
+leaf products, post-additions.  The default schedule runs depth 2 as one
+level of the algorithm's Kronecker square <4,4,4;49> (--schedule fused);
+--schedule levels runs two levels of <2,2,2;7>.
 
 Other workloads, each printing one JSON line of the same shape:
   --workload batched    512 products, n log-uniform in [128, 2048] (multiples
@@ -63,6 +65,9 @@ def parse():
     ap.add_argument("--algo", default="winograd")
     ap.add_argument("--depth", type=int, default=2)
     ap.add_argument("--cutoff", type=int, default=0)
+    ap.add_argument("--schedule", choices=("fused", "levels"), default="fused",
+                    help="fused: the depth-d power of the algorithm (Kronecker construction) as one level; "
+                         "levels: d levels of the algorithm")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=("square", "batched", "serving", "precision", "algorithms", "copy"),
                     default="square")
@@ -162,6 +167,12 @@ def run_square(args):
     C = torch.empty_like(A)
     Cc = torch.empty_like(A)
     algo = mf.mf_algo_builtin(args.algo)
+    # schedule: d levels of the algorithm, or its d-th Kronecker power run as one level
+    exec_algo, exec_depth = algo, args.depth
+    if args.schedule == "fused" and args.depth > 1:
+        for _ in range(args.depth - 1):
+            exec_algo = mf.mf_algo_compose(exec_algo, algo)
+        exec_depth = 1
     stream = torch.cuda.current_stream()
     timed = timer(torch, stream)
 
@@ -170,11 +181,11 @@ def run_square(args):
 
     # fast product: warm-up, then the timed region with per-phase events
     for _ in range(args.warmup):
-        mf.mf_fastmm(algo, args.depth, args.cutoff, A, B, C)
+        mf.mf_fastmm(exec_algo, exec_depth, args.cutoff, A, B, C)
     torch.cuda.synchronize()
     mf.mf_phase_timing_read()
     mf.mf_phase_timing(True)
-    ms_per_step = timed(lambda: mf.mf_fastmm(algo, args.depth, args.cutoff, A, B, C), args.steps, 0)
+    ms_per_step = timed(lambda: mf.mf_fastmm(exec_algo, exec_depth, args.cutoff, A, B, C), args.steps, 0)
     mf.mf_phase_timing(False)
     phase_ms, calls = mf.mf_phase_timing_read()
     phase_avg = [x / max(1, calls) for x in phase_ms]
@@ -188,20 +199,22 @@ def run_square(args):
     m_true = n / p ** d
     gemm_flops = R ** d * 2.0 * m_true ** 3
     gemm_tflops = gemm_flops / (phase_avg[1] * 1e-3) / 1e12
-    workload = f"fp64 n={n} {args.algo} depth {d}"
+    sched = "Kronecker-fused" if exec_depth == 1 and d > 1 else "level by level"
+    workload = f"fp64 n={n} {args.algo} depth {d} ({sched})"
     roofline = {"bound": "mfma", "achieved": round(gemm_tflops, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(gemm_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
                 "traffic": traffic_for(workload), "kernel": "gemm_grouped<double>",
                 "kernel_ms": round(phase_avg[1], 4)}
 
     # pre-addition phase against HBM: read A and B once, write the materialised blocks
-    mat = mf.mf_workspace_bytes(algo, d, args.cutoff, n)  # includes group outputs when split
+    mat = mf.mf_workspace_bytes(exec_algo, exec_depth, args.cutoff, n)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": workload, "n": n, "algo": args.algo, "depth": d, "cutoff": args.cutoff,
-                   "storage": "fp64", "leaf": "fp64 MFMA", "inputs": "uniform[-1,1] seeds 10, 11"},
+        "config": {"workload": workload, "n": n, "algo": args.algo, "depth": d, "schedule": sched,
+                   "cutoff": args.cutoff, "storage": "fp64", "leaf": "fp64 MFMA",
+                   "inputs": "uniform[-1,1] seeds 10, 11"},
         "classical_ms": round(classical_ms, 4),
         "classical_gflops": round(flops / (classical_ms * 1e-3) / 1e9, 1),
         "speedup_vs_classical": round(classical_ms / ms_per_step, 4),

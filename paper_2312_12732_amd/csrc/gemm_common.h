@@ -73,7 +73,10 @@ __device__ __forceinline__ void work_of(int b, int tiles_m, int tiles_n, int gro
   if ((total & 7) == 0) L = (b & 7) * (total >> 3) + (b >> 3);
   *grp = L / G;
   L -= *grp * G;
-  constexpr int BAND = 8;
+#ifndef MF_GEMM_BAND
+#define MF_GEMM_BAND 8
+#endif
+  constexpr int BAND = MF_GEMM_BAND;
   const int per_band = BAND * tiles_n;
   const int band = L / per_band;
   const int first = band * BAND;

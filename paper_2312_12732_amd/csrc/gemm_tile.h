@@ -30,6 +30,9 @@ namespace mf {
 #ifndef MF_GEMM_FRAG_DB
 #define MF_GEMM_FRAG_DB 1
 #endif
+#ifndef MF_GEMM_SETPRIO
+#define MF_GEMM_SETPRIO 0
+#endif
 
 template <int BM_, int BN_, int WAVES_M_, int WAVES_N_, int WAVES_PER_SIMD_>
 struct TileCfg {
@@ -260,11 +263,13 @@ __device__ __forceinline__ void k_loop(T* lds, const T* __restrict__ pa, int lda
 #if MF_GEMM_FRAG_DB
     T fa[2][WM_T], fb[2][WN_T];
     load_frags<T, Cfg>(As, Bs, 0, wm, wn, lr, lk, fa[0], fb[0]);
+    if (MF_GEMM_SETPRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       if (s + 1 < BK / 4) load_frags<T, Cfg>(As, Bs, s + 1, wm, wn, lr, lk, fa[(s + 1) & 1], fb[(s + 1) & 1]);
       mfma_step<T, Cfg>(fa[s & 1], fb[s & 1], acc);
     }
+    if (MF_GEMM_SETPRIO) __builtin_amdgcn_s_setprio(0);
 #else
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {

@@ -106,6 +106,9 @@ __device__ __forceinline__ void combine_body(const CombArgs<T>& g, const CombSet
 template <class T, int NIN, int NOUT, int VEC, bool FULL>
 __device__ __forceinline__ void combine_acc_body(const CombArgs<T>& g, const CombSet& set, int i, int j) {
   typedef T tv __attribute__((ext_vector_type(VEC)));
+  // inputs are read CHUNK at a time (all loads of a chunk issued before any
+  // is used), so every wave keeps several HBM reads in flight
+  constexpr int CHUNK = NIN % 8 == 0 ? 8 : NIN % 7 == 0 ? 7 : NIN % 9 == 0 ? 9 : 1;
   const CombIn* ins = g.ins + set.in_beg;
   const int nout = set.out_end - set.out_beg;
   int coef_off[NOUT];
@@ -115,31 +118,38 @@ __device__ __forceinline__ void combine_acc_body(const CombArgs<T>& g, const Com
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) acc[o] = (tv)(T(0));
   uint32_t started = 0;  // bit o: output o has its first term (wave-uniform)
-  for (int k = 0; k < NIN; ++k) {
-    const CombIn v = load_uniform(ins + k);
-    const T* p = comb_src(g, v.src) + v.off + (int64_t)i * v.ld + j;
-    tv x;
-    if (FULL) {
-      x = *reinterpret_cast<const tv*>(p);
-    } else {
-      const bool vec = v.src == SRC_WS || g.vec_in;
-      if (vec && i < v.vr && j + VEC <= v.vc) {
-        x = *reinterpret_cast<const tv*>(p);
-      } else {
+  for (int k0 = 0; k0 < NIN; k0 += CHUNK) {
+    tv x[CHUNK];
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) x[q] = (i < v.vr && j + q < v.vc) ? p[q] : T(0);
+    for (int u = 0; u < CHUNK; ++u) {
+      const CombIn v = load_uniform(ins + k0 + u);
+      const T* p = comb_src(g, v.src) + v.off + (int64_t)i * v.ld + j;
+      if (FULL) {
+        x[u] = *reinterpret_cast<const tv*>(p);
+      } else {
+        const bool vec = v.src == SRC_WS || g.vec_in;
+        if (vec && i < v.vr && j + VEC <= v.vc) {
+          x[u] = *reinterpret_cast<const tv*>(p);
+        } else {
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) x[u][q] = (i < v.vr && j + q < v.vc) ? p[q] : T(0);
+        }
       }
     }
 #pragma unroll
-    for (int o = 0; o < NOUT; ++o) {
-      const T ck = o < nout ? (T)load_uniform(g.coef + coef_off[o] + k) : T(0);
-      if (ck != T(0)) {
-        if (!(started >> o & 1u)) {
-          acc[o] = ck == T(1) ? x : ck * x;
-          started |= 1u << o;
-        } else {
+    for (int u = 0; u < CHUNK; ++u) {
+      const int k = k0 + u;
 #pragma unroll
-          for (int q = 0; q < VEC; ++q) acc[o][q] = fma_t(ck, x[q], acc[o][q]);
+      for (int o = 0; o < NOUT; ++o) {
+        const T ck = o < nout ? (T)load_uniform(g.coef + coef_off[o] + k) : T(0);
+        if (ck != T(0)) {
+          if (!(started >> o & 1u)) {
+            acc[o] = ck == T(1) ? x[u] : ck * x[u];
+            started |= 1u << o;
+          } else {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) acc[o][q] = fma_t(ck, x[u][q], acc[o][q]);
+          }
         }
       }
     }

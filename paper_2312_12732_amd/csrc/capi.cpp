@@ -130,6 +130,24 @@ mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, h
   return MF_OK;
 }
 
+// run() with the workspace taken from the stream-ordered pool for the call.
+mf_status run_with_pool(const Plan& pl, const void* A, const void* B, void* C, hipStream_t s) {
+  void* ws = nullptr;
+  if (pl.ws_bytes > 0) {
+    hipError_t e = hipMallocAsync(&ws, pl.ws_bytes, s);
+    if (e != hipSuccess || !ws) {
+      (void)hipGetLastError();
+      return fail(MF_ERR_NOMEM, "workspace allocation of " + std::to_string(pl.ws_bytes) + " bytes failed");
+    }
+  }
+  mf_status st = run(pl, A, B, C, ws, s);
+  if (ws) {
+    hipError_t e = hipFreeAsync(ws, s);
+    if (e != hipSuccess && st == MF_OK) st = fail(MF_ERR_HIP, "workspace release failed");
+  }
+  return st;
+}
+
 }  // namespace
 }  // namespace mf
 
@@ -304,21 +322,7 @@ mf_status mf_fastmm(const mf_algo* algo, int depth, int cutoff, const void* A, c
   std::shared_ptr<const Plan> pl;
   st = plan_for(algo, depth, cutoff, n, dtype, &pl);
   if (st != MF_OK) return st;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  void* ws = nullptr;
-  if (pl->ws_bytes > 0) {
-    hipError_t e = hipMallocAsync(&ws, pl->ws_bytes, s);
-    if (e != hipSuccess || !ws) {
-      (void)hipGetLastError();
-      return fail(MF_ERR_NOMEM, "workspace allocation of " + std::to_string(pl->ws_bytes) + " bytes failed");
-    }
-  }
-  st = run(*pl, A, B, C, ws, s);
-  if (ws) {
-    hipError_t e = hipFreeAsync(ws, s);
-    if (e != hipSuccess && st == MF_OK) st = fail(MF_ERR_HIP, "workspace release failed");
-  }
-  return st;
+  return run_with_pool(*pl, A, B, C, static_cast<hipStream_t>(stream));
 }
 
 mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int dtype, mf_stream stream) {
@@ -328,7 +332,7 @@ mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int 
   std::shared_ptr<const Plan> pl;
   st = get_plan(nullptr, 0, 0, n, dtype, kStandaloneMinWorkgroups, &pl);
   if (st != MF_OK) return st;
-  return run(*pl, A, B, C, nullptr, static_cast<hipStream_t>(stream));
+  return run_with_pool(*pl, A, B, C, static_cast<hipStream_t>(stream));
 }
 
 mf_status mf_phase_timing(int enable) {

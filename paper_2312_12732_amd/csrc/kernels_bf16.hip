@@ -4,17 +4,24 @@
 // position of every output block of its group; the post-addition is fused
 // into the epilogue in FP32).  The leaf product runs on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation:
-//   BF16:    operands rounded to BF16 (round to nearest even) when staged
-//            into LDS;
+//   BF16:    operands rounded to BF16 (round to nearest even);
 //   BF16x3:  split-BF16 compensated product: x = hi + lo with
 //            hi = bf16(x), lo = bf16(x - hi); the product is accumulated as
 //            hi_a lo_b + lo_a hi_b + hi_a hi_b (the lo_a lo_b term dropped),
 //            recovering close to FP32 product accuracy.
+//
+// Two launches.  The staging kernel converts every leaf operand once: the A
+// operand of each product to row-major BF16 planes, the B operand transposed
+// (so that both have k contiguous), zero beyond the view's valid extent, into
+// the plan's BF16 region of the workspace.  The GEMM kernel then streams
+// 16-byte BF16 rows straight into LDS: no conversion, no masking, and half
+// the operand bytes of FP32 per plane.
+//
 // MFMA lane layout (16 x 16 x 32): lane l holds A[l % 16][8 (l / 16) + t] and
 // B[8 (l / 16) + t][l % 16] for t = 0..7; element v of the result is
-// D[4 (l / 16) + v][l % 16].  Both LDS tiles are therefore stored with k
-// contiguous (A row-major, B transposed) so a fragment is one 16-byte read.
-#include "gemm_common.h"
+// D[4 (l / 16) + v][l % 16].  Both LDS tiles are stored with k contiguous
+// (A row-major, B transposed) so a fragment is one 16-byte read.
+#include "gemm_tile.h"
 
 namespace mf {
 
@@ -25,12 +32,83 @@ typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = kLeafTile, BN = kLeafTile, BK = 32;
-constexpr int KS = BK + 8;           // bf16 elements per LDS row (16-byte aligned, conflict-free reads)
-constexpr int NTHREADS = 256;        // 4 waves, 2 x 2, each 64 x 64
-constexpr int WT = 4;                // 16 x 16 tiles per wave side
-constexpr int A_LOADS = BM * BK / 4 / NTHREADS;  // float4 loads of A per thread (4)
-constexpr int B_COLS_PER_T = 1;                  // B: one column, BK / 2 consecutive k per thread
-static_assert(A_LOADS == 4, "A staging assumes 4 float4 loads per thread");
+constexpr int KS = BK + 8;     // bf16 elements per LDS row: 80 bytes, 16-byte aligned, conflict-free reads
+constexpr int NTHREADS = 256;  // 4 waves, 2 x 2, each 64 x 64
+constexpr int WT = 4;          // 16 x 16 tiles per wave side
+constexpr int LOADS = BM * BK / 8 / NTHREADS;  // 16-byte loads per thread, operand and plane (2)
+static_assert(LOADS * 8 * NTHREADS == BM * BK && BM == BN, "staging assumes square tiles");
+
+// ---------------------------------------------------------------------------
+// Staging: FP32 leaf operand views -> BF16 planes
+// ---------------------------------------------------------------------------
+
+constexpr int ST = 64;  // staging tile (ST x ST elements per workgroup of 256 threads)
+
+// Block (x, y, z): columns x*64.., rows y*64.. of operand z (z < nprod: A of
+// product z; otherwise B of product z - nprod, written transposed).
+template <bool X3>
+__global__ void __launch_bounds__(256) stage_bf16(GemmArgs<float> g, __bf16* dst_base, int nprod, int64_t plane) {
+  __shared__ float tile[ST][ST + 1];
+  const int z = blockIdx.z;
+  const bool bside = z >= nprod;
+  const ProdDesc pd = load_uniform(g.prods + (bside ? z - nprod : z));
+  const float* src = bside ? src_ptr(g, pd.b_src) + pd.b_off : src_ptr(g, pd.a_src) + pd.a_off;
+  const int ld = bside ? pd.ldb : pd.lda;
+  const int vr = bside ? pd.b_vr : pd.a_vr, vc = bside ? pd.b_vc : pd.a_vc;
+  const int r0 = blockIdx.y * ST, c0 = blockIdx.x * ST;
+  const int t = threadIdx.x;
+  const int m = g.m;
+  __bf16* hi = dst_base + (size_t)z * (X3 ? 2 : 1) * plane;
+  __bf16* lo = hi + plane;
+  // thread t reads 4 consecutive columns of rows t / 16 + 16 q
+  const int cc = (t % 16) * 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int rr = t / 16 + 16 * q;
+    const int i = r0 + rr;
+    f4 v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = c0 + cc + u;
+      v[u] = (i < vr && j < vc) ? src[(size_t)i * ld + j] : 0.f;
+    }
+    if (!bside) {
+      bf4 h, l;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        h[u] = (__bf16)v[u];
+        l[u] = (__bf16)(v[u] - (float)h[u]);
+      }
+      *reinterpret_cast<bf4*>(hi + (size_t)i * m + c0 + cc) = h;
+      if (X3) *reinterpret_cast<bf4*>(lo + (size_t)i * m + c0 + cc) = l;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tile[rr][cc + u] = v[u];
+    }
+  }
+  if (!bside) return;  // uniform per workgroup
+  __syncthreads();
+  // transposed: output row c0 + c holds column c of the tile; thread t writes
+  // 4 consecutive k (tile rows) of output rows t / 16 + 16 q
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = t / 16 + 16 * q;
+    const int kk = (t % 16) * 4;
+    bf4 h, l;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float x = tile[kk + u][c];
+      h[u] = (__bf16)x;
+      l[u] = (__bf16)(x - (float)h[u]);
+    }
+    *reinterpret_cast<bf4*>(hi + (size_t)(c0 + c) * m + r0 + kk) = h;
+    if (X3) *reinterpret_cast<bf4*>(lo + (size_t)(c0 + c) * m + r0 + kk) = l;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GEMM on staged BF16 operands
+// ---------------------------------------------------------------------------
 
 template <bool X3>
 struct Lds {
@@ -38,113 +116,74 @@ struct Lds {
   __bf16 b[2][X3 ? 2 : 1][BN * KS];  // [buffer][hi|lo][col][k]
 };
 
-// Round to BF16 and, for the split form, the BF16 residual.
-__device__ __forceinline__ void split(float x, __bf16* hi, __bf16* lo) {
-  const __bf16 h = (__bf16)x;
-  *hi = h;
-  *lo = (__bf16)(x - (float)h);
+constexpr int PLANES_MAX = 2;
+
+// 16-byte piece idx of a 128 x 32 tile -> (row, first k).
+__device__ __forceinline__ void piece(int idx, int& row, int& kc) {
+  row = idx / (BK / 8);
+  kc = (idx % (BK / 8)) * 8;
 }
 
-template <bool MASKED>
-__device__ __forceinline__ void load_a(const float* __restrict__ pa, int lda, int vr, int vc, int i0, int k0, int t,
-                                       f4 (&ra)[A_LOADS]) {
+template <bool X3>
+__device__ __forceinline__ void load_stage(const __bf16* a, const __bf16* b, int64_t plane, int m, int i0, int j0,
+                                           int k0, int t, bf8 (&ra)[PLANES_MAX][LOADS],
+                                           bf8 (&rb)[PLANES_MAX][LOADS]) {
+  constexpr int P = X3 ? 2 : 1;
 #pragma unroll
-  for (int q = 0; q < A_LOADS; ++q) {
-    const int idx = t + NTHREADS * q;
-    const int row = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
-    const int gi = i0 + row, gk = k0 + kq;
-    if (!MASKED) {
-      ra[q] = *reinterpret_cast<const f4*>(pa + (size_t)gi * lda + gk);
-    } else {
-      f4 v = {0.f, 0.f, 0.f, 0.f};
+  for (int pl = 0; pl < P; ++pl) {
+    const __amdgpu_buffer_rsrc_t sa = raw_rsrc(a + pl * plane + (size_t)i0 * m + k0);
+    const __amdgpu_buffer_rsrc_t sb = raw_rsrc(b + pl * plane + (size_t)j0 * m + k0);
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (gi < vr && gk + u < vc) v[u] = pa[(size_t)gi * lda + gk + u];
-      ra[q] = v;
+    for (int q = 0; q < LOADS; ++q) {
+      int row, kc;
+      piece(t + NTHREADS * q, row, kc);
+      const int off = (row * m + kc) * 2;  // row < 128, m <= 2^19: below 2^31 bytes
+      ra[pl][q] = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(sa, off, 0, 0));
+      rb[pl][q] = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(sb, off, 0, 0));
     }
-  }
-}
-
-// B: thread t stages column j = t % BN, k = (t / BN) * (BK / 2) + 0..15.
-template <bool MASKED>
-__device__ __forceinline__ void load_b(const float* __restrict__ pb, int ldb, int vr, int vc, int j0, int k0, int t,
-                                       float (&rb)[BK / 2]) {
-  const int j = j0 + t % BN, kb = k0 + (t / BN) * (BK / 2);
-#pragma unroll
-  for (int u = 0; u < BK / 2; ++u) {
-    if (!MASKED)
-      rb[u] = pb[(size_t)(kb + u) * ldb + j];
-    else
-      rb[u] = (kb + u < vr && j < vc) ? pb[(size_t)(kb + u) * ldb + j] : 0.f;
   }
 }
 
 template <bool X3>
-__device__ __forceinline__ void store_ab(Lds<X3>& L, int buf, int t, const f4 (&ra)[A_LOADS],
-                                         const float (&rb)[BK / 2]) {
+__device__ __forceinline__ void store_stage(Lds<X3>& L, int buf, int t, const bf8 (&ra)[PLANES_MAX][LOADS],
+                                            const bf8 (&rb)[PLANES_MAX][LOADS]) {
+  constexpr int P = X3 ? 2 : 1;
 #pragma unroll
-  for (int q = 0; q < A_LOADS; ++q) {
-    const int idx = t + NTHREADS * q;
-    const int row = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
-    bf4 h, l;
+  for (int pl = 0; pl < P; ++pl)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      __bf16 hh, ll;
-      split(ra[q][u], &hh, &ll);
-      h[u] = hh;
-      l[u] = ll;
+    for (int q = 0; q < LOADS; ++q) {
+      int row, kc;
+      piece(t + NTHREADS * q, row, kc);
+      *reinterpret_cast<bf8*>(&L.a[buf][pl][row * KS + kc]) = ra[pl][q];
+      *reinterpret_cast<bf8*>(&L.b[buf][pl][row * KS + kc]) = rb[pl][q];
     }
-    *reinterpret_cast<bf4*>(&L.a[buf][0][row * KS + kq]) = h;
-    if (X3) *reinterpret_cast<bf4*>(&L.a[buf][X3 ? 1 : 0][row * KS + kq]) = l;
-  }
-  const int j = t % BN, kb = (t / BN) * (BK / 2);
-#pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    bf8 h, l;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      __bf16 hh, ll;
-      split(rb[8 * half + u], &hh, &ll);
-      h[u] = hh;
-      l[u] = ll;
-    }
-    *reinterpret_cast<bf8*>(&L.b[buf][0][j * KS + kb + 8 * half]) = h;
-    if (X3) *reinterpret_cast<bf8*>(&L.b[buf][X3 ? 1 : 0][j * KS + kb + 8 * half]) = l;
-  }
 }
 
-template <bool X3, bool MASKED>
-__device__ __forceinline__ void k_loop(Lds<X3>& L, const float* __restrict__ pa, int lda, int a_vr, int a_vc,
-                                       const float* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0, int j0,
-                                       int KT, int t, int wm, int wn, int lr, int lk, f4 (&acc)[WT][WT]) {
-  f4 ra[A_LOADS];
-  float rb[BK / 2];
-  load_a<MASKED>(pa, lda, a_vr, a_vc, i0, 0, t, ra);
-  load_b<MASKED>(pb, ldb, b_vr, b_vc, j0, 0, t, rb);
-  store_ab<X3>(L, 0, t, ra, rb);
+template <bool X3>
+__device__ __forceinline__ void k_loop(Lds<X3>& L, const __bf16* a, const __bf16* b, int64_t plane, int m, int i0,
+                                       int j0, int t, int wm, int wn, int lr, int lk, f4 (&acc)[WT][WT]) {
+  bf8 ra[PLANES_MAX][LOADS], rb[PLANES_MAX][LOADS];
+  const int KT = m / BK;
+  load_stage<X3>(a, b, plane, m, i0, j0, 0, t, ra, rb);
+  store_stage<X3>(L, 0, t, ra, rb);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < KT;
-    if (more) {
-      load_a<MASKED>(pa, lda, a_vr, a_vc, i0, (kt + 1) * BK, t, ra);
-      load_b<MASKED>(pb, ldb, b_vr, b_vc, j0, (kt + 1) * BK, t, rb);
-    }
+    if (more) load_stage<X3>(a, b, plane, m, i0, j0, (kt + 1) * BK, t, ra, rb);
     bf8 ah[WT], bh[WT];
 #pragma unroll
-    for (int mi = 0; mi < WT; ++mi)
-      ah[mi] = *reinterpret_cast<const bf8*>(&L.a[cur][0][(wm + 16 * mi + lr) * KS + 8 * lk]);
+    for (int mi = 0; mi < WT; ++mi) ah[mi] = *reinterpret_cast<const bf8*>(&L.a[cur][0][(wm + 16 * mi + lr) * KS + 8 * lk]);
 #pragma unroll
-    for (int ni = 0; ni < WT; ++ni)
-      bh[ni] = *reinterpret_cast<const bf8*>(&L.b[cur][0][(wn + 16 * ni + lr) * KS + 8 * lk]);
-    if (X3) {
+    for (int ni = 0; ni < WT; ++ni) bh[ni] = *reinterpret_cast<const bf8*>(&L.b[cur][0][(wn + 16 * ni + lr) * KS + 8 * lk]);
+    if constexpr (X3) {
       bf8 al[WT], bl[WT];
 #pragma unroll
       for (int mi = 0; mi < WT; ++mi)
-        al[mi] = *reinterpret_cast<const bf8*>(&L.a[cur][X3 ? 1 : 0][(wm + 16 * mi + lr) * KS + 8 * lk]);
+        al[mi] = *reinterpret_cast<const bf8*>(&L.a[cur][1][(wm + 16 * mi + lr) * KS + 8 * lk]);
 #pragma unroll
       for (int ni = 0; ni < WT; ++ni)
-        bl[ni] = *reinterpret_cast<const bf8*>(&L.b[cur][X3 ? 1 : 0][(wn + 16 * ni + lr) * KS + 8 * lk]);
+        bl[ni] = *reinterpret_cast<const bf8*>(&L.b[cur][1][(wn + 16 * ni + lr) * KS + 8 * lk]);
 #pragma unroll
       for (int mi = 0; mi < WT; ++mi)
 #pragma unroll
@@ -160,13 +199,14 @@ __device__ __forceinline__ void k_loop(Lds<X3>& L, const float* __restrict__ pa,
         for (int ni = 0; ni < WT; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
     }
-    if (more) store_ab<X3>(L, cur ^ 1, t, ra, rb);
+    if (more) store_stage<X3>(L, cur ^ 1, t, ra, rb);
     __syncthreads();
   }
 }
 
 template <bool X3>
-__global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_grouped(GemmArgs<float> g) {
+__global__ void __launch_bounds__(NTHREADS, 2)
+    gemm_bf16_grouped(GemmArgs<float> g, const __bf16* __restrict__ staged, int nprod, int64_t plane) {
   __shared__ Lds<X3> L;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -175,29 +215,22 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_grouped(GemmArgs<float>
   int grp, ti, tj;
   work_of(blockIdx.x, g.tiles_m, g.tiles_n, g.groups, &grp, &ti, &tj);
   const int i0 = ti * BM, j0 = tj * BN;
-  const int KT = g.m / BK;
-  const int r_beg = g.group_beg[grp], r_end = g.group_beg[grp + 1];
+  const int r_beg = load_uniform(g.group_beg + grp), r_end = load_uniform(g.group_beg + grp + 1);
+  constexpr int P = X3 ? 2 : 1;
 
   for (int r = r_beg; r < r_end; ++r) {
-    const ProdDesc pd = g.prods[r];
-    const float* pa = src_ptr(g, pd.a_src) + pd.a_off;
-    const float* pb = src_ptr(g, pd.b_src) + pd.b_off;
-    const bool vec_a = pd.a_src == SRC_WS || g.vec_in;
+    const ProdDesc pd = load_uniform(g.prods + r);
+    const __bf16* a = staged + (size_t)r * P * plane;
+    const __bf16* b = staged + (size_t)(nprod + r) * P * plane;
     f4 acc[WT][WT];
 #pragma unroll
     for (int mi = 0; mi < WT; ++mi)
 #pragma unroll
       for (int ni = 0; ni < WT; ++ni) acc[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
-    const bool interior = vec_a && i0 + BM <= pd.a_vr && pd.a_vc >= g.m && pd.b_vr >= g.m && j0 + BN <= pd.b_vc;
-    if (interior)
-      k_loop<X3, false>(L, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr, lk,
-                        acc);
-    else
-      k_loop<X3, true>(L, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr, lk,
-                       acc);
+    k_loop<X3>(L, a, b, plane, g.m, i0, j0, t, wm, wn, lr, lk, acc);
 
     for (int e = pd.epi_beg; e < pd.epi_end; ++e) {
-      const EpiDesc ed = g.epis[e];
+      const EpiDesc ed = load_uniform(g.epis + e);
       float* pc = dst_ptr(g, ed.c_src) + ed.c_off;
       const bool full = (i0 + BM <= ed.c_vr) && (j0 + BN <= ed.c_vc);
       const float coef = (float)ed.coef;
@@ -220,6 +253,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) gemm_bf16_grouped(GemmArgs<float>
 
 hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
                             hipStream_t s) {
+  (void)vec_in;  // the staged operands are always aligned and whole
   GemmArgs<float> g;
   g.A = static_cast<const float*>(A);
   g.B = static_cast<const float*>(B);
@@ -232,12 +266,25 @@ hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* 
   g.m = (int)pl.m;
   g.tiles_m = (int)(pl.m / bf::BM);
   g.tiles_n = (int)(pl.m / bf::BN);
-  g.vec_in = vec_in ? 1 : 0;
+  g.vec_in = 0;
+  if (pl.bf_base < 0 || !ws) return hipErrorInvalidValue;
+  __bf16* staged = reinterpret_cast<__bf16*>(static_cast<char*>(ws) + pl.bf_base);
+  const int nprod = (int)pl.prods.size();
+  const int64_t plane = pl.m * pl.m;
+  const dim3 sgrid((unsigned)(pl.m / bf::ST), (unsigned)(pl.m / bf::ST), (unsigned)(2 * nprod));
+  if (x3)
+    hipLaunchKernelGGL(bf::stage_bf16<true>, sgrid, dim3(256), 0, s, g, staged, nprod, plane);
+  else
+    hipLaunchKernelGGL(bf::stage_bf16<false>, sgrid, dim3(256), 0, s, g, staged, nprod, plane);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n * (unsigned)g.groups;
   if (x3)
-    hipLaunchKernelGGL(bf::gemm_bf16_grouped<true>, dim3(grid), dim3(bf::NTHREADS), 0, s, g);
+    hipLaunchKernelGGL(bf::gemm_bf16_grouped<true>, dim3(grid), dim3(bf::NTHREADS), 0, s, g,
+                       (const __bf16*)staged, nprod, plane);
   else
-    hipLaunchKernelGGL(bf::gemm_bf16_grouped<false>, dim3(grid), dim3(bf::NTHREADS), 0, s, g);
+    hipLaunchKernelGGL(bf::gemm_bf16_grouped<false>, dim3(grid), dim3(bf::NTHREADS), 0, s, g,
+                       (const __bf16*)staged, nprod, plane);
   return hipGetLastError();
 }
 

@@ -155,6 +155,12 @@ struct Plan {
   std::vector<EpiDesc> epis;
   std::vector<int32_t> group_beg;  // groups + 1 entries
   std::vector<CombineStage> pre, post;  // in launch order
+  // BF16 leaves: every leaf operand is staged once as BF16 (two planes, hi
+  // and lo, for split-BF16x3) in the workspace from this byte offset on: the
+  // A operands of products 0..R-1 (row-major m x m), then the B operands
+  // transposed (row j holds column j), each plane m x m.
+  int64_t bf_base = -1;
+  int bf_planes = 0;
   // device copy (one allocation, owned by the plan), made on first use
   mutable std::once_flag uploaded;
   mutable mf_status upload_status = MF_OK;

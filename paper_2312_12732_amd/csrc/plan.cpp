@@ -81,6 +81,16 @@ void finish_set(CombineStage* st, CombSet set) {
   st->sets.push_back(set);
 }
 
+// BF16 leaves: reserve the staged operands (see Plan::bf_base) after
+// everything else in the workspace.
+void finish_bf16(Plan* pl) {
+  const int leaf = (pl->dtype >> 8) & 0xff;
+  if (leaf != 2 && leaf != 3) return;
+  pl->bf_planes = leaf == 3 ? 2 : 1;
+  pl->bf_base = (int64_t)round_up((int64_t)pl->ws_bytes, 256);
+  pl->ws_bytes = (size_t)pl->bf_base + (size_t)2 * pl->prods.size() * pl->bf_planes * pl->m * pl->m * 2;
+}
+
 mf_status build_classical(int64_t n, Plan* pl) {
   pl->P = pl->P_outer = 1;
   pl->R = pl->groups = 1;
@@ -102,6 +112,7 @@ mf_status build_classical(int64_t n, Plan* pl) {
   ed.coef = 1.0;
   pl->epis.push_back(ed);
   pl->group_beg = {0, 1};
+  finish_bf16(pl);
   return MF_OK;
 }
 
@@ -365,6 +376,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
     }
   }
   pl->ws_bytes = (size_t)ws * pl->elem;
+  finish_bf16(pl);
   return MF_OK;
 }
 

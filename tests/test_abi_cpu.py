@@ -290,3 +290,17 @@ def test_plan_query_closed_forms():
     # materialised child is a whole 512 x 512 workspace block, zeros included, as the leaf GEMM reads it
     q = mf.mf_plan_query(w, 1, 0, 1000)
     assert q["leaf_m"] == 512 and q["pre_bytes"] == 2 * 8 * (1000 * 1000 + 4 * 512 * 512)
+
+
+def test_workspace_bytes_bf16_staging():
+    """BF16 leaves stage every leaf operand once as BF16 planes (2 planes for
+    split-BF16x3): A operands and transposed B operands, m x m each, placed
+    after the FP32 workspace (256-byte aligned)."""
+    s = mf.mf_algo_builtin("strassen")
+    f32 = mf.mf_workspace_bytes(s, 1, 0, 8192, mf.MF_F32)
+    base = -(-f32 // 256) * 256
+    for leaf, planes in ((mf.MF_LEAF_BF16, 1), (mf.MF_LEAF_BF16X3, 2)):
+        assert mf.mf_workspace_bytes(s, 1, 0, 8192, mf.MF_F32 | leaf) == base + 2 * 7 * planes * 4096 ** 2 * 2
+        # classical: one product, a 1000 x 1000 problem in a 1024 leaf
+        assert mf.mf_workspace_bytes(s, 0, 0, 1000, mf.MF_F32 | leaf) == 2 * planes * 1024 ** 2 * 2
+    assert mf.mf_workspace_bytes(s, 0, 0, 1000, mf.MF_F32 | mf.MF_LEAF_F32) == 0

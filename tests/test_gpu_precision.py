@@ -129,3 +129,19 @@ def test_precision_determinism():
         mf.mf_fastmm(s, 2, 0, A, B, C2, leaf=leaf)
         torch.cuda.synchronize()
         assert torch.equal(C1, C2)
+
+
+@pytest.mark.parametrize("leaf", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("n,depth", [(4000, 0), (4001, 1), (3000, 2)])
+def test_bf16_staging_large_ragged(leaf, n, depth):
+    """BF16 leaf operands are staged (A row-major, B transposed, zero padding)
+    before the GEMM: ragged sizes over many staging tiles, integer inputs
+    (exact in BF16 and in the FP32 sums) compared exactly on sampled rows and
+    columns, first and last included."""
+    A = mi.int_uniform(n, 90).astype(np.float64)
+    B = mi.int_uniform(n, 91).astype(np.float64)
+    got = run(mf.mf_algo_builtin("winograd") if depth else None, depth, A, B, LEAVES[leaf])
+    rows = np.unique(np.concatenate([np.random.default_rng(n).choice(n, size=24, replace=False), [0, n - 1]]))
+    cols = np.unique(np.concatenate([np.random.default_rng(n + 1).choice(n, size=24, replace=False), [0, n - 1]]))
+    assert np.array_equal(got[rows], om.rows_reference(A, B, rows))
+    assert np.array_equal(got[:, cols], A @ B[:, cols])

@@ -118,16 +118,20 @@ void mf_algo_free(mf_algo* a);
  * the number of leaf products stays within 2^16 (sizes are rounded up at each
  * split); depth 0 (or cutoff >= n) is the classical product.  Sizes that the split factor does not divide are
  * handled by virtual zero padding (no copy of A, B or C).  Temporaries come
- * from a stream-ordered pool owned by the library.  A, B, C: device
- * pointers to n x n matrices of the storage type of `dtype`. */
+ * from a stream-ordered pool owned by the library, one per device, which
+ * keeps the memory it has reserved until the process ends (so repeated calls
+ * do not map fresh device memory).  A, B, C: device pointers to n x n
+ * matrices of the storage type of `dtype`. */
 mf_status mf_fastmm(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C,
                     int64_t n, int dtype, mf_stream stream);
 
-/* C = A B by the library's own MFMA GEMM (no fast algorithm). */
+/* C = A B by the library's own MFMA GEMM (no fast algorithm).  BF16 leaves
+ * stage the operands in workspace from the library's pool. */
 mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int dtype, mf_stream stream);
 
 /* Bytes of device workspace mf_fastmm_ws needs for this request (0 for a
- * classical product). */
+ * classical product with leaves in the storage type; BF16 leaves stage every
+ * leaf operand as BF16 planes). */
 mf_status mf_workspace_bytes(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
                              size_t* bytes);
 

@@ -337,7 +337,7 @@ mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* cons
       if (ws_bytes < b->ws_bytes) return fail(MF_ERR_SHAPE, "workspace too small");
       if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(MF_ERR_ARG, "workspace must be 256-byte aligned");
     } else {
-      if (hipMallocAsync(&ws, b->ws_bytes, s) != hipSuccess || !ws) {
+      if (workspace_alloc(&ws, b->ws_bytes, s) != hipSuccess || !ws) {
         (void)hipGetLastError();
         return fail(MF_ERR_NOMEM, "batch workspace allocation failed");
       }
@@ -364,7 +364,7 @@ mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* cons
                              b->d_insts, s);
   }
   if (e != hipSuccess) st = fail(MF_ERR_HIP, std::string("batch launch failed: ") + hipGetErrorString(e));
-  if (own && hipFreeAsync(ws, s) != hipSuccess && st == MF_OK) st = fail(MF_ERR_HIP, "workspace release failed");
+  if (own && workspace_free(ws, s) != hipSuccess && st == MF_OK) st = fail(MF_ERR_HIP, "workspace release failed");
   return st;
 }
 

@@ -130,11 +130,56 @@ mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, h
   return MF_OK;
 }
 
-// run() with the workspace taken from the stream-ordered pool for the call.
+constexpr int kMaxDevices = 64;
+
+// One pool per device, made on first use and kept until the process ends.
+hipMemPool_t device_pool(int dev) {
+  static std::mutex mu;
+  static hipMemPool_t pools[kMaxDevices] = {};
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!pools[dev]) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    uint64_t keep = UINT64_MAX;
+    if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipMemPoolDestroy(pool);
+      return nullptr;
+    }
+    pools[dev] = pool;
+  }
+  return pools[dev];
+}
+
+}  // namespace
+
+hipError_t workspace_alloc(void** p, size_t bytes, hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  hipMemPool_t pool = device_pool(dev);
+  if (!pool) return hipErrorOutOfMemory;
+  return hipMallocFromPoolAsync(p, bytes, pool, s);
+}
+
+hipError_t workspace_free(void* p, hipStream_t s) { return hipFreeAsync(p, s); }
+
+namespace {
+
+// run() with the workspace taken from the library's pool for the call.
 mf_status run_with_pool(const Plan& pl, const void* A, const void* B, void* C, hipStream_t s) {
   void* ws = nullptr;
   if (pl.ws_bytes > 0) {
-    hipError_t e = hipMallocAsync(&ws, pl.ws_bytes, s);
+    hipError_t e = workspace_alloc(&ws, pl.ws_bytes, s);
     if (e != hipSuccess || !ws) {
       (void)hipGetLastError();
       return fail(MF_ERR_NOMEM, "workspace allocation of " + std::to_string(pl.ws_bytes) + " bytes failed");
@@ -142,7 +187,7 @@ mf_status run_with_pool(const Plan& pl, const void* A, const void* B, void* C, h
   }
   mf_status st = run(pl, A, B, C, ws, s);
   if (ws) {
-    hipError_t e = hipFreeAsync(ws, s);
+    hipError_t e = workspace_free(ws, s);
     if (e != hipSuccess && st == MF_OK) st = fail(MF_ERR_HIP, "workspace release failed");
   }
   return st;

@@ -283,6 +283,13 @@ hipError_t launch_batch_phase(int elem, bool gemm, const BatchTask* tasks, int t
                               const StageRec* stages, const GemmRec* gemms, const BatchInst* insts, hipStream_t s);
 bool batch_nin_supported(int nin);
 
+// Workspace for one call, from the library's stream-ordered pool on the
+// current device.  The pool keeps the memory it has reserved (release
+// threshold at its maximum), so repeated calls reuse it instead of mapping
+// fresh device memory each time.
+hipError_t workspace_alloc(void** p, size_t bytes, hipStream_t s);
+hipError_t workspace_free(void* p, hipStream_t s);
+
 // Thread-local error message.
 mf_status fail(mf_status st, const std::string& msg);
 void clear_error();

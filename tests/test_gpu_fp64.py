@@ -209,6 +209,29 @@ def test_full_size_sampled_rows(n, name, depth):
     assert np.isfinite(got).all()
 
 
+def test_bench_configuration_sampled():
+    """The benchmarked configuration itself: n = 8192 FP64, Strassen-Winograd
+    depth 2 run Kronecker-fused (one level of <4,4,4;49>), on the benchmark's
+    inputs (uniform, seeds 10 and 11), and on integer inputs exactly; rows
+    sampled, first and last included, and the same for the level-by-level
+    schedule, whose result must agree within the bound."""
+    n = 8192
+    w = mf.mf_algo_builtin("winograd")
+    fused = mf.mf_algo_compose(w, w)
+    A = mi.uniform(n, 10)
+    B = mi.uniform(n, 11)
+    rows = np.unique(np.concatenate([np.random.default_rng(6).choice(n, size=40, replace=False), [0, n - 1]]))
+    ref = om.rows_reference(A, B, rows)
+    got_f = run_fast(fused, 1, 0, A, B)
+    got_l = run_fast(w, 2, 0, A, B)
+    assert om.rel_fro_error(got_f[rows], ref) < FP64_TOL
+    assert om.rel_fro_error(got_l[rows], ref) < FP64_TOL
+    assert om.rel_fro_error(got_f, got_l) < FP64_TOL
+    Ai = mi.int_uniform(n, 12).astype(np.float64)
+    Bi = mi.int_uniform(n, 13).astype(np.float64)
+    assert np.array_equal(run_fast(fused, 1, 0, Ai, Bi)[rows], om.rows_reference(Ai, Bi, rows))
+
+
 # ------------------------------------------------------------- large leaves
 # Full-size exactness of the GEMM on large leaves: classical n = 4000, 4001
 # (masked edge tiles: valid extent 4000 / 4001 inside a 4096 leaf), 4096 and

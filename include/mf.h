@@ -171,8 +171,12 @@ mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A
  * every instance, level 1, ..., all GEMM tiles (largest leaves first), then
  * the post-addition levels.  A run launches each phase once over all
  * instances (one workgroup per task), so instances of different sizes share
- * the GPU within every launch.  A batch plan is immutable; it must not run
- * concurrently with itself (runs on one stream are fine). */
+ * the GPU within every launch.  Every instance runs the plan mf_fastmm uses
+ * for the same arguments, so its result is bitwise that of the standalone
+ * call.  Supported algorithm shapes: combinations of 4, 7, 8, 9 or 16
+ * inputs, and of 27 (at most 9 outputs), 49 or 64 (at most 16 outputs)
+ * inputs; other shapes give MF_ERR_UNSUPPORTED.  A batch plan is immutable;
+ * it must not run concurrently with itself (runs on one stream are fine). */
 typedef struct mf_batch mf_batch;
 
 /* Plan a batch (host only; device state is made on the first run).  The

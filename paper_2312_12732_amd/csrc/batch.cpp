@@ -69,12 +69,15 @@ mf_status build_batch(mf_batch* b, const std::vector<const mf_algo*>& algos, con
   std::map<const Plan*, Recs> recs;
   for (int i = 0; i < b->count; ++i) {
     std::shared_ptr<const Plan> pl;
-    mf_status st = get_plan(depth[i] > 0 ? algos[i] : nullptr, depth[i], cutoff[i], b->n[i], b->dtype, 0, &pl);
+    mf_status st = get_plan(depth[i] > 0 ? algos[i] : nullptr, depth[i], cutoff[i], b->n[i], b->dtype,
+                            kStandaloneMinWorkgroups, &pl);
     if (st != MF_OK) return st;
     for (const CombineStage& cs : pl->pre)
-      if (!batch_nin_supported(cs.nin)) return fail(MF_ERR_UNSUPPORTED, "algorithm shape not supported in batches");
+      if (!batch_stage_supported(cs.nin, cs.nout_max, kPersistentBatch))
+        return fail(MF_ERR_UNSUPPORTED, "algorithm shape not supported in batches");
     for (const CombineStage& cs : pl->post)
-      if (!batch_nin_supported(cs.nin)) return fail(MF_ERR_UNSUPPORTED, "algorithm shape not supported in batches");
+      if (!batch_stage_supported(cs.nin, cs.nout_max, kPersistentBatch))
+        return fail(MF_ERR_UNSUPPORTED, "algorithm shape not supported in batches");
     b->plans.push_back(pl);
     if (!recs.count(pl.get())) {
       Recs r;

@@ -47,7 +47,9 @@ __device__ __forceinline__ int load_relaxed(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <class T>
+// WIDE: also the many-input combinations (27, 49, 64 inputs), through the
+// register-accumulating body (the phase form has the registers for them).
+template <class T, bool WIDE>
 __device__ __forceinline__ void run_combine(const BatchArgs& g, const BatchTask& tk) {
   const StageRec st = load_uniform(g.stages + tk.rec);
   const BatchInst in = load_uniform(g.insts + tk.inst);
@@ -65,16 +67,34 @@ __device__ __forceinline__ void run_combine(const BatchArgs& g, const BatchTask&
   a.vec_out = in.vec_out;
   const CombSet set = load_uniform(st.sets + tk.a);
   const bool full = set.full && in.vec_in && in.vec_out;
+  auto chunk = [&](auto body, int vec) {
+    for (int64_t e = tk.e0 + (int64_t)threadIdx.x * vec; e < tk.e1; e += (int64_t)Tile128::NTHREADS * vec) {
+      const int i = (int)(e / st.m), j = (int)(e % st.m);
+      body(i, j);
+    }
+  };
+  if constexpr (WIDE) {
+    if (st.nin >= 27) {
+      auto wide = [&](auto nin_c, auto nout_c) {
+        constexpr int NIN = decltype(nin_c)::value, NOUT = decltype(nout_c)::value;
+        if (full)
+          chunk([&](int i, int j) { combine_acc_body<T, NIN, NOUT, 2, true>(a, set, i, j); }, 2);
+        else
+          chunk([&](int i, int j) { combine_acc_body<T, NIN, NOUT, 2, false>(a, set, i, j); }, 2);
+      };
+      if (st.nin == 27) wide(std::integral_constant<int, 27>(), std::integral_constant<int, 9>());
+      if (st.nin == 49) wide(std::integral_constant<int, 49>(), std::integral_constant<int, 16>());
+      if (st.nin == 64) wide(std::integral_constant<int, 64>(), std::integral_constant<int, 16>());
+      return;
+    }
+  }
   with_nin(st.nin, [&](auto nin_c) {
     constexpr int NIN = decltype(nin_c)::value;
     constexpr int VEC = NIN <= 4 ? 4 : (NIN <= 9 ? 2 : 1);
-    for (int64_t e = tk.e0 + (int64_t)threadIdx.x * VEC; e < tk.e1; e += (int64_t)Tile128::NTHREADS * VEC) {
-      const int i = (int)(e / st.m), j = (int)(e % st.m);
-      if (full)
-        combine_body<T, NIN, VEC, true>(a, set, i, j);
-      else
-        combine_body<T, NIN, VEC, false>(a, set, i, j);
-    }
+    if (full)
+      chunk([&](int i, int j) { combine_body<T, NIN, VEC, true>(a, set, i, j); }, VEC);
+    else
+      chunk([&](int i, int j) { combine_body<T, NIN, VEC, false>(a, set, i, j); }, VEC);
   });
 }
 
@@ -143,7 +163,7 @@ __global__ void __launch_bounds__(Tile128::NTHREADS, Tile128::WAVES_PER_SIMD) ba
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     if (tk.type == 0)
-      run_combine<T>(g, tk);
+      run_combine<T, false>(g, tk);
     else
       run_gemm<T>(g, tk, lds);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -159,7 +179,7 @@ __global__ void __launch_bounds__(Tile128::NTHREADS, Tile128::WAVES_PER_SIMD) ba
 template <class T>
 __global__ void __launch_bounds__(Tile128::NTHREADS) batch_combine_phase(BatchArgs g, int task0) {
   const BatchTask tk = load_uniform(g.tasks + task0 + blockIdx.x);
-  run_combine<T>(g, tk);
+  run_combine<T, true>(g, tk);
 }
 
 template <class T>
@@ -176,8 +196,10 @@ __global__ void fill_zero(int* p, int count) {
 
 }  // namespace
 
-bool batch_nin_supported(int nin) {
-  return nin == 4 || nin == 7 || nin == 8 || nin == 9 || nin == 16;
+bool batch_stage_supported(int nin, int nout_max, bool persistent) {
+  if (nin == 4 || nin == 7 || nin == 8 || nin == 9 || nin == 16) return true;
+  if (persistent) return false;
+  return (nin == 27 && nout_max <= 9) || ((nin == 49 || nin == 64) && nout_max <= 16);
 }
 
 hipError_t launch_fill_zero(int* p, int count, hipStream_t s) {

@@ -229,8 +229,8 @@ struct BatchTask {
 // moves fewer bytes but its read-modify-writes stall the MFMA pipes; on
 // MI355X at n = 8192 (FP64 Winograd) storing every product is faster at
 // depth 1 / 2 / 3: 14.82 / 14.30 / 15.05 ms against 15.13 / 14.86 / 16.23 ms
-// with outer levels only until 1024 workgroups.  A batch (min_wg 0) fuses
-// every level into the epilogue.
+// with outer levels only until 1024 workgroups.  Batches use the same plans,
+// so an instance's result is bitwise that of the standalone call.
 // Returns an mf_status and sets the thread's error message on failure.
 #ifndef MF_STANDALONE_MIN_WG
 #define MF_STANDALONE_MIN_WG (int64_t(1) << 62)
@@ -281,7 +281,9 @@ hipError_t launch_fill_zero(int* p, int count, hipStream_t s);
 // its own launch, one workgroup per task.
 hipError_t launch_batch_phase(int elem, bool gemm, const BatchTask* tasks, int task0, int count,
                               const StageRec* stages, const GemmRec* gemms, const BatchInst* insts, hipStream_t s);
-bool batch_nin_supported(int nin);
+// Whether a combination stage can run inside a batch (the persistent form
+// supports only the narrow shapes).
+bool batch_stage_supported(int nin, int nout_max, bool persistent);
 
 // Workspace for one call, from the library's stream-ordered pool on the
 // current device.  The pool keeps the memory it has reserved (release

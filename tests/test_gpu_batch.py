@@ -106,3 +106,25 @@ def test_batch_rejects_mismatched_inputs():
     A = torch.zeros(256, 256, dtype=torch.float64, device="cuda:0")
     with pytest.raises(ValueError):
         mf.mf_batch_run(b, [A, A], [A, A], [torch.empty_like(A), torch.empty_like(A)])
+
+
+def test_batch_bitwise_equals_standalone_fast():
+    """Every instance runs the plan of the standalone call with the same
+    arguments: results agree bit for bit on uniform inputs."""
+    s = mf.mf_algo_builtin("winograd")
+    s2 = mf.mf_algo_compose(s, s)
+    sizes = [1024, 700, 1536, 512, 1000]
+    algos = [s, s, s2, s, s]
+    depths = [2, 1, 1, 3, 2]
+    for code, tdt in ((mf.MF_F64, torch.float64), (mf.MF_F32, torch.float32)):
+        b = mf.mf_batch_create(sizes, algos, depths, [0] * len(sizes), code)
+        As = [mi.uniform(n, 1000 + i) for i, n in enumerate(sizes)]
+        Bs = [mi.uniform(n, 1100 + i) for i, n in enumerate(sizes)]
+        Cs = run(b, As, Bs, tdt)
+        for A, B, C, al, d in zip(As, Bs, Cs, algos, depths):
+            dA = torch.from_numpy(A).to("cuda:0", tdt)
+            dB = torch.from_numpy(B).to("cuda:0", tdt)
+            dC = torch.empty_like(dA)
+            mf.mf_fastmm(al, d, 0, dA, dB, dC)
+            torch.cuda.synchronize()
+            assert np.array_equal(C, dC.cpu().numpy().astype(np.float64))

@@ -256,3 +256,22 @@ def test_large_tile_fast_depth1_int_exact_rows(n):
     got = run_fast(mf.mf_algo_builtin("winograd"), 1, 0, A, B)
     rows = np.unique(np.concatenate([np.random.default_rng(n).choice(n, size=32, replace=False), [0, n - 1]]))
     assert np.array_equal(got[rows], om.rows_reference(A, B, rows))
+
+
+def test_largest_configuration_sampled():
+    """n = 16384 (the largest size of the workloads): Strassen-Winograd depth
+    1 and depth 2 Kronecker-fused, sampled rows against the oracle within the
+    bound, and integer inputs exactly."""
+    n = 16384
+    w = mf.mf_algo_builtin("winograd")
+    A = mi.uniform(n, 20)
+    B = mi.uniform(n, 21)
+    rows = np.unique(np.concatenate([np.random.default_rng(7).choice(n, size=24, replace=False), [0, n - 1]]))
+    ref = om.rows_reference(A, B, rows)
+    for algo, depth in ((w, 1), (mf.mf_algo_compose(w, w), 1)):
+        got = run_fast(algo, depth, 0, A, B)
+        assert om.rel_fro_error(got[rows], ref) < FP64_TOL
+    Ai = mi.int_uniform(n, 22).astype(np.float64)
+    Bi = mi.int_uniform(n, 23).astype(np.float64)
+    got = run_fast(w, 2, 0, Ai, Bi)
+    assert np.array_equal(got[rows], om.rows_reference(Ai, Bi, rows))

@@ -21,6 +21,8 @@
 // B[8 (l / 16) + t][l % 16] for t = 0..7; element v of the result is
 // D[4 (l / 16) + v][l % 16].  Both LDS tiles are stored with k contiguous
 // (A row-major, B transposed) so a fragment is one 16-byte read.
+#include <type_traits>
+
 #include "gemm_tile.h"
 
 namespace mf {
@@ -31,12 +33,9 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = kLeafTile, BN = kLeafTile, BK = 32;
+constexpr int BK = 32;
 constexpr int KS = BK + 8;     // bf16 elements per LDS row: 80 bytes, 16-byte aligned, conflict-free reads
-constexpr int NTHREADS = 256;  // 4 waves, 2 x 2, each 64 x 64
-constexpr int WT = 4;          // 16 x 16 tiles per wave side
-constexpr int LOADS = BM * BK / 8 / NTHREADS;  // 16-byte loads per thread, operand and plane (2)
-static_assert(LOADS * 8 * NTHREADS == BM * BK && BM == BN, "staging assumes square tiles");
+constexpr int NTHREADS = 256;  // 4 waves, 2 x 2
 
 // ---------------------------------------------------------------------------
 // Staging: FP32 leaf operand views -> BF16 planes
@@ -110,111 +109,144 @@ __global__ void __launch_bounds__(256) stage_bf16(GemmArgs<float> g, __bf16* dst
 // GEMM on staged BF16 operands
 // ---------------------------------------------------------------------------
 
-template <bool X3>
+// Tile geometry: a BM_ x BN_ output tile per workgroup of 4 waves (2 x 2),
+// each wave (BM_ / 2) x (BN_ / 2) = WTM x WTN MFMA tiles of 16 x 16.
+//   Cfg128: 128 x 128, waves of 64 x 64 (BF16 and split-BF16x3);
+//   Cfg256: 256 x 128, waves of 128 x 64: per MFMA a quarter fewer LDS
+//           fragment reads and operand loads (BF16 only: the x3 form would
+//           need more registers than two waves per SIMD have).
+template <int BM_, int BN_>
+struct BfCfg {
+  static constexpr int BM = BM_, BN = BN_;
+  static constexpr int WTM = BM / 32, WTN = BN / 32;  // 16 x 16 tiles per wave
+  static constexpr int A_LOADS = BM * BK / 8 / NTHREADS, B_LOADS = BN * BK / 8 / NTHREADS;
+  static_assert(A_LOADS * 8 * NTHREADS == BM * BK && B_LOADS * 8 * NTHREADS == BN * BK, "whole 16-byte pieces");
+};
+using Cfg128 = BfCfg<128, 128>;
+using Cfg256 = BfCfg<256, 128>;
+
+template <class C, bool X3>
 struct Lds {
-  __bf16 a[2][X3 ? 2 : 1][BM * KS];  // [buffer][hi|lo][row][k]
-  __bf16 b[2][X3 ? 2 : 1][BN * KS];  // [buffer][hi|lo][col][k]
+  __bf16 a[2][X3 ? 2 : 1][C::BM * KS];  // [buffer][hi|lo][row][k]
+  __bf16 b[2][X3 ? 2 : 1][C::BN * KS];  // [buffer][hi|lo][col][k]
 };
 
 constexpr int PLANES_MAX = 2;
 
-// 16-byte piece idx of a 128 x 32 tile -> (row, first k).
+// 16-byte piece idx of a rows x 32 tile -> (row, first k).
 __device__ __forceinline__ void piece(int idx, int& row, int& kc) {
   row = idx / (BK / 8);
   kc = (idx % (BK / 8)) * 8;
 }
 
-template <bool X3>
+template <class C, bool X3>
 __device__ __forceinline__ void load_stage(const __bf16* a, const __bf16* b, int64_t plane, int m, int i0, int j0,
-                                           int k0, int t, bf8 (&ra)[PLANES_MAX][LOADS],
-                                           bf8 (&rb)[PLANES_MAX][LOADS]) {
+                                           int k0, int t, bf8 (&ra)[PLANES_MAX][C::A_LOADS],
+                                           bf8 (&rb)[PLANES_MAX][C::B_LOADS]) {
   constexpr int P = X3 ? 2 : 1;
 #pragma unroll
   for (int pl = 0; pl < P; ++pl) {
     const __amdgpu_buffer_rsrc_t sa = raw_rsrc(a + pl * plane + (size_t)i0 * m + k0);
     const __amdgpu_buffer_rsrc_t sb = raw_rsrc(b + pl * plane + (size_t)j0 * m + k0);
 #pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
+    for (int q = 0; q < C::A_LOADS; ++q) {
       int row, kc;
       piece(t + NTHREADS * q, row, kc);
-      const int off = (row * m + kc) * 2;  // row < 128, m <= 2^19: below 2^31 bytes
+      const int off = (row * m + kc) * 2;  // row < 256, m <= 2^19: below 2^31 bytes
       ra[pl][q] = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(sa, off, 0, 0));
+    }
+#pragma unroll
+    for (int q = 0; q < C::B_LOADS; ++q) {
+      int row, kc;
+      piece(t + NTHREADS * q, row, kc);
+      const int off = (row * m + kc) * 2;
       rb[pl][q] = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(sb, off, 0, 0));
     }
   }
 }
 
-template <bool X3>
-__device__ __forceinline__ void store_stage(Lds<X3>& L, int buf, int t, const bf8 (&ra)[PLANES_MAX][LOADS],
-                                            const bf8 (&rb)[PLANES_MAX][LOADS]) {
+template <class C, bool X3>
+__device__ __forceinline__ void store_stage(Lds<C, X3>& L, int buf, int t, const bf8 (&ra)[PLANES_MAX][C::A_LOADS],
+                                            const bf8 (&rb)[PLANES_MAX][C::B_LOADS]) {
   constexpr int P = X3 ? 2 : 1;
 #pragma unroll
-  for (int pl = 0; pl < P; ++pl)
+  for (int pl = 0; pl < P; ++pl) {
 #pragma unroll
-    for (int q = 0; q < LOADS; ++q) {
+    for (int q = 0; q < C::A_LOADS; ++q) {
       int row, kc;
       piece(t + NTHREADS * q, row, kc);
       *reinterpret_cast<bf8*>(&L.a[buf][pl][row * KS + kc]) = ra[pl][q];
+    }
+#pragma unroll
+    for (int q = 0; q < C::B_LOADS; ++q) {
+      int row, kc;
+      piece(t + NTHREADS * q, row, kc);
       *reinterpret_cast<bf8*>(&L.b[buf][pl][row * KS + kc]) = rb[pl][q];
     }
+  }
 }
 
-template <bool X3>
-__device__ __forceinline__ void k_loop(Lds<X3>& L, const __bf16* a, const __bf16* b, int64_t plane, int m, int i0,
-                                       int j0, int t, int wm, int wn, int lr, int lk, f4 (&acc)[WT][WT]) {
-  bf8 ra[PLANES_MAX][LOADS], rb[PLANES_MAX][LOADS];
+template <class C, bool X3>
+__device__ __forceinline__ void k_loop(Lds<C, X3>& L, const __bf16* a, const __bf16* b, int64_t plane, int m, int i0,
+                                       int j0, int t, int wm, int wn, int lr, int lk,
+                                       f4 (&acc)[C::WTM][C::WTN]) {
+  constexpr int WTM = C::WTM, WTN = C::WTN;
+  bf8 ra[PLANES_MAX][C::A_LOADS], rb[PLANES_MAX][C::B_LOADS];
   const int KT = m / BK;
-  load_stage<X3>(a, b, plane, m, i0, j0, 0, t, ra, rb);
-  store_stage<X3>(L, 0, t, ra, rb);
+  load_stage<C, X3>(a, b, plane, m, i0, j0, 0, t, ra, rb);
+  store_stage<C, X3>(L, 0, t, ra, rb);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < KT;
-    if (more) load_stage<X3>(a, b, plane, m, i0, j0, (kt + 1) * BK, t, ra, rb);
-    bf8 ah[WT], bh[WT];
+    if (more) load_stage<C, X3>(a, b, plane, m, i0, j0, (kt + 1) * BK, t, ra, rb);
+    bf8 ah[WTM], bh[WTN];
 #pragma unroll
-    for (int mi = 0; mi < WT; ++mi) ah[mi] = *reinterpret_cast<const bf8*>(&L.a[cur][0][(wm + 16 * mi + lr) * KS + 8 * lk]);
+    for (int mi = 0; mi < WTM; ++mi)
+      ah[mi] = *reinterpret_cast<const bf8*>(&L.a[cur][0][(wm + 16 * mi + lr) * KS + 8 * lk]);
 #pragma unroll
-    for (int ni = 0; ni < WT; ++ni) bh[ni] = *reinterpret_cast<const bf8*>(&L.b[cur][0][(wn + 16 * ni + lr) * KS + 8 * lk]);
+    for (int ni = 0; ni < WTN; ++ni)
+      bh[ni] = *reinterpret_cast<const bf8*>(&L.b[cur][0][(wn + 16 * ni + lr) * KS + 8 * lk]);
     if constexpr (X3) {
-      bf8 al[WT], bl[WT];
+      bf8 al[WTM], bl[WTN];
 #pragma unroll
-      for (int mi = 0; mi < WT; ++mi)
+      for (int mi = 0; mi < WTM; ++mi)
         al[mi] = *reinterpret_cast<const bf8*>(&L.a[cur][1][(wm + 16 * mi + lr) * KS + 8 * lk]);
 #pragma unroll
-      for (int ni = 0; ni < WT; ++ni)
+      for (int ni = 0; ni < WTN; ++ni)
         bl[ni] = *reinterpret_cast<const bf8*>(&L.b[cur][1][(wn + 16 * ni + lr) * KS + 8 * lk]);
 #pragma unroll
-      for (int mi = 0; mi < WT; ++mi)
+      for (int mi = 0; mi < WTM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < WT; ++ni) {
+        for (int ni = 0; ni < WTN; ++ni) {
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
         }
     } else {
 #pragma unroll
-      for (int mi = 0; mi < WT; ++mi)
+      for (int mi = 0; mi < WTM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < WT; ++ni)
+        for (int ni = 0; ni < WTN; ++ni)
           acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
     }
-    if (more) store_stage<X3>(L, cur ^ 1, t, ra, rb);
+    if (more) store_stage<C, X3>(L, cur ^ 1, t, ra, rb);
     __syncthreads();
   }
 }
 
-template <bool X3>
+template <class C, bool X3>
 __global__ void __launch_bounds__(NTHREADS, 2)
     gemm_bf16_grouped(GemmArgs<float> g, const __bf16* __restrict__ staged, int nprod, int64_t plane) {
-  __shared__ Lds<X3> L;
+  __shared__ Lds<C, X3> L;
+  constexpr int WTM = C::WTM, WTN = C::WTN;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave >> 1) * (C::BM / 2), wn = (wave & 1) * (C::BN / 2);
   const int lr = lane & 15, lk = lane >> 4;
   int grp, ti, tj;
   work_of(blockIdx.x, g.tiles_m, g.tiles_n, g.groups, &grp, &ti, &tj);
-  const int i0 = ti * BM, j0 = tj * BN;
+  const int i0 = ti * C::BM, j0 = tj * C::BN;
   const int r_beg = load_uniform(g.group_beg + grp), r_end = load_uniform(g.group_beg + grp + 1);
   constexpr int P = X3 ? 2 : 1;
 
@@ -222,22 +254,22 @@ __global__ void __launch_bounds__(NTHREADS, 2)
     const ProdDesc pd = load_uniform(g.prods + r);
     const __bf16* a = staged + (size_t)r * P * plane;
     const __bf16* b = staged + (size_t)(nprod + r) * P * plane;
-    f4 acc[WT][WT];
+    f4 acc[WTM][WTN];
 #pragma unroll
-    for (int mi = 0; mi < WT; ++mi)
+    for (int mi = 0; mi < WTM; ++mi)
 #pragma unroll
-      for (int ni = 0; ni < WT; ++ni) acc[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
-    k_loop<X3>(L, a, b, plane, g.m, i0, j0, t, wm, wn, lr, lk, acc);
+      for (int ni = 0; ni < WTN; ++ni) acc[mi][ni] = f4{0.f, 0.f, 0.f, 0.f};
+    k_loop<C, X3>(L, a, b, plane, g.m, i0, j0, t, wm, wn, lr, lk, acc);
 
     for (int e = pd.epi_beg; e < pd.epi_end; ++e) {
       const EpiDesc ed = load_uniform(g.epis + e);
       float* pc = dst_ptr(g, ed.c_src) + ed.c_off;
-      const bool full = (i0 + BM <= ed.c_vr) && (j0 + BN <= ed.c_vc);
+      const bool full = (i0 + C::BM <= ed.c_vr) && (j0 + C::BN <= ed.c_vc);
       const float coef = (float)ed.coef;
 #pragma unroll
-      for (int mi = 0; mi < WT; ++mi)
+      for (int mi = 0; mi < WTM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < WT; ++ni)
+        for (int ni = 0; ni < WTN; ++ni)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = i0 + wm + 16 * mi + 4 * lk + v;
@@ -250,6 +282,10 @@ __global__ void __launch_bounds__(NTHREADS, 2)
 }
 
 }  // namespace bf
+
+#ifndef MF_BF16_BIG_TILES
+#define MF_BF16_BIG_TILES 1
+#endif
 
 hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
                             hipStream_t s) {
@@ -264,8 +300,6 @@ hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* 
   g.group_beg = pl.d_group_beg;
   g.groups = pl.groups;
   g.m = (int)pl.m;
-  g.tiles_m = (int)(pl.m / bf::BM);
-  g.tiles_n = (int)(pl.m / bf::BN);
   g.vec_in = 0;
   if (pl.bf_base < 0 || !ws) return hipErrorInvalidValue;
   __bf16* staged = reinterpret_cast<__bf16*>(static_cast<char*>(ws) + pl.bf_base);
@@ -278,13 +312,21 @@ hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* 
     hipLaunchKernelGGL(bf::stage_bf16<false>, sgrid, dim3(256), 0, s, g, staged, nprod, plane);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n * (unsigned)g.groups;
+  const __bf16* st = staged;
+  auto launch = [&](auto cfg, auto x3c) {
+    typedef decltype(cfg) Cf;
+    constexpr bool X = decltype(x3c)::value;
+    g.tiles_m = (int)(pl.m / Cf::BM);
+    g.tiles_n = (int)(pl.m / Cf::BN);
+    const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n * (unsigned)g.groups;
+    hipLaunchKernelGGL((bf::gemm_bf16_grouped<Cf, X>), dim3(grid), dim3(bf::NTHREADS), 0, s, g, st, nprod, plane);
+  };
   if (x3)
-    hipLaunchKernelGGL(bf::gemm_bf16_grouped<true>, dim3(grid), dim3(bf::NTHREADS), 0, s, g,
-                       (const __bf16*)staged, nprod, plane);
+    launch(bf::Cfg128{}, std::true_type{});
+  else if (MF_BF16_BIG_TILES && pl.m % bf::Cfg256::BM == 0)
+    launch(bf::Cfg256{}, std::false_type{});
   else
-    hipLaunchKernelGGL(bf::gemm_bf16_grouped<false>, dim3(grid), dim3(bf::NTHREADS), 0, s, g,
-                       (const __bf16*)staged, nprod, plane);
+    launch(bf::Cfg128{}, std::false_type{});
   return hipGetLastError();
 }
 

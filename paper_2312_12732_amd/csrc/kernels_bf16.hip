@@ -10,17 +10,17 @@
 //            hi_a lo_b + lo_a hi_b + hi_a hi_b (the lo_a lo_b term dropped),
 //            recovering close to FP32 product accuracy.
 //
-// Two launches.  The staging kernel converts every leaf operand once: the A
-// operand of each product to row-major BF16 planes, the B operand transposed
-// (so that both have k contiguous), zero beyond the view's valid extent, into
-// the plan's BF16 region of the workspace.  The GEMM kernel then streams
-// 16-byte BF16 rows straight into LDS: no conversion, no masking, and half
-// the operand bytes of FP32 per plane.
+// Two launches.  The staging kernel converts every leaf operand once into the
+// plan's BF16 region of the workspace: the A operand of each product by rows,
+// the B operand transposed (so that both run along k), zero beyond the view's
+// valid extent, in the block order described below.  The GEMM kernel then
+// copies contiguous 1 KiB blocks straight into LDS: no conversion, no
+// masking, and half the operand bytes of FP32 per plane.
 //
 // MFMA lane layout (16 x 16 x 32): lane l holds A[l % 16][8 (l / 16) + t] and
 // B[8 (l / 16) + t][l % 16] for t = 0..7; element v of the result is
-// D[4 (l / 16) + v][l % 16].  Both LDS tiles are stored with k contiguous
-// (A row-major, B transposed) so a fragment is one 16-byte read.
+// D[4 (l / 16) + v][l % 16].  Both LDS tiles hold k contiguous in 16-byte
+// groups (A by rows, B transposed) so a fragment is one 16-byte read.
 #include <type_traits>
 
 #include "gemm_tile.h"
@@ -34,74 +34,113 @@ typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int BK = 32;
-constexpr int KS = BK + 8;     // bf16 elements per LDS row: 80 bytes, 16-byte aligned, conflict-free reads
-constexpr int NTHREADS = 256;  // 4 waves, 2 x 2
+// Operand layout, shared by the staged planes in HBM and the LDS tiles.  A
+// plane (m x m; its rows are the rows of A or the columns of B, k runs along
+// each row) is cut into blocks of 16 rows x 32 k (1 KiB), stored k-block
+// major: block (K, R) starts at element 512 (K (m / 16) + R).  Inside a
+// block, row r holds its 64 bytes in four 16-byte slots, k group g
+// (k = 8g .. 8g + 7) in slot g ^ ((r >> 1) & 3).
+//   * The operand tile of one K step (BM rows) is BM / 16 consecutive blocks:
+//     each wave load instruction reads 1 KiB of contiguous bytes (8 whole
+//     cache lines), and its LDS image is a plain copy.  With row-major planes
+//     every load instruction touched 16 rows in 16 cache lines and the
+//     texture data path was 97% busy at 0.44 MFMA utilisation.
+//   * The MFMA fragment reads (lanes 0-15 on 16 rows of one k group; lane
+//     group l / 16 on k group l / 16) and the linear LDS writes run with no
+//     bank conflict on gfx950 (measured SQ_LDS_BANK_CONFLICT = 0 for each
+//     pattern; rows padded to 80 bytes cost 4 conflict cycles per fragment
+//     read and 8 per write).
+constexpr int KS = BK;  // bf16 elements per LDS row (64 bytes)
+
+// Element offset of k group g (8 elements) of row r inside a block-ordered tile.
+__device__ __forceinline__ int lds_slot(int r, int g) { return r * KS + 8 * (g ^ ((r >> 1) & 3)); }
+
+// Element offset in a staged plane (leaf size m) of element (row i, k).
+__device__ __forceinline__ int64_t staged_off(int i, int k, int m) {
+  return ((int64_t)(k / BK) * (m / 16) + i / 16) * (16 * BK) + lds_slot(i % 16, (k % BK) / 8) + k % 8;
+}
 
 // ---------------------------------------------------------------------------
-// Staging: FP32 leaf operand views -> BF16 planes
+// Staging: the last pre-addition level, fused with the BF16 conversion
 // ---------------------------------------------------------------------------
 
-constexpr int ST = 64;  // staging tile (ST x ST elements per workgroup of 256 threads)
 
-// Block (x, y, z): columns x*64.., rows y*64.. of operand z (z < nprod: A of
-// product z; otherwise B of product z - nprod, written transposed).
-template <bool X3>
-__global__ void __launch_bounds__(256) stage_bf16(GemmArgs<float> g, __bf16* dst_base, int nprod, int64_t plane) {
-  __shared__ float tile[ST][ST + 1];
-  const int z = blockIdx.z;
-  const bool bside = z >= nprod;
-  const ProdDesc pd = load_uniform(g.prods + (bside ? z - nprod : z));
-  const float* src = bside ? src_ptr(g, pd.b_src) + pd.b_off : src_ptr(g, pd.a_src) + pd.a_off;
-  const int ld = bside ? pd.ldb : pd.lda;
-  const int vr = bside ? pd.b_vr : pd.a_vr, vc = bside ? pd.b_vc : pd.a_vc;
-  const int r0 = blockIdx.y * ST, c0 = blockIdx.x * ST;
-  const int t = threadIdx.x;
+constexpr int ST = 32;  // staging tile: ST x ST elements of every input of a set per workgroup
+
+template <int NIN>
+struct CoefRow {
+  float c[NIN];
+};
+
+// Block (x, y): tile x (row-major over the m x m quarter) of staging set y.
+// Thread t owns 4 elements of the tile: for A operands (side 0) row lr and
+// columns lc .. lc + 3 of every input (staged row r0 + lr, k = c0 + lc ..);
+// for B operands (side 1) column lr and rows lc .. lc + 3 (staged row
+// c0 + lr, k = r0 + lc ..), so that the transposition happens in the loads
+// and every input value is read once, into registers (zero outside a view's
+// valid extent).  Each output of the set is then z = sum_k coef[k] in_k in
+// FP32, in input order, the first nonzero term scaled and the others added by
+// fused multiply-add (an exact add or subtract for the coefficients +-1),
+// rounded to BF16 (and the BF16 rest for split-BF16x3) and written in the
+// block order of the staged planes.  vec_in: views of the caller's A and B
+// may be read as aligned 16-byte vectors (workspace views always can).
+template <int NIN, bool X3>
+__global__ void __launch_bounds__(256)
+    stage_sets(GemmArgs<float> g, __bf16* dst_base, int64_t plane, const StageSet* __restrict__ sets,
+               const CombIn* __restrict__ ins, const StageOut* __restrict__ outs, const float* __restrict__ coef,
+               int vec_in) {
+  const StageSet ss = load_uniform(sets + blockIdx.y);
   const int m = g.m;
-  __bf16* hi = dst_base + (size_t)z * (X3 ? 2 : 1) * plane;
-  __bf16* lo = hi + plane;
-  // thread t reads 4 consecutive columns of rows t / 16 + 16 q
-  const int cc = (t % 16) * 4;
+  const int tiles_x = m / ST;
+  const int r0 = (int)(blockIdx.x / tiles_x) * ST, c0 = (int)(blockIdx.x % tiles_x) * ST;
+  const int t = threadIdx.x;
+  const int lr = t / 8, lc = (t % 8) * 4;
+  const bool bside = ss.side != 0;
+  f4 x[NIN];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int rr = t / 16 + 16 * q;
-    const int i = r0 + rr;
-    f4 v;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int j = c0 + cc + u;
-      v[u] = (i < vr && j < vc) ? src[(size_t)i * ld + j] : 0.f;
-    }
+  for (int k = 0; k < NIN; ++k) {
+    const CombIn in = load_uniform(ins + ss.in_beg + k);
+    const float* src = src_ptr(g, in.src) + in.off;
     if (!bside) {
-      bf4 h, l;
+      const int i = r0 + lr, j = c0 + lc;
+      if (r0 + ST <= in.vr && c0 + ST <= in.vc && (vec_in || in.src == SRC_WS)) {
+        x[k] = *reinterpret_cast<const f4*>(src + (size_t)i * in.ld + j);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[k][u] = (i < in.vr && j + u < in.vc) ? src[(size_t)i * in.ld + j + u] : 0.f;
+      }
+    } else {
+      const int j = c0 + lr;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        h[u] = (__bf16)v[u];
-        l[u] = (__bf16)(v[u] - (float)h[u]);
+        const int i = r0 + lc + u;
+        x[k][u] = (i < in.vr && j < in.vc) ? src[(size_t)i * in.ld + j] : 0.f;
       }
-      *reinterpret_cast<bf4*>(hi + (size_t)i * m + c0 + cc) = h;
-      if (X3) *reinterpret_cast<bf4*>(lo + (size_t)i * m + c0 + cc) = l;
-    } else {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) tile[rr][cc + u] = v[u];
     }
   }
-  if (!bside) return;  // uniform per workgroup
-  __syncthreads();
-  // transposed: output row c0 + c holds column c of the tile; thread t writes
-  // 4 consecutive k (tile rows) of output rows t / 16 + 16 q
+  const int srow = bside ? c0 + lr : r0 + lr, sk = bside ? r0 + lc : c0 + lc;
+  for (int o = ss.out_beg; o < ss.out_end; ++o) {
+    const StageOut so = load_uniform(outs + o);
+    const CoefRow<NIN> cr = load_uniform(reinterpret_cast<const CoefRow<NIN>*>(coef + so.coef_off));
+    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+    bool first = true;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int c = t / 16 + 16 * q;
-    const int kk = (t % 16) * 4;
+    for (int k = 0; k < NIN; ++k) {
+      const float c = cr.c[k];
+      if (c == 0.f) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = first ? c * x[k][u] : __builtin_fmaf(c, x[k][u], acc[u]);
+      first = false;
+    }
+    __bf16* hi = dst_base + (size_t)so.z * (X3 ? 2 : 1) * plane;
     bf4 h, l;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const float x = tile[kk + u][c];
-      h[u] = (__bf16)x;
-      l[u] = (__bf16)(x - (float)h[u]);
+      h[u] = (__bf16)acc[u];
+      l[u] = (__bf16)(acc[u] - (float)h[u]);
     }
-    *reinterpret_cast<bf4*>(hi + (size_t)(c0 + c) * m + r0 + kk) = h;
-    if (X3) *reinterpret_cast<bf4*>(lo + (size_t)(c0 + c) * m + r0 + kk) = l;
+    *reinterpret_cast<bf4*>(hi + staged_off(srow, sk, m)) = h;
+    if (X3) *reinterpret_cast<bf4*>(hi + plane + staged_off(srow, sk, m)) = l;
   }
 }
 
@@ -109,59 +148,59 @@ __global__ void __launch_bounds__(256) stage_bf16(GemmArgs<float> g, __bf16* dst
 // GEMM on staged BF16 operands
 // ---------------------------------------------------------------------------
 
-// Tile geometry: a BM_ x BN_ output tile per workgroup of 4 waves (2 x 2),
-// each wave (BM_ / 2) x (BN_ / 2) = WTM x WTN MFMA tiles of 16 x 16.
-//   Cfg128: 128 x 128, waves of 64 x 64 (BF16 and split-BF16x3);
-//   Cfg256: 256 x 128, waves of 128 x 64: per MFMA a quarter fewer LDS
-//           fragment reads and operand loads (BF16 only: the x3 form would
-//           need more registers than two waves per SIMD have).
-template <int BM_, int BN_>
+// Tile geometry: a BM_ x BN_ output tile per workgroup of WM_ x WN_ waves,
+// each wave (BM_ / WM_) x (BN_ / WN_) = WTM x WTN MFMA tiles of 16 x 16; two
+// waves per SIMD either way.
+//   Cfg128: 128 x 128, 2 x 2 waves of 64 x 64 (BF16 and split-BF16x3),
+//           two workgroups per CU;
+//   Cfg256: 256 x 128, 2 x 2 waves of 128 x 64, two workgroups per CU: a
+//           quarter fewer LDS fragment reads per MFMA (BF16 only: the x3
+//           form's hi and lo fragments do not fit this wave tile);
+//   CfgSq:  256 x 256, 2 x 4 waves of 128 x 64, one workgroup per CU: the
+//           wave tile of Cfg256 with a third less operand traffic from L2
+//           per flop, which bounds BF16 at these tile sizes;
+//   CfgW:   256 x 128, 4 x 2 waves of 64 x 64, one workgroup per CU (either
+//           form).
+template <int BM_, int BN_, int WM_, int WN_>
 struct BfCfg {
-  static constexpr int BM = BM_, BN = BN_;
-  static constexpr int WTM = BM / 32, WTN = BN / 32;  // 16 x 16 tiles per wave
-  static constexpr int A_LOADS = BM * BK / 8 / NTHREADS, B_LOADS = BN * BK / 8 / NTHREADS;
-  static_assert(A_LOADS * 8 * NTHREADS == BM * BK && B_LOADS * 8 * NTHREADS == BN * BK, "whole 16-byte pieces");
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
+  static constexpr int NT = 64 * WM * WN;                       // threads per workgroup
+  static constexpr int MIN_BLOCKS = 512 / NT;                   // two waves per SIMD
+  static constexpr int WTM = BM / WM / 16, WTN = BN / WN / 16;  // 16 x 16 tiles per wave
+  static constexpr int A_LOADS = BM * BK / 8 / NT, B_LOADS = BN * BK / 8 / NT;
+  static_assert(A_LOADS * 8 * NT == BM * BK && B_LOADS * 8 * NT == BN * BK, "whole 16-byte pieces");
 };
-using Cfg128 = BfCfg<128, 128>;
-using Cfg256 = BfCfg<256, 128>;
+using Cfg128 = BfCfg<128, 128, 2, 2>;
+using Cfg256 = BfCfg<256, 128, 2, 2>;
+using CfgSq = BfCfg<256, 256, 2, 4>;
+using CfgW = BfCfg<256, 128, 4, 2>;
 
 template <class C, bool X3>
 struct Lds {
-  __bf16 a[2][X3 ? 2 : 1][C::BM * KS];  // [buffer][hi|lo][row][k]
-  __bf16 b[2][X3 ? 2 : 1][C::BN * KS];  // [buffer][hi|lo][col][k]
+  __bf16 a[2][X3 ? 2 : 1][C::BM * KS];  // [buffer][hi|lo][block order, as staged]
+  __bf16 b[2][X3 ? 2 : 1][C::BN * KS];
 };
 
 constexpr int PLANES_MAX = 2;
 
-// 16-byte piece idx of a rows x 32 tile -> (row, first k).
-__device__ __forceinline__ void piece(int idx, int& row, int& kc) {
-  row = idx / (BK / 8);
-  kc = (idx % (BK / 8)) * 8;
-}
-
+// The operand tiles of one K step are contiguous in the staged planes and
+// in LDS (same block order): thread t moves 16-byte pieces t + NT q.
 template <class C, bool X3>
 __device__ __forceinline__ void load_stage(const __bf16* a, const __bf16* b, int64_t plane, int m, int i0, int j0,
                                            int k0, int t, bf8 (&ra)[PLANES_MAX][C::A_LOADS],
                                            bf8 (&rb)[PLANES_MAX][C::B_LOADS]) {
   constexpr int P = X3 ? 2 : 1;
+  const int64_t kb = (int64_t)(k0 / BK) * (m / 16);
 #pragma unroll
   for (int pl = 0; pl < P; ++pl) {
-    const __amdgpu_buffer_rsrc_t sa = raw_rsrc(a + pl * plane + (size_t)i0 * m + k0);
-    const __amdgpu_buffer_rsrc_t sb = raw_rsrc(b + pl * plane + (size_t)j0 * m + k0);
+    const __amdgpu_buffer_rsrc_t sa = raw_rsrc(a + pl * plane + (kb + i0 / 16) * (16 * BK));
+    const __amdgpu_buffer_rsrc_t sb = raw_rsrc(b + pl * plane + (kb + j0 / 16) * (16 * BK));
 #pragma unroll
-    for (int q = 0; q < C::A_LOADS; ++q) {
-      int row, kc;
-      piece(t + NTHREADS * q, row, kc);
-      const int off = (row * m + kc) * 2;  // row < 256, m <= 2^19: below 2^31 bytes
-      ra[pl][q] = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(sa, off, 0, 0));
-    }
+    for (int q = 0; q < C::A_LOADS; ++q)
+      ra[pl][q] = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(sa, (t + C::NT * q) * 16, 0, 0));
 #pragma unroll
-    for (int q = 0; q < C::B_LOADS; ++q) {
-      int row, kc;
-      piece(t + NTHREADS * q, row, kc);
-      const int off = (row * m + kc) * 2;
-      rb[pl][q] = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(sb, off, 0, 0));
-    }
+    for (int q = 0; q < C::B_LOADS; ++q)
+      rb[pl][q] = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(sb, (t + C::NT * q) * 16, 0, 0));
   }
 }
 
@@ -172,27 +211,99 @@ __device__ __forceinline__ void store_stage(Lds<C, X3>& L, int buf, int t, const
 #pragma unroll
   for (int pl = 0; pl < P; ++pl) {
 #pragma unroll
-    for (int q = 0; q < C::A_LOADS; ++q) {
-      int row, kc;
-      piece(t + NTHREADS * q, row, kc);
-      *reinterpret_cast<bf8*>(&L.a[buf][pl][row * KS + kc]) = ra[pl][q];
-    }
+    for (int q = 0; q < C::A_LOADS; ++q) *reinterpret_cast<bf8*>(&L.a[buf][pl][(t + C::NT * q) * 8]) = ra[pl][q];
 #pragma unroll
-    for (int q = 0; q < C::B_LOADS; ++q) {
-      int row, kc;
-      piece(t + NTHREADS * q, row, kc);
-      *reinterpret_cast<bf8*>(&L.b[buf][pl][row * KS + kc]) = rb[pl][q];
-    }
+    for (int q = 0; q < C::B_LOADS; ++q) *reinterpret_cast<bf8*>(&L.b[buf][pl][(t + C::NT * q) * 8]) = rb[pl][q];
   }
 }
+
+// MFMA work of one K step from LDS buffer cur.
+template <class C, bool X3>
+__device__ __forceinline__ void mma_step(const Lds<C, X3>& L, int cur, int wm, int wn, int lr, int lk,
+                                         f4 (&acc)[C::WTM][C::WTN]) {
+  constexpr int WTM = C::WTM, WTN = C::WTN;
+  bf8 ah[WTM], bh[WTN];
+#pragma unroll
+  for (int mi = 0; mi < WTM; ++mi)
+    ah[mi] = *reinterpret_cast<const bf8*>(&L.a[cur][0][lds_slot(wm + 16 * mi + lr, lk)]);
+#pragma unroll
+  for (int ni = 0; ni < WTN; ++ni)
+    bh[ni] = *reinterpret_cast<const bf8*>(&L.b[cur][0][lds_slot(wn + 16 * ni + lr, lk)]);
+  if constexpr (X3) {
+    bf8 al[WTM], bl[WTN];
+#pragma unroll
+    for (int mi = 0; mi < WTM; ++mi)
+      al[mi] = *reinterpret_cast<const bf8*>(&L.a[cur][1][lds_slot(wm + 16 * mi + lr, lk)]);
+#pragma unroll
+    for (int ni = 0; ni < WTN; ++ni)
+      bl[ni] = *reinterpret_cast<const bf8*>(&L.b[cur][1][lds_slot(wn + 16 * ni + lr, lk)]);
+#pragma unroll
+    for (int mi = 0; mi < WTM; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < WTN; ++ni) {
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+      }
+  } else {
+#pragma unroll
+    for (int mi = 0; mi < WTM; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < WTN; ++ni)
+        acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+  }
+}
+
+// K loop.  MF_BF16_PREFETCH = 1: the loads of step k+1 are issued at the start
+// of step k and written to LDS at its end.  MF_BF16_PREFETCH = 2: two register
+// sets; the loads of step k+2 are issued at the start of step k and written to
+// LDS at the end of step k+1, so two steps of MFMA work cover their latency.
+// The leaf size is a multiple of 128, so the number of steps (m / 32) is a
+// multiple of 4; past the end the loads repeat the last step (in bounds, never
+// read back).
+#ifndef MF_BF16_PREFETCH
+#define MF_BF16_PREFETCH 2
+#endif
+// MF_BF16_FENCE = 1 keeps the scheduler from sinking the loads of a step below
+// its MFMAs (it does so to save registers, which shortens the prefetch
+// distance); measured slower than leaving the schedule to the compiler.
+#ifndef MF_BF16_FENCE
+#define MF_BF16_FENCE 0
+#endif
+#if MF_BF16_FENCE
+#define MF_BF16_ISSUE_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define MF_BF16_ISSUE_FENCE() ((void)0)
+#endif
 
 template <class C, bool X3>
 __device__ __forceinline__ void k_loop(Lds<C, X3>& L, const __bf16* a, const __bf16* b, int64_t plane, int m, int i0,
                                        int j0, int t, int wm, int wn, int lr, int lk,
                                        f4 (&acc)[C::WTM][C::WTN]) {
-  constexpr int WTM = C::WTM, WTN = C::WTN;
-  bf8 ra[PLANES_MAX][C::A_LOADS], rb[PLANES_MAX][C::B_LOADS];
   const int KT = m / BK;
+#if MF_BF16_PREFETCH == 2
+  bf8 ra0[PLANES_MAX][C::A_LOADS], rb0[PLANES_MAX][C::B_LOADS];
+  bf8 ra1[PLANES_MAX][C::A_LOADS], rb1[PLANES_MAX][C::B_LOADS];
+  load_stage<C, X3>(a, b, plane, m, i0, j0, 0, t, ra0, rb0);
+  load_stage<C, X3>(a, b, plane, m, i0, j0, BK, t, ra1, rb1);
+  store_stage<C, X3>(L, 0, t, ra0, rb0);
+  __syncthreads();
+  for (int kt = 0; kt < KT; kt += 2) {
+    // LDS buffer 0 holds step kt; set 1 holds step kt + 1 (in flight)
+    load_stage<C, X3>(a, b, plane, m, i0, j0, min(kt + 2, KT - 1) * BK, t, ra0, rb0);
+    MF_BF16_ISSUE_FENCE();
+    mma_step<C, X3>(L, 0, wm, wn, lr, lk, acc);
+    store_stage<C, X3>(L, 1, t, ra1, rb1);
+    __syncthreads();
+    // LDS buffer 1 holds step kt + 1; set 0 holds step kt + 2 (in flight)
+    load_stage<C, X3>(a, b, plane, m, i0, j0, min(kt + 3, KT - 1) * BK, t, ra1, rb1);
+    MF_BF16_ISSUE_FENCE();
+    mma_step<C, X3>(L, 1, wm, wn, lr, lk, acc);
+    store_stage<C, X3>(L, 0, t, ra0, rb0);
+    __syncthreads();
+  }
+#else
+  bf8 ra[PLANES_MAX][C::A_LOADS], rb[PLANES_MAX][C::B_LOADS];
   load_stage<C, X3>(a, b, plane, m, i0, j0, 0, t, ra, rb);
   store_stage<C, X3>(L, 0, t, ra, rb);
   __syncthreads();
@@ -200,49 +311,21 @@ __device__ __forceinline__ void k_loop(Lds<C, X3>& L, const __bf16* a, const __b
     const int cur = kt & 1;
     const bool more = kt + 1 < KT;
     if (more) load_stage<C, X3>(a, b, plane, m, i0, j0, (kt + 1) * BK, t, ra, rb);
-    bf8 ah[WTM], bh[WTN];
-#pragma unroll
-    for (int mi = 0; mi < WTM; ++mi)
-      ah[mi] = *reinterpret_cast<const bf8*>(&L.a[cur][0][(wm + 16 * mi + lr) * KS + 8 * lk]);
-#pragma unroll
-    for (int ni = 0; ni < WTN; ++ni)
-      bh[ni] = *reinterpret_cast<const bf8*>(&L.b[cur][0][(wn + 16 * ni + lr) * KS + 8 * lk]);
-    if constexpr (X3) {
-      bf8 al[WTM], bl[WTN];
-#pragma unroll
-      for (int mi = 0; mi < WTM; ++mi)
-        al[mi] = *reinterpret_cast<const bf8*>(&L.a[cur][1][(wm + 16 * mi + lr) * KS + 8 * lk]);
-#pragma unroll
-      for (int ni = 0; ni < WTN; ++ni)
-        bl[ni] = *reinterpret_cast<const bf8*>(&L.b[cur][1][(wn + 16 * ni + lr) * KS + 8 * lk]);
-#pragma unroll
-      for (int mi = 0; mi < WTM; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < WTN; ++ni) {
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
-        }
-    } else {
-#pragma unroll
-      for (int mi = 0; mi < WTM; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < WTN; ++ni)
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
-    }
+    mma_step<C, X3>(L, cur, wm, wn, lr, lk, acc);
     if (more) store_stage<C, X3>(L, cur ^ 1, t, ra, rb);
     __syncthreads();
   }
+#endif
 }
 
 template <class C, bool X3>
-__global__ void __launch_bounds__(NTHREADS, 2)
+__global__ void __launch_bounds__(C::NT, C::MIN_BLOCKS)
     gemm_bf16_grouped(GemmArgs<float> g, const __bf16* __restrict__ staged, int nprod, int64_t plane) {
   __shared__ Lds<C, X3> L;
   constexpr int WTM = C::WTM, WTN = C::WTN;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wm = (wave >> 1) * (C::BM / 2), wn = (wave & 1) * (C::BN / 2);
+  const int wm = (wave / C::WN) * (C::BM / C::WM), wn = (wave % C::WN) * (C::BN / C::WN);
   const int lr = lane & 15, lk = lane >> 4;
   int grp, ti, tj;
   work_of(blockIdx.x, g.tiles_m, g.tiles_n, g.groups, &grp, &ti, &tj);
@@ -283,13 +366,19 @@ __global__ void __launch_bounds__(NTHREADS, 2)
 
 }  // namespace bf
 
-#ifndef MF_BF16_BIG_TILES
-#define MF_BF16_BIG_TILES 1
+bool stage_supported(int nin) { return nin == 1 || nin == 4 || nin == 9 || nin == 16; }
+
+// Tile choice per form: 0 Cfg128, 1 Cfg256, 2 CfgSq, 3 CfgW (a choice whose
+// tile does not divide the leaf size falls back to Cfg128).
+#ifndef MF_BF16_TILE
+#define MF_BF16_TILE 2
+#endif
+#ifndef MF_BF16X3_TILE
+#define MF_BF16X3_TILE 3
 #endif
 
 hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
                             hipStream_t s) {
-  (void)vec_in;  // the staged operands are always aligned and whole
   GemmArgs<float> g;
   g.A = static_cast<const float*>(A);
   g.B = static_cast<const float*>(B);
@@ -301,15 +390,29 @@ hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* 
   g.groups = pl.groups;
   g.m = (int)pl.m;
   g.vec_in = 0;
-  if (pl.bf_base < 0 || !ws) return hipErrorInvalidValue;
+  if (pl.bf_base < 0 || !ws || pl.bf_outs.size() != 2 * pl.prods.size()) return hipErrorInvalidValue;
   __bf16* staged = reinterpret_cast<__bf16*>(static_cast<char*>(ws) + pl.bf_base);
   const int nprod = (int)pl.prods.size();
   const int64_t plane = pl.m * pl.m;
-  const dim3 sgrid((unsigned)(pl.m / bf::ST), (unsigned)(pl.m / bf::ST), (unsigned)(2 * nprod));
-  if (x3)
-    hipLaunchKernelGGL(bf::stage_bf16<true>, sgrid, dim3(256), 0, s, g, staged, nprod, plane);
-  else
-    hipLaunchKernelGGL(bf::stage_bf16<false>, sgrid, dim3(256), 0, s, g, staged, nprod, plane);
+  const dim3 sgrid((unsigned)((pl.m / bf::ST) * (pl.m / bf::ST)), (unsigned)pl.bf_sets.size());
+  const int vin = vec_in ? 1 : 0;
+  bool staged_ok = false;
+  auto stage = [&](auto nin) {
+    constexpr int N = decltype(nin)::value;
+    if (pl.bf_nin != N) return;
+    staged_ok = true;
+    if (x3)
+      hipLaunchKernelGGL((bf::stage_sets<N, true>), sgrid, dim3(256), 0, s, g, staged, plane, pl.d_bf_sets,
+                         pl.d_bf_ins, pl.d_bf_outs, pl.d_bf_coef, vin);
+    else
+      hipLaunchKernelGGL((bf::stage_sets<N, false>), sgrid, dim3(256), 0, s, g, staged, plane, pl.d_bf_sets,
+                         pl.d_bf_ins, pl.d_bf_outs, pl.d_bf_coef, vin);
+  };
+  stage(std::integral_constant<int, 1>{});
+  stage(std::integral_constant<int, 4>{});
+  stage(std::integral_constant<int, 9>{});
+  stage(std::integral_constant<int, 16>{});
+  if (!staged_ok) return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const __bf16* st = staged;
@@ -319,14 +422,20 @@ hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* 
     g.tiles_m = (int)(pl.m / Cf::BM);
     g.tiles_n = (int)(pl.m / Cf::BN);
     const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n * (unsigned)g.groups;
-    hipLaunchKernelGGL((bf::gemm_bf16_grouped<Cf, X>), dim3(grid), dim3(bf::NTHREADS), 0, s, g, st, nprod, plane);
+    hipLaunchKernelGGL((bf::gemm_bf16_grouped<Cf, X>), dim3(grid), dim3(Cf::NT), 0, s, g, st, nprod, plane);
+  };
+  auto pick = [&](int choice, auto x3c) {
+    if constexpr (!decltype(x3c)::value) {  // tiles whose wave tile only the BF16 form fits
+      if (choice == 1 && pl.m % bf::Cfg256::BM == 0) return launch(bf::Cfg256{}, x3c);
+      if (choice == 2 && pl.m % bf::CfgSq::BM == 0) return launch(bf::CfgSq{}, x3c);
+    }
+    if (choice == 3 && pl.m % bf::CfgW::BM == 0) return launch(bf::CfgW{}, x3c);
+    launch(bf::Cfg128{}, x3c);
   };
   if (x3)
-    launch(bf::Cfg128{}, std::true_type{});
-  else if (MF_BF16_BIG_TILES && pl.m % bf::Cfg256::BM == 0)
-    launch(bf::Cfg256{}, std::false_type{});
+    pick(MF_BF16X3_TILE, std::true_type{});
   else
-    launch(bf::Cfg128{}, std::false_type{});
+    pick(MF_BF16_TILE, std::false_type{});
   return hipGetLastError();
 }
 

@@ -124,6 +124,22 @@ struct CombineStage {
   mutable double* d_coef = nullptr;
 };
 
+// BF16 leaves: the last pre-addition level runs fused with the BF16 staging.
+// One set per block of the level above: its nin quarters are the inputs, and
+// each child that is a leaf operand is staged operand z = sum_k coef[k] in_k
+// (z < products: the A operand of product z, by rows; otherwise the B
+// operand of product z - products, transposed).
+struct StageSet {
+  int32_t in_beg;
+  int32_t out_beg, out_end;
+  int32_t side;  // 0: A operands, 1: B operands
+};
+
+struct StageOut {
+  int32_t z;
+  int32_t coef_off;  // nin coefficients, one per input (zeros included)
+};
+
 // ---------------------------------------------------------------------------
 // Plans
 // ---------------------------------------------------------------------------
@@ -161,6 +177,13 @@ struct Plan {
   // transposed (row j holds column j), each plane m x m.
   int64_t bf_base = -1;
   int bf_planes = 0;
+  // The staging sets (see StageSet): every staged operand is the output of
+  // exactly one set; bf_nin inputs per set, each quarter of size m.
+  int bf_nin = 0;
+  std::vector<StageSet> bf_sets;
+  std::vector<CombIn> bf_ins;
+  std::vector<StageOut> bf_outs;
+  std::vector<float> bf_coef;
   // device copy (one allocation, owned by the plan), made on first use
   mutable std::once_flag uploaded;
   mutable mf_status upload_status = MF_OK;
@@ -168,6 +191,10 @@ struct Plan {
   mutable ProdDesc* d_prods = nullptr;
   mutable EpiDesc* d_epis = nullptr;
   mutable int32_t* d_group_beg = nullptr;
+  mutable StageSet* d_bf_sets = nullptr;
+  mutable CombIn* d_bf_ins = nullptr;
+  mutable StageOut* d_bf_outs = nullptr;
+  mutable float* d_bf_coef = nullptr;
   ~Plan();
 };
 
@@ -270,6 +297,8 @@ hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* 
                             hipStream_t s);
 // Input counts with a compiled linear-combination kernel.
 bool combine_supported(int nin);
+// BF16 staging sets exist for this many inputs per set.
+bool stage_supported(int nin);
 
 // Persistent batched kernel: runs `ntasks` tasks with `grid` workgroups.
 // ctr holds nctr counters, then the ticket, then the abort flag (all must be

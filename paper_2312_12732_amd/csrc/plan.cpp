@@ -41,6 +41,9 @@ struct Blk {
   int32_t vr = 0, vc = 0;
   double scale = 1.0;
   bool zero = true;
+  // BF16 leaves: the staging set that forms this leaf operand and its
+  // coefficients (see Plan::bf_sets)
+  int32_t stage_set = -1, stage_coef = -1;
 };
 
 // Quarter k (row-major in the p x p split) of block b, of size s.
@@ -81,14 +84,45 @@ void finish_set(CombineStage* st, CombSet set) {
   st->sets.push_back(set);
 }
 
+bool bf16_leaves(int dtype) {
+  const int leaf = (dtype >> 8) & 0xff;
+  return leaf == 2 || leaf == 3;
+}
+
 // BF16 leaves: reserve the staged operands (see Plan::bf_base) after
-// everything else in the workspace.
-void finish_bf16(Plan* pl) {
+// everything else in the workspace, and list the outputs of every staging
+// set: ops_a[z] / ops_b[z] are the leaf blocks of product z.
+void finish_bf16(Plan* pl, const std::vector<Blk>& ops_a, const std::vector<Blk>& ops_b) {
+  if (!bf16_leaves(pl->dtype)) return;
   const int leaf = (pl->dtype >> 8) & 0xff;
-  if (leaf != 2 && leaf != 3) return;
   pl->bf_planes = leaf == 3 ? 2 : 1;
   pl->bf_base = (int64_t)round_up((int64_t)pl->ws_bytes, 256);
   pl->ws_bytes = (size_t)pl->bf_base + (size_t)2 * pl->prods.size() * pl->bf_planes * pl->m * pl->m * 2;
+  const int32_t np = (int32_t)pl->prods.size();
+  std::vector<std::vector<StageOut>> per_set(pl->bf_sets.size());
+  for (int32_t z = 0; z < np; ++z) {
+    const Blk& a = ops_a[(size_t)z];
+    const Blk& b = ops_b[(size_t)z];
+    per_set[(size_t)a.stage_set].push_back({z, a.stage_coef});
+    per_set[(size_t)b.stage_set].push_back({np + z, b.stage_coef});
+  }
+  pl->bf_outs.clear();
+  for (size_t k = 0; k < per_set.size(); ++k) {
+    pl->bf_sets[k].out_beg = (int32_t)pl->bf_outs.size();
+    pl->bf_outs.insert(pl->bf_outs.end(), per_set[k].begin(), per_set[k].end());
+    pl->bf_sets[k].out_end = (int32_t)pl->bf_outs.size();
+  }
+}
+
+// BF16 leaves: a staging set over the p^2 quarters q of one block; returns
+// its index.
+int32_t add_stage_set(Plan* pl, int side, const std::vector<Blk>& q) {
+  StageSet ss{};
+  ss.in_beg = (int32_t)pl->bf_ins.size();
+  ss.side = side;
+  for (const Blk& b : q) pl->bf_ins.push_back(as_input(b));
+  pl->bf_sets.push_back(ss);
+  return (int32_t)pl->bf_sets.size() - 1;
 }
 
 mf_status build_classical(int64_t n, Plan* pl) {
@@ -112,7 +146,21 @@ mf_status build_classical(int64_t n, Plan* pl) {
   ed.coef = 1.0;
   pl->epis.push_back(ed);
   pl->group_beg = {0, 1};
-  finish_bf16(pl);
+  if (bf16_leaves(pl->dtype)) {  // each operand is a set of one input
+    Blk ops[2];
+    pl->bf_nin = 1;
+    for (int side = 0; side < 2; ++side) {
+      Blk& b = ops[side];
+      b.src = side == 0 ? SRC_A : SRC_B;
+      b.ld = (int32_t)n;
+      b.vr = b.vc = (int32_t)n;
+      b.zero = false;
+      b.stage_set = add_stage_set(pl, side, {b});
+      b.stage_coef = (int32_t)pl->bf_coef.size();
+      pl->bf_coef.push_back(1.0f);
+    }
+    finish_bf16(pl, {ops[0]}, {ops[1]});
+  }
   return MF_OK;
 }
 
@@ -129,6 +177,10 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
     return fail(MF_ERR_UNSUPPORTED, "no linear-combination kernel for this algorithm shape");
   const int64_t P = ipow(p, L);
   pl->P = (int)P;
+  if (bf16_leaves(dtype)) {
+    if (!stage_supported(p2)) return fail(MF_ERR_UNSUPPORTED, "no BF16 staging kernel for this algorithm shape");
+    pl->bf_nin = p2;
+  }
   pl->m = round_up((n + P - 1) / P, kLeafTile);
   pl->npad = pl->m * P;
   const int64_t m = pl->m;
@@ -153,7 +205,9 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
     return off;
   };
 
-  // ---- pre-addition stages, level by level, both operands in each launch
+  // ---- pre-addition stages, level by level, both operands in each launch.
+  // BF16 leaves fuse the last level into the staging kernel: its linear
+  // combinations become term lists instead of FP32 workspace blocks.
   std::vector<Blk> leaves[2];
   {
     std::vector<Blk> cur[2];
@@ -179,6 +233,38 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
         for (const Blk& b : cur[side]) {
           std::vector<Blk> q(p2);
           for (int k = 0; k < p2; ++k) q[k] = quarter(b, k, p, sz);
+          if (lev == L && bf16_leaves(pl->dtype)) {
+            // last level fused with the BF16 staging: every nonzero child is
+            // an output of this block's staging set (aliased ones included)
+            if (b.zero) {
+              next[side].resize(next[side].size() + (size_t)R);
+              continue;
+            }
+            const int32_t set_idx = add_stage_set(pl, side, q);
+            for (int r = 0; r < R; ++r) {
+              Blk child;
+              const int32_t coef_off = (int32_t)pl->bf_coef.size();
+              bool any = false;
+              for (int k = 0; k < p2; ++k) {
+                const double x = q[k].zero ? 0.0 : X[(size_t)k * R + r] * b.scale;
+                any = any || x != 0.0;
+                pl->bf_coef.push_back((float)x);
+              }
+              if (!any) pl->bf_coef.resize((size_t)coef_off);
+              if (any) {
+                child.src = SRC_WS;
+                child.off = 0;
+                child.ld = (int32_t)sz;
+                child.vr = child.vc = (int32_t)sz;
+                child.scale = 1.0;
+                child.zero = false;
+                child.stage_set = set_idx;
+                child.stage_coef = coef_off;
+              }
+              next[side].push_back(child);
+            }
+            continue;
+          }
           CombSet set{};
           set.in_beg = (int32_t)st.ins.size();
           set.out_beg = (int32_t)st.outs.size();
@@ -238,6 +324,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
 
   // ---- grouped leaf products with the inner post-addition in the epilogue
   std::vector<char> group_empty(G, 1);
+  std::vector<Blk> ops_a, ops_b;  // BF16 leaves: the leaf blocks in product order
   for (int g = 0; g < G; ++g) {
     pl->group_beg.push_back((int32_t)pl->prods.size());
     const int nout = Pi * Pi;
@@ -290,6 +377,10 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
       }
       pd.epi_end = (int32_t)pl->epis.size();
       pl->prods.push_back(pd);
+      if (bf16_leaves(pl->dtype)) {
+        ops_a.push_back(a);
+        ops_b.push_back(b);
+      }
       group_empty[g] = 0;
     }
     // Output blocks that no product of the group feeds are zero; the first
@@ -376,7 +467,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
     }
   }
   pl->ws_bytes = (size_t)ws * pl->elem;
-  finish_bf16(pl);
+  finish_bf16(pl, ops_a, ops_b);
   return MF_OK;
 }
 
@@ -394,7 +485,11 @@ mf_status upload(const Plan* pl) {
   };
   std::vector<Part> parts = {{pl->prods.data(), bytes_of(pl->prods), 0},
                              {pl->epis.data(), bytes_of(pl->epis), 0},
-                             {pl->group_beg.data(), bytes_of(pl->group_beg), 0}};
+                             {pl->group_beg.data(), bytes_of(pl->group_beg), 0},
+                             {pl->bf_sets.data(), bytes_of(pl->bf_sets), 0},
+                             {pl->bf_ins.data(), bytes_of(pl->bf_ins), 0},
+                             {pl->bf_outs.data(), bytes_of(pl->bf_outs), 0},
+                             {pl->bf_coef.data(), bytes_of(pl->bf_coef), 0}};
   std::vector<const CombineStage*> stages;
   for (const auto& st : pl->pre) stages.push_back(&st);
   for (const auto& st : pl->post) stages.push_back(&st);
@@ -425,11 +520,15 @@ mf_status upload(const Plan* pl) {
   pl->d_prods = reinterpret_cast<ProdDesc*>(d + parts[0].off);
   pl->d_epis = reinterpret_cast<EpiDesc*>(d + parts[1].off);
   pl->d_group_beg = reinterpret_cast<int32_t*>(d + parts[2].off);
+  pl->d_bf_sets = reinterpret_cast<StageSet*>(d + parts[3].off);
+  pl->d_bf_ins = reinterpret_cast<CombIn*>(d + parts[4].off);
+  pl->d_bf_outs = reinterpret_cast<StageOut*>(d + parts[5].off);
+  pl->d_bf_coef = reinterpret_cast<float*>(d + parts[6].off);
   for (size_t i = 0; i < stages.size(); ++i) {
-    stages[i]->d_sets = reinterpret_cast<CombSet*>(d + parts[3 + 4 * i].off);
-    stages[i]->d_ins = reinterpret_cast<CombIn*>(d + parts[4 + 4 * i].off);
-    stages[i]->d_outs = reinterpret_cast<CombOut*>(d + parts[5 + 4 * i].off);
-    stages[i]->d_coef = reinterpret_cast<double*>(d + parts[6 + 4 * i].off);
+    stages[i]->d_sets = reinterpret_cast<CombSet*>(d + parts[7 + 4 * i].off);
+    stages[i]->d_ins = reinterpret_cast<CombIn*>(d + parts[8 + 4 * i].off);
+    stages[i]->d_outs = reinterpret_cast<CombOut*>(d + parts[9 + 4 * i].off);
+    stages[i]->d_coef = reinterpret_cast<double*>(d + parts[10 + 4 * i].off);
   }
   return MF_OK;
 }

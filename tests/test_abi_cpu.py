@@ -295,12 +295,19 @@ def test_plan_query_closed_forms():
 def test_workspace_bytes_bf16_staging():
     """BF16 leaves stage every leaf operand once as BF16 planes (2 planes for
     split-BF16x3): A operands and transposed B operands, m x m each, placed
-    after the FP32 workspace (256-byte aligned)."""
+    after the FP32 workspace (256-byte aligned).  The last pre-addition level
+    is fused into the staging, so its sums take no FP32 workspace: Strassen at
+    depth 1 keeps only the 7 stored products (the FP32 leaves also hold the 4
+    + 4 materialised operand sums)."""
     s = mf.mf_algo_builtin("strassen")
-    f32 = mf.mf_workspace_bytes(s, 1, 0, 8192, mf.MF_F32)
-    base = -(-f32 // 256) * 256
+    m2 = 4096 ** 2
+    assert mf.mf_workspace_bytes(s, 1, 0, 8192, mf.MF_F32) == (8 + 7) * m2 * 4
     for leaf, planes in ((mf.MF_LEAF_BF16, 1), (mf.MF_LEAF_BF16X3, 2)):
-        assert mf.mf_workspace_bytes(s, 1, 0, 8192, mf.MF_F32 | leaf) == base + 2 * 7 * planes * 4096 ** 2 * 2
+        assert mf.mf_workspace_bytes(s, 1, 0, 8192, mf.MF_F32 | leaf) == 7 * m2 * 4 + 2 * 7 * planes * m2 * 2
+        # depth 2: the 8 level-1 sums (4096^2) are stored, level 2 is fused; 49 stored products (2048^2) and
+        # the 7 level-1 results of the post-addition (4096^2)
+        assert mf.mf_workspace_bytes(s, 2, 0, 8192, mf.MF_F32 | leaf) == \
+            (8 * m2 + 49 * m2 // 4 + 7 * m2) * 4 + 2 * 49 * planes * (m2 // 4) * 2
         # classical: one product, a 1000 x 1000 problem in a 1024 leaf
         assert mf.mf_workspace_bytes(s, 0, 0, 1000, mf.MF_F32 | leaf) == 2 * planes * 1024 ** 2 * 2
     assert mf.mf_workspace_bytes(s, 0, 0, 1000, mf.MF_F32 | mf.MF_LEAF_F32) == 0

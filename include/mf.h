@@ -131,7 +131,8 @@ mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int 
 
 /* Bytes of device workspace mf_fastmm_ws needs for this request (0 for a
  * classical product with leaves in the storage type; BF16 leaves stage every
- * leaf operand as BF16 planes). */
+ * leaf operand as BF16 planes, and their last pre-addition level writes those
+ * planes directly, so its FP32 sums take no workspace). */
 mf_status mf_workspace_bytes(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
                              size_t* bytes);
 

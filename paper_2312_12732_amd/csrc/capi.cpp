@@ -111,6 +111,8 @@ mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, h
     if (ph == 0) {
       for (const CombineStage& st : pl.pre)
         if (e == hipSuccess) e = launch_combine(st, (int)pl.elem, A, B, C, ws, vec_in, vec_c, s);
+      // BF16 leaves: the last pre-addition level, fused with the staging
+      if (e == hipSuccess && (leaf == 2 || leaf == 3)) e = launch_stage_bf16(pl, leaf == 3, A, B, C, ws, vec_in, s);
     } else if (ph == 2) {
       for (const CombineStage& st : pl.post)
         if (e == hipSuccess) e = launch_combine(st, (int)pl.elem, A, B, C, ws, vec_in, vec_c, s);

@@ -377,8 +377,9 @@ bool stage_supported(int nin) { return nin == 1 || nin == 4 || nin == 9 || nin =
 #define MF_BF16X3_TILE 3
 #endif
 
-hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
-                            hipStream_t s) {
+namespace {
+
+GemmArgs<float> bf_args(const Plan& pl, const void* A, const void* B, void* C, void* ws) {
   GemmArgs<float> g;
   g.A = static_cast<const float*>(A);
   g.B = static_cast<const float*>(B);
@@ -390,9 +391,20 @@ hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* 
   g.groups = pl.groups;
   g.m = (int)pl.m;
   g.vec_in = 0;
-  if (pl.bf_base < 0 || !ws || pl.bf_outs.size() != 2 * pl.prods.size()) return hipErrorInvalidValue;
+  return g;
+}
+
+bool bf_plan_ok(const Plan& pl, const void* ws) {
+  return pl.bf_base >= 0 && ws && pl.bf_outs.size() == 2 * pl.prods.size();
+}
+
+}  // namespace
+
+hipError_t launch_stage_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
+                             hipStream_t s) {
+  if (!bf_plan_ok(pl, ws)) return hipErrorInvalidValue;
+  const GemmArgs<float> g = bf_args(pl, A, B, C, ws);
   __bf16* staged = reinterpret_cast<__bf16*>(static_cast<char*>(ws) + pl.bf_base);
-  const int nprod = (int)pl.prods.size();
   const int64_t plane = pl.m * pl.m;
   const dim3 sgrid((unsigned)((pl.m / bf::ST) * (pl.m / bf::ST)), (unsigned)pl.bf_sets.size());
   const int vin = vec_in ? 1 : 0;
@@ -413,9 +425,17 @@ hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* 
   stage(std::integral_constant<int, 9>{});
   stage(std::integral_constant<int, 16>{});
   if (!staged_ok) return hipErrorInvalidValue;
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const __bf16* st = staged;
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
+                            hipStream_t s) {
+  (void)vec_in;  // the staged operands are aligned and whole
+  if (!bf_plan_ok(pl, ws)) return hipErrorInvalidValue;
+  GemmArgs<float> g = bf_args(pl, A, B, C, ws);
+  const __bf16* st = reinterpret_cast<const __bf16*>(static_cast<char*>(ws) + pl.bf_base);
+  const int nprod = (int)pl.prods.size();
+  const int64_t plane = pl.m * pl.m;
   auto launch = [&](auto cfg, auto x3c) {
     typedef decltype(cfg) Cf;
     constexpr bool X = decltype(x3c)::value;

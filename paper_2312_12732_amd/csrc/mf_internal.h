@@ -173,8 +173,9 @@ struct Plan {
   std::vector<CombineStage> pre, post;  // in launch order
   // BF16 leaves: every leaf operand is staged once as BF16 (two planes, hi
   // and lo, for split-BF16x3) in the workspace from this byte offset on: the
-  // A operands of products 0..R-1 (row-major m x m), then the B operands
-  // transposed (row j holds column j), each plane m x m.
+  // A operands of the products in product order, then their B operands
+  // transposed (row j holds column j), each plane m x m in the block order of
+  // the BF16 GEMM (16 x 32 blocks, k-block major).
   int64_t bf_base = -1;
   int bf_planes = 0;
   // The staging sets (see StageSet): every staged operand is the output of
@@ -293,6 +294,10 @@ hipError_t launch_gemm_f64(const Plan& pl, const void* A, const void* B, void* C
                            hipStream_t s);
 hipError_t launch_gemm_f32(const Plan& pl, const void* A, const void* B, void* C, void* ws, bool vec_in,
                            hipStream_t s);
+// BF16 leaves: the staging launch (the last pre-addition level fused with the
+// conversion to BF16 planes), then the grouped GEMM on the staged planes.
+hipError_t launch_stage_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
+                             hipStream_t s);
 hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
                             hipStream_t s);
 // Input counts with a compiled linear-combination kernel.

@@ -145,3 +145,37 @@ def test_bf16_staging_large_ragged(leaf, n, depth):
     cols = np.unique(np.concatenate([np.random.default_rng(n + 1).choice(n, size=24, replace=False), [0, n - 1]]))
     assert np.array_equal(got[rows], om.rows_reference(A, B, rows))
     assert np.array_equal(got[:, cols], A @ B[:, cols])
+
+
+@pytest.mark.parametrize("leaf", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("name,n", [("444", 300), ("444", 301), ("classical3", 299), ("winograd", 301)])
+def test_bf16_staging_sets_int_exact(leaf, name, n):
+    """BF16 leaves fuse the last pre-addition level into the staging: one
+    staging set per block of the level above, 16 inputs for <4,4,4;49>
+    (Winograd composed with itself), 9 for the <3,3,3;27> classical control,
+    4 for Winograd.  Ragged sizes put quarters partly or wholly in the virtual
+    padding; odd n makes the caller's rows unaligned (element-wise loads).
+    Integer inputs in [-2, 2] keep every staged operand (|T| <= 16 * 2) exact in
+    BF16 and every sum below 2^24, so the result must be the integer product."""
+    A = mi.int_uniform(n, 92, -2, 2).astype(np.float64)
+    B = mi.int_uniform(n, 93, -2, 2).astype(np.float64)
+    w = mf.mf_algo_builtin("winograd")
+    algo = mf.mf_algo_compose(w, w) if name == "444" else mf.mf_algo_builtin(name)
+    got = run(algo, 1, A, B, LEAVES[leaf])
+    assert np.array_equal(got, A @ B)
+
+
+@pytest.mark.parametrize("leaf", ["bf16", "bf16x3"])
+def test_bf16_fused_depth2_uniform_error(leaf):
+    """Kronecker-fused depth 2 (one level of <4,4,4;49>) with BF16 leaves
+    matches the level-by-level depth 2 within the leaf tolerance, and both stay
+    within it against the FP64 oracle."""
+    n = 512
+    A = mi.uniform(n, 94).astype(np.float32).astype(np.float64)
+    B = mi.uniform(n, 95).astype(np.float32).astype(np.float64)
+    w = mf.mf_algo_builtin("winograd")
+    ref = ref64(A, B)
+    fused = run(mf.mf_algo_compose(w, w), 1, A, B, LEAVES[leaf])
+    level = run(w, 2, A, B, LEAVES[leaf])
+    assert om.rel_fro_error(fused, ref) < TOL[leaf]
+    assert om.rel_fro_error(level, ref) < TOL[leaf]

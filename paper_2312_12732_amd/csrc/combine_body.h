@@ -39,6 +39,20 @@ __device__ __forceinline__ T* comb_dst(const CombArgs<T>& g, int dst) {
   return dst == SRC_C ? g.C : g.ws;
 }
 
+// Streaming stores of whole output vectors: MF_COMB_NT = 1 marks them
+// non-temporal.
+#ifndef MF_COMB_NT
+#define MF_COMB_NT 0
+#endif
+template <class V>
+__device__ __forceinline__ void store_out(V* p, const V& v) {
+#if MF_COMB_NT
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
 template <class T, int NIN, int VEC, bool FULL>
 __device__ __forceinline__ void combine_body(const CombArgs<T>& g, const CombSet& set, int i, int j) {
   typedef T tv __attribute__((ext_vector_type(VEC)));
@@ -83,12 +97,12 @@ __device__ __forceinline__ void combine_body(const CombArgs<T>& g, const CombSet
     if (!started) acc = (tv)(T(0));
     T* p = comb_dst(g, po.dst) + po.off + (int64_t)i * po.ld + j;
     if (FULL) {
-      *reinterpret_cast<tv*>(p) = acc;
+      store_out(reinterpret_cast<tv*>(p), acc);
     } else {
       if (i >= po.vr) continue;
       const bool vec = po.dst == SRC_WS || g.vec_out;
       if (vec && j + VEC <= po.vc) {
-        *reinterpret_cast<tv*>(p) = acc;
+        store_out(reinterpret_cast<tv*>(p), acc);
       } else {
 #pragma unroll
         for (int q = 0; q < VEC; ++q)
@@ -160,12 +174,12 @@ __device__ __forceinline__ void combine_acc_body(const CombArgs<T>& g, const Com
     const CombOut po = load_uniform(g.outs + set.out_beg + o);
     T* p = comb_dst(g, po.dst) + po.off + (int64_t)i * po.ld + j;
     if (FULL) {
-      *reinterpret_cast<tv*>(p) = acc[o];
+      store_out(reinterpret_cast<tv*>(p), acc[o]);
     } else {
       if (i >= po.vr) continue;
       const bool vec = po.dst == SRC_WS || g.vec_out;
       if (vec && j + VEC <= po.vc) {
-        *reinterpret_cast<tv*>(p) = acc[o];
+        store_out(reinterpret_cast<tv*>(p), acc[o]);
       } else {
 #pragma unroll
         for (int q = 0; q < VEC; ++q)

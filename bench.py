@@ -616,7 +616,9 @@ def run_algorithms(args):
     cases = [("classical", None, 0)]
     cases += [(f"strassen d{d}", stras, d) for d in (1, 2, 3)]
     cases += [(f"winograd d{d}", wino, d) for d in (1, 2, 3)]
-    cases += [("<4,4,4;49> d1", c444, 1), ("rebased strassen d1", rebased, 1), ("rebased strassen d2", rebased, 2),
+    c888 = mf.mf_algo_compose(c444, wino)
+    cases += [("<4,4,4;49> d1", c444, 1), ("<8,8,8;343> d1 (Kronecker-fused depth 3)", c888, 1),
+              ("rebased strassen d1", rebased, 1), ("rebased strassen d2", rebased, 2),
               ("<3,3,3;27> d1 (control)", c3, 1)]
     results = []
     for n in (4096, 8192):

@@ -67,6 +67,14 @@ Algo compose(const Algo& outer, const Algo& inner) {
   // grid at position (I % p2, J % p2) inside it; product r = r1 * R2 + r2 has
   // the product of the outer and inner coefficients.
   Algo c;
+  auto flat = [](const Algo& a) {
+    if (!a.factors.empty()) return a.factors;
+    Algo f = a;
+    f.factors.clear();
+    return std::vector<Algo>{f};
+  };
+  c.factors = flat(outer);
+  for (const Algo& f : flat(inner)) c.factors.push_back(f);
   const int p1 = outer.p, p2 = inner.p, R1 = outer.R, R2 = inner.R;
   c.p = p1 * p2;
   c.R = R1 * R2;

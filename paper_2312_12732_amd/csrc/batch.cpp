@@ -73,10 +73,10 @@ mf_status build_batch(mf_batch* b, const std::vector<const mf_algo*>& algos, con
                             kStandaloneMinWorkgroups, &pl);
     if (st != MF_OK) return st;
     for (const CombineStage& cs : pl->pre)
-      if (!batch_stage_supported(cs.nin, cs.nout_max, kPersistentBatch))
+      if (cs.kron3 || !batch_stage_supported(cs.nin, cs.nout_max, kPersistentBatch))
         return fail(MF_ERR_UNSUPPORTED, "algorithm shape not supported in batches");
     for (const CombineStage& cs : pl->post)
-      if (!batch_stage_supported(cs.nin, cs.nout_max, kPersistentBatch))
+      if (cs.kron3 || !batch_stage_supported(cs.nin, cs.nout_max, kPersistentBatch))
         return fail(MF_ERR_UNSUPPORTED, "algorithm shape not supported in batches");
     b->plans.push_back(pl);
     if (!recs.count(pl.get())) {

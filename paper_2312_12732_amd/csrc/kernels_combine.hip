@@ -41,6 +41,152 @@ __global__ void __launch_bounds__(256) combine_acc(CombArgs<T> g) {
     combine_acc_body<T, NIN, NOUT, VEC, false>(g, set, i, j);
 }
 
+// ---------------------------------------------------------------------------
+// Kronecker-factored combinations: one level of <8,8,8;343>, the
+// three-factor composition of <2,2,2;7> algorithms (U = U1 (x) U2 (x) U3, and
+// so for V and W; Section 2, the Kronecker construction).  A set has 64
+// blocks on one side and 343 on the other, too many for coefficients per
+// output, so the sums run factor by factor in registers:
+//   pre:  T[r1 r2 r3] = sum_t1 U1[t1,r1] sum_t2 U2[t2,r2] sum_t3 U3[t3,r3] X[t1 t2 t3]
+//   post: C[c1 c2 c3] = sum_r1 W1[c1,r1] sum_r2 W2[c2,r2] sum_r3 W3[c3,r3] P[r1 r2 r3]
+// The same sums as the composed coefficients give, associated factor by
+// factor (so not bitwise those of the generic kernels; integers stay exact).
+// Every input element is read once and every stored output written once.
+// ---------------------------------------------------------------------------
+
+template <class T, int VEC>
+__device__ __forceinline__ void kron_load(const CombArgs<T>& g, const CombIn& v, int i, int j,
+                                          T (&x)[VEC]) {
+  typedef T tv __attribute__((ext_vector_type(VEC)));
+  const T* p = comb_src(g, v.src) + v.off + (int64_t)i * v.ld + j;
+  const bool vec = v.src == SRC_WS || g.vec_in;
+  if (vec && i < v.vr && j + VEC <= v.vc) {
+    const tv y = *reinterpret_cast<const tv*>(p);
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) x[q] = y[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) x[q] = (i < v.vr && j + q < v.vc) ? p[q] : T(0);
+  }
+}
+
+template <class T, int VEC>
+__device__ __forceinline__ void kron_store(const CombArgs<T>& g, const CombOut& po, int i, int j,
+                                           const T (&x)[VEC]) {
+  typedef T tv __attribute__((ext_vector_type(VEC)));
+  if (i >= po.vr) return;  // also every output that is not stored (empty extent)
+  T* p = comb_dst(g, po.dst) + po.off + (int64_t)i * po.ld + j;
+  const bool vec = po.dst == SRC_WS || g.vec_out;
+  if (vec && j + VEC <= po.vc) {
+    tv y;
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) y[q] = x[q];
+    *reinterpret_cast<tv*>(p) = y;
+  } else {
+#pragma unroll
+    for (int q = 0; q < VEC; ++q)
+      if (j + q < po.vc) p[q] = x[q];
+  }
+}
+
+// c * x + acc on VEC lanes, skipped for c = 0 (c is wave-uniform)
+template <class T, int VEC>
+__device__ __forceinline__ void kron_axpy(T c, const T (&x)[VEC], T (&acc)[VEC]) {
+  if (c == T(0)) return;
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) acc[q] = fma_t(c, x[q], acc[q]);
+}
+
+// Register budget: the pre-addition holds the 64 inputs (two waves per SIMD;
+// three spill).  The post-addition holds the 64 outputs; unrolling its r2
+// loop hoists up to 49 loads and drops it to one wave per SIMD (FP64 n = 8192:
+// 1.41 ms against 1.00 ms not unrolled).
+#ifndef MF_KRON_PRE_WAVES
+#define MF_KRON_PRE_WAVES 2
+#endif
+#ifndef MF_KRON_POST_UNROLL
+#define MF_KRON_POST_UNROLL 1
+#endif
+
+template <class T, int VEC>
+__global__ void __launch_bounds__(256, MF_KRON_PRE_WAVES) kron3_pre(CombArgs<T> g) {
+  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  const int64_t mm = (int64_t)g.m * g.m;
+  if (e >= mm) return;
+  const int i = (int)(e / g.m), j = (int)(e % g.m);
+  const CombSet set = load_uniform(g.sets + blockIdx.y);
+  const double* cf = g.coef + load_uniform(g.outs + set.out_beg).coef_off;  // U1 | U2 | U3, each 4 x 7
+  T x[64][VEC];
+#pragma unroll
+  for (int t = 0; t < 64; ++t) kron_load<T, VEC>(g, load_uniform(g.ins + set.in_beg + t), i, j, x[t]);
+  for (int r1 = 0; r1 < 7; ++r1) {
+    T y[16][VEC] = {};
+#pragma unroll
+    for (int t1 = 0; t1 < 4; ++t1) {
+      const T c = (T)load_uniform(cf + t1 * 7 + r1);
+#pragma unroll
+      for (int t = 0; t < 16; ++t) kron_axpy<T, VEC>(c, x[16 * t1 + t], y[t]);
+    }
+#pragma unroll
+    for (int r2 = 0; r2 < 7; ++r2) {
+      T z[4][VEC] = {};
+#pragma unroll
+      for (int t2 = 0; t2 < 4; ++t2) {
+        const T c = (T)load_uniform(cf + 28 + t2 * 7 + r2);
+#pragma unroll
+        for (int t3 = 0; t3 < 4; ++t3) kron_axpy<T, VEC>(c, y[4 * t2 + t3], z[t3]);
+      }
+#pragma unroll
+      for (int r3 = 0; r3 < 7; ++r3) {
+        T o[VEC] = {};
+#pragma unroll
+        for (int t3 = 0; t3 < 4; ++t3) kron_axpy<T, VEC>((T)load_uniform(cf + 56 + t3 * 7 + r3), z[t3], o);
+        kron_store<T, VEC>(g, load_uniform(g.outs + set.out_beg + 49 * r1 + 7 * r2 + r3), i, j, o);
+      }
+    }
+  }
+}
+
+template <class T, int VEC>
+__global__ void __launch_bounds__(256) kron3_post(CombArgs<T> g) {
+  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  const int64_t mm = (int64_t)g.m * g.m;
+  if (e >= mm) return;
+  const int i = (int)(e / g.m), j = (int)(e % g.m);
+  const CombSet set = load_uniform(g.sets + blockIdx.y);
+  const double* cf = g.coef + load_uniform(g.outs + set.out_beg).coef_off;  // W1 | W2 | W3, each 4 x 7
+  T out[64][VEC] = {};
+  for (int r1 = 0; r1 < 7; ++r1) {
+    T t[16][VEC] = {};
+#pragma unroll MF_KRON_POST_UNROLL
+    for (int r2 = 0; r2 < 7; ++r2) {
+      T P[7][VEC];
+#pragma unroll
+      for (int r3 = 0; r3 < 7; ++r3)
+        kron_load<T, VEC>(g, load_uniform(g.ins + set.in_beg + 49 * r1 + 7 * r2 + r3), i, j, P[r3]);
+      T u[4][VEC] = {};
+#pragma unroll
+      for (int c3 = 0; c3 < 4; ++c3)
+#pragma unroll
+        for (int r3 = 0; r3 < 7; ++r3) kron_axpy<T, VEC>((T)load_uniform(cf + 56 + c3 * 7 + r3), P[r3], u[c3]);
+#pragma unroll
+      for (int c2 = 0; c2 < 4; ++c2) {
+        const T c = (T)load_uniform(cf + 28 + c2 * 7 + r2);
+#pragma unroll
+        for (int c3 = 0; c3 < 4; ++c3) kron_axpy<T, VEC>(c, u[c3], t[4 * c2 + c3]);
+      }
+    }
+#pragma unroll
+    for (int c1 = 0; c1 < 4; ++c1) {
+      const T c = (T)load_uniform(cf + c1 * 7 + r1);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) kron_axpy<T, VEC>(c, t[k], out[16 * c1 + k]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 64; ++c) kron_store<T, VEC>(g, load_uniform(g.outs + set.out_beg + c), i, j, out[c]);
+}
+
 #ifndef MF_COMB_VEC_SMALL
 #define MF_COMB_VEC_SMALL 4
 #endif
@@ -63,6 +209,14 @@ static hipError_t launch_combine_t(const CombineStage& cs, const void* A, const 
   g.vec_out = vec_out ? 1 : 0;
   const int64_t mm = cs.m * cs.m;
   auto grid = [&](int vec) { return dim3((unsigned)((mm / vec + 255) / 256), (unsigned)cs.sets.size(), 1); };
+  if (cs.kron3) {
+    constexpr int V = sizeof(T) == 8 ? 1 : 2;
+    if (cs.kpost)
+      hipLaunchKernelGGL((kron3_post<T, V>), grid(V), dim3(256), 0, s, g);
+    else
+      hipLaunchKernelGGL((kron3_pre<T, V>), grid(V), dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
   // many inputs, few outputs: outputs in registers, inputs streamed with wide loads
   if (cs.nin >= 27 && cs.nout_max <= 16) {
     switch (cs.nin) {

@@ -25,6 +25,9 @@ struct Algo {
   int p = 0;
   int R = 0;
   std::vector<double> U, V, W;
+  // A Kronecker composition (compose, power) keeps its factors, outermost
+  // first, each without factors of its own; empty for any other algorithm.
+  std::vector<Algo> factors;
   double u(int k, int r) const { return U[(size_t)k * R + r]; }
   double v(int k, int r) const { return V[(size_t)k * R + r]; }
   double w(int k, int r) const { return W[(size_t)k * R + r]; }
@@ -111,6 +114,16 @@ struct CombSet {
 // A linear-combination launch over m x m blocks: one operand set per
 // blockIdx.y.
 struct CombineStage {
+  // kron3 = 1: a level of a three-factor Kronecker composition of <2,2,2;7>
+  // algorithms (<8,8,8;343>).  Each set then lists its inputs and outputs in
+  // factor order (index t = 16 t1 + 4 t2 + t3 over the factors' 2 x 2 block
+  // indices, r = 49 r1 + 7 r2 + r3 over their products; outputs that are
+  // not stored have an empty extent), and its coefficients are the three
+  // 4 x 7 factor matrices, starting at the first output's coef_off.  kpost:
+  // the post-addition (inputs are products, outputs blocks) rather than the
+  // pre-addition.
+  int kron3 = 0;
+  int kpost = 0;
   int nin = 0;
   int nout_max = 0;  // most outputs of any set
   int64_t m = 0;

@@ -72,6 +72,36 @@ CombIn as_input(const Blk& b) {
   return in;
 }
 
+// A three-factor Kronecker composition of <2,2,2;7> algorithms (<8,8,8;343>):
+// its levels run on the factor-by-factor combination kernels.
+bool is_kron3(const Algo& a) {
+  if (a.factors.size() != 3) return false;
+  for (const Algo& f : a.factors)
+    if (f.p != 2 || f.R != 7) return false;
+  return true;
+}
+
+// Block index (row-major in the 8 x 8 split) of factor-order index
+// t = 16 t1 + 4 t2 + t3, where t_f = 2 i_f + j_f is the block of factor f.
+int kron3_block(int t) {
+  const int t1 = t / 16, t2 = (t / 4) % 4, t3 = t % 4;
+  const int I = 4 * (t1 / 2) + 2 * (t2 / 2) + t3 / 2;
+  const int J = 4 * (t1 % 2) + 2 * (t2 % 2) + t3 % 2;
+  return I * 8 + J;
+}
+
+// The three 4 x 7 factor matrices of X (U, V or W of each factor), the
+// first scaled by `scale`.
+void kron3_coef(const Algo& a, char which, double scale, std::vector<double>* out) {
+  for (int f = 0; f < 3; ++f)
+    for (int t = 0; t < 4; ++t)
+      for (int r = 0; r < 7; ++r) {
+        const Algo& F = a.factors[(size_t)f];
+        const double x = which == 'u' ? F.u(t, r) : which == 'v' ? F.v(t, r) : F.w(t, r);
+        out->push_back(f == 0 ? x * scale : x);
+      }
+}
+
 void finish_set(CombineStage* st, CombSet set) {
   bool full = true;
   for (int k = 0; k < st->nin; ++k) {
@@ -173,7 +203,8 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
   if (L == 0) return build_classical(n, pl);
 
   const int p = algo->p, p2 = p * p, R = algo->R;
-  if (!combine_supported(p2) || !combine_supported(R))
+  const bool kron3 = is_kron3(*algo);
+  if (!kron3 && (!combine_supported(p2) || !combine_supported(R)))
     return fail(MF_ERR_UNSUPPORTED, "no linear-combination kernel for this algorithm shape");
   const int64_t P = ipow(p, L);
   pl->P = (int)P;
@@ -227,6 +258,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
       CombineStage st;
       st.nin = p2;
       st.m = sz;
+      st.kron3 = kron3 ? 1 : 0;
       std::vector<Blk> next[2];
       for (int side = 0; side < 2; ++side) {
         const std::vector<double>& X = side == 0 ? algo->U : algo->V;
@@ -268,6 +300,11 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
           CombSet set{};
           set.in_beg = (int32_t)st.ins.size();
           set.out_beg = (int32_t)st.outs.size();
+          // kron3: every product has an output entry (empty unless stored) and
+          // the set's coefficients are the factor matrices
+          const int32_t kcoef = (int32_t)st.coef.size();
+          if (kron3) kron3_coef(*algo, side == 0 ? 'u' : 'v', b.scale, &st.coef);
+          bool stored = false;
           for (int r = 0; r < R; ++r) {
             int nnz = 0, last = -1;
             for (int k = 0; k < p2; ++k)
@@ -287,9 +324,14 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
               co.dst = SRC_WS;
               co.ld = (int32_t)sz;
               co.vr = co.vc = (int32_t)sz;
-              co.coef_off = (int32_t)st.coef.size();
-              for (int k = 0; k < p2; ++k) st.coef.push_back(q[k].zero ? 0.0 : X[(size_t)k * R + r] * b.scale);
+              if (kron3) {
+                co.coef_off = kcoef;
+              } else {
+                co.coef_off = (int32_t)st.coef.size();
+                for (int k = 0; k < p2; ++k) st.coef.push_back(q[k].zero ? 0.0 : X[(size_t)k * R + r] * b.scale);
+              }
               st.outs.push_back(co);
+              stored = true;
               child.src = SRC_WS;
               child.off = co.off;
               child.ld = (int32_t)sz;
@@ -297,11 +339,20 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
               child.scale = 1.0;
               child.zero = false;
             }
+            if (kron3 && (int32_t)st.outs.size() == set.out_beg + r) {  // not stored: an empty entry
+              CombOut co{};
+              co.dst = SRC_WS;
+              co.coef_off = kcoef;
+              st.outs.push_back(co);
+            }
             next[side].push_back(child);
           }
           set.out_end = (int32_t)st.outs.size();
-          if (set.out_end > set.out_beg) {
-            for (int k = 0; k < p2; ++k) st.ins.push_back(as_input(q[k]));
+          if (kron3 && !stored) {  // nothing to store: drop the set
+            st.outs.resize((size_t)set.out_beg);
+            st.coef.resize((size_t)kcoef);
+          } else if (set.out_end > set.out_beg) {
+            for (int k = 0; k < p2; ++k) st.ins.push_back(as_input(q[kron3 ? kron3_block(k) : k]));
             finish_set(&st, set);
           }
         }
@@ -424,6 +475,8 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
       CombineStage st;
       st.nin = R;
       st.m = csz;
+      st.kron3 = kron3 ? 1 : 0;
+      st.kpost = 1;
       std::vector<Blk> parents(nparent);
       for (int q = 0; q < nparent; ++q) {
         Blk par;
@@ -445,17 +498,30 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
         set.in_beg = (int32_t)st.ins.size();
         for (int r = 0; r < R; ++r) st.ins.push_back(as_input(child[(size_t)q * R + r]));
         set.out_beg = (int32_t)st.outs.size();
-        for (int c = 0; c < p2; ++c) {
+        const int32_t kcoef = (int32_t)st.coef.size();
+        if (kron3) kron3_coef(*algo, 'w', 1.0, &st.coef);
+        for (int t = 0; t < p2; ++t) {
+          const int c = kron3 ? kron3_block(t) : t;
           const Blk qb = quarter(par, c, p, csz);
-          if (qb.zero) continue;
           CombOut co{};
+          if (qb.zero) {
+            if (!kron3) continue;
+            co.dst = SRC_WS;  // kron3: an entry with an empty extent
+            co.coef_off = kcoef;
+            st.outs.push_back(co);
+            continue;
+          }
           co.off = qb.off;
           co.dst = qb.src;
           co.ld = qb.ld;
           co.vr = qb.vr;
           co.vc = qb.vc;
-          co.coef_off = (int32_t)st.coef.size();
-          for (int r = 0; r < R; ++r) st.coef.push_back(algo->w(c, r));
+          if (kron3) {
+            co.coef_off = kcoef;
+          } else {
+            co.coef_off = (int32_t)st.coef.size();
+            for (int r = 0; r < R; ++r) st.coef.push_back(algo->w(c, r));
+          }
           st.outs.push_back(co);
         }
         set.out_end = (int32_t)st.outs.size();

@@ -311,3 +311,20 @@ def test_workspace_bytes_bf16_staging():
         # classical: one product, a 1000 x 1000 problem in a 1024 leaf
         assert mf.mf_workspace_bytes(s, 0, 0, 1000, mf.MF_F32 | leaf) == 2 * planes * 1024 ** 2 * 2
     assert mf.mf_workspace_bytes(s, 0, 0, 1000, mf.MF_F32 | mf.MF_LEAF_F32) == 0
+
+
+def test_kron3_plan_closed_form():
+    """Depth 3 Kronecker-fused (<8,8,8;343>, three factors of Winograd) is one
+    level: 343 products of n/8, pre-addition bytes 2 * 8 * (n^2 + (7^3 - 3^3) m^2)
+    (every quarter of A and B read once, the 316 non-aliased operands written
+    once), post-addition 8 * (343 m^2 + n^2), workspace (2 * 316 + 343) m^2 * 8."""
+    w = mf.mf_algo_builtin("winograd")
+    c8 = mf.mf_algo_compose(mf.mf_algo_compose(w, w), w)
+    n, m = 8192, 1024
+    q = mf.mf_plan_query(c8, 1, 0, n, mf.MF_F64)
+    assert q["levels"] == 1 and q["products"] == 343 and q["leaf_m"] == m
+    assert q["pre_stages"] == 1 and q["post_stages"] == 1
+    assert q["pre_bytes"] == 2 * 8 * (n * n + 316 * m * m)
+    assert q["post_bytes"] == 8 * (343 * m * m + n * n)
+    assert mf.mf_workspace_bytes(c8, 1, 0, n) == (2 * 316 + 343) * m * m * 8
+    assert mf.mf_workspace_bytes(c8, 1, 0, 4096, mf.MF_F32) == (2 * 316 + 343) * 512 * 512 * 4

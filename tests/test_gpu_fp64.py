@@ -275,3 +275,53 @@ def test_largest_configuration_sampled():
     Bi = mi.int_uniform(n, 23).astype(np.float64)
     got = run_fast(w, 2, 0, Ai, Bi)
     assert np.array_equal(got[rows], om.rows_reference(Ai, Bi, rows))
+
+
+# ------------------------------------------ Kronecker-fused depth 3 (<8,8,8;343>)
+
+def kron3(name):
+    a = mf.mf_algo_builtin(name)
+    return mf.mf_algo_compose(mf.mf_algo_compose(a, a), a)
+
+
+@pytest.mark.parametrize("name", ["winograd", "strassen"])
+@pytest.mark.parametrize("n", [1000, 1024])
+def test_kron3_int_exact(name, n):
+    """Depth 3 as one level of <8,8,8;343> (the three-factor Kronecker
+    composition), whose pre- and post-additions run factor by factor: 64
+    quarter blocks in, 343 products; 343 products in, 64 blocks out.  n = 1000
+    puts part of the 8 x 8 split in the virtual padding.  Integer inputs keep
+    every intermediate below 2^53 (|T| <= 64 * 8, |P| <= 128 * 512^2, sums of
+    343 such), so the result is the exact product."""
+    A = mi.int_uniform(n, 96)
+    B = mi.int_uniform(n, 97)
+    got = run_fast(kron3(name), 1, 0, A.astype(np.float64), B.astype(np.float64))
+    assert np.array_equal(got, om.classical_mm(A, B).astype(np.float64))
+
+
+def test_kron3_uniform_error_and_determinism():
+    """uniform[-1,1]: within the FP64 bound against the oracle, equal to the
+    level-by-level depth 3 within the same bound, and bitwise reproducible."""
+    n = 1024
+    A = mi.uniform(n, 98)
+    B = mi.uniform(n, 99)
+    ref = om.classical_mm(A, B)
+    w = mf.mf_algo_builtin("winograd")
+    fused = run_fast(kron3("winograd"), 1, 0, A, B)
+    level = run_fast(w, 3, 0, A, B)
+    assert om.rel_fro_error(fused, ref) < FP64_TOL
+    assert om.rel_fro_error(level, ref) < FP64_TOL
+    assert np.array_equal(fused, run_fast(kron3("winograd"), 1, 0, A, B))
+
+
+def test_kron3_fp32_storage():
+    """FP32 storage and leaves through the same factor-by-factor kernels."""
+    n = 1024
+    A = mi.uniform(n, 100).astype(np.float32)
+    B = mi.uniform(n, 101).astype(np.float32)
+    dA, dB = torch.from_numpy(A).to("cuda:0"), torch.from_numpy(B).to("cuda:0")
+    dC = torch.full_like(dA, float("nan"))
+    mf.mf_fastmm(kron3("winograd"), 1, 0, dA, dB, dC)
+    torch.cuda.synchronize()
+    ref = om.classical_mm(A.astype(np.float64), B.astype(np.float64))
+    assert om.rel_fro_error(dC.cpu().numpy().astype(np.float64), ref) < 2e-5

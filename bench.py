@@ -2,12 +2,13 @@
 """Benchmark of the fast bilinear matrix product on one MI355X.
 
 Default workload (``--workload square``): effective GFLOP/s = 2 n^3 / t of
-the fast FP64 product (Strassen-Winograd, depth 2) at n = 8192, next to the
+the fast FP64 product (Strassen-Winograd, depth 3) at n = 8192, next to the
 library's own classical FP64 MFMA GEMM, with inputs resident in HBM.  One
-step is one whole product C = A B: pre-additions, the grouped GEMM of the 49
-leaf products, post-additions.  The default schedule runs depth 2 as one
-level of the algorithm's Kronecker square <4,4,4;49> (--schedule fused);
---schedule levels runs two levels of <2,2,2;7>.
+step is one whole product C = A B: pre-additions, the grouped GEMM of the 343
+leaf products, post-additions.  The default schedule runs depth 3 as one
+level of the algorithm's Kronecker cube <8,8,8;343> (--schedule fused);
+--schedule levels runs three levels of <2,2,2;7>, and --depth 2 the square
+<4,4,4;49>.
 
 Other workloads, each printing one JSON line of the same shape:
   --workload batched    512 products, n log-uniform in [128, 2048] (multiples
@@ -29,7 +30,7 @@ Other workloads, each printing one JSON line of the same shape:
                         phase rooflines and error vs the oracle
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload square]
-                       [--n N] [--algo winograd] [--depth 2] [--no-cpu-baseline]
+                       [--n N] [--algo winograd] [--depth 3] [--no-cpu-baseline]
 
 The `roofline` object reports the dominant kernel against its MI355X peak,
 timed live with HIP events recorded on the launch stream.  The
@@ -63,7 +64,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--algo", default="winograd")
-    ap.add_argument("--depth", type=int, default=2)
+    ap.add_argument("--depth", type=int, default=3)
     ap.add_argument("--cutoff", type=int, default=0)
     ap.add_argument("--schedule", choices=("fused", "levels"), default="fused",
                     help="fused: the depth-d power of the algorithm (Kronecker construction) as one level; "

@@ -232,6 +232,28 @@ def test_bench_configuration_sampled():
     assert np.array_equal(run_fast(fused, 1, 0, Ai, Bi)[rows], om.rows_reference(Ai, Bi, rows))
 
 
+def test_bench_default_depth3_sampled():
+    """The benchmark's default: n = 8192 FP64, Strassen-Winograd depth 3 run
+    Kronecker-fused (one level of <8,8,8;343>), on the benchmark's inputs
+    (uniform, seeds 10 and 11) within the bound on sampled rows, first and
+    last included; agreeing with the level-by-level depth 3 within the bound;
+    exact on integer inputs ([-8, 8]: |T| <= 512, every sum below 2^53)."""
+    n = 8192
+    w = mf.mf_algo_builtin("winograd")
+    c888 = mf.mf_algo_compose(mf.mf_algo_compose(w, w), w)
+    A = mi.uniform(n, 10)
+    B = mi.uniform(n, 11)
+    rows = np.unique(np.concatenate([np.random.default_rng(8).choice(n, size=40, replace=False), [0, n - 1]]))
+    ref = om.rows_reference(A, B, rows)
+    got_f = run_fast(c888, 1, 0, A, B)
+    got_l = run_fast(w, 3, 0, A, B)
+    assert om.rel_fro_error(got_f[rows], ref) < FP64_TOL
+    assert om.rel_fro_error(got_f, got_l) < FP64_TOL
+    Ai = mi.int_uniform(n, 14).astype(np.float64)
+    Bi = mi.int_uniform(n, 15).astype(np.float64)
+    assert np.array_equal(run_fast(c888, 1, 0, Ai, Bi)[rows], om.rows_reference(Ai, Bi, rows))
+
+
 # ------------------------------------------------------------- large leaves
 # Full-size exactness of the GEMM on large leaves: classical n = 4000, 4001
 # (masked edge tiles: valid extent 4000 / 4001 inside a 4096 leaf), 4096 and

@@ -595,9 +595,12 @@ def run_precision(args):
                                "on the FP32-rounded inputs",
                    "headline": f"n={head['n']} {head['leaf']} depth {head['depth']} {head['schedule']}"},
         "results": results,
-        "roofline": {"bound": "mfma", "achieved": head["mfma_tflops"], "peak": BF16_MFMA_PEAK_TFLOPS,
+        "roofline": {"bound": "mfma", "achieved": head["mfma_tflops"],
+                     "peak": FP32_MFMA_PEAK_TFLOPS if head["leaf"] == "f32" else BF16_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": head["mfma_frac"], "traffic": None,
-                     "kernel": "gemm_bf16_grouped<CfgW, true>", "kernel_ms": head["gemm_ms"]},
+                     "kernel": {"f32": "gemm_grouped<float>", "bf16": "gemm_bf16_grouped<CfgSq, false>",
+                                "bf16x3": "gemm_bf16_grouped<CfgW, true>"}[head["leaf"]],
+                     "kernel_ms": head["gemm_ms"]},
     }
     print(json.dumps(out), flush=True)
 

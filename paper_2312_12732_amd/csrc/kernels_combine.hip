@@ -115,7 +115,8 @@ __global__ void __launch_bounds__(256, MF_KRON_PRE_WAVES) kron3_pre(CombArgs<T> 
   if (e >= mm) return;
   const int i = (int)(e / g.m), j = (int)(e % g.m);
   const CombSet set = load_uniform(g.sets + blockIdx.y);
-  const double* cf = g.coef + load_uniform(g.outs + set.out_beg).coef_off;  // U1 | U2 | U3, each 4 x 7
+  // U1 | U2 | U3 (each 4 x 7), then the 343 output offsets
+  const double* cf = g.coef + load_uniform(g.outs + set.out_beg).coef_off;
   T x[64][VEC];
 #pragma unroll
   for (int t = 0; t < 64; ++t) kron_load<T, VEC>(g, load_uniform(g.ins + set.in_beg + t), i, j, x[t]);
@@ -141,7 +142,20 @@ __global__ void __launch_bounds__(256, MF_KRON_PRE_WAVES) kron3_pre(CombArgs<T> 
         T o[VEC] = {};
 #pragma unroll
         for (int t3 = 0; t3 < 4; ++t3) kron_axpy<T, VEC>((T)load_uniform(cf + 56 + t3 * 7 + r3), z[t3], o);
-        kron_store<T, VEC>(g, load_uniform(g.outs + set.out_beg + 49 * r1 + 7 * r2 + r3), i, j, o);
+        // stored operands are whole m x m workspace blocks (offset -1: not stored)
+        const double off = load_uniform(cf + 84 + 49 * r1 + 7 * r2 + r3);
+        if (off >= 0.0) {
+          T* p = g.ws + (int64_t)off + (int64_t)i * g.m + j;
+          if (VEC == 1) {
+            p[0] = o[0];
+          } else {
+            typedef T tv __attribute__((ext_vector_type(VEC)));
+            tv y;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) y[q] = o[q];
+            *reinterpret_cast<tv*>(p) = y;
+          }
+        }
       }
     }
   }
@@ -154,16 +168,28 @@ __global__ void __launch_bounds__(256) kron3_post(CombArgs<T> g) {
   if (e >= mm) return;
   const int i = (int)(e / g.m), j = (int)(e % g.m);
   const CombSet set = load_uniform(g.sets + blockIdx.y);
-  const double* cf = g.coef + load_uniform(g.outs + set.out_beg).coef_off;  // W1 | W2 | W3, each 4 x 7
+  // W1 | W2 | W3 (each 4 x 7), then the 343 input offsets
+  const double* cf = g.coef + load_uniform(g.outs + set.out_beg).coef_off;
   T out[64][VEC] = {};
   for (int r1 = 0; r1 < 7; ++r1) {
     T t[16][VEC] = {};
 #pragma unroll MF_KRON_POST_UNROLL
     for (int r2 = 0; r2 < 7; ++r2) {
+      // products are whole m x m workspace blocks (offset -1: an empty group, zero)
       T P[7][VEC];
 #pragma unroll
-      for (int r3 = 0; r3 < 7; ++r3)
-        kron_load<T, VEC>(g, load_uniform(g.ins + set.in_beg + 49 * r1 + 7 * r2 + r3), i, j, P[r3]);
+      for (int r3 = 0; r3 < 7; ++r3) {
+        const double off = load_uniform(cf + 84 + 49 * r1 + 7 * r2 + r3);
+        const T* p = g.ws + (int64_t)(off >= 0.0 ? off : 0.0) + (int64_t)i * g.m + j;
+        if (VEC == 1) {
+          P[r3][0] = off >= 0.0 ? p[0] : T(0);
+        } else {
+          typedef T tv __attribute__((ext_vector_type(VEC)));
+          const tv y = off >= 0.0 ? *reinterpret_cast<const tv*>(p) : tv{};
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) P[r3][q] = y[q];
+        }
+      }
       T u[4][VEC] = {};
 #pragma unroll
       for (int c3 = 0; c3 < 4; ++c3)

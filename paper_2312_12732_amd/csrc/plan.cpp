@@ -348,6 +348,14 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
             next[side].push_back(child);
           }
           set.out_end = (int32_t)st.outs.size();
+          if (kron3 && stored) {
+            // then the element offset in the workspace of each product's
+            // operand (-1: not stored); every stored one is an sz x sz block
+            for (int r = 0; r < R; ++r) {
+              const CombOut& co = st.outs[(size_t)set.out_beg + r];
+              st.coef.push_back(co.vr > 0 ? (double)co.off : -1.0);
+            }
+          }
           if (kron3 && !stored) {  // nothing to store: drop the set
             st.outs.resize((size_t)set.out_beg);
             st.coef.resize((size_t)kcoef);
@@ -499,7 +507,18 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
         for (int r = 0; r < R; ++r) st.ins.push_back(as_input(child[(size_t)q * R + r]));
         set.out_beg = (int32_t)st.outs.size();
         const int32_t kcoef = (int32_t)st.coef.size();
-        if (kron3) kron3_coef(*algo, 'w', 1.0, &st.coef);
+        if (kron3) {
+          // the factor matrices, then the element offset in the workspace of
+          // each product (-1: an empty group, read as zero); every product is
+          // a csz x csz block
+          kron3_coef(*algo, 'w', 1.0, &st.coef);
+          for (int r = 0; r < R; ++r) {
+            const Blk& cb = child[(size_t)q * R + r];
+            if (!cb.zero && (cb.src != SRC_WS || cb.ld != csz || cb.vr != csz || cb.vc != csz))
+              return fail(MF_ERR_UNSUPPORTED, "Kronecker post-addition needs whole workspace blocks");
+            st.coef.push_back(cb.zero ? -1.0 : (double)cb.off);
+          }
+        }
         for (int t = 0; t < p2; ++t) {
           const int c = kron3 ? kron3_block(t) : t;
           const Blk qb = quarter(par, c, p, csz);

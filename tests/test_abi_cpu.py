@@ -328,3 +328,14 @@ def test_kron3_plan_closed_form():
     assert q["post_bytes"] == 8 * (343 * m * m + n * n)
     assert mf.mf_workspace_bytes(c8, 1, 0, n) == (2 * 316 + 343) * m * m * 8
     assert mf.mf_workspace_bytes(c8, 1, 0, 4096, mf.MF_F32) == (2 * 316 + 343) * 512 * 512 * 4
+
+
+def test_kron3_unsupported_forms():
+    """<8,8,8;343> is not staged for BF16 leaves (at most 16 inputs per staging
+    set): the plan reports MF_ERR_UNSUPPORTED instead of running."""
+    w = mf.mf_algo_builtin("winograd")
+    c8 = mf.mf_algo_compose(mf.mf_algo_compose(w, w), w)
+    for leaf in (mf.MF_LEAF_BF16, mf.MF_LEAF_BF16X3):
+        with pytest.raises(Exception) as ei:
+            mf.mf_workspace_bytes(c8, 1, 0, 4096, mf.MF_F32 | leaf)
+        assert "UNSUPPORTED" in str(ei.value)

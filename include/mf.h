@@ -216,7 +216,9 @@ void mf_batch_free(mf_batch* b);
 /* ---- Autotuner of the batched form ------------------------------------------
  * For each of nsizes sizes n[i], measures every candidate plan where it will
  * run, in a batch of many products of that size, and picks the
- * one with the least device time per product.  Candidates, ncand =
+ * one with the least device time per product; a fast plan is taken only if it
+ * beats the classical GEMM by at least 5% (the margin pays for the addition
+ * launches it adds to a mixed batch).  Candidates, ncand =
  * 1 + nalgos * max_depth of them: index 0 is the classical GEMM; index
  * 1 + j * max_depth + (d - 1) is algos[j] at depth d (1 <= d <= max_depth).
  * A depth whose levels the plan would not take for that size (see

@@ -16,6 +16,8 @@
 
 namespace mf {
 
+constexpr double kMinGain = 0.05;  // least relative gain of a fast plan over the classical one
+
 hipError_t launch_fill_uniform(void* p, int64_t count, int elem, uint64_t seed, hipStream_t s);
 
 namespace {
@@ -135,6 +137,12 @@ mf_status mf_autotune_batch(int nsizes, const int64_t* n, int dtype, const mf_al
         best_c = c;
       }
     }
+    // A fast plan must beat the classical GEMM by kMinGain: measured in a
+    // batch of its own size, it does not pay for the launches its addition
+    // phases add to a mixed batch (FP64, 512 sizes in [128, 2048]: plans won
+    // by 2-3% made the mixed batch 2% slower than all-classical).
+    const double classical = out_ms[(size_t)i * ncand];
+    if (best_c != 0 && classical > 0.0 && best > (1.0 - kMinGain) * classical) best_c = 0;
     out_choice[i] = best_c;
   }
   return MF_OK;

@@ -22,9 +22,13 @@ def test_tuner_candidates_and_choice():
     assert ms[1][1] > 0 and ms[1][2] == -1
     # 512: both depths are real plans
     assert all(x > 0 for x in ms[2])
+    # the fastest candidate, unless it beats the classical GEMM by less than 5%
     for (al, d), row in zip(choices, ms):
-        c = 0 if d == 0 else d
-        assert row[c] == min(x for x in row if x > 0)
+        best = min(x for x in row if x > 0)
+        if d == 0:
+            assert row[0] == best or best > 0.95 * row[0]
+        else:
+            assert row[d] == best and best <= 0.95 * row[0]
 
 
 def test_tuned_batch_is_exact():

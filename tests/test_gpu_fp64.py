@@ -307,14 +307,15 @@ def kron3(name):
 
 
 @pytest.mark.parametrize("name", ["winograd", "strassen"])
-@pytest.mark.parametrize("n", [1000, 1024])
+@pytest.mark.parametrize("n", [1000, 1001, 1024])
 def test_kron3_int_exact(name, n):
     """Depth 3 as one level of <8,8,8;343> (the three-factor Kronecker
     composition), whose pre- and post-additions run factor by factor: 64
     quarter blocks in, 343 products; 343 products in, 64 blocks out.  n = 1000
     puts part of the 8 x 8 split in the virtual padding.  Integer inputs keep
     every intermediate below 2^53 (|T| <= 64 * 8, |P| <= 128 * 512^2, sums of
-    343 such), so the result is the exact product."""
+    343 such), so the result is the exact product.  n = 1001 also makes the
+    caller's rows unaligned (element-wise loads and stores)."""
     A = mi.int_uniform(n, 96)
     B = mi.int_uniform(n, 97)
     got = run_fast(kron3(name), 1, 0, A.astype(np.float64), B.astype(np.float64))

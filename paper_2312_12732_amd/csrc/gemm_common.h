@@ -63,9 +63,13 @@ __device__ __forceinline__ T* dst_ptr(const GemmArgs<T>& g, int dst) {
 
 // Map a workgroup id to (group, tile position).  Workgroups are dealt
 // round-robin to the 8 XCDs; regroup so that each XCD works on a contiguous
-// range of (group, position) pairs, and walk positions in bands of 8 tile
+// range of (group, position) pairs, and walk positions in bands of BAND tile
 // rows so that concurrently running tiles share operand panels in the XCD's
-// L2.
+// L2 (8 for the FP64/FP32 tiles; the BF16 kernel passes its own).
+#ifndef MF_GEMM_BAND
+#define MF_GEMM_BAND 8
+#endif
+template <int BAND = MF_GEMM_BAND>
 __device__ __forceinline__ void work_of(int b, int tiles_m, int tiles_n, int groups, int* grp, int* ti, int* tj) {
   const int G = tiles_m * tiles_n;
   const int total = G * groups;
@@ -73,10 +77,6 @@ __device__ __forceinline__ void work_of(int b, int tiles_m, int tiles_n, int gro
   if ((total & 7) == 0) L = (b & 7) * (total >> 3) + (b >> 3);
   *grp = L / G;
   L -= *grp * G;
-#ifndef MF_GEMM_BAND
-#define MF_GEMM_BAND 8
-#endif
-  constexpr int BAND = MF_GEMM_BAND;
   const int per_band = BAND * tiles_n;
   const int band = L / per_band;
   const int first = band * BAND;

@@ -339,3 +339,18 @@ def test_kron3_unsupported_forms():
         with pytest.raises(Exception) as ei:
             mf.mf_workspace_bytes(c8, 1, 0, 4096, mf.MF_F32 | leaf)
         assert "UNSUPPORTED" in str(ei.value)
+
+
+def test_composition_is_associative():
+    """(F1 x F2) x F3 and F1 x (F2 x F3) are the same <8,8,8;343> algorithm (the
+    block re-indexing of the Kronecker construction is mixed-radix), and it
+    satisfies the Brent equations (checked when the library builds it)."""
+    w = mf.mf_algo_builtin("winograd")
+    s = mf.mf_algo_builtin("strassen")
+    left = mf.mf_algo_compose(mf.mf_algo_compose(w, s), w)
+    right = mf.mf_algo_compose(w, mf.mf_algo_compose(s, w))
+    for x, y in zip(left.uvw(), right.uvw()):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+    U, V, W = left.uvw()[:3]
+    again = mf.mf_algo_from_uvw(8, np.asarray(U), np.asarray(V), np.asarray(W))
+    assert again.info()["R"] == 343

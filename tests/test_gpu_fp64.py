@@ -302,11 +302,14 @@ def test_largest_configuration_sampled():
 # ------------------------------------------ Kronecker-fused depth 3 (<8,8,8;343>)
 
 def kron3(name):
+    if name == "mixed":  # Winograd x Strassen x Winograd: the factors differ
+        w, s = mf.mf_algo_builtin("winograd"), mf.mf_algo_builtin("strassen")
+        return mf.mf_algo_compose(mf.mf_algo_compose(w, s), w)
     a = mf.mf_algo_builtin(name)
     return mf.mf_algo_compose(mf.mf_algo_compose(a, a), a)
 
 
-@pytest.mark.parametrize("name", ["winograd", "strassen"])
+@pytest.mark.parametrize("name", ["winograd", "strassen", "mixed"])
 @pytest.mark.parametrize("n", [1000, 1001, 1024])
 def test_kron3_int_exact(name, n):
     """Depth 3 as one level of <8,8,8;343> (the three-factor Kronecker

@@ -340,9 +340,10 @@ def test_kron3_uniform_error_and_determinism():
     assert np.array_equal(fused, run_fast(kron3("winograd"), 1, 0, A, B))
 
 
-def test_kron3_fp32_storage():
-    """FP32 storage and leaves through the same factor-by-factor kernels."""
-    n = 1024
+@pytest.mark.parametrize("n", [1000, 1024])
+def test_kron3_fp32_storage(n):
+    """FP32 storage and leaves through the same factor-by-factor kernels (two
+    elements per thread), whole and ragged."""
     A = mi.uniform(n, 100).astype(np.float32)
     B = mi.uniform(n, 101).astype(np.float32)
     dA, dB = torch.from_numpy(A).to("cuda:0"), torch.from_numpy(B).to("cuda:0")

@@ -54,7 +54,7 @@ typedef enum {
   MF_ERR_SHAPE = -3,       /* sizes inconsistent with the algorithm or the workspace */
   MF_ERR_NOMEM = -4,       /* device or host allocation failed */
   MF_ERR_HIP = -5,         /* a HIP runtime call or kernel launch failed */
-  MF_ERR_UNSUPPORTED = -6  /* valid request that this build does not implement */
+  MF_ERR_UNSUPPORTED = -6  /* valid request that the library does not implement */
 } mf_status;
 
 /* Element type of A, B, C (low byte) and precision of the leaf products

@@ -158,8 +158,9 @@ mf_status mf_plan_query(const mf_algo* algo, int depth, int cutoff, int64_t n, i
 
 /* As mf_fastmm, with caller-owned device workspace of ws_bytes bytes
  * (256-byte aligned; MF_ERR_SHAPE if smaller than mf_workspace_bytes).  The
- * workspace must not be used by other work until the call has completed on
- * `stream`. */
+ * first mf_workspace_bytes bytes must not overlap A, B or C (MF_ERR_ARG,
+ * detected by address range).  The workspace must not be used by other work
+ * until the call has completed on `stream`. */
 mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C,
                        int64_t n, int dtype, void* workspace, size_t ws_bytes, mf_stream stream);
 

@@ -39,10 +39,12 @@ mf_status new_handle(const Algo& a, mf_algo** out) {
   return MF_OK;
 }
 
-bool overlaps(const void* x, const void* y, size_t bytes) {
+// Byte ranges [x, x + xb) and [y, y + yb) intersect.
+bool overlaps(const void* x, size_t xb, const void* y, size_t yb) {
   const uintptr_t a = reinterpret_cast<uintptr_t>(x), b = reinterpret_cast<uintptr_t>(y);
-  return a < b + bytes && b < a + bytes;
+  return a < b + yb && b < a + xb;
 }
+bool overlaps(const void* x, const void* y, size_t bytes) { return overlaps(x, bytes, y, bytes); }
 
 mf_status check_request(const mf_algo* algo, bool need_algo, int depth, int cutoff, const void* A,
                         const void* B, void* C, int64_t n, int dtype) {
@@ -95,7 +97,18 @@ mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, h
   const bool vec_in = rows16 && aligned16(A) && aligned16(B);
   const bool vec_c = rows16 && aligned16(C);
   const int leaf = (pl.dtype >> 8) & 0xff;
-  std::array<hipEvent_t, kPhases + 1> ev{};
+  // Timing events of this call; destroyed on every early return, handed to
+  // the timing list once the whole call has been enqueued.
+  struct Events {
+    std::array<hipEvent_t, kPhases + 1> ev{};
+    bool keep = false;
+    ~Events() {
+      if (!keep)
+        for (hipEvent_t x : ev)
+          if (x) (void)hipEventDestroy(x);
+    }
+  } events;
+  auto& ev = events.ev;
   bool timed = false;
   {
     std::lock_guard<std::mutex> lk(timing().mu);
@@ -103,7 +116,10 @@ mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, h
   }
   if (timed) {
     for (auto& x : ev)
-      if (hipEventCreate(&x) != hipSuccess) return fail(MF_ERR_HIP, "hipEventCreate failed");
+      if (hipEventCreate(&x) != hipSuccess) {
+        x = nullptr;
+        return fail(MF_ERR_HIP, "hipEventCreate failed");
+      }
   }
   for (int ph = 0; ph < kPhases; ++ph) {
     if (timed && hipEventRecord(ev[ph], s) != hipSuccess) return fail(MF_ERR_HIP, "hipEventRecord failed");
@@ -128,6 +144,7 @@ mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, h
     if (hipEventRecord(ev[kPhases], s) != hipSuccess) return fail(MF_ERR_HIP, "hipEventRecord failed");
     std::lock_guard<std::mutex> lk(timing().mu);
     timing().calls.push_back(ev);
+    events.keep = true;
   }
   return MF_OK;
 }
@@ -357,6 +374,10 @@ mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A
     if (!workspace) return fail(MF_ERR_ARG, "workspace is NULL");
     if (ws_bytes < pl->ws_bytes) return fail(MF_ERR_SHAPE, "workspace too small");
     if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(MF_ERR_ARG, "workspace must be 256-byte aligned");
+    const size_t mat = (size_t)n * (size_t)n * pl->elem;
+    if (overlaps(workspace, pl->ws_bytes, A, mat) || overlaps(workspace, pl->ws_bytes, B, mat) ||
+        overlaps(workspace, pl->ws_bytes, C, mat))
+      return fail(MF_ERR_ARG, "workspace overlaps A, B or C");
   }
   return run(*pl, A, B, C, workspace, static_cast<hipStream_t>(stream));
 }

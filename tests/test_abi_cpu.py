@@ -223,6 +223,28 @@ def test_fastmm_argument_validation_without_device():
     assert mf.lib.mf_classical_mm(None, None, None, 0, mf.MF_F64, None) == mf.MF_OK
 
 
+def test_fastmm_ws_validation_without_device():
+    # The caller's workspace is checked for size, alignment and overlap with
+    # A, B and C before anything is enqueued (the addresses are never read).
+    s = mf.mf_algo_builtin("strassen")
+    n = 256
+    need = mf.mf_workspace_bytes(s, 1, 0, n)
+    mat = n * n * 8
+    A, B, C, W = 0x1000000, 0x2000000, 0x3000000, 0x4000000
+
+    def call(ws, nbytes):
+        return mf.lib.mf_fastmm_ws(s.handle, 1, 0, ctypes.c_void_p(A), ctypes.c_void_p(B), ctypes.c_void_p(C), n,
+                                   mf.MF_F64, ctypes.c_void_p(ws), nbytes, None)
+
+    assert call(0, need) == mf.MF_ERR_ARG                     # NULL workspace
+    assert call(W, need - 1) == mf.MF_ERR_SHAPE               # too small
+    assert call(W + 128, need) == mf.MF_ERR_ARG               # not 256-byte aligned
+    assert call(A + mat - 256, need) == mf.MF_ERR_ARG         # starts inside A
+    assert "overlaps" in mf.mf_last_error()
+    assert call(B - need + 256, need) == mf.MF_ERR_ARG        # ends inside B
+    assert call(C - 256 * 1024, need + 256 * 1024) == mf.MF_ERR_ARG  # covers C
+
+
 def test_unsupported_algorithm_shape_is_reported():
     # split factor 5 (25 inputs per block combination) has no compiled kernel
     c5 = oa.classical_algo(5)

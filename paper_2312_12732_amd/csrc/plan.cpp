@@ -618,14 +618,27 @@ mf_status upload(const Plan* pl) {
   return MF_OK;
 }
 
+// A plan's descriptors live on the device that was current when it was
+// first run, so the device is part of the key (-1 where none is visible:
+// host-only queries).
 struct Key {
   uint64_t algo;
-  int levels, dtype;
+  int levels, dtype, device;
   int64_t n, min_wg;
   bool operator<(const Key& o) const {
-    return std::tie(algo, levels, dtype, n, min_wg) < std::tie(o.algo, o.levels, o.dtype, o.n, o.min_wg);
+    return std::tie(algo, levels, dtype, device, n, min_wg) <
+           std::tie(o.algo, o.levels, o.dtype, o.device, o.n, o.min_wg);
   }
 };
+
+int current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    dev = -1;
+  }
+  return dev;
+}
 
 // Heap-allocated and never destroyed: plans may hold device memory, which must
 // not be released from static destructors after the HIP runtime is gone.
@@ -655,7 +668,7 @@ int levels_for(int64_t n, int p, int R, int depth, int cutoff) {
 mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg,
                    std::shared_ptr<const Plan>* out) {
   const int levels = algo ? levels_for(n, algo->a.p, algo->a.R, depth, cutoff) : 0;
-  const Key key{levels == 0 ? 0 : algo->id, levels, dtype, n, levels == 0 ? 0 : min_wg};
+  const Key key{levels == 0 ? 0 : algo->id, levels, dtype, current_device(), n, levels == 0 ? 0 : min_wg};
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = cache().find(key);

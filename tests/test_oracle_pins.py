@@ -277,8 +277,6 @@ def test_rebase_rejects_non_unimodular():
 @pytest.mark.parametrize("n", [2, 4, 8, 16, 64, 256])
 @pytest.mark.parametrize("depth", [0, 1, 2, 3])
 def test_fast_equals_classical_on_ints(name, n, depth):
-    if n == 256 and depth == 3 and name != "strassen_paper":
-        pytest.skip("covered by the paper's form at this size")
     alg = ALL_BASE[name]()
     A = mi.int_uniform(n, 3)
     B = mi.int_uniform(n, 4)

@@ -352,6 +352,24 @@ def test_kron3_plan_closed_form():
     assert mf.mf_workspace_bytes(c8, 1, 0, 4096, mf.MF_F32) == (2 * 316 + 343) * 512 * 512 * 4
 
 
+@pytest.mark.parametrize("n", [1000, 1001, 1024, 8000])
+def test_kron3_plan_closed_form_ragged(n):
+    """Sizes that 8 x the 128 leaf tile does not divide: the leaf is padded to
+    m = 128 * ceil(ceil(n / 8) / 128).  Input views exclude the virtual padding,
+    so the quarters of A and B still total n^2 elements read; workspace blocks
+    are written whole (m^2 each, zeros in the padding); C is written over its
+    n^2 valid elements."""
+    w = mf.mf_algo_builtin("winograd")
+    c8 = mf.mf_algo_compose(mf.mf_algo_compose(w, w), w)
+    m = 128 * -(-(-(-n // 8)) // 128)
+    for dtype, eb in ((mf.MF_F64, 8), (mf.MF_F32, 4)):
+        q = mf.mf_plan_query(c8, 1, 0, n, dtype)
+        assert q["leaf_m"] == m and q["products"] == 343
+        assert q["pre_bytes"] == 2 * eb * (n * n + 316 * m * m)
+        assert q["post_bytes"] == eb * (343 * m * m + n * n)
+        assert mf.mf_workspace_bytes(c8, 1, 0, n, dtype) == (2 * 316 + 343) * m * m * eb
+
+
 def test_kron3_unsupported_forms():
     """<8,8,8;343> is not staged for BF16 leaves (at most 16 inputs per staging
     set): the plan reports MF_ERR_UNSUPPORTED instead of running."""

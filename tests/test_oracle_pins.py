@@ -211,6 +211,32 @@ def test_compose_nnz_and_aliases():
     assert len(oa.single_coefficient_columns(s2.V)) == 9
 
 
+@pytest.mark.parametrize("name", list(ALL_BASE))
+def test_cube_brent_and_counts(name):
+    # <8,8,8;343> = F (x) F (x) F: the 64^3 Brent equations hold exactly, and
+    # nonzeros and single-coefficient (aliased) columns multiply factor by
+    # factor, since a composed coefficient is the product of one coefficient
+    # from each factor.
+    f = ALL_BASE[name]()
+    c = oa.power(f, 3)
+    assert (c.p, c.R) == (8, 343)
+    assert oa.brent_violations(c) == 0
+    for X, Xf in ((c.U, f.U), (c.V, f.V), (c.W, f.W)):
+        assert np.count_nonzero(X) == np.count_nonzero(Xf) ** 3
+    assert len(oa.single_coefficient_columns(c.U)) == len(oa.single_coefficient_columns(f.U)) ** 3
+    assert len(oa.single_coefficient_columns(c.V)) == len(oa.single_coefficient_columns(f.V)) ** 3
+
+
+@pytest.mark.parametrize("n", [64, 100])
+def test_cube_equals_three_levels_on_ints(n):
+    w = ALL_BASE["winograd"]()
+    A = mi.int_uniform(n, 43)
+    B = mi.int_uniform(n, 44)
+    fused = om.fast_mm(A, B, oa.power(w, 3), depth=1)
+    assert np.array_equal(fused, om.fast_mm(A, B, w, depth=3))
+    assert np.array_equal(fused, A @ B)
+
+
 def test_raw_kron_without_reindexing_fails():
     # Plain np.kron of the factor matrices uses the nested row order; the
     # composition needs the row-major re-indexing.

@@ -309,7 +309,7 @@ def kron3(name):
     return mf.mf_algo_compose(mf.mf_algo_compose(a, a), a)
 
 
-@pytest.mark.parametrize("name", ["winograd", "strassen", "mixed"])
+@pytest.mark.parametrize("name", ["winograd", "strassen", "strassen1969", "mixed"])
 @pytest.mark.parametrize("n", [1000, 1001, 1024])
 def test_kron3_int_exact(name, n):
     """Depth 3 as one level of <8,8,8;343> (the three-factor Kronecker
@@ -318,7 +318,9 @@ def test_kron3_int_exact(name, n):
     puts part of the 8 x 8 split in the virtual padding.  Integer inputs keep
     every intermediate below 2^53 (|T| <= 64 * 8, |P| <= 128 * 512^2, sums of
     343 such), so the result is the exact product.  n = 1001 also makes the
-    caller's rows unaligned (element-wise loads and stores)."""
+    caller's rows unaligned (element-wise loads and stores).  Strassen's 1969
+    form has 2 aliased operands per side and factor instead of 3, so its cube
+    stores 335 operands per side instead of 316."""
     A = mi.int_uniform(n, 96)
     B = mi.int_uniform(n, 97)
     got = run_fast(kron3(name), 1, 0, A.astype(np.float64), B.astype(np.float64))

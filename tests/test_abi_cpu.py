@@ -373,19 +373,18 @@ def test_kron3_plan_closed_form_ragged(n):
 @pytest.mark.parametrize("table", ["WINOGRAD", "STRASSEN_PAPER", "STRASSEN_1969"])
 def test_kron3_stored_operands_match_oracle_aliases(table):
     """The library stores every operand of <8,8,8;343> except the aliased
-    ones (a single +1 coefficient), so its pre-addition writes are
-    (343 - aliased) m^2 per side.  Both sides build the cube from the same
-    printed factor table; the aliased count comes from the oracle's own
-    composition."""
+    ones (a single nonzero coefficient: a block view whose coefficient goes
+    into the epilogue), so its pre-addition writes are (343 - aliased) m^2 per
+    side.  Both sides build the cube from the same printed factor table; the
+    aliased count comes from the oracle's own composition."""
     U, V, W, conv = mi.as_float_tables(getattr(mi, table))
     f = mf.mf_algo_from_uvw(2, U, V, W, conv)
     c8 = mf.mf_algo_compose(mf.mf_algo_compose(f, f), f)
     cube = oa.power(oa.canonical(2, U, V, W, conv), 3)
-
-    def plus_one(X):
-        return [r for r in oa.single_coefficient_columns(X) if X[:, r][X[:, r] != 0][0] == 1]
-
-    stored = (343 - len(plus_one(cube.U))) + (343 - len(plus_one(cube.V)))
+    aliased_u = len(oa.single_coefficient_columns(cube.U))
+    aliased_v = len(oa.single_coefficient_columns(cube.V))
+    assert (aliased_u, aliased_v) == ((8, 8) if table == "STRASSEN_1969" else (27, 27))
+    stored = (343 - aliased_u) + (343 - aliased_v)
     n, m = 4096, 512
     q = mf.mf_plan_query(c8, 1, 0, n, mf.MF_F64)
     assert q["pre_bytes"] == 8 * (2 * n * n + stored * m * m)

@@ -8,7 +8,11 @@ or calls anything in this package, and this package shares no code with it.
 Parity status: every function here is pinned by not-gpu tests against facts
 fixed by the paper or by mathematics (the paper's worked example, Brent
 equations, the textbook product, brute force on tiny inputs, closed forms,
-planted mistakes).  No function is parity-unpinned.
+planted mistakes).  That includes ``rows_reference``, the sampled-row form of
+the definition that checks every full-size product: it is pinned row by row
+against a brute-force triple loop, exact sums, closed forms (identity,
+permutation, rank one) and planted mistakes (a transposed operand, shifted
+rows).  No function is parity-unpinned.
 """
 from .algebra import (Algo, brent_violations, canonical, classical_algo, compose, power,  # noqa: F401
                       rebase, single_coefficient_columns, transpose_index)

@@ -384,3 +384,81 @@ def test_error_metrics_closed_form():
     A = np.eye(4)
     assert om.componentwise_error(C + 0.5, C, np.ones((4, 4)), A) == pytest.approx(0.5)
     assert om.max_scaled_error(C + 0.25, C, 2 * np.ones((4, 4)), A) == pytest.approx(0.125)
+
+
+# ----------------------------------------------------- sampled definition rows
+# rows_reference is the checker of every full-size parity test: row i of the
+# definition C_ij = sum_k A_ik B_kj (Section 2) for sampled i only.
+
+@pytest.mark.parametrize("n", [1, 4, 7, 13])
+def test_rows_reference_matches_brute_force_rows(n):
+    A = mi.int_uniform(n, 300 + n)
+    B = mi.int_uniform(n, 400 + n)
+    rows = sorted(set(np.random.default_rng(n).integers(0, n, size=max(1, n // 2)).tolist()))
+    got = om.rows_reference(A, B, rows)
+    full = brute_force_mm(A.tolist(), B.tolist())
+    assert got.shape == (len(rows), n)
+    for a, i in enumerate(rows):
+        assert got[a].tolist() == [float(x) for x in full[i]]
+
+
+def test_rows_reference_float_rows_close_to_exact_sum():
+    import math
+    n = 11
+    A = mi.uniform(n, 31)
+    B = mi.uniform(n, 32)
+    rows = [0, 5, 10]
+    got = om.rows_reference(A, B, rows)
+    for a, i in enumerate(rows):
+        for j in range(n):
+            exact = math.fsum(A[i, t] * B[t, j] for t in range(n))
+            assert abs(got[a, j] - exact) <= 1e-15 * n
+
+
+def test_rows_reference_closed_forms():
+    n = 16
+    A = mi.int_uniform(n, 41)
+    rows = [2, 3, 11]
+    # identity on the right: the sampled rows of A themselves
+    assert np.array_equal(om.rows_reference(A, np.eye(n, dtype=np.int64), rows), A[rows].astype(np.float64))
+    # permutation on the right moves columns: (A P)[i, perm[j]] = A[i, j]
+    perm = np.random.default_rng(6).permutation(n)
+    P = np.zeros((n, n), dtype=np.int64)
+    P[np.arange(n), perm] = 1
+    got = om.rows_reference(A, P, rows)
+    assert np.array_equal(got[:, perm], A[rows].astype(np.float64))
+    # rank one: rows of (u v^T)(x y^T) are (v . x) u_i y^T
+    g = np.random.default_rng(7)
+    u, v, x, y = (g.integers(-5, 6, size=n) for _ in range(4))
+    got = om.rows_reference(np.outer(u, v), np.outer(x, y), rows)
+    assert np.array_equal(got, (int(v @ x) * np.outer(u, y))[rows].astype(np.float64))
+
+
+def test_rows_reference_planted_mistakes_are_caught():
+    """A transposed B, shifted rows or a transposed A all change the rows."""
+    n = 9
+    A = mi.int_uniform(n, 51)
+    B = mi.int_uniform(n, 52)
+    rows = [1, 4, 8]
+    want = np.array([[sum(int(A[i, t]) * int(B[t, j]) for t in range(n)) for j in range(n)] for i in rows],
+                    dtype=np.float64)
+    assert np.array_equal(om.rows_reference(A, B, rows), want)
+    assert not np.array_equal(om.rows_reference(A, B.T.copy(), rows), want)
+    assert not np.array_equal(om.rows_reference(A, B, [r - 1 for r in rows]), want)
+    assert not np.array_equal(om.rows_reference(A.T.copy(), B, rows), want)
+
+
+def test_flop_count_and_unit_roundoff_closed_forms():
+    # the classical product of two n x n matrices takes n^3 multiplications and n^2 (n - 1) additions;
+    # effective GFLOP/s counts 2 n^3 (Section 2's definition, one multiply-add per term)
+    for n in (1, 2, 3, 10, 8192):
+        assert om.flops(n) == 2.0 * n * n * n
+    # unit roundoff of IEEE double: 1 + u rounds back to 1 (ties to even), 1 + 2u does not
+    u = om.unit_roundoff()
+    assert 1.0 + u == 1.0 and 1.0 + 2 * u > 1.0
+    assert om.unit_roundoff(24) == float(np.finfo(np.float32).eps) / 2
+    # transpose_index is an involution that swaps the 2-d block index
+    for p in (2, 3, 4):
+        for t in range(p * p):
+            assert oa.transpose_index(oa.transpose_index(t, p), p) == t
+            assert oa.transpose_index(t, p) == (t % p) * p + t // p

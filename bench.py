@@ -235,7 +235,7 @@ def run_square(args):
 
 
 # ---------------------------------------------------------------------------
-# Batched form: 512 uneven products in one persistent launch per dtype.
+# Batched form: 512 uneven products per dtype, one launch per phase.
 # ---------------------------------------------------------------------------
 
 BATCH_COUNT, BATCH_SEED, BATCH_OPERAND_SEED = 512, 30, 31
@@ -258,15 +258,22 @@ def run_batched(args):
     stream = torch.cuda.current_stream()
     timed = timer(torch, stream)
     sizes = mi.batch_sizes(BATCH_COUNT, BATCH_SEED)
+    # candidates of the tuner: the paper's Strassen, Strassen-Winograd and
+    # <4,4,4;49> (Winograd composed with itself), each at depth 1..2
+    stras = mf.mf_algo_builtin("strassen")
     wino = mf.mf_algo_builtin("winograd")
-    R = 7
+    c444 = mf.mf_algo_compose(wino, wino)
+    cands = [stras, wino, c444]
+    cand_names = {id(stras): "strassen", id(wino): "winograd", id(c444): "<4,4,4;49>"}
+    cand_R = {id(stras): 7, id(wino): 7, id(c444): 49}
+    cand_p = {id(stras): 2, id(wino): 2, id(c444): 4}
     flops = sum(2.0 * n ** 3 for n in sizes)
     per_dtype = {}
     for name, code, tdt, peak in (("f64", mf.MF_F64, torch.float64, FP64_MFMA_PEAK_TFLOPS),
                                   ("f32", mf.MF_F32, torch.float32, FP32_MFMA_PEAK_TFLOPS)):
         distinct = sorted(set(sizes))
         t0 = time.perf_counter()
-        choices, tune_ms = mf.mf_autotune_batch(distinct, code, [wino], 3)
+        choices, tune_ms = mf.mf_autotune_batch(distinct, code, cands, 2)
         tune_s = time.perf_counter() - t0
         pick = dict(zip(distinct, choices))
         As, Bs, Cs = [], [], []
@@ -297,12 +304,14 @@ def run_batched(args):
             for A, B, C in zip(As, Bs, Cs):
                 mf.mf_classical_mm(A, B, C)
         ms_loop = timed(standalone, max(2, args.steps // 2), 1)
-        # algorithmic leaf work of the tuned batch: R^d products of size n / 2^d each
-        leaf_flops = sum((R / 8.0) ** d * 2.0 * n ** 3 for n, d in zip(sizes, depths))
+        # algorithmic leaf work of the tuned batch: R^d products of size n / p^d each
+        leaf_flops = sum((1.0 if d == 0 else (cand_R[id(a)] / cand_p[id(a)] ** 3) ** d) * 2.0 * n ** 3
+                         for n, a, d in zip(sizes, algos, depths))
         achieved = leaf_flops / (ms_tuned * 1e-3) / 1e12
         hist = {}
         for n in sizes:
-            key = "classical" if pick[n][1] == 0 else f"winograd d{pick[n][1]}"
+            a, d = pick[n]
+            key = "classical" if d == 0 else f"{cand_names[id(a)]} d{d}"
             hist[key] = hist.get(key, 0) + 1
         per_dtype[name] = {
             "ms_per_step": round(ms_tuned, 4),
@@ -334,14 +343,16 @@ def run_batched(args):
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "batched: 512 products, n = 64 round(exp(U(ln 128, ln 2048)) / 64) (seed 30), "
                                "FP64 batch and FP32 batch, operands from the counter generator (seeds 2(31+i), "
-                               "2(31+i)+1), autotuned (winograd, depth) per size",
+                               "2(31+i)+1), (algorithm, depth) per size autotuned over classical, Strassen, "
+                               "Strassen-Winograd and <4,4,4;49> at depth 1-2",
                    "count": BATCH_COUNT, "total_flops": flops},
         "both_dtypes_ms": round(total_ms, 4),
         "per_dtype": per_dtype,
         "roofline": f64["roofline"],
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = batch_cpu_baseline(sizes, pick)
+        out["cpu_baseline"] = batch_cpu_baseline(sizes, {n: (None if a is None else cand_names[id(a)], d)
+                                                         for n, (a, d) in pick.items()})
     print(json.dumps(out), flush=True)
 
 
@@ -366,15 +377,19 @@ def batch_instance_error(n, i, C_dev, npdt):
 
 
 def batch_cpu_baseline(sizes, pick):
-    """Oracle fast products of the FP64 batch, in instance order, for about 10 s."""
+    """Oracle fast products of the FP64 batch, in instance order, for about 10 s.
+    pick: size -> (algorithm name or None, depth), as the tuner chose."""
     import numpy as np
 
     import mf_inputs as mi
     from oracle import algebra as oa
     from oracle import matmul as om
 
-    U, V, W, conv = mi.as_float_tables(mi.WINOGRAD)
-    alg = oa.canonical(2, U, V, W, conv)
+    def table(t):
+        U, V, W, conv = mi.as_float_tables(t)
+        return oa.canonical(2, U, V, W, conv)
+    wino = table(mi.WINOGRAD)
+    oracle_algos = {"strassen": table(mi.STRASSEN_PAPER), "winograd": wino, "<4,4,4;49>": oa.compose(wino, wino)}
     done, work, elapsed = 0, 0.0, 0.0
     for i, n in enumerate(sizes):
         if elapsed >= 10.0:
@@ -383,7 +398,11 @@ def batch_cpu_baseline(sizes, pick):
         A = mi.counter_uniform(n * n, sa, np.float64).reshape(n, n)
         B = mi.counter_uniform(n * n, sb, np.float64).reshape(n, n)
         t0 = time.perf_counter()
-        om.fast_mm(A, B, alg, pick[n][1], 0)
+        name, depth = pick[n]
+        if name is None:
+            om.classical_mm(A, B)
+        else:
+            om.fast_mm(A, B, oracle_algos[name], depth, 0)
         elapsed += time.perf_counter() - t0
         work += 2.0 * n ** 3
         done += 1

@@ -14,10 +14,14 @@
  *     C_c = sum_r W[c,r] P_r,                             r = 0..R-1.
  *
  * Execution is a data flow of three phases on the caller's HIP stream:
- * pre-additions (linear combinations of operand blocks), R block products
- * (GEMM) and post-additions (fused into the GEMM epilogue).  Recursion to
- * depth d is executed as one level of the composed algorithm of split factor
- * p^d (the Kronecker construction of Section 2).
+ * pre-additions (linear combinations of operand blocks, one launch per
+ * recursion level), the R^d leaf block products (one grouped MFMA GEMM
+ * launch whose epilogue stores every product once in the workspace) and
+ * post-additions (one launch per level, innermost first, combining the
+ * stored products into the blocks of C).  Recursion to depth d runs level by
+ * level; to run it as one level of the composed algorithm of split factor
+ * p^d (the Kronecker construction of Section 2), compose the algorithm with
+ * mf_algo_compose and call it at depth 1.
  *
  * Conventions for every entry point:
  *  - Device pointers are HIP device allocations; host pointers are ordinary
@@ -113,10 +117,13 @@ mf_status mf_algo_get_uvw(const mf_algo* a, double* U, double* V, double* W);
 /* Release an algorithm (NULL is ignored). */
 void mf_algo_free(mf_algo* a);
 
-/* C = A B with up to `depth` levels of `algo`.  A level is taken while
- * levels remain, the current size exceeds `cutoff` and the 128 leaf tile, and
- * the number of leaf products stays within 2^16 (sizes are rounded up at each
- * split); depth 0 (or cutoff >= n) is the classical product.  Sizes that the split factor does not divide are
+/* C = A B with up to `depth` levels of `algo` (equation "strassen" of
+ * Section 2 applied recursively: T_r, S_r from the blocks of the level above,
+ * P_r = T_r S_r by recursion or by the leaf GEMM, C_c = sum_r W[c,r] P_r).
+ * A level is taken while levels remain, the current size exceeds `cutoff`
+ * and the 128 leaf tile, and the number of leaf products stays within 2^16
+ * (sizes are rounded up at each split); depth 0 (or cutoff >= n) is the
+ * classical product.  Sizes that the split factor does not divide are
  * handled by virtual zero padding (no copy of A, B or C).  Temporaries come
  * from a stream-ordered pool owned by the library, one per device, which
  * keeps the memory it has reserved until the process ends (so repeated calls
@@ -125,8 +132,11 @@ void mf_algo_free(mf_algo* a);
 mf_status mf_fastmm(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C,
                     int64_t n, int dtype, mf_stream stream);
 
-/* C = A B by the library's own MFMA GEMM (no fast algorithm).  BF16 leaves
- * stage the operands in workspace from the library's pool. */
+/* C = A B by the library's own MFMA GEMM, no fast algorithm: the definition
+ * C_ij = sum_k A_ik B_kj (Section 2, equation "basic"; the same product as
+ * the classical blocked recursion of equation "recursion").  dtype as for
+ * mf_fastmm.  BF16 leaves stage the operands in workspace from the library's
+ * pool. */
 mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int dtype, mf_stream stream);
 
 /* Bytes of device workspace mf_fastmm_ws needs for this request (0 for a
@@ -178,7 +188,7 @@ mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A
  * call.  Supported algorithm shapes: combinations of 4, 7, 8, 9 or 16
  * inputs, and of 27 (at most 9 outputs), 49 or 64 (at most 16 outputs)
  * inputs; other shapes give MF_ERR_UNSUPPORTED.  A batch plan is immutable;
- * it must not run concurrently with itself (runs on one stream are fine). */
+ * its runs are ordered (see mf_batch_run). */
 typedef struct mf_batch mf_batch;
 
 /* Plan a batch (host only; device state is made on the first run).  The
@@ -192,7 +202,11 @@ mf_status mf_batch_workspace_bytes(const mf_batch* b, size_t* bytes);
 /* Run the batch on `stream`.  A, B, C: host arrays of `count` device
  * pointers to n[i] x n[i] row-major matrices (C_i must not overlap A_i or
  * B_i).  workspace: NULL (stream-ordered pool of the library) or a caller
- * buffer of at least mf_batch_workspace_bytes, 256-byte aligned. */
+ * buffer of at least mf_batch_workspace_bytes, 256-byte aligned, whose first
+ * mf_batch_workspace_bytes bytes overlap no A_i, B_i or C_i (MF_ERR_ARG).
+ * Runs of one batch are ordered: a run issued on another stream (or from
+ * another host thread) starts after the previous run has finished, since
+ * every run rewrites the batch's device instance table. */
 mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* const* B, void* const* C,
                        void* workspace, size_t ws_bytes, mf_stream stream);
 

@@ -1,7 +1,8 @@
 // Autotuner of the batched form: for each product size it measures every
 // candidate plan (classical, or a given algorithm at depth 1..max_depth)
-// where it will run - many products of that size sharing one persistent
-// launch - and picks the plan with the least device time per product.
+// where it will run - many products of that size in one batch, which runs
+// as one launch per phase - and picks the plan with the least device time per
+// product.
 //
 // The GEMM tile shape is fixed (128 x 128, one compiled shape per element
 // type), so the tuned parameters are the algorithm and the recursion depth;

@@ -1,6 +1,7 @@
 // Batched execution: many independent products C_i = A_i B_i, each with its
-// own algorithm, depth and size, planned as one task list and run by one
-// persistent launch (kernels_batch.hip).
+// own algorithm, depth and size, planned as one task list in topological
+// order and run as one launch per phase over all instances
+// (kernels_batch.hip).
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -41,7 +42,11 @@ struct mf_batch {
   mutable int* d_ctr = nullptr;
   mutable mf::BatchInst* h_insts = nullptr;  // pinned staging of the instance table
   mutable hipEvent_t copied = nullptr;        // the last run's table copy has executed
+  mutable hipEvent_t finished = nullptr;      // the last run's kernels have executed
+  mutable std::mutex run_mu;                  // serialises runs issued from several host threads
   ~mf_batch() {
+    if (finished) (void)hipEventSynchronize(finished);
+    if (finished) (void)hipEventDestroy(finished);
     if (copied) (void)hipEventSynchronize(copied);
     if (copied) (void)hipEventDestroy(copied);
     if (h_insts) (void)hipHostFree(h_insts);
@@ -198,12 +203,17 @@ mf_status upload_batch(const mf_batch* b) {
     mf_status st = ensure_device(*sp.first);
     if (st != MF_OK) return st;
     const CombineStage& cs = sp.second >= 0 ? sp.first->pre[sp.second] : sp.first->post[-1 - sp.second];
-    stage_recs.push_back(StageRec{cs.d_sets, cs.d_ins, cs.d_outs, cs.d_coef, cs.nin, (int32_t)cs.m});
+    const char* d = sp.first->desc();
+    stage_recs.push_back(StageRec{img_at<CombSet>(d, cs.img_sets), img_at<CombIn>(d, cs.img_ins),
+                                  img_at<CombOut>(d, cs.img_outs), img_at<double>(d, cs.img_coef), cs.nin,
+                                  (int32_t)cs.m});
   }
   for (const Plan* pl : b->gemm_list) {
     mf_status st = ensure_device(*pl);
     if (st != MF_OK) return st;
-    gemm_recs.push_back(GemmRec{pl->d_prods, pl->d_epis, pl->d_group_beg, pl->groups, (int32_t)pl->m,
+    const char* d = pl->desc();
+    gemm_recs.push_back(GemmRec{img_at<ProdDesc>(d, pl->img_prods), img_at<EpiDesc>(d, pl->img_epis),
+                                img_at<int32_t>(d, pl->img_group_beg), pl->groups, (int32_t)pl->m,
                                 (int32_t)(pl->m / kLeafTile), 0});
   }
   auto align = [](size_t x) { return (x + 255) / 256 * 256; };
@@ -234,7 +244,8 @@ mf_status upload_batch(const mf_batch* b) {
   b->d_insts = static_cast<BatchInst*>(b->run_dev);
   if (hipHostMalloc(reinterpret_cast<void**>(&b->h_insts), (size_t)b->count * sizeof(BatchInst), hipHostMallocDefault) !=
           hipSuccess ||
-      hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->finished, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     return fail(MF_ERR_NOMEM, "pinned staging allocation of the batch failed");
   }
@@ -339,6 +350,16 @@ mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* cons
     if (workspace) {
       if (ws_bytes < b->ws_bytes) return fail(MF_ERR_SHAPE, "workspace too small");
       if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(MF_ERR_ARG, "workspace must be 256-byte aligned");
+      // the part of the workspace a run uses must not overlap any operand
+      const uintptr_t w0 = reinterpret_cast<uintptr_t>(workspace), w1 = w0 + b->ws_bytes;
+      for (int i = 0; i < b->count; ++i) {
+        const size_t bytes = (size_t)b->n[i] * (size_t)b->n[i] * b->elem;
+        for (const void* p : {A[i], B[i], static_cast<const void*>(C[i])}) {
+          const uintptr_t x = reinterpret_cast<uintptr_t>(p);
+          if (x < w1 && w0 < x + bytes)
+            return fail(MF_ERR_ARG, "workspace overlaps A, B or C of instance " + std::to_string(i));
+        }
+      }
     } else {
       if (workspace_alloc(&ws, b->ws_bytes, s) != hipSuccess || !ws) {
         (void)hipGetLastError();
@@ -349,11 +370,20 @@ mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* cons
   }
   for (int i = 0; i < b->count; ++i) insts[i].ws = static_cast<char*>(ws) + b->ws_off[i];
   mf_status st = MF_OK;
-  // The pinned staging buffer is reused: wait until the previous run's copy
-  // out of it has executed.
-  if (hipEventSynchronize(b->copied) != hipSuccess) return fail(MF_ERR_HIP, "waiting for the previous run failed");
+  // One instance table per batch, rewritten by every run.  Runs are ordered:
+  // host threads take the lock; the pinned staging buffer is reused once the
+  // previous run's copy out of it has executed; and the device table is
+  // overwritten only after the previous run's kernels (on whatever stream
+  // they were issued) have finished reading it.
+  std::lock_guard<std::mutex> lk(b->run_mu);
+  if (hipEventSynchronize(b->copied) != hipSuccess) {
+    if (own) (void)workspace_free(ws, s);
+    return fail(MF_ERR_HIP, "waiting for the previous run failed");
+  }
   memcpy(b->h_insts, insts.data(), insts.size() * sizeof(BatchInst));
-  hipError_t e = hipMemcpyAsync(b->d_insts, b->h_insts, insts.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s);
+  hipError_t e = hipStreamWaitEvent(s, b->finished, 0);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_insts, b->h_insts, insts.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(b->copied, s);
   if (kPersistentBatch) {
     if (e == hipSuccess) e = launch_fill_zero(b->d_ctr, b->nctr + 2, s);
@@ -366,6 +396,7 @@ mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* cons
                              b->phase_range[p].second - b->phase_range[p].first, b->d_stages, b->d_gemms,
                              b->d_insts, s);
   }
+  if (e == hipSuccess) e = hipEventRecord(b->finished, s);
   if (e != hipSuccess) st = fail(MF_ERR_HIP, std::string("batch launch failed: ") + hipGetErrorString(e));
   if (own && workspace_free(ws, s) != hipSuccess && st == MF_OK) st = fail(MF_ERR_HIP, "workspace release failed");
   return st;

@@ -1,0 +1,153 @@
+"""GPU parity of the batched form on its benchmark workload: sizes
+n = 64 round(exp(U(ln 128, ln 2048)) / 64) drawn with seed 30, FP64 and FP32
+batches, every instance checked against the CPU oracle.  Plans cycle through
+the classical GEMM, the paper's Strassen, Strassen-Winograd at depth 1 and 2
+and <4,4,4;49> (Winograd composed with itself), so every eligible algorithm
+runs inside one batch; a second test drives a batch from the autotuner with
+Strassen and <4,4,4;49> among its candidates."""
+import numpy as np
+import pytest
+
+import mf_inputs as mi
+from oracle import matmul as om
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mf = pytest.importorskip("paper_2312_12732_amd.mf", reason="libmf.so not built")
+
+COUNT = 64
+
+
+def config4_sizes():
+    """The first COUNT sizes of the 512-instance draw, with its largest size
+    (2048) in place of the last one so that the top of the range is covered."""
+    full = mi.batch_sizes(512, 30)
+    sizes = full[:COUNT]
+    sizes[-1] = max(full)
+    assert max(sizes) == 2048 and min(sizes) >= 128 and all(n % 64 == 0 for n in sizes)
+    return sizes
+
+
+def cycled_plans():
+    wino = mf.mf_algo_builtin("winograd")
+    stras = mf.mf_algo_builtin("strassen")
+    c444 = mf.mf_algo_compose(wino, wino)
+    return [(None, 0), (stras, 1), (wino, 1), (wino, 2), (c444, 1)]
+
+
+def run_batch(sizes, algos, depths, code, tdt, seed0):
+    b = mf.mf_batch_create(sizes, algos, depths, [0] * len(sizes), code)
+    dA, dB, dC = [], [], []
+    for i, n in enumerate(sizes):
+        A = torch.empty(n, n, dtype=tdt, device="cuda:0")
+        B = torch.empty(n, n, dtype=tdt, device="cuda:0")
+        mf.mf_fill_uniform(A, 2 * (seed0 + i))
+        mf.mf_fill_uniform(B, 2 * (seed0 + i) + 1)
+        dA.append(A)
+        dB.append(B)
+        dC.append(torch.full_like(A, float("nan")))
+    mf.mf_batch_run(b, dA, dB, dC)
+    torch.cuda.synchronize()
+    assert not b.aborted()
+    return b, dA, dB, dC
+
+
+def host_operands(n, i, seed0, npdt):
+    A = mi.counter_uniform(n * n, 2 * (seed0 + i), npdt).astype(np.float64).reshape(n, n)
+    B = mi.counter_uniform(n * n, 2 * (seed0 + i) + 1, npdt).astype(np.float64).reshape(n, n)
+    return A, B
+
+
+@pytest.mark.parametrize("name", ["f64", "f32"])
+def test_config4_every_instance_against_oracle(name):
+    code, tdt, npdt, tol = {"f64": (mf.MF_F64, torch.float64, np.float64, 1e-11),
+                            "f32": (mf.MF_F32, torch.float32, np.float32, 2e-5)}[name]
+    sizes = config4_sizes()
+    plans = cycled_plans()
+    algos = [plans[i % len(plans)][0] for i in range(len(sizes))]
+    depths = [plans[i % len(plans)][1] for i in range(len(sizes))]
+    print(f"config4 {name}: {len(sizes)} instances, sizes {min(sizes)}..{max(sizes)}", flush=True)
+    _, _, _, dC = run_batch(sizes, algos, depths, code, tdt, 31)
+    worst = 0.0
+    for i, n in enumerate(sizes):
+        A, B = host_operands(n, i, 31, npdt)
+        rows = np.sort(np.random.default_rng(i).choice(n, size=min(n, 48), replace=False))
+        got = dC[i][torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+        assert np.isfinite(got).all(), f"instance {i} (n={n}) has non-finite entries"
+        err = om.rel_fro_error(got, om.rows_reference(A, B, rows))
+        worst = max(worst, err)
+        assert err < tol, f"instance {i} n={n} depth {depths[i]}: rel err {err:.3e}"
+    print(f"config4 {name}: worst sampled rel err {worst:.3e}", flush=True)
+
+
+def test_config4_fp64_integer_exact():
+    """Integer-valued FP64 operands: every instance equals the exact product."""
+    sizes = config4_sizes()
+    plans = cycled_plans()
+    algos = [plans[(i + 2) % len(plans)][0] for i in range(len(sizes))]
+    depths = [plans[(i + 2) % len(plans)][1] for i in range(len(sizes))]
+    b = mf.mf_batch_create(sizes, algos, depths, [0] * len(sizes), mf.MF_F64)
+    As = [mi.int_uniform(n, 3000 + i) for i, n in enumerate(sizes)]
+    Bs = [mi.int_uniform(n, 4000 + i) for i, n in enumerate(sizes)]
+    dA = [torch.from_numpy(a.astype(np.float64)).cuda() for a in As]
+    dB = [torch.from_numpy(x.astype(np.float64)).cuda() for x in Bs]
+    dC = [torch.full_like(a, float("nan")) for a in dA]
+    mf.mf_batch_run(b, dA, dB, dC)
+    torch.cuda.synchronize()
+    for i, (A, B) in enumerate(zip(As, Bs)):
+        assert np.array_equal(dC[i].cpu().numpy(), om.classical_mm(A, B).astype(np.float64)), f"instance {i}"
+
+
+def test_tuner_with_strassen_and_444_candidates_drives_exact_batch():
+    """The tuner measures the paper's Strassen, Strassen-Winograd and
+    <4,4,4;49> at every depth a size admits; the batch it picks is exact."""
+    stras = mf.mf_algo_builtin("strassen")
+    wino = mf.mf_algo_builtin("winograd")
+    c444 = mf.mf_algo_compose(wino, wino)
+    sizes = [128, 640, 1024, 2048]
+    choices, ms = mf.mf_autotune_batch(sizes, mf.MF_F64, [stras, wino, c444], 2, work_flops=4e10,
+                                       max_copies=64, reps=1)
+    # candidates: classical, strassen d1 d2, winograd d1 d2, <4,4,4;49> d1 d2
+    assert all(len(row) == 7 for row in ms)
+    assert ms[0][1:] == [-1] * 6  # 128: no level is taken
+    for row in ms[2:]:  # 1024 and 2048: every algorithm runs at depth 1
+        assert row[0] > 0 and row[1] > 0 and row[3] > 0 and row[5] > 0
+    pick = dict(zip(sizes, choices))
+    run_sizes = [2048, 128, 1024, 640, 2048]
+    b = mf.mf_batch_create(run_sizes, [pick[n][0] for n in run_sizes], [pick[n][1] for n in run_sizes],
+                           [0] * len(run_sizes), mf.MF_F64)
+    As = [mi.int_uniform(n, 5000 + i) for i, n in enumerate(run_sizes)]
+    Bs = [mi.int_uniform(n, 6000 + i) for i, n in enumerate(run_sizes)]
+    dA = [torch.from_numpy(a.astype(np.float64)).cuda() for a in As]
+    dB = [torch.from_numpy(x.astype(np.float64)).cuda() for x in Bs]
+    dC = [torch.full_like(a, float("nan")) for a in dA]
+    mf.mf_batch_run(b, dA, dB, dC)
+    torch.cuda.synchronize()
+    for i, (A, B) in enumerate(zip(As, Bs)):
+        assert np.array_equal(dC[i].cpu().numpy(), om.classical_mm(A, B).astype(np.float64)), f"instance {i}"
+
+
+def test_batch_runs_on_two_streams_in_a_row():
+    """One batch plan run back to back on two streams with different operands:
+    the second run's instance table must not reach the device before the first
+    run's kernels have read theirs."""
+    wino = mf.mf_algo_builtin("winograd")
+    sizes = [1024, 512, 768]
+    b = mf.mf_batch_create(sizes, [wino] * 3, [2, 1, 1], [0] * 3, mf.MF_F64)
+    ops = []
+    for r in range(2):
+        As = [mi.int_uniform(n, 7000 + 10 * r + i) for i, n in enumerate(sizes)]
+        Bs = [mi.int_uniform(n, 7500 + 10 * r + i) for i, n in enumerate(sizes)]
+        dA = [torch.from_numpy(a.astype(np.float64)).cuda() for a in As]
+        dB = [torch.from_numpy(x.astype(np.float64)).cuda() for x in Bs]
+        dC = [torch.full_like(a, float("nan")) for a in dA]
+        ops.append((As, Bs, dA, dB, dC))
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    mf.mf_batch_run(b, *ops[0][2:], stream=s1)
+    mf.mf_batch_run(b, *ops[1][2:], stream=s2)
+    torch.cuda.synchronize()
+    for As, Bs, _, _, dC in ops:
+        for A, B, C in zip(As, Bs, dC):
+            assert np.array_equal(C.cpu().numpy(), om.classical_mm(A, B).astype(np.float64))

@@ -39,6 +39,8 @@ mf_status new_handle(const Algo& a, mf_algo** out) {
   return MF_OK;
 }
 
+}  // namespace
+
 // Byte ranges [x, x + xb) and [y, y + yb) intersect.
 bool overlaps(const void* x, size_t xb, const void* y, size_t yb) {
   const uintptr_t a = reinterpret_cast<uintptr_t>(x), b = reinterpret_cast<uintptr_t>(y);
@@ -74,6 +76,8 @@ mf_status plan_for(const mf_algo* algo, int depth, int cutoff, int64_t n, int dt
   return get_plan(depth > 0 ? algo : nullptr, depth, cutoff, n, dtype, kStandaloneMinWorkgroups, pl);
 }
 
+namespace {
+
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 // Phase timing: when enabled, every call records a HIP event on its stream
@@ -88,9 +92,11 @@ PhaseTiming& timing() {
   return *t;
 }
 
-mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, hipStream_t s) {
-  mf_status st = ensure_device(pl);
-  if (st != MF_OK) return st;
+}  // namespace
+
+// Enqueues the phases of one product on stream s.  desc: device address of a
+// copy of the plan's descriptor image; ws: the plan's workspace.
+mf_status run_at(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws, hipStream_t s) {
   // Rows start on 16-byte boundaries when the bases do and a row is a whole
   // number of 16-byte units.
   const bool rows16 = (pl.n * (int64_t)pl.elem) % 16 == 0;
@@ -126,18 +132,19 @@ mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, h
     hipError_t e = hipSuccess;
     if (ph == 0) {
       for (const CombineStage& st : pl.pre)
-        if (e == hipSuccess) e = launch_combine(st, (int)pl.elem, A, B, C, ws, vec_in, vec_c, s);
+        if (e == hipSuccess) e = launch_combine(st, desc, (int)pl.elem, A, B, C, ws, vec_in, vec_c, s);
       // BF16 leaves: the last pre-addition level, fused with the staging
-      if (e == hipSuccess && (leaf == 2 || leaf == 3)) e = launch_stage_bf16(pl, leaf == 3, A, B, C, ws, vec_in, s);
+      if (e == hipSuccess && (leaf == 2 || leaf == 3))
+        e = launch_stage_bf16(pl, desc, leaf == 3, A, B, C, ws, vec_in, s);
     } else if (ph == 2) {
       for (const CombineStage& st : pl.post)
-        if (e == hipSuccess) e = launch_combine(st, (int)pl.elem, A, B, C, ws, vec_in, vec_c, s);
+        if (e == hipSuccess) e = launch_combine(st, desc, (int)pl.elem, A, B, C, ws, vec_in, vec_c, s);
     } else if (pl.elem == 8)
-      e = launch_gemm_f64(pl, A, B, C, ws, vec_in, s);
+      e = launch_gemm_f64(pl, desc, A, B, C, ws, vec_in, s);
     else if (leaf == 2 || leaf == 3)
-      e = launch_gemm_bf16(pl, leaf == 3, A, B, C, ws, vec_in, s);
+      e = launch_gemm_bf16(pl, desc, leaf == 3, A, B, C, ws, vec_in, s);
     else
-      e = launch_gemm_f32(pl, A, B, C, ws, vec_in, s);
+      e = launch_gemm_f32(pl, desc, A, B, C, ws, vec_in, s);
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   }
   if (timed) {
@@ -149,7 +156,14 @@ mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, h
   return MF_OK;
 }
 
-constexpr int kMaxDevices = 64;
+namespace {
+
+// run_at() with the plan's own device copy of its descriptors.
+mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, hipStream_t s) {
+  mf_status st = ensure_device(pl);
+  if (st != MF_OK) return st;
+  return run_at(pl, pl.desc(), A, B, C, ws, s);
+}
 
 // One pool per device, made on first use and kept until the process ends.
 hipMemPool_t device_pool(int dev) {

@@ -66,10 +66,7 @@ __device__ __forceinline__ T* dst_ptr(const GemmArgs<T>& g, int dst) {
 // range of (group, position) pairs, and walk positions in bands of BAND tile
 // rows so that concurrently running tiles share operand panels in the XCD's
 // L2 (8 for the FP64/FP32 tiles; the BF16 kernel passes its own).
-#ifndef MF_GEMM_BAND
-#define MF_GEMM_BAND 8
-#endif
-template <int BAND = MF_GEMM_BAND>
+template <int BAND = 8>
 __device__ __forceinline__ void work_of(int b, int tiles_m, int tiles_n, int groups, int* grp, int* ti, int* tj) {
   const int G = tiles_m * tiles_n;
   const int total = G * groups;

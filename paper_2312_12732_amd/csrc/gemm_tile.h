@@ -5,8 +5,7 @@
 // WAVES_M x WAVES_N waves, each wave (BM / WAVES_M) x (BN / WAVES_N) made of
 // 16 x 16 MFMA tiles, K step 16 (4 MFMA k-steps of 4), LDS double-buffered.
 // Tile128: 128 x 128, 8 waves of 64 x 32, two workgroups per CU (4 waves per
-// SIMD).  Tile256: 256 x 128, 8 waves of 128 x 32, one workgroup per CU (2
-// waves per SIMD, accumulators in 128 of each wave's 256 registers).  Both MFMAs used (v_mfma_f64_16x16x4_f64, v_mfma_f32_16x16x4_f32) take
+// SIMD).  Both MFMAs used (v_mfma_f64_16x16x4_f64, v_mfma_f32_16x16x4_f32) take
 //   A operand: lane l holds A[l % 16][l / 16]   (16 x 4)
 //   B operand: lane l holds B[l / 16][l % 16]   (4 x 16)
 // and return 4 values per lane:
@@ -27,13 +26,6 @@
 
 namespace mf {
 
-#ifndef MF_GEMM_FRAG_DB
-#define MF_GEMM_FRAG_DB 1
-#endif
-#ifndef MF_GEMM_SETPRIO
-#define MF_GEMM_SETPRIO 0
-#endif
-
 template <int BM_, int BN_, int WAVES_M_, int WAVES_N_, int WAVES_PER_SIMD_>
 struct TileCfg {
   static constexpr int BM = BM_, BN = BN_, BK = 16;
@@ -51,7 +43,6 @@ struct TileCfg {
   static_assert(BM % kLeafTile == 0 && BN % kLeafTile == 0, "tiles are multiples of the leaf granularity");
 };
 using Tile128 = TileCfg<128, 128, 2, 4, 4>;
-using Tile256 = TileCfg<256, 128, 2, 4, 2>;
 
 // Element pair idx of the A tile -> (row, kp): the pair A[row][kp..kp+1].
 // LDS has 32 four-byte banks and serves 128 bytes per cycle (16 lanes of a
@@ -260,24 +251,15 @@ __device__ __forceinline__ void k_loop(T* lds, const T* __restrict__ pa, int lda
     if (more) load((kt + 1) * BK);
     const T* As = a_buf(cur);
     const T* Bs = b_buf(cur);
-#if MF_GEMM_FRAG_DB
+    // fragments double-buffered: the reads of k-step s + 1 are issued before
+    // the MFMAs of k-step s
     T fa[2][WM_T], fb[2][WN_T];
     load_frags<T, Cfg>(As, Bs, 0, wm, wn, lr, lk, fa[0], fb[0]);
-    if (MF_GEMM_SETPRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       if (s + 1 < BK / 4) load_frags<T, Cfg>(As, Bs, s + 1, wm, wn, lr, lk, fa[(s + 1) & 1], fb[(s + 1) & 1]);
       mfma_step<T, Cfg>(fa[s & 1], fb[s & 1], acc);
     }
-    if (MF_GEMM_SETPRIO) __builtin_amdgcn_s_setprio(0);
-#else
-#pragma unroll
-    for (int s = 0; s < BK / 4; ++s) {
-      T fa[WM_T], fb[WN_T];
-      load_frags<T, Cfg>(As, Bs, s, wm, wn, lr, lk, fa, fb);
-      mfma_step<T, Cfg>(fa, fb, acc);
-    }
-#endif
     if (more) store_tiles<T, Cfg>(a_buf(cur ^ 1), b_buf(cur ^ 1), t, ra, rb);
     __syncthreads();
   }
@@ -285,7 +267,10 @@ __device__ __forceinline__ void k_loop(T* lds, const T* __restrict__ pa, int lda
 
 // One work item of the grouped GEMM: tile (ti, tj) of every product of group
 // grp, in product order, each followed by its epilogue post-additions.
-template <class T, class Cfg>
+// FULL: the host has checked that every operand view and every epilogue
+// output of the plan covers its whole m x m block with 16-byte aligned rows,
+// so no tile needs the masked load path or a masked store.
+template <class T, class Cfg, bool FULL = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti, int tj, T* lds) {
   typedef typename Mfma<T>::v4 v4;
   constexpr int BM = Cfg::BM, BN = Cfg::BN, WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, WAVES_N = Cfg::WAVES_N;
@@ -310,12 +295,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
 #pragma unroll
       for (int ni = 0; ni < WN_T; ++ni) acc[mi][ni] = v4{T(0), T(0), T(0), T(0)};
 
-    const bool interior = vec_a && vec_b && i0 + BM <= pd.a_vr && pd.a_vc >= g.m && pd.b_vr >= g.m &&
-                          j0 + BN <= pd.b_vc;
+    const bool interior = FULL || (vec_a && vec_b && i0 + BM <= pd.a_vr && pd.a_vc >= g.m && pd.b_vr >= g.m &&
+                                   j0 + BN <= pd.b_vc);
     if (interior)
       k_loop<T, Cfg, false>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
                        lk, acc);
-    else
+    else if constexpr (!FULL)
       k_loop<T, Cfg, true>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
                       lk, acc);
 
@@ -323,7 +308,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
     for (int e = pd.epi_beg; e < pd.epi_end; ++e) {
       const EpiDesc ed = load_uniform(g.epis + e);
       T* pc = dst_ptr(g, ed.c_src) + ed.c_off;
-      const bool full = (i0 + BM <= ed.c_vr) && (j0 + BN <= ed.c_vc);
+      const bool full = FULL || ((i0 + BM <= ed.c_vr) && (j0 + BN <= ed.c_vc));
       const T coef = (T)ed.coef;
 #pragma unroll
       for (int mi = 0; mi < WM_T; ++mi)

@@ -151,16 +151,14 @@ __global__ void __launch_bounds__(256)
 // Tile geometry: a BM_ x BN_ output tile per workgroup of WM_ x WN_ waves,
 // each wave (BM_ / WM_) x (BN_ / WN_) = WTM x WTN MFMA tiles of 16 x 16; two
 // waves per SIMD either way.
-//   Cfg128: 128 x 128, 2 x 2 waves of 64 x 64 (BF16 and split-BF16x3),
-//           two workgroups per CU;
-//   Cfg256: 256 x 128, 2 x 2 waves of 128 x 64, two workgroups per CU: a
-//           quarter fewer LDS fragment reads per MFMA (BF16 only: the x3
-//           form's hi and lo fragments do not fit this wave tile);
-//   CfgSq:  256 x 256, 2 x 4 waves of 128 x 64, one workgroup per CU: the
-//           wave tile of Cfg256 with a third less operand traffic from L2
-//           per flop, which bounds BF16 at these tile sizes;
-//   CfgW:   256 x 128, 4 x 2 waves of 64 x 64, one workgroup per CU (either
-//           form).
+//   Cfg128: 128 x 128, 2 x 2 waves of 64 x 64, two workgroups per CU (either
+//           form; leaves that the larger tiles do not divide);
+//   CfgSq:  256 x 256, 2 x 4 waves of 128 x 64, one workgroup per CU (BF16:
+//           a third less operand traffic from L2 per flop than two 256 x 128
+//           tiles, which bounds BF16 at these tile sizes; the x3 form's hi
+//           and lo fragments do not fit its wave tile);
+//   CfgW:   256 x 128, 4 x 2 waves of 64 x 64, one workgroup per CU
+//           (split-BF16x3).
 template <int BM_, int BN_, int WM_, int WN_>
 struct BfCfg {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
@@ -171,7 +169,6 @@ struct BfCfg {
   static_assert(A_LOADS * 8 * NT == BM * BK && B_LOADS * 8 * NT == BN * BK, "whole 16-byte pieces");
 };
 using Cfg128 = BfCfg<128, 128, 2, 2>;
-using Cfg256 = BfCfg<256, 128, 2, 2>;
 using CfgSq = BfCfg<256, 256, 2, 4>;
 using CfgW = BfCfg<256, 128, 4, 2>;
 
@@ -254,34 +251,18 @@ __device__ __forceinline__ void mma_step(const Lds<C, X3>& L, int cur, int wm, i
   }
 }
 
-// K loop.  MF_BF16_PREFETCH = 1: the loads of step k+1 are issued at the start
-// of step k and written to LDS at its end.  MF_BF16_PREFETCH = 2: two register
-// sets; the loads of step k+2 are issued at the start of step k and written to
-// LDS at the end of step k+1, so two steps of MFMA work cover their latency.
-// The leaf size is a multiple of 128, so the number of steps (m / 32) is a
-// multiple of 4; past the end the loads repeat the last step (in bounds, never
-// read back).
-#ifndef MF_BF16_PREFETCH
-#define MF_BF16_PREFETCH 2
-#endif
-// MF_BF16_FENCE = 1 keeps the scheduler from sinking the loads of a step below
-// its MFMAs (it does so to save registers, which shortens the prefetch
-// distance); measured slower than leaving the schedule to the compiler.
-#ifndef MF_BF16_FENCE
-#define MF_BF16_FENCE 0
-#endif
-#if MF_BF16_FENCE
-#define MF_BF16_ISSUE_FENCE() __builtin_amdgcn_sched_barrier(0)
-#else
-#define MF_BF16_ISSUE_FENCE() ((void)0)
-#endif
-
+// K loop: two register sets; the loads of step k+2 are issued at the start
+// of step k and written to LDS at the end of step k+1, so two steps of MFMA
+// work cover their latency (one step ahead measured 2-6% slower; a scheduling
+// fence that keeps the loads above the MFMAs measured slower than the
+// compiler's own order).  The leaf size is a multiple of 128, so the number of
+// steps (m / 32) is a multiple of 4; past the end the loads repeat the last
+// step (in bounds, never read back).
 template <class C, bool X3>
 __device__ __forceinline__ void k_loop(Lds<C, X3>& L, const __bf16* a, const __bf16* b, int64_t plane, int m, int i0,
                                        int j0, int t, int wm, int wn, int lr, int lk,
                                        f4 (&acc)[C::WTM][C::WTN]) {
   const int KT = m / BK;
-#if MF_BF16_PREFETCH == 2
   bf8 ra0[PLANES_MAX][C::A_LOADS], rb0[PLANES_MAX][C::B_LOADS];
   bf8 ra1[PLANES_MAX][C::A_LOADS], rb1[PLANES_MAX][C::B_LOADS];
   load_stage<C, X3>(a, b, plane, m, i0, j0, 0, t, ra0, rb0);
@@ -291,38 +272,20 @@ __device__ __forceinline__ void k_loop(Lds<C, X3>& L, const __bf16* a, const __b
   for (int kt = 0; kt < KT; kt += 2) {
     // LDS buffer 0 holds step kt; set 1 holds step kt + 1 (in flight)
     load_stage<C, X3>(a, b, plane, m, i0, j0, min(kt + 2, KT - 1) * BK, t, ra0, rb0);
-    MF_BF16_ISSUE_FENCE();
     mma_step<C, X3>(L, 0, wm, wn, lr, lk, acc);
     store_stage<C, X3>(L, 1, t, ra1, rb1);
     __syncthreads();
     // LDS buffer 1 holds step kt + 1; set 0 holds step kt + 2 (in flight)
     load_stage<C, X3>(a, b, plane, m, i0, j0, min(kt + 3, KT - 1) * BK, t, ra1, rb1);
-    MF_BF16_ISSUE_FENCE();
     mma_step<C, X3>(L, 1, wm, wn, lr, lk, acc);
     store_stage<C, X3>(L, 0, t, ra0, rb0);
     __syncthreads();
   }
-#else
-  bf8 ra[PLANES_MAX][C::A_LOADS], rb[PLANES_MAX][C::B_LOADS];
-  load_stage<C, X3>(a, b, plane, m, i0, j0, 0, t, ra, rb);
-  store_stage<C, X3>(L, 0, t, ra, rb);
-  __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    const bool more = kt + 1 < KT;
-    if (more) load_stage<C, X3>(a, b, plane, m, i0, j0, (kt + 1) * BK, t, ra, rb);
-    mma_step<C, X3>(L, cur, wm, wn, lr, lk, acc);
-    if (more) store_stage<C, X3>(L, cur ^ 1, t, ra, rb);
-    __syncthreads();
-  }
-#endif
 }
 
 // XCD bands of 4 tile rows: at n = 16384 2-3% faster than 8 (and than 2) for
 // the 256-row tiles, one workgroup per CU.
-#ifndef MF_BF16_BAND
-#define MF_BF16_BAND 4
-#endif
+constexpr int kBand = 4;
 
 template <class C, bool X3>
 __global__ void __launch_bounds__(C::NT, C::MIN_BLOCKS)
@@ -334,7 +297,7 @@ __global__ void __launch_bounds__(C::NT, C::MIN_BLOCKS)
   const int wm = (wave / C::WN) * (C::BM / C::WM), wn = (wave % C::WN) * (C::BN / C::WN);
   const int lr = lane & 15, lk = lane >> 4;
   int grp, ti, tj;
-  work_of<MF_BF16_BAND>(blockIdx.x, g.tiles_m, g.tiles_n, g.groups, &grp, &ti, &tj);
+  work_of<kBand>(blockIdx.x, g.tiles_m, g.tiles_n, g.groups, &grp, &ti, &tj);
   const int i0 = ti * C::BM, j0 = tj * C::BN;
   const int r_beg = load_uniform(g.group_beg + grp), r_end = load_uniform(g.group_beg + grp + 1);
   constexpr int P = X3 ? 2 : 1;
@@ -374,26 +337,18 @@ __global__ void __launch_bounds__(C::NT, C::MIN_BLOCKS)
 
 bool stage_supported(int nin) { return nin == 1 || nin == 4 || nin == 9 || nin == 16; }
 
-// Tile choice per form: 0 Cfg128, 1 Cfg256, 2 CfgSq, 3 CfgW (a choice whose
-// tile does not divide the leaf size falls back to Cfg128).
-#ifndef MF_BF16_TILE
-#define MF_BF16_TILE 2
-#endif
-#ifndef MF_BF16X3_TILE
-#define MF_BF16X3_TILE 3
-#endif
 
 namespace {
 
-GemmArgs<float> bf_args(const Plan& pl, const void* A, const void* B, void* C, void* ws) {
+GemmArgs<float> bf_args(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws) {
   GemmArgs<float> g;
   g.A = static_cast<const float*>(A);
   g.B = static_cast<const float*>(B);
   g.C = static_cast<float*>(C);
   g.ws = static_cast<float*>(ws);
-  g.prods = pl.d_prods;
-  g.epis = pl.d_epis;
-  g.group_beg = pl.d_group_beg;
+  g.prods = img_at<ProdDesc>(desc, pl.img_prods);
+  g.epis = img_at<EpiDesc>(desc, pl.img_epis);
+  g.group_beg = img_at<int32_t>(desc, pl.img_group_beg);
   g.groups = pl.groups;
   g.m = (int)pl.m;
   g.vec_in = 0;
@@ -406,10 +361,14 @@ bool bf_plan_ok(const Plan& pl, const void* ws) {
 
 }  // namespace
 
-hipError_t launch_stage_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
-                             hipStream_t s) {
+hipError_t launch_stage_bf16(const Plan& pl, const char* desc, bool x3, const void* A, const void* B, void* C,
+                             void* ws, bool vec_in, hipStream_t s) {
   if (!bf_plan_ok(pl, ws)) return hipErrorInvalidValue;
-  const GemmArgs<float> g = bf_args(pl, A, B, C, ws);
+  const GemmArgs<float> g = bf_args(pl, desc, A, B, C, ws);
+  const StageSet* sets = img_at<StageSet>(desc, pl.img_bf_sets);
+  const CombIn* ins = img_at<CombIn>(desc, pl.img_bf_ins);
+  const StageOut* outs = img_at<StageOut>(desc, pl.img_bf_outs);
+  const float* coef = img_at<float>(desc, pl.img_bf_coef);
   __bf16* staged = reinterpret_cast<__bf16*>(static_cast<char*>(ws) + pl.bf_base);
   const int64_t plane = pl.m * pl.m;
   const dim3 sgrid((unsigned)((pl.m / bf::ST) * (pl.m / bf::ST)), (unsigned)pl.bf_sets.size());
@@ -420,11 +379,11 @@ hipError_t launch_stage_bf16(const Plan& pl, bool x3, const void* A, const void*
     if (pl.bf_nin != N) return;
     staged_ok = true;
     if (x3)
-      hipLaunchKernelGGL((bf::stage_sets<N, true>), sgrid, dim3(256), 0, s, g, staged, plane, pl.d_bf_sets,
-                         pl.d_bf_ins, pl.d_bf_outs, pl.d_bf_coef, vin);
+      hipLaunchKernelGGL((bf::stage_sets<N, true>), sgrid, dim3(256), 0, s, g, staged, plane, sets, ins, outs,
+                         coef, vin);
     else
-      hipLaunchKernelGGL((bf::stage_sets<N, false>), sgrid, dim3(256), 0, s, g, staged, plane, pl.d_bf_sets,
-                         pl.d_bf_ins, pl.d_bf_outs, pl.d_bf_coef, vin);
+      hipLaunchKernelGGL((bf::stage_sets<N, false>), sgrid, dim3(256), 0, s, g, staged, plane, sets, ins, outs,
+                         coef, vin);
   };
   stage(std::integral_constant<int, 1>{});
   stage(std::integral_constant<int, 4>{});
@@ -434,11 +393,11 @@ hipError_t launch_stage_bf16(const Plan& pl, bool x3, const void* A, const void*
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
-                            hipStream_t s) {
+hipError_t launch_gemm_bf16(const Plan& pl, const char* desc, bool x3, const void* A, const void* B, void* C,
+                            void* ws, bool vec_in, hipStream_t s) {
   (void)vec_in;  // the staged operands are aligned and whole
   if (!bf_plan_ok(pl, ws)) return hipErrorInvalidValue;
-  GemmArgs<float> g = bf_args(pl, A, B, C, ws);
+  GemmArgs<float> g = bf_args(pl, desc, A, B, C, ws);
   const __bf16* st = reinterpret_cast<const __bf16*>(static_cast<char*>(ws) + pl.bf_base);
   const int nprod = (int)pl.prods.size();
   const int64_t plane = pl.m * pl.m;
@@ -450,18 +409,19 @@ hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* 
     const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n * (unsigned)g.groups;
     hipLaunchKernelGGL((bf::gemm_bf16_grouped<Cf, X>), dim3(grid), dim3(Cf::NT), 0, s, g, st, nprod, plane);
   };
-  auto pick = [&](int choice, auto x3c) {
-    if constexpr (!decltype(x3c)::value) {  // tiles whose wave tile only the BF16 form fits
-      if (choice == 1 && pl.m % bf::Cfg256::BM == 0) return launch(bf::Cfg256{}, x3c);
-      if (choice == 2 && pl.m % bf::CfgSq::BM == 0) return launch(bf::CfgSq{}, x3c);
-    }
-    if (choice == 3 && pl.m % bf::CfgW::BM == 0) return launch(bf::CfgW{}, x3c);
-    launch(bf::Cfg128{}, x3c);
-  };
-  if (x3)
-    pick(MF_BF16X3_TILE, std::true_type{});
-  else
-    pick(MF_BF16_TILE, std::false_type{});
+  // BF16: CfgSq; split-BF16x3: CfgW; Cfg128 for leaves the larger tiles do
+  // not divide
+  if (x3) {
+    if (pl.m % bf::CfgW::BM == 0)
+      launch(bf::CfgW{}, std::true_type{});
+    else
+      launch(bf::Cfg128{}, std::true_type{});
+  } else {
+    if (pl.m % bf::CfgSq::BM == 0)
+      launch(bf::CfgSq{}, std::false_type{});
+    else
+      launch(bf::Cfg128{}, std::false_type{});
+  }
   return hipGetLastError();
 }
 

@@ -97,22 +97,12 @@ __device__ __forceinline__ void kron_axpy(T c, const T (&x)[VEC], T (&acc)[VEC])
   for (int q = 0; q < VEC; ++q) acc[q] = fma_t(c, x[q], acc[q]);
 }
 
-// Register budget: the pre-addition holds the 64 inputs (two waves per SIMD;
-// three spill).  The post-addition holds the 64 outputs; unrolling its r2
-// loop hoists up to 49 loads and drops it to one wave per SIMD (FP64 n = 8192:
-// 1.41 ms against 1.00 ms not unrolled).
-#ifndef MF_KRON_PRE_WAVES
-#define MF_KRON_PRE_WAVES 2
-#endif
-#ifndef MF_KRON_POST_UNROLL
-#define MF_KRON_POST_UNROLL 1
-#endif
-#ifndef MF_KRON_POST_PREFETCH
-#define MF_KRON_POST_PREFETCH 0
-#endif
-
+// Register budget: the pre-addition holds the 64 inputs, 195 VGPRs, so it
+// runs at two waves per SIMD (asking for three spills).  The post-addition
+// holds the 64 outputs; its r2 loop stays rolled (unrolled it hoists up to 49
+// loads and drops to one wave per SIMD: FP64 n = 8192, 1.41 ms against 1.00).
 template <class T, int VEC>
-__global__ void __launch_bounds__(256, MF_KRON_PRE_WAVES) kron3_pre(CombArgs<T> g) {
+__global__ void __launch_bounds__(256, 2) kron3_pre(CombArgs<T> g) {
   const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
   const int64_t mm = (int64_t)g.m * g.m;
   if (e >= mm) return;
@@ -177,8 +167,8 @@ __global__ void __launch_bounds__(256) kron3_post(CombArgs<T> g) {
   // products are whole m x m workspace blocks (offset -1: an empty group,
   // zero), each read unconditionally (block 0 for an empty group) and then
   // selected, which measured faster than a conditional load (FP64 n = 8192:
-  // 0.75 against 0.86 ms).  MF_KRON_POST_PREFETCH = 1 issues the 7 loads of
-  // the next (r1, r2) before the current 7 are used: 0.91 ms, off.
+  // 0.75 against 0.86 ms).  (Issuing the 7 loads of the next (r1, r2) before
+  // the current 7 are used measured slower: 0.91 ms.)
   auto load7 = [&](int k, T (&P)[7][VEC]) {
 #pragma unroll
     for (int r3 = 0; r3 < 7; ++r3) {
@@ -190,24 +180,12 @@ __global__ void __launch_bounds__(256) kron3_post(CombArgs<T> g) {
       for (int q = 0; q < VEC; ++q) P[r3][q] = off >= 0.0 ? y[q] : T(0);
     }
   };
-#if MF_KRON_POST_PREFETCH
-  T Pn[7][VEC];
-  load7(0, Pn);
-#endif
   for (int r1 = 0; r1 < 7; ++r1) {
     T t[16][VEC] = {};
-#pragma unroll MF_KRON_POST_UNROLL
+#pragma unroll 1
     for (int r2 = 0; r2 < 7; ++r2) {
       T P[7][VEC];
-#if MF_KRON_POST_PREFETCH
-#pragma unroll
-      for (int r3 = 0; r3 < 7; ++r3)
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) P[r3][q] = Pn[r3][q];
-      if (7 * r1 + r2 + 1 < 49) load7(7 * r1 + r2 + 1, Pn);
-#else
       load7(7 * r1 + r2, P);
-#endif
       T u[4][VEC] = {};
 #pragma unroll
       for (int c3 = 0; c3 < 4; ++c3)
@@ -231,23 +209,20 @@ __global__ void __launch_bounds__(256) kron3_post(CombArgs<T> g) {
   for (int c = 0; c < 64; ++c) kron_store<T, VEC>(g, load_uniform(g.outs + set.out_beg + c), i, j, out[c]);
 }
 
-#ifndef MF_COMB_VEC_SMALL
-#define MF_COMB_VEC_SMALL 4
-#endif
 
 template <class T>
-static hipError_t launch_combine_t(const CombineStage& cs, const void* A, const void* B, void* C, void* ws,
-                                   bool vec_in, bool vec_out, hipStream_t s) {
+static hipError_t launch_combine_t(const CombineStage& cs, const char* desc, const void* A, const void* B, void* C,
+                                   void* ws, bool vec_in, bool vec_out, hipStream_t s) {
   if (cs.sets.empty()) return hipSuccess;
   CombArgs<T> g;
   g.A = static_cast<const T*>(A);
   g.B = static_cast<const T*>(B);
   g.C = static_cast<T*>(C);
   g.ws = static_cast<T*>(ws);
-  g.sets = cs.d_sets;
-  g.ins = cs.d_ins;
-  g.outs = cs.d_outs;
-  g.coef = cs.d_coef;
+  g.sets = img_at<CombSet>(desc, cs.img_sets);
+  g.ins = img_at<CombIn>(desc, cs.img_ins);
+  g.outs = img_at<CombOut>(desc, cs.img_outs);
+  g.coef = img_at<double>(desc, cs.img_coef);
   g.m = (int)cs.m;
   g.vec_in = vec_in ? 1 : 0;
   g.vec_out = vec_out ? 1 : 0;
@@ -284,11 +259,11 @@ static hipError_t launch_combine_t(const CombineStage& cs, const void* A, const 
   switch (cs.nin) {
 #define MF_COMB_CASE(N, V) \
   case N: hipLaunchKernelGGL((combine<T, N, V>), grid(V), dim3(256), 0, s, g); break;
-    MF_COMB_CASE(4, MF_COMB_VEC_SMALL)
-    MF_COMB_CASE(7, MF_COMB_VEC_SMALL)
-    MF_COMB_CASE(8, MF_COMB_VEC_SMALL)
-    MF_COMB_CASE(9, MF_COMB_VEC_SMALL)
-    MF_COMB_CASE(16, MF_COMB_VEC_SMALL)
+    MF_COMB_CASE(4, 4)
+    MF_COMB_CASE(7, 4)
+    MF_COMB_CASE(8, 4)
+    MF_COMB_CASE(9, 4)
+    MF_COMB_CASE(16, 4)
     MF_COMB_CASE(27, 1)
     MF_COMB_CASE(36, 1)
     MF_COMB_CASE(49, 1)
@@ -308,10 +283,10 @@ bool combine_supported(int nin) {
   }
 }
 
-hipError_t launch_combine(const CombineStage& cs, int elem, const void* A, const void* B, void* C, void* ws,
-                          bool vec_in, bool vec_out, hipStream_t s) {
-  return elem == 8 ? launch_combine_t<double>(cs, A, B, C, ws, vec_in, vec_out, s)
-                   : launch_combine_t<float>(cs, A, B, C, ws, vec_in, vec_out, s);
+hipError_t launch_combine(const CombineStage& cs, const char* desc, int elem, const void* A, const void* B, void* C,
+                          void* ws, bool vec_in, bool vec_out, hipStream_t s) {
+  return elem == 8 ? launch_combine_t<double>(cs, desc, A, B, C, ws, vec_in, vec_out, s)
+                   : launch_combine_t<float>(cs, desc, A, B, C, ws, vec_in, vec_out, s);
 }
 
 }  // namespace mf

@@ -131,11 +131,16 @@ struct CombineStage {
   std::vector<CombIn> ins;
   std::vector<CombOut> outs;
   std::vector<double> coef;
-  mutable CombSet* d_sets = nullptr;
-  mutable CombIn* d_ins = nullptr;
-  mutable CombOut* d_outs = nullptr;
-  mutable double* d_coef = nullptr;
+  // byte offsets of sets, ins, outs and coef in the plan's descriptor image
+  size_t img_sets = 0, img_ins = 0, img_outs = 0, img_coef = 0;
 };
+
+// Device pointer to an entry of a descriptor image: `base` is where the image
+// sits in device memory, `off` the entry's byte offset in it.
+template <class T>
+inline const T* img_at(const char* base, size_t off) {
+  return reinterpret_cast<const T*>(base + off);
+}
 
 // BF16 leaves: the last pre-addition level runs fused with the BF16 staging.
 // One set per block of the level above: its nin quarters are the inputs, and
@@ -198,17 +203,19 @@ struct Plan {
   std::vector<CombIn> bf_ins;
   std::vector<StageOut> bf_outs;
   std::vector<float> bf_coef;
-  // device copy (one allocation, owned by the plan), made on first use
+  // Descriptor image: every descriptor array above, each at a 256-byte
+  // aligned byte offset, as the kernels read it from device memory.  Made
+  // when the plan is built; the kernels get the device address of a copy of
+  // it (the plan's own, or one the caller's call placed elsewhere).
+  std::vector<char> image;
+  size_t img_prods = 0, img_epis = 0, img_group_beg = 0;
+  size_t img_bf_sets = 0, img_bf_ins = 0, img_bf_outs = 0, img_bf_coef = 0;
+  // the plan's own device copy of the image (one allocation, owned by the
+  // plan), made on first use
   mutable std::once_flag uploaded;
   mutable mf_status upload_status = MF_OK;
   mutable void* dev = nullptr;
-  mutable ProdDesc* d_prods = nullptr;
-  mutable EpiDesc* d_epis = nullptr;
-  mutable int32_t* d_group_beg = nullptr;
-  mutable StageSet* d_bf_sets = nullptr;
-  mutable CombIn* d_bf_ins = nullptr;
-  mutable StageOut* d_bf_outs = nullptr;
-  mutable float* d_bf_coef = nullptr;
+  const char* desc() const { return static_cast<const char*>(dev); }
   ~Plan();
 };
 
@@ -273,15 +280,13 @@ struct BatchTask {
 // with outer levels only until 1024 workgroups.  Batches use the same plans,
 // so an instance's result is bitwise that of the standalone call.
 // Returns an mf_status and sets the thread's error message on failure.
-#ifndef MF_STANDALONE_MIN_WG
-#define MF_STANDALONE_MIN_WG (int64_t(1) << 62)
-#endif
-constexpr int64_t kStandaloneMinWorkgroups = MF_STANDALONE_MIN_WG;
+constexpr int64_t kStandaloneMinWorkgroups = int64_t(1) << 62;
 mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg,
                    std::shared_ptr<const Plan>* out);
 
-// Copies the plan's descriptors to the device once (host-only queries such as
-// the workspace size never touch the device).
+// Copies the plan's descriptor image to the device once (host-only queries
+// such as the workspace size never touch the device); afterwards pl.desc()
+// is its device address.
 mf_status ensure_device(const Plan& pl);
 
 // Releases the cached plans of an algorithm handle that is being freed.
@@ -301,18 +306,19 @@ int levels_for(int64_t n, int p, int R, int depth, int cutoff);
 // Kernel launchers.  vec_in / vec_out: rows of A and B / of C start on
 // 16-byte boundaries.
 constexpr int kPhases = 3;  // pre-addition, grouped GEMM, outer post-addition
-hipError_t launch_combine(const CombineStage& cs, int elem, const void* A, const void* B, void* C, void* ws,
-                          bool vec_in, bool vec_out, hipStream_t s);
-hipError_t launch_gemm_f64(const Plan& pl, const void* A, const void* B, void* C, void* ws, bool vec_in,
-                           hipStream_t s);
-hipError_t launch_gemm_f32(const Plan& pl, const void* A, const void* B, void* C, void* ws, bool vec_in,
-                           hipStream_t s);
+// desc: device address of a copy of the plan's descriptor image.
+hipError_t launch_combine(const CombineStage& cs, const char* desc, int elem, const void* A, const void* B, void* C,
+                          void* ws, bool vec_in, bool vec_out, hipStream_t s);
+hipError_t launch_gemm_f64(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws,
+                           bool vec_in, hipStream_t s);
+hipError_t launch_gemm_f32(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws,
+                           bool vec_in, hipStream_t s);
 // BF16 leaves: the staging launch (the last pre-addition level fused with the
 // conversion to BF16 planes), then the grouped GEMM on the staged planes.
-hipError_t launch_stage_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
-                             hipStream_t s);
-hipError_t launch_gemm_bf16(const Plan& pl, bool x3, const void* A, const void* B, void* C, void* ws, bool vec_in,
-                            hipStream_t s);
+hipError_t launch_stage_bf16(const Plan& pl, const char* desc, bool x3, const void* A, const void* B, void* C,
+                             void* ws, bool vec_in, hipStream_t s);
+hipError_t launch_gemm_bf16(const Plan& pl, const char* desc, bool x3, const void* A, const void* B, void* C,
+                            void* ws, bool vec_in, hipStream_t s);
 // Input counts with a compiled linear-combination kernel.
 bool combine_supported(int nin);
 // BF16 staging sets exist for this many inputs per set.
@@ -331,6 +337,21 @@ hipError_t launch_batch_phase(int elem, bool gemm, const BatchTask* tasks, int t
 // Whether a combination stage can run inside a batch (the persistent form
 // supports only the narrow shapes).
 bool batch_stage_supported(int nin, int nout_max, bool persistent);
+
+// Request checks shared by the entry points of one product: arguments,
+// sizes, dtype code, alignment and overlap of C with A or B (sets the
+// thread's error message on failure).
+mf_status check_request(const mf_algo* algo, bool need_algo, int depth, int cutoff, const void* A, const void* B,
+                        void* C, int64_t n, int dtype);
+// The plan of a standalone product (classical when depth is 0).
+mf_status plan_for(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
+                   std::shared_ptr<const Plan>* pl);
+// Enqueues the phases of one product on stream s.  desc: device address of
+// a copy of the plan's descriptor image; ws: the plan's workspace.
+mf_status run_at(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws, hipStream_t s);
+// Byte ranges [x, x + xb) and [y, y + yb) intersect.
+bool overlaps(const void* x, size_t xb, const void* y, size_t yb);
+constexpr int kMaxDevices = 64;
 
 // Workspace for one call, from the library's stream-ordered pool on the
 // current device.  The pool keeps the memory it has reserved (release

@@ -561,59 +561,48 @@ size_t bytes_of(const std::vector<T>& v) {
   return v.size() * sizeof(T);
 }
 
-mf_status upload(const Plan* pl) {
+// Lays out every descriptor array of the plan in one image, each at a
+// 256-byte aligned offset (an empty array still takes one aligned slot).
+void make_image(Plan* pl) {
   auto align = [](size_t x) { return (x + 255) / 256 * 256; };
-  struct Part {
-    const void* src;
-    size_t bytes;
-    size_t off;
-  };
-  std::vector<Part> parts = {{pl->prods.data(), bytes_of(pl->prods), 0},
-                             {pl->epis.data(), bytes_of(pl->epis), 0},
-                             {pl->group_beg.data(), bytes_of(pl->group_beg), 0},
-                             {pl->bf_sets.data(), bytes_of(pl->bf_sets), 0},
-                             {pl->bf_ins.data(), bytes_of(pl->bf_ins), 0},
-                             {pl->bf_outs.data(), bytes_of(pl->bf_outs), 0},
-                             {pl->bf_coef.data(), bytes_of(pl->bf_coef), 0}};
-  std::vector<const CombineStage*> stages;
-  for (const auto& st : pl->pre) stages.push_back(&st);
-  for (const auto& st : pl->post) stages.push_back(&st);
-  for (const CombineStage* st : stages) {
-    parts.push_back({st->sets.data(), bytes_of(st->sets), 0});
-    parts.push_back({st->ins.data(), bytes_of(st->ins), 0});
-    parts.push_back({st->outs.data(), bytes_of(st->outs), 0});
-    parts.push_back({st->coef.data(), bytes_of(st->coef), 0});
-  }
   size_t total = 0;
-  for (auto& q : parts) {
-    q.off = total;
-    total += align(std::max<size_t>(q.bytes, 1));
+  std::vector<std::pair<const void*, size_t>> parts;
+  auto place = [&](const void* src, size_t bytes, size_t* off) {
+    *off = total;
+    parts.push_back({src, bytes});
+    total += align(std::max<size_t>(bytes, 1));
+  };
+  place(pl->prods.data(), bytes_of(pl->prods), &pl->img_prods);
+  place(pl->epis.data(), bytes_of(pl->epis), &pl->img_epis);
+  place(pl->group_beg.data(), bytes_of(pl->group_beg), &pl->img_group_beg);
+  place(pl->bf_sets.data(), bytes_of(pl->bf_sets), &pl->img_bf_sets);
+  place(pl->bf_ins.data(), bytes_of(pl->bf_ins), &pl->img_bf_ins);
+  place(pl->bf_outs.data(), bytes_of(pl->bf_outs), &pl->img_bf_outs);
+  place(pl->bf_coef.data(), bytes_of(pl->bf_coef), &pl->img_bf_coef);
+  for (std::vector<CombineStage>* list : {&pl->pre, &pl->post})
+    for (CombineStage& st : *list) {
+      place(st.sets.data(), bytes_of(st.sets), &st.img_sets);
+      place(st.ins.data(), bytes_of(st.ins), &st.img_ins);
+      place(st.outs.data(), bytes_of(st.outs), &st.img_outs);
+      place(st.coef.data(), bytes_of(st.coef), &st.img_coef);
+    }
+  pl->image.assign(total, 0);
+  size_t off = 0;
+  for (const auto& q : parts) {
+    if (q.second) memcpy(pl->image.data() + off, q.first, q.second);
+    off += align(std::max<size_t>(q.second, 1));
   }
-  std::vector<char> host(total, 0);
-  for (auto& q : parts)
-    if (q.bytes) memcpy(host.data() + q.off, q.src, q.bytes);
-  if (hipMalloc(&pl->dev, total) != hipSuccess) {
+}
+
+mf_status upload(const Plan* pl) {
+  if (hipMalloc(&pl->dev, pl->image.size()) != hipSuccess) {
     (void)hipGetLastError();
     pl->dev = nullptr;
     return MF_ERR_NOMEM;
   }
-  if (hipMemcpy(pl->dev, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemcpy(pl->dev, pl->image.data(), pl->image.size(), hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipGetLastError();
     return MF_ERR_HIP;
-  }
-  char* d = static_cast<char*>(pl->dev);
-  pl->d_prods = reinterpret_cast<ProdDesc*>(d + parts[0].off);
-  pl->d_epis = reinterpret_cast<EpiDesc*>(d + parts[1].off);
-  pl->d_group_beg = reinterpret_cast<int32_t*>(d + parts[2].off);
-  pl->d_bf_sets = reinterpret_cast<StageSet*>(d + parts[3].off);
-  pl->d_bf_ins = reinterpret_cast<CombIn*>(d + parts[4].off);
-  pl->d_bf_outs = reinterpret_cast<StageOut*>(d + parts[5].off);
-  pl->d_bf_coef = reinterpret_cast<float*>(d + parts[6].off);
-  for (size_t i = 0; i < stages.size(); ++i) {
-    stages[i]->d_sets = reinterpret_cast<CombSet*>(d + parts[7 + 4 * i].off);
-    stages[i]->d_ins = reinterpret_cast<CombIn*>(d + parts[8 + 4 * i].off);
-    stages[i]->d_outs = reinterpret_cast<CombOut*>(d + parts[9 + 4 * i].off);
-    stages[i]->d_coef = reinterpret_cast<double*>(d + parts[10 + 4 * i].off);
   }
   return MF_OK;
 }
@@ -680,6 +669,7 @@ mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dt
   auto pl = std::make_shared<Plan>();
   const mf_status st = build(levels == 0 ? nullptr : &algo->a, depth, cutoff, n, dtype, min_wg, pl.get());
   if (st != MF_OK) return st;
+  make_image(pl.get());
   std::lock_guard<std::mutex> lk(g_mu);
   auto ins = cache().emplace(key, pl);
   *out = ins.first->second;

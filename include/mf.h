@@ -284,6 +284,15 @@ mf_status mf_server_need_bytes(const mf_server* s, int64_t n, int dtype, size_t*
  * host memory of n*n elements that receives C.  MF_ERR_NOMEM if the request
  * alone exceeds the budget.  *id: request index (may be NULL). */
 mf_status mf_server_submit(mf_server* s, int64_t n, int dtype, uint64_t seed, void* host_out, int64_t* id);
+/* Enqueue a request on caller-owned device operands: C = A B for n x n
+ * row-major A, B, C of the storage type of dtype (MF_F64 or MF_F32; C must not
+ * overlap A or B, MF_ERR_ARG).  The request is admitted against the HBM of its
+ * workspace only; A and B must stay valid and unchanged, and C untouched by
+ * other work, until the request has completed (mf_server_drain).  Its plan is
+ * the same pure function of (n, dtype) as for mf_server_submit, so C is
+ * bitwise what mf_server_submit would give for the same operands. */
+mf_status mf_server_submit_operands(mf_server* s, int64_t n, int dtype, const void* A, const void* B, void* C,
+                                    int64_t* id);
 /* Submit `count` requests from a replay thread at arrival times t_arrive[k]
  * seconds after the call (host arrays are copied). */
 mf_status mf_server_replay(mf_server* s, int count, const double* t_arrive, const int64_t* n, const int* dtype,
@@ -299,6 +308,11 @@ mf_status mf_server_stats(mf_server* s, int64_t* count, double* t_arrive, double
  * operation on its slot's stream to its completion, -1 if not done; ms must
  * hold as many entries as mf_server_stats reports requests. */
 mf_status mf_server_device_ms(mf_server* s, double* ms);
+/* Per request (in id order): the start and end of its device work on the
+ * device's own timeline, in ms since an origin event recorded when the
+ * server started (-1 if not done); requests whose intervals intersect ran on
+ * the device at the same time.  Arrays as for mf_server_device_ms. */
+mf_status mf_server_device_interval(mf_server* s, double* start_ms, double* end_ms);
 /* Stop the worker after the queue drains and release the server. */
 void mf_server_free(mf_server* s);
 

@@ -141,6 +141,11 @@ struct Req {
   int dtype;
   uint64_t seed;
   void* host_out;  // pinned host buffer for C, or NULL
+  // caller-owned device operands (NULL: A and B generated from the seed in
+  // the request's arena block, C there too)
+  const void* A_user = nullptr;
+  const void* B_user = nullptr;
+  void* C_user = nullptr;
   size_t need = 0;
   int depth = 0;
   double t_arrive = 0, t_admit = 0, t_done = 0;
@@ -149,6 +154,9 @@ struct Req {
   mf_status status = MF_OK;
   bool done = false;
   double device_ms = -1;  // from the request's first launch to its completion, on its stream
+  // the same interval on the device timeline: ms since the server's origin
+  // event (recorded when the server started)
+  double device_start = -1, device_end = -1;
 };
 
 size_t round256(size_t x) { return (x + 255) / 256 * 256; }
@@ -161,6 +169,7 @@ struct mf_server {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;        // completion, per slot
   std::vector<hipEvent_t> start_events;  // start of the request's device work, per slot
+  hipEvent_t origin = nullptr;           // device time 0 of the per-request intervals
   char* arena = nullptr;                 // hbm_budget bytes of device memory for admitted requests
   std::vector<int64_t> slot_req;  // request id per slot, -1 if free
   std::mutex mu;
@@ -191,14 +200,16 @@ int depth_for(const mf_server* s, int64_t n, int dtype) {
   return d;
 }
 
-mf_status need_bytes(const mf_server* s, int64_t n, int dtype, int depth, size_t* bytes) {
+// HBM a request is admitted against: A, B and C (unless the caller owns them)
+// and the workspace of its plan.
+mf_status need_bytes(const mf_server* s, int64_t n, int dtype, int depth, bool own_operands, size_t* bytes) {
   size_t ws = 0;
   if (depth > 0) {
     mf_status st = mf_workspace_bytes(s->algo, depth, 0, n, dtype, &ws);
     if (st != MF_OK) return st;
   }
   const size_t elem = (dtype & 0xff) == MF_F64 ? 8 : 4;
-  *bytes = 3 * round256((size_t)n * (size_t)n * elem) + round256(ws);
+  *bytes = (own_operands ? 3 * round256((size_t)n * (size_t)n * elem) : 0) + round256(ws);
   return MF_OK;
 }
 
@@ -206,17 +217,18 @@ mf_status need_bytes(const mf_server* s, int64_t n, int dtype, int depth, size_t
 mf_status launch_request(mf_server* s, Req& r) {
   hipStream_t st = s->streams[r.slot];
   const size_t elem = (r.dtype & 0xff) == MF_F64 ? 8 : 4;
-  const size_t mat = round256((size_t)r.n * (size_t)r.n * elem);
+  const bool own = r.A_user == nullptr;
+  const size_t mat = own ? round256((size_t)r.n * (size_t)r.n * elem) : 0;
   if (hipEventRecord(s->start_events[r.slot], st) != hipSuccess) return fail(MF_ERR_HIP, "start event failed");
   char* mem = s->arena + r.off;  // reserved by admission until the completion is observed
-  void* A = mem;
-  void* B = mem + mat;
-  void* C = mem + 2 * mat;
+  const void* A = own ? static_cast<const void*>(mem) : r.A_user;
+  const void* B = own ? static_cast<const void*>(mem + mat) : r.B_user;
+  void* C = own ? static_cast<void*>(mem + 2 * mat) : r.C_user;
   void* ws = mem + 3 * mat;
   const int64_t cnt = r.n * r.n;
   mf_status res = MF_OK;
-  if (launch_fill_uniform(A, cnt, (int)elem, r.seed * 2 + 0, st) != hipSuccess ||
-      launch_fill_uniform(B, cnt, (int)elem, r.seed * 2 + 1, st) != hipSuccess)
+  if (own && (launch_fill_uniform(const_cast<void*>(A), cnt, (int)elem, r.seed * 2 + 0, st) != hipSuccess ||
+              launch_fill_uniform(const_cast<void*>(B), cnt, (int)elem, r.seed * 2 + 1, st) != hipSuccess))
     res = fail(MF_ERR_HIP, "operand generation launch failed");
   if (res == MF_OK) {
     if (r.depth > 0)
@@ -247,9 +259,14 @@ void worker_loop(mf_server* s) {
       Req& r = s->reqs[id];
       r.t_done = now_s() - s->t0;
       if (q != hipSuccess && r.status == MF_OK) r.status = MF_ERR_HIP;
-      float ms = 0.f;
+      float ms = 0.f, t_start = 0.f, t_end = 0.f;
       if (q == hipSuccess && hipEventElapsedTime(&ms, s->start_events[k], s->events[k]) == hipSuccess)
         r.device_ms = ms;
+      if (q == hipSuccess && hipEventElapsedTime(&t_start, s->origin, s->start_events[k]) == hipSuccess &&
+          hipEventElapsedTime(&t_end, s->origin, s->events[k]) == hipSuccess) {
+        r.device_start = t_start;
+        r.device_end = t_end;
+      }
       r.done = true;
       s->adm.release(id);
       s->slot_req[k] = -1;
@@ -321,6 +338,12 @@ mf_status mf_server_create(const mf_server_config* cfg, const mf_algo* algo, mf_
     s->start_events.push_back(ev0);
     s->slot_req.push_back(-1);
   }
+  if (hipEventCreate(&s->origin) != hipSuccess || hipEventRecord(s->origin, s->streams[0]) != hipSuccess ||
+      hipEventSynchronize(s->origin) != hipSuccess) {
+    (void)hipGetLastError();
+    mf_server_free(s);
+    return fail(MF_ERR_HIP, "origin event failed");
+  }
   s->t0 = now_s();
   s->worker = std::thread(worker_loop, s);
   *out = s;
@@ -331,21 +354,16 @@ mf_status mf_server_need_bytes(const mf_server* s, int64_t n, int dtype, size_t*
   clear_error();
   if (!s || !bytes || n < 1) return fail(MF_ERR_ARG, "invalid argument");
   if ((dtype & 0xff) != MF_F64 && (dtype & 0xff) != MF_F32) return fail(MF_ERR_ARG, "unknown dtype");
-  return need_bytes(s, n, dtype, depth_for(s, n, dtype), bytes);
+  return need_bytes(s, n, dtype, depth_for(s, n, dtype), true, bytes);
 }
 
-mf_status mf_server_submit(mf_server* s, int64_t n, int dtype, uint64_t seed, void* host_out, int64_t* id) {
-  clear_error();
-  if (!s || n < 1 || n > (1 << 16)) return fail(MF_ERR_ARG, "invalid argument");
-  if ((dtype & ~0xff) != 0 || ((dtype & 0xff) != MF_F64 && (dtype & 0xff) != MF_F32))
-    return fail(MF_ERR_ARG, "serving takes MF_F64 or MF_F32 (native leaves)");
-  Req r{};
-  r.n = n;
-  r.dtype = dtype;
-  r.seed = seed;
-  r.host_out = host_out;
-  r.depth = depth_for(s, n, dtype);
-  mf_status st = need_bytes(s, n, dtype, r.depth, &r.need);
+}  // extern "C"
+
+namespace {
+
+mf_status enqueue(mf_server* s, Req r, int64_t* id) {
+  r.depth = depth_for(s, r.n, r.dtype);
+  mf_status st = need_bytes(s, r.n, r.dtype, r.depth, r.A_user == nullptr, &r.need);
   if (st != MF_OK) return st;
   if (r.need > s->cfg.hbm_budget) return fail(MF_ERR_NOMEM, "request needs more HBM than the whole budget");
   std::lock_guard<std::mutex> lk(s->mu);
@@ -356,6 +374,48 @@ mf_status mf_server_submit(mf_server* s, int64_t n, int dtype, uint64_t seed, vo
   s->cv.notify_all();
   if (id) *id = r.id;
   return MF_OK;
+}
+
+bool serving_dtype(int dtype) {
+  return (dtype & ~0xff) == 0 && ((dtype & 0xff) == MF_F64 || (dtype & 0xff) == MF_F32);
+}
+
+}  // namespace
+
+extern "C" {
+
+mf_status mf_server_submit(mf_server* s, int64_t n, int dtype, uint64_t seed, void* host_out, int64_t* id) {
+  clear_error();
+  if (!s || n < 1 || n > (1 << 16)) return fail(MF_ERR_ARG, "invalid argument");
+  if (!serving_dtype(dtype)) return fail(MF_ERR_ARG, "serving takes MF_F64 or MF_F32 (native leaves)");
+  Req r{};
+  r.n = n;
+  r.dtype = dtype;
+  r.seed = seed;
+  r.host_out = host_out;
+  return enqueue(s, r, id);
+}
+
+mf_status mf_server_submit_operands(mf_server* s, int64_t n, int dtype, const void* A, const void* B, void* C,
+                                    int64_t* id) {
+  clear_error();
+  if (!s || n < 1 || n > (1 << 16)) return fail(MF_ERR_ARG, "invalid argument");
+  if (!serving_dtype(dtype)) return fail(MF_ERR_ARG, "serving takes MF_F64 or MF_F32 (native leaves)");
+  if (!A || !B || !C) return fail(MF_ERR_ARG, "A, B and C must be non-NULL");
+  const size_t elem = (dtype & 0xff) == MF_F64 ? 8 : 4;
+  if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(C)) &
+      (elem - 1))
+    return fail(MF_ERR_ARG, "A, B and C must be aligned to the element size");
+  const size_t bytes = (size_t)n * (size_t)n * elem;
+  if (overlaps(C, bytes, A, bytes) || overlaps(C, bytes, B, bytes)) return fail(MF_ERR_ARG, "C overlaps A or B");
+  Req r{};
+  r.n = n;
+  r.dtype = dtype;
+  r.host_out = nullptr;
+  r.A_user = A;
+  r.B_user = B;
+  r.C_user = C;
+  return enqueue(s, r, id);
 }
 
 mf_status mf_server_replay(mf_server* s, int count, const double* t_arrive, const int64_t* n, const int* dtype,
@@ -419,6 +479,7 @@ void mf_server_free(mf_server* s) {
   for (auto& st : s->streams) (void)hipStreamSynchronize(st);
   for (auto& e : s->events) (void)hipEventDestroy(e);
   for (auto& e : s->start_events) (void)hipEventDestroy(e);
+  if (s->origin) (void)hipEventDestroy(s->origin);
   for (auto& st : s->streams) (void)hipStreamDestroy(st);
   if (s->arena) (void)hipFree(s->arena);
   delete s;
@@ -429,6 +490,17 @@ mf_status mf_server_device_ms(mf_server* s, double* ms) {
   if (!s || !ms) return fail(MF_ERR_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(s->mu);
   for (size_t k = 0; k < s->reqs.size(); ++k) ms[k] = s->reqs[k].device_ms;
+  return MF_OK;
+}
+
+mf_status mf_server_device_interval(mf_server* s, double* start_ms, double* end_ms) {
+  clear_error();
+  if (!s || !start_ms || !end_ms) return fail(MF_ERR_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (size_t k = 0; k < s->reqs.size(); ++k) {
+    start_ms[k] = s->reqs[k].device_start;
+    end_ms[k] = s->reqs[k].device_end;
+  }
   return MF_OK;
 }
 

@@ -44,7 +44,8 @@ EXPORTED = ["mf_algo_from_uvw", "mf_algo_builtin", "mf_algo_compose", "mf_algo_r
             "mf_fastmm_ws", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read", "mf_batch_create",
             "mf_batch_workspace_bytes", "mf_batch_run", "mf_batch_aborted", "mf_batch_tasks", "mf_batch_free",
             "mf_server_create", "mf_server_need_bytes", "mf_server_submit", "mf_server_replay", "mf_server_drain",
-            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform", "mf_autotune_batch", "mf_plan_query", "mf_batch_phases", "mf_server_device_ms"]
+            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform", "mf_autotune_batch", "mf_plan_query", "mf_batch_phases", "mf_server_device_ms",
+            "mf_server_submit_operands", "mf_server_device_interval"]
 
 
 class ServerConfig(ctypes.Structure):
@@ -104,6 +105,8 @@ def _load():
         "mf_server_stats": ([P, LP, DP, DP, DP, LP, ctypes.POINTER(I)], I),
         "mf_server_free": ([P], None),
         "mf_server_device_ms": ([P, DP], I),
+        "mf_server_device_interval": ([P, DP, DP], I),
+        "mf_server_submit_operands": ([P, I64, I, P, P, P, LP], I),
         "mf_admission_simulate": ([I, DP, DP, ctypes.POINTER(ctypes.c_size_t), I, ctypes.c_size_t, I, DP, DP,
                                    ctypes.POINTER(ctypes.c_size_t)], I),
         "mf_fill_uniform": ([P, I64, I, ctypes.c_uint64, P], I),
@@ -417,6 +420,16 @@ class Server:
         _check(lib.mf_server_submit(self._h, n, dtype_code, seed, ptr, ctypes.byref(rid)))
         return rid.value
 
+    def submit_operands(self, A, B, C):
+        """C = A B on caller-owned torch device tensors (kept alive until drained)."""
+        _check_operands(A, B, C)
+        rid = ctypes.c_int64()
+        _check(lib.mf_server_submit_operands(self._h, A.shape[0], _dtype_code(A, 0), ctypes.c_void_p(A.data_ptr()),
+                                             ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(C.data_ptr()),
+                                             ctypes.byref(rid)))
+        self._keep = getattr(self, "_keep", []) + [(A, B, C)]
+        return rid.value
+
     def replay(self, t_arrive, ns, dtype_codes, seeds):
         k = len(ns)
         t = np.ascontiguousarray(t_arrive, dtype=np.float64)
@@ -442,7 +455,10 @@ class Server:
                                    dp.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
         dev = np.zeros(c)
         _check(lib.mf_server_device_ms(self._h, _dptr(dev)))
-        return {"t_arrive": ta, "t_admit": tm, "t_done": td, "n": nn, "depth": dp, "device_ms": dev}
+        d0, d1 = np.zeros(c), np.zeros(c)
+        _check(lib.mf_server_device_interval(self._h, _dptr(d0), _dptr(d1)))
+        return {"t_arrive": ta, "t_admit": tm, "t_done": td, "n": nn, "depth": dp, "device_ms": dev,
+                "device_start_ms": d0, "device_end_ms": d1}
 
 
 def mf_admission_simulate(t_arrive, service, need, slots, budget, allow_overtake=False):

@@ -70,13 +70,25 @@ def test_classical_fp64_close(n):
 
 # ------------------------------------------------------- fast, bit-exact ints
 
+def levels_taken(algo, depth, n):
+    return mf.mf_plan_query(algo, depth, 0, n)["levels"]
+
+
+# levels the planner takes: a level needs the current size above the 128 leaf
+# tile, so n = 256 takes one level at any depth, n = 300 two (300 -> 150 -> 75)
+# and n >= 1024 all three
+EXPECTED_LEVELS = {256: 1, 300: 2, 1024: 3, 1025: 3, 1500: 3}
+
+
 @pytest.mark.parametrize("name", ["strassen", "winograd", "strassen1969"])
 @pytest.mark.parametrize("depth", [1, 2, 3])
-@pytest.mark.parametrize("n", [256, 300, 1024])
+@pytest.mark.parametrize("n", [256, 300, 1024, 1025, 1500])
 def test_fast_int_exact(name, depth, n):
     A = mi.int_uniform(n, 3)
     B = mi.int_uniform(n, 4)
-    got = run_fast(mf.mf_algo_builtin(name), depth, 0, A.astype(np.float64), B.astype(np.float64))
+    algo = mf.mf_algo_builtin(name)
+    assert levels_taken(algo, depth, n) == min(depth, EXPECTED_LEVELS[n])
+    got = run_fast(algo, depth, 0, A.astype(np.float64), B.astype(np.float64))
     want = om.classical_mm(A, B)
     # the oracle's own fast executor reaches the same integers
     if n <= 300:
@@ -138,12 +150,28 @@ def test_composed_444_49_matches_depth2():
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 129, 255])
-def test_fast_tiny_and_ragged_exact(n):
+def test_tiny_sizes_take_at_most_one_level_and_stay_exact(n):
+    """Requests for depth 1-3 at sizes up to 255: n <= 128 runs the classical
+    GEMM (no level is taken), 129 and 255 one level; all exact."""
     A = mi.int_uniform(n, 13)
     B = mi.int_uniform(n, 14)
+    algo = mf.mf_algo_builtin("strassen")
     for depth in (1, 2, 3):
-        got = run_fast(mf.mf_algo_builtin("strassen"), depth, 0, A.astype(np.float64), B.astype(np.float64))
+        assert levels_taken(algo, depth, n) == (0 if n <= 128 else 1)
+        got = run_fast(algo, depth, 0, A.astype(np.float64), B.astype(np.float64))
         assert np.array_equal(got, (A @ B).astype(np.float64)), (n, depth)
+
+
+@pytest.mark.parametrize("n", [1025, 1500, 2047])
+def test_three_levels_on_ragged_sizes_exact(n):
+    """Depth 3 really taken (three levels of virtual padding) at ragged n."""
+    A = mi.int_uniform(n, 15)
+    B = mi.int_uniform(n, 16)
+    for name in ("strassen", "winograd"):
+        algo = mf.mf_algo_builtin(name)
+        assert levels_taken(algo, 3, n) == 3
+        got = run_fast(algo, 3, 0, A.astype(np.float64), B.astype(np.float64))
+        assert np.array_equal(got, (A @ B).astype(np.float64)), (name, n)
 
 
 def test_cutoff_selects_levels():

@@ -194,23 +194,53 @@ mf_status build_classical(int64_t n, Plan* pl) {
   return MF_OK;
 }
 
+// The algorithm of every recursion level, outermost first.  An algorithm
+// runs as one level of its own when linear-combination kernels exist for its
+// shape (p^2 inputs per pre-addition set, R per post-addition set) or when it
+// is a three-factor composition of <2,2,2;7> algorithms (factor-by-factor
+// kernels).  A Kronecker composition without such kernels (for example a 2 x 3
+// split, <6,6,6;189>) runs as its factors, one level each, outer factor first:
+// the same algorithm (the composed coefficients are the factors' products),
+// evaluated level by level.  One level of the algorithm is taken while levels
+// remain, the current size exceeds the cutoff and the leaf tile, and the leaf
+// count stays within the limit; a level taken is taken whole (all of its
+// factors).  Returns false if some level has no kernel.
+bool level_sequence(const Algo& a, int depth, int cutoff, int64_t n, std::vector<const Algo*>* seq) {
+  seq->clear();
+  std::vector<const Algo*> unit;
+  const bool direct = is_kron3(a) || (combine_supported(a.p * a.p) && combine_supported(a.R));
+  if (direct || a.factors.empty()) {
+    unit.push_back(&a);
+  } else {
+    for (const Algo& f : a.factors) unit.push_back(&f);
+  }
+  for (const Algo* f : unit)
+    if (f != &a || !is_kron3(a))
+      if (!combine_supported(f->p * f->p) || !combine_supported(f->R)) return false;
+  const int L = levels_for(n, a.p, a.R, depth, cutoff);
+  for (int d = 0; d < L; ++d) seq->insert(seq->end(), unit.begin(), unit.end());
+  return true;
+}
+
 mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg, Plan* pl) {
   pl->n = n;
   pl->dtype = dtype;
   pl->elem = (dtype & 0xff) == MF_F64 ? 8 : 4;
-  const int L = algo ? levels_for(n, algo->p, algo->R, depth, cutoff) : 0;
+  std::vector<const Algo*> seq;
+  if (algo && !level_sequence(*algo, depth, cutoff, n, &seq))
+    return fail(MF_ERR_UNSUPPORTED, "no linear-combination kernel for this algorithm shape");
+  const int L = (int)seq.size();
   pl->levels = L;
   if (L == 0) return build_classical(n, pl);
 
-  const int p = algo->p, p2 = p * p, R = algo->R;
-  const bool kron3 = is_kron3(*algo);
-  if (!kron3 && (!combine_supported(p2) || !combine_supported(R)))
-    return fail(MF_ERR_UNSUPPORTED, "no linear-combination kernel for this algorithm shape");
-  const int64_t P = ipow(p, L);
+  const bool kron3 = is_kron3(*seq[0]);
+  int64_t P = 1;
+  for (const Algo* f : seq) P *= f->p;
   pl->P = (int)P;
   if (bf16_leaves(dtype)) {
-    if (!stage_supported(p2)) return fail(MF_ERR_UNSUPPORTED, "no BF16 staging kernel for this algorithm shape");
-    pl->bf_nin = p2;
+    const int p2_last = seq.back()->p * seq.back()->p;
+    if (!stage_supported(p2_last)) return fail(MF_ERR_UNSUPPORTED, "no BF16 staging kernel for this algorithm shape");
+    pl->bf_nin = p2_last;
   }
   pl->m = round_up((n + P - 1) / P, kLeafTile);
   pl->npad = pl->m * P;
@@ -218,16 +248,25 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
   const int64_t positions = (m / kLeafTile) * (m / kLeafTile);
 
   // Outer levels split off as groups (with post-addition stages) until the
-  // grouped GEMM has enough workgroups.
+  // grouped GEMM has enough workgroups; the inner levels run as one composed
+  // algorithm in the GEMM epilogue.
   int Lo = 0;
-  while (Lo < L && positions * ipow(R, Lo) < min_wg) ++Lo;
+  int64_t outer_products = 1;
+  while (Lo < L && positions * outer_products < min_wg) outer_products *= seq[(size_t)Lo++]->R;
   const int Li = L - Lo;
   pl->levels_outer = Lo;
-  const Algo Fi = Li > 0 ? power(*algo, Li) : Algo{};
+  Algo Fi;
+  if (Li > 0) {
+    Fi = *seq[(size_t)L - 1];
+    for (int l = L - 2; l >= Lo; --l) Fi = compose(*seq[(size_t)l], Fi);
+  }
   const int Pi = Li > 0 ? Fi.p : 1, Ri = Li > 0 ? Fi.R : 1;
-  pl->P_outer = (int)ipow(p, Lo);
-  pl->R = (int)ipow(R, L);
-  pl->groups = (int)ipow(R, Lo);
+  int64_t P_outer = 1, R_all = 1;
+  for (int l = 0; l < Lo; ++l) P_outer *= seq[(size_t)l]->p;
+  for (const Algo* f : seq) R_all *= f->R;
+  pl->P_outer = (int)P_outer;
+  pl->R = (int)R_all;
+  pl->groups = (int)outer_products;
   pl->m_outer = (int64_t)Pi * m;
   int64_t ws = 0;  // workspace elements allocated so far
   auto alloc = [&](int64_t elems) {
@@ -254,6 +293,8 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
     }
     int64_t size = pl->npad;
     for (int lev = 1; lev <= L; ++lev) {
+      const Algo& al = *seq[(size_t)lev - 1];
+      const int p = al.p, p2 = p * p, R = al.R;
       const int64_t sz = size / p;
       CombineStage st;
       st.nin = p2;
@@ -261,7 +302,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
       st.kron3 = kron3 ? 1 : 0;
       std::vector<Blk> next[2];
       for (int side = 0; side < 2; ++side) {
-        const std::vector<double>& X = side == 0 ? algo->U : algo->V;
+        const std::vector<double>& X = side == 0 ? al.U : al.V;
         for (const Blk& b : cur[side]) {
           std::vector<Blk> q(p2);
           for (int k = 0; k < p2; ++k) q[k] = quarter(b, k, p, sz);
@@ -303,7 +344,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
           // kron3: every product has an output entry (empty unless stored) and
           // the set's coefficients are the factor matrices
           const int32_t kcoef = (int32_t)st.coef.size();
-          if (kron3) kron3_coef(*algo, side == 0 ? 'u' : 'v', b.scale, &st.coef);
+          if (kron3) kron3_coef(al, side == 0 ? 'u' : 'v', b.scale, &st.coef);
           bool stored = false;
           for (int r = 0; r < R; ++r) {
             int nnz = 0, last = -1;
@@ -478,7 +519,10 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
     }
     int64_t csz = mo;  // size of a child result
     for (int lev = Lo; lev >= 1; --lev) {
-      const int nparent = (int)ipow(R, lev - 1);
+      const Algo& al = *seq[(size_t)lev - 1];
+      const int p = al.p, p2 = p * p, R = al.R;
+      int nparent = 1;
+      for (int l = 0; l < lev - 1; ++l) nparent *= seq[(size_t)l]->R;
       const int64_t psz = csz * p;
       CombineStage st;
       st.nin = R;
@@ -511,7 +555,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
           // the factor matrices, then the element offset in the workspace of
           // each product (-1: an empty group, read as zero); every product is
           // a csz x csz block
-          kron3_coef(*algo, 'w', 1.0, &st.coef);
+          kron3_coef(al, 'w', 1.0, &st.coef);
           for (int r = 0; r < R; ++r) {
             const Blk& cb = child[(size_t)q * R + r];
             if (!cb.zero && (cb.src != SRC_WS || cb.ld != csz || cb.vr != csz || cb.vc != csz))
@@ -539,7 +583,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
             co.coef_off = kcoef;
           } else {
             co.coef_off = (int32_t)st.coef.size();
-            for (int r = 0; r < R; ++r) st.coef.push_back(algo->w(c, r));
+            for (int r = 0; r < R; ++r) st.coef.push_back(al.w(c, r));
           }
           st.outs.push_back(co);
         }

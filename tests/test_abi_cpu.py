@@ -414,3 +414,45 @@ def test_composition_is_associative():
     U, V, W = left.uvw()[:3]
     again = mf.mf_algo_from_uvw(8, np.asarray(U), np.asarray(V), np.asarray(W))
     assert again.info()["R"] == 343
+
+
+# ------------------------------------------------- split factors 2 and 3
+# <6,6,6;189>: the paper's Strassen composed with the classical <3,3,3;27>
+# in either order (Section 2: factor 6 = 2 x 3 or 3 x 2, and the order changes
+# the temporary space and the error).  No kernel combines 36 blocks into 189
+# products and back, so the planner runs the composition as its two factors,
+# one level each, outer factor first.
+
+def test_mixed_factor_composition_brent_and_shape():
+    s = mf.mf_algo_builtin("strassen")
+    c3 = mf.mf_algo_builtin("classical3")
+    for outer, inner in ((s, c3), (c3, s)):
+        a = mf.mf_algo_compose(outer, inner)
+        assert a.info()["n0"] == 6 and a.info()["R"] == 189
+        q = mf.mf_plan_query(a, 1, 0, 2048)
+        assert q["levels"] == 2 and q["products"] == 189
+        # leaf: ceil(2048 / 6) = 342 rounded up to the 128 tile
+        assert q["leaf_m"] == 384
+
+
+def test_mixed_factor_workspace_by_order():
+    """Workspace of the two orders at n = 2048 (m = 384, n' = 6 m), in m^2
+    elements: Strassen first materialises 4 + 4 blocks of (3m)^2 at level 1
+    (the classical level aliases every block), stores 189 products and 7
+    level-1 parents of (3m)^2: 72 + 189 + 63 = 324.  Classical first aliases
+    level 1 and materialises 27 x (4 + 4) blocks of m^2 at level 2, stores 189
+    products and 27 parents of (2m)^2: 216 + 189 + 108 = 513."""
+    s = mf.mf_algo_builtin("strassen")
+    c3 = mf.mf_algo_builtin("classical3")
+    m = 384
+    assert mf.mf_workspace_bytes(mf.mf_algo_compose(s, c3), 1, 0, 2048) == 8 * 324 * m * m
+    assert mf.mf_workspace_bytes(mf.mf_algo_compose(c3, s), 1, 0, 2048) == 8 * 513 * m * m
+
+
+def test_mixed_factor_matches_oracle_composition():
+    s = mf.mf_algo_builtin("strassen")
+    c3 = mf.mf_algo_builtin("classical3")
+    o_s = oracle_table(mi.STRASSEN_PAPER)
+    o_c3 = oa.classical_algo(3)
+    for (outer, inner), (o_out, o_in) in (((s, c3), (o_s, o_c3)), ((c3, s), (o_c3, o_s))):
+        assert same(mf.mf_algo_compose(outer, inner), oa.compose(o_out, o_in))

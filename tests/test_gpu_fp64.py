@@ -382,3 +382,42 @@ def test_kron3_fp32_storage(n):
     torch.cuda.synchronize()
     ref = om.classical_mm(A.astype(np.float64), B.astype(np.float64))
     assert om.rel_fro_error(dC.cpu().numpy().astype(np.float64), ref) < 2e-5
+
+
+# ------------------------------------------- split factors 2 and 3 (<6,6,6;189>)
+
+@pytest.mark.parametrize("order", ["strassen_then_classical3", "classical3_then_strassen"])
+@pytest.mark.parametrize("n", [300, 1000, 2048])
+def test_mixed_split_factors_int_exact(order, n):
+    """The paper's Strassen composed with the classical <3,3,3;27> in either
+    order (split factor 6 = 2 x 3 or 3 x 2), run as two levels: exact on
+    integers; at n = 300 also equal to the oracle's composed algorithm."""
+    s = mf.mf_algo_builtin("strassen")
+    c3 = mf.mf_algo_builtin("classical3")
+    algo = mf.mf_algo_compose(s, c3) if order.startswith("strassen") else mf.mf_algo_compose(c3, s)
+    assert mf.mf_plan_query(algo, 1, 0, n)["levels"] == 2
+    A = mi.int_uniform(n, 17)
+    B = mi.int_uniform(n, 18)
+    want = om.classical_mm(A, B)
+    if n == 300:
+        o_s, o_c3 = oracle_algo("strassen"), oa.classical_algo(3)
+        o_alg = oa.compose(o_s, o_c3) if order.startswith("strassen") else oa.compose(o_c3, o_s)
+        assert np.array_equal(om.fast_mm(A, B, o_alg, 1), want)
+    got = run_fast(algo, 1, 0, A.astype(np.float64), B.astype(np.float64))
+    assert np.array_equal(got, want.astype(np.float64))
+
+
+def test_mixed_split_factors_fp64_error_by_order():
+    """Both orders within the FP64 bound at n = 2048; their errors differ
+    (different summation order), as the paper notes for 2 x 3 against 3 x 2."""
+    s = mf.mf_algo_builtin("strassen")
+    c3 = mf.mf_algo_builtin("classical3")
+    A = mi.uniform(2048, 10)
+    B = mi.uniform(2048, 11)
+    ref = om.classical_mm(A, B)
+    errs = {}
+    for name, algo in (("2x3", mf.mf_algo_compose(s, c3)), ("3x2", mf.mf_algo_compose(c3, s))):
+        errs[name] = om.rel_fro_error(run_fast(algo, 1, 0, A, B), ref)
+        assert errs[name] < FP64_TOL
+    print(f"<6,6,6;189> n=2048 rel err: 2x3 {errs['2x3']:.3e}, 3x2 {errs['3x2']:.3e}", flush=True)
+    assert errs["2x3"] != errs["3x2"]

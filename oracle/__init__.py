@@ -12,7 +12,10 @@ planted mistakes).  That includes ``rows_reference``, the sampled-row form of
 the definition that checks every full-size product: it is pinned row by row
 against a brute-force triple loop, exact sums, closed forms (identity,
 permutation, rank one) and planted mistakes (a transposed operand, shifted
-rows).  No function is parity-unpinned.
+rows).  The exact integer product (float64 BLAS below the 2^53 bound, the
+integer loop above it) is pinned against the integer loop, Python's big
+integers and a planted case where the float path would round.  No function
+is parity-unpinned.
 """
 from .algebra import (Algo, brent_violations, canonical, classical_algo, compose, power,  # noqa: F401
                       rebase, single_coefficient_columns, transpose_index)

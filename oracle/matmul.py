@@ -4,8 +4,11 @@ TEST INFRASTRUCTURE ONLY.  Nothing on the product path imports this module;
 only the tests, the smoke check and the CPU-baseline leg of the benchmark do.
 
 * ``classical_mm``  the plain definition C_ij = sum_k A_ik B_kj (Section 2),
-  computed by numpy's matmul (OpenBLAS for float64, numpy's exact integer
-  loop for int64).
+  computed by numpy's matmul: OpenBLAS for float64; for integer operands
+  exactly, by OpenBLAS on the values as float64 when K max|A| max|B| < 2^53
+  (then every product and partial sum is an integer below 2^53, which float64
+  holds exactly, so no sum rounds in any order) and by numpy's integer loop
+  otherwise.
 * ``fast_mm``       the recursive fast algorithm of equation "strassen"
   (Section 2): form T_r and S_r from the coefficient columns, multiply
   recursively, and distribute P_r into the C blocks, product by product in
@@ -28,10 +31,27 @@ import numpy as np
 from .algebra import Algo
 
 
+def _int_bound(X: np.ndarray) -> int:
+    """max |x| over an integer array, as a Python int (0 if empty)."""
+    return max(abs(int(X.max())), abs(int(X.min()))) if X.size else 0
+
+
+def exact_in_float64(A: np.ndarray, B: np.ndarray) -> bool:
+    """Integer operands whose products and partial sums of A B all stay below
+    2^53 in magnitude (K max|A| max|B| < 2^53)."""
+    if not (np.issubdtype(A.dtype, np.integer) and np.issubdtype(B.dtype, np.integer)):
+        return False
+    return A.shape[1] * _int_bound(A) * _int_bound(B) < 2 ** 53
+
+
 def classical_mm(A: np.ndarray, B: np.ndarray) -> np.ndarray:
-    """C = A B by definition (library matmul in the element type given)."""
+    """C = A B by definition (library matmul in the element type given;
+    integer operands exactly, see the module docstring)."""
     if A.ndim != 2 or B.ndim != 2 or A.shape[1] != B.shape[0]:
         raise ValueError("shape mismatch")
+    if exact_in_float64(A, B):
+        C = np.matmul(A.astype(np.float64), B.astype(np.float64))
+        return C.astype(np.result_type(A.dtype, B.dtype))
     return np.matmul(A, B)
 
 
@@ -133,7 +153,12 @@ def componentwise_error(C_hat, C_ref, A, B) -> float:
 
 
 def rows_reference(A: np.ndarray, B: np.ndarray, rows) -> np.ndarray:
-    """Exact-definition rows C[i, :] = A[i, :] B for sampled i (float64)."""
+    """Exact-definition rows C[i, :] = A[i, :] B for sampled i, returned as
+    float64 (integer operands: the exact integer rows of classical_mm)."""
+    A = np.asarray(A)
+    B = np.asarray(B)
+    if np.issubdtype(A.dtype, np.integer) and np.issubdtype(B.dtype, np.integer):
+        return classical_mm(A[rows], B).astype(np.float64)
     return np.matmul(np.asarray(A, np.float64)[rows], np.asarray(B, np.float64))
 
 

@@ -53,6 +53,11 @@ def run_batch(sizes, algos, depths, code, tdt, seed0):
     return b, dA, dB, dC
 
 
+def assert_exact(C_dev, A, B, i):
+    """C equals the integer product A B, entry for entry."""
+    assert np.array_equal(C_dev.cpu().numpy(), om.classical_mm(A, B).astype(np.float64)), f"instance {i}"
+
+
 def host_operands(n, i, seed0, npdt):
     A = mi.counter_uniform(n * n, 2 * (seed0 + i), npdt).astype(np.float64).reshape(n, n)
     B = mi.counter_uniform(n * n, 2 * (seed0 + i) + 1, npdt).astype(np.float64).reshape(n, n)
@@ -96,7 +101,7 @@ def test_config4_fp64_integer_exact():
     mf.mf_batch_run(b, dA, dB, dC)
     torch.cuda.synchronize()
     for i, (A, B) in enumerate(zip(As, Bs)):
-        assert np.array_equal(dC[i].cpu().numpy(), om.classical_mm(A, B).astype(np.float64)), f"instance {i}"
+        assert_exact(dC[i], A, B, i)
 
 
 def test_tuner_with_strassen_and_444_candidates_drives_exact_batch():
@@ -125,7 +130,7 @@ def test_tuner_with_strassen_and_444_candidates_drives_exact_batch():
     mf.mf_batch_run(b, dA, dB, dC)
     torch.cuda.synchronize()
     for i, (A, B) in enumerate(zip(As, Bs)):
-        assert np.array_equal(dC[i].cpu().numpy(), om.classical_mm(A, B).astype(np.float64)), f"instance {i}"
+        assert_exact(dC[i], A, B, i)
 
 
 def test_batch_runs_on_two_streams_in_a_row():

@@ -76,6 +76,45 @@ def test_classical_closed_forms():
     assert np.array_equal(got, int(v @ x) * np.outer(u, y))
 
 
+def test_classical_int_exact_path_matches_integer_loop():
+    """Integer operands within the 2^53 bound go through float64 BLAS; the
+    result equals numpy's integer loop (a separate implementation of the
+    definition) on ragged rectangular shapes and at a moderate size."""
+    g = np.random.default_rng(11)
+    for m, k, n in ((1, 1, 1), (3, 5, 2), (17, 64, 33), (200, 301, 150)):
+        A = g.integers(-8, 9, size=(m, k))
+        B = g.integers(-8, 9, size=(k, n))
+        assert om.exact_in_float64(A, B)
+        got = om.classical_mm(A, B)
+        assert got.dtype == np.int64
+        assert np.array_equal(got, np.matmul(A, B))
+
+
+def test_classical_int_beyond_the_float64_bound_stays_exact():
+    """Entries 2^27 + 1: one product (2^54 + 2^28 + 1) already has no float64
+    representation, so the float path would round; the oracle must take the
+    integer loop and match Python's big integers."""
+    v = 2 ** 27 + 1
+    A = np.array([[v, v], [v, -v]], dtype=np.int64)
+    B = np.array([[v, 1], [v, v]], dtype=np.int64)
+    assert not om.exact_in_float64(A, B)
+    want = brute_force_mm(A.tolist(), B.tolist())
+    assert om.classical_mm(A, B).tolist() == want
+    # planted mistake: the float path on the same operands is wrong
+    wrong = np.matmul(A.astype(np.float64), B.astype(np.float64)).astype(np.int64)
+    assert wrong.tolist() != want
+    # rows_reference takes the same exact path
+    assert om.rows_reference(A, B, [1]).tolist() == [[float(x) for x in want[1]]]
+
+
+def test_exact_in_float64_bound_is_tight():
+    # K max|A| max|B| = 2^53 - 2^26 passes, 2^53 does not
+    A = np.full((1, 1), 2 ** 26, dtype=np.int64)
+    assert om.exact_in_float64(A, np.full((1, 1), 2 ** 27 - 1, dtype=np.int64))
+    assert not om.exact_in_float64(A, np.full((1, 1), 2 ** 27, dtype=np.int64))
+    assert not om.exact_in_float64(np.ones((1, 1)), np.ones((1, 1)))  # floats never take the integer path
+
+
 # -------------------------------------------------------- worked example
 
 def _parse_terms(s):

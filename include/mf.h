@@ -174,6 +174,24 @@ mf_status mf_plan_query(const mf_algo* algo, int depth, int cutoff, int64_t n, i
 mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C,
                        int64_t n, int dtype, void* workspace, size_t ws_bytes, mf_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * mf_fastmm, but the plan's descriptors and its workspace live in one fixed
+ * device array of MF_NOALLOC_SCRATCH_BYTES bytes per GPU, which the library
+ * holds from the first call on that GPU until the process ends; the call
+ * itself allocates no device memory (the descriptors are copied into the
+ * array on `stream`).  A request whose descriptors (rounded up to 256 bytes)
+ * plus mf_workspace_bytes exceed the array is rejected with MF_ERR_SHAPE
+ * before anything is enqueued (FP64, Strassen depth 1: up to n of about
+ * 2900).  Every call on one GPU uses the same array, and nothing in it is
+ * assumed to be zero: calls on one stream are ordered, but calls that
+ * overlap on one GPU (other streams, other host threads) race on it and give
+ * wrong results.  The result is bitwise that of mf_fastmm with the same
+ * arguments.  No phase timing is recorded. */
+#define MF_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+mf_status mf_fastmm_noalloc(const mf_algo* algo, int depth, int cutoff, const void* A, const void* B, void* C,
+                            int64_t n, int dtype, mf_stream stream);
+
 /* ---- Batched execution ----------------------------------------------------
  * Many independent products C_i = A_i B_i (i < count) of sizes n[i], each
  * with its own algorithm (algos[i], NULL when depth[i] == 0), depth and

@@ -96,7 +96,8 @@ PhaseTiming& timing() {
 
 // Enqueues the phases of one product on stream s.  desc: device address of a
 // copy of the plan's descriptor image; ws: the plan's workspace.
-mf_status run_at(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws, hipStream_t s) {
+mf_status run_at(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws, hipStream_t s,
+                 bool may_time) {
   // Rows start on 16-byte boundaries when the bases do and a row is a whole
   // number of 16-byte units.
   const bool rows16 = (pl.n * (int64_t)pl.elem) % 16 == 0;
@@ -118,7 +119,7 @@ mf_status run_at(const Plan& pl, const char* desc, const void* A, const void* B,
   bool timed = false;
   {
     std::lock_guard<std::mutex> lk(timing().mu);
-    timed = timing().enabled;
+    timed = timing().enabled && may_time;
   }
   if (timed) {
     for (auto& x : ev)

@@ -347,8 +347,10 @@ mf_status check_request(const mf_algo* algo, bool need_algo, int depth, int cuto
 mf_status plan_for(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
                    std::shared_ptr<const Plan>* pl);
 // Enqueues the phases of one product on stream s.  desc: device address of
-// a copy of the plan's descriptor image; ws: the plan's workspace.
-mf_status run_at(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws, hipStream_t s);
+// a copy of the plan's descriptor image; ws: the plan's workspace.  may_time:
+// whether the call may record phase-timing events (creating them).
+mf_status run_at(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws, hipStream_t s,
+                 bool may_time = true);
 // Byte ranges [x, x + xb) and [y, y + yb) intersect.
 bool overlaps(const void* x, size_t xb, const void* y, size_t yb);
 constexpr int kMaxDevices = 64;

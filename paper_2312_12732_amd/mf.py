@@ -41,10 +41,11 @@ MF_W_DEEPMIND_CT = 1
 
 EXPORTED = ["mf_algo_from_uvw", "mf_algo_builtin", "mf_algo_compose", "mf_algo_rebase", "mf_algo_info",
             "mf_algo_get_uvw", "mf_algo_free", "mf_fastmm", "mf_classical_mm", "mf_workspace_bytes",
-            "mf_fastmm_ws", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read", "mf_batch_create",
-            "mf_batch_workspace_bytes", "mf_batch_run", "mf_batch_aborted", "mf_batch_tasks", "mf_batch_free",
-            "mf_server_create", "mf_server_need_bytes", "mf_server_submit", "mf_server_replay", "mf_server_drain",
-            "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform", "mf_autotune_batch", "mf_plan_query", "mf_batch_phases", "mf_server_device_ms",
+            "mf_fastmm_ws", "mf_fastmm_noalloc", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read",
+            "mf_batch_create", "mf_batch_workspace_bytes", "mf_batch_run", "mf_batch_aborted", "mf_batch_tasks",
+            "mf_batch_free", "mf_server_create", "mf_server_need_bytes", "mf_server_submit", "mf_server_replay",
+            "mf_server_drain", "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform",
+            "mf_autotune_batch", "mf_plan_query", "mf_batch_phases", "mf_server_device_ms",
             "mf_server_submit_operands", "mf_server_device_interval"]
 
 
@@ -88,6 +89,7 @@ def _load():
         "mf_classical_mm": ([P, P, P, I64, I, P], I),
         "mf_workspace_bytes": ([P, I, I, I64, I, ctypes.POINTER(ctypes.c_size_t)], I),
         "mf_fastmm_ws": ([P, I, I, P, P, P, I64, I, P, ctypes.c_size_t, P], I),
+        "mf_fastmm_noalloc": ([P, I, I, P, P, P, I64, I, P], I),
         "mf_last_error": ([], ctypes.c_char_p),
         "mf_phase_timing": ([I], I),
         "mf_batch_create": ([I, LP, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(I), I, AP], I),
@@ -240,6 +242,16 @@ def mf_fastmm_ws(algo: Algo, depth: int, cutoff: int, A, B, C, workspace, leaf: 
     _check(lib.mf_fastmm_ws(algo.handle, depth, cutoff, ctypes.c_void_p(A.data_ptr()),
                             ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(C.data_ptr()), A.shape[0],
                             _dtype_code(A, leaf), ctypes.c_void_p(workspace.data_ptr()), nbytes, _stream(stream)))
+    return C
+
+
+def mf_fastmm_noalloc(algo: Algo, depth: int, cutoff: int, A, B, C, leaf: int = MF_LEAF_NATIVE, stream=None):
+    """As mf_fastmm, with descriptors and workspace in the library's fixed
+    per-GPU scratch array (no device allocation in the call)."""
+    _check_operands(A, B, C)
+    _check(lib.mf_fastmm_noalloc(algo.handle, depth, cutoff, ctypes.c_void_p(A.data_ptr()),
+                                 ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(C.data_ptr()), A.shape[0],
+                                 _dtype_code(A, leaf), _stream(stream)))
     return C
 
 

@@ -152,6 +152,16 @@ def int_uniform(n: int, seed: int, lo: int = -8, hi: int = 8) -> np.ndarray:
     return rng(seed).integers(lo, hi + 1, size=(n, n), dtype=np.int64)
 
 
+def uniform_rect(rows: int, cols: int, seed: int, dtype=np.float64) -> np.ndarray:
+    """rows x cols matrix with entries i.i.d. uniform in [-1, 1]."""
+    return rng(seed).uniform(-1.0, 1.0, size=(rows, cols)).astype(dtype)
+
+
+def int_uniform_rect(rows: int, cols: int, seed: int, lo: int = -8, hi: int = 8) -> np.ndarray:
+    """rows x cols int64 matrix with entries i.i.d. uniform in {lo, ..., hi}."""
+    return rng(seed).integers(lo, hi + 1, size=(rows, cols), dtype=np.int64)
+
+
 def log_uniform_diag(n: int, seed: int, lo: float = 1e-4, hi: float = 1e4) -> np.ndarray:
     """Vector of n scale factors, log-uniform in [lo, hi]."""
     return np.exp(rng(seed).uniform(math.log(lo), math.log(hi), size=n))

@@ -297,6 +297,21 @@ def run_batched(args):
         errs = []
         for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
             errs.append(batch_instance_error(sizes[i], i, Cs[i], np.float64 if name == "f64" else np.float32))
+        # the same batch in one persistent launch; sizes whose tuned plan has
+        # combinations wider than the persistent kernel takes (<4,4,4;49>) run
+        # their best narrow candidate
+        pers_pick = narrow_picks(distinct, choices, tune_ms, cands[:2], 2)
+        pers = mf.mf_batch_create(sizes, [pers_pick[n][0] for n in sizes], [pers_pick[n][1] for n in sizes],
+                                  [0] * len(sizes), code, form=mf.MF_BATCH_PERSISTENT)
+        ms_pers = timed(lambda: mf.mf_batch_run(pers, As, Bs, Cs), args.steps, args.warmup)
+        assert not pers.aborted(), "persistent batch aborted"
+        pers_errs = [batch_instance_error(sizes[i], i, Cs[i], np.float64 if name == "f64" else np.float32)
+                     for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1]))]
+        pers_hist = {}
+        for n in sizes:
+            a, d = pers_pick[n]
+            key = "classical" if d == 0 else f"{cand_names[id(a)]} d{d}"
+            pers_hist[key] = pers_hist.get(key, 0) + 1
         ms_plain = timed(lambda: mf.mf_batch_run(plain, As, Bs, Cs), args.steps, args.warmup)
         assert not plain.aborted(), "classical batch aborted"
 
@@ -323,6 +338,10 @@ def run_batched(args):
             "speedup_vs_classical_batch": round(ms_plain / ms_tuned, 4),
             "speedup_vs_standalone_loop": round(ms_loop / ms_tuned, 4),
             "plans": hist,
+            "persistent_ms": round(ms_pers, 4),
+            "persistent_gflops": round(flops / (ms_pers * 1e-3) / 1e9, 1),
+            "persistent_plans": pers_hist,
+            "persistent_sampled_rel_err": [float(f"{e:.3e}") for e in pers_errs],
             "tuning_s": round(tune_s, 2),
             "tuning_crossovers": crossover_table(distinct, choices, tune_ms),
             "sampled_rel_err": [float(f"{e:.3e}") for e in errs],
@@ -354,6 +373,25 @@ def run_batched(args):
         out["cpu_baseline"] = batch_cpu_baseline(sizes, {n: (None if a is None else cand_names[id(a)], d)
                                                          for n, (a, d) in pick.items()})
     print(json.dumps(out), flush=True)
+
+
+def narrow_picks(distinct, choices, tune_ms, narrow, max_depth):
+    """size -> (algorithm, depth): the tuner's choice where it is one of the
+    `narrow` algorithms (or classical), else the fastest classical or narrow
+    candidate, a fast one only if it beats classical by 5 % (the tuner's rule)."""
+    out = {}
+    for n, (a, d), ms in zip(distinct, choices, tune_ms):
+        if d == 0 or any(a is x for x in narrow):
+            out[n] = (a, d)
+            continue
+        best, best_ms = (None, 0), ms[0]
+        for j, alg in enumerate(narrow):
+            for dd in range(1, max_depth + 1):
+                t = ms[1 + j * max_depth + dd - 1]
+                if 0 <= t < 0.95 * ms[0] and t < best_ms:
+                    best, best_ms = (alg, dd), t
+        out[n] = best
+    return out
 
 
 def crossover_table(distinct, choices, tune_ms):

@@ -48,7 +48,7 @@ struct BatchGuard {
   ~BatchGuard() { mf_batch_free(b); }
 };
 
-constexpr size_t kMaxTuneBytes = size_t(8) << 30;  // operands of one tuning batch
+constexpr size_t kMaxTuneBytes = size_t(8) << 30;  // operands, and workspace, of one tuning batch
 
 }  // namespace
 
@@ -109,13 +109,21 @@ mf_status mf_autotune_batch(int nsizes, const int64_t* n, int dtype, const mf_al
       if (c > 0) {
         al = algos[(c - 1) / max_depth];
         depth = 1 + (c - 1) % max_depth;
-        if (levels_for(ni, al->a.p, al->a.R, depth, 0) != depth) continue;  // repeats a shallower plan
+        if (levels_for(ni, ni, ni, al->a.m0, al->a.k0, al->a.n0, al->a.R, depth, 0) != depth) continue;  // repeats a shallower plan
       }
-      std::vector<const mf_algo*> av(copies, al);
-      std::vector<int> dv(copies, depth), cv(copies, 0);
-      std::vector<int64_t> nv(copies, ni);
+      // the copies this candidate runs: as many as its workspace allows
+      // within the tuning budget (the operands of the others stay unused)
+      size_t ws1 = 0;
+      if (al) {
+        const mf_status wst = mf_workspace_bytes(al, depth, 0, ni, dtype, &ws1);
+        if (wst != MF_OK) return wst;
+      }
+      const int cc = (int)std::max<size_t>(1, std::min<size_t>((size_t)copies, ws1 ? kMaxTuneBytes / ws1 : copies));
+      std::vector<const mf_algo*> av(cc, al);
+      std::vector<int> dv(cc, depth), cv(cc, 0);
+      std::vector<int64_t> nv(cc, ni);
       BatchGuard bg;
-      mf_status st = mf_batch_create(copies, nv.data(), av.data(), dv.data(), cv.data(), dtype, &bg.b);
+      mf_status st = mf_batch_create(cc, nv.data(), av.data(), dv.data(), cv.data(), dtype, &bg.b);
       if (st != MF_OK) return st;
       st = mf_batch_run(bg.b, pa.data(), pb.data(), pc.data(), nullptr, 0, stream);  // untimed: upload, pool
       if (st != MF_OK) return st;
@@ -132,7 +140,7 @@ mf_status mf_autotune_batch(int nsizes, const int64_t* n, int dtype, const mf_al
       if (aborted) return fail(MF_ERR_HIP, "a tuning batch aborted (wait limit exceeded)");
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev.e0, ev.e1) != hipSuccess) return fail(MF_ERR_HIP, "hipEventElapsedTime failed");
-      *slot = (double)ms / reps / copies;
+      *slot = (double)ms / reps / cc;
       if (best < 0 || *slot < best) {
         best = *slot;
         best_c = c;

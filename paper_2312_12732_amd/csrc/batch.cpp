@@ -13,6 +13,7 @@
 struct mf_batch {
   int count = 0;
   int dtype = MF_F64;
+  bool persistent = false;  // MF_BATCH_PERSISTENT: one launch; else one launch per phase
   size_t elem = 8;
   std::vector<int64_t> n;
   std::vector<std::shared_ptr<const mf::Plan>> plans;
@@ -58,12 +59,6 @@ struct mf_batch {
 namespace mf {
 namespace {
 
-// Execution form of a batch run.  true: the persistent kernel (one launch,
-// ticket and stage counters).  false: one launch per phase.  The persistent
-// form stays off until its restructured task loop has been validated on the
-// device; the phase form needs no cross-workgroup waits.
-constexpr bool kPersistentBatch = false;
-
 constexpr int64_t kChunk = 32768;  // elements per combination task
 
 mf_status build_batch(mf_batch* b, const std::vector<const mf_algo*>& algos, const int* depth, const int* cutoff) {
@@ -77,11 +72,12 @@ mf_status build_batch(mf_batch* b, const std::vector<const mf_algo*>& algos, con
     mf_status st = get_plan(depth[i] > 0 ? algos[i] : nullptr, depth[i], cutoff[i], b->n[i], b->dtype,
                             kStandaloneMinWorkgroups, &pl);
     if (st != MF_OK) return st;
+    if (!pl->square) return fail(MF_ERR_UNSUPPORTED, "batches take square algorithms");
     for (const CombineStage& cs : pl->pre)
-      if (cs.kron3 || !batch_stage_supported(cs.nin, cs.nout_max, kPersistentBatch))
+      if (cs.kron3 || !batch_stage_supported(cs.nin, cs.nout_max, b->persistent))
         return fail(MF_ERR_UNSUPPORTED, "algorithm shape not supported in batches");
     for (const CombineStage& cs : pl->post)
-      if (cs.kron3 || !batch_stage_supported(cs.nin, cs.nout_max, kPersistentBatch))
+      if (cs.kron3 || !batch_stage_supported(cs.nin, cs.nout_max, b->persistent))
         return fail(MF_ERR_UNSUPPORTED, "algorithm shape not supported in batches");
     b->plans.push_back(pl);
     if (!recs.count(pl.get())) {
@@ -265,9 +261,15 @@ extern "C" {
 
 mf_status mf_batch_create(int count, const int64_t* n, const mf_algo* const* algos, const int* depth,
                           const int* cutoff, int dtype, mf_batch** out) {
+  return mf_batch_create_form(count, n, algos, depth, cutoff, dtype, MF_BATCH_PHASES, out);
+}
+
+mf_status mf_batch_create_form(int count, const int64_t* n, const mf_algo* const* algos, const int* depth,
+                               const int* cutoff, int dtype, int form, mf_batch** out) {
   clear_error();
   if (!out) return fail(MF_ERR_ARG, "out is NULL");
   *out = nullptr;
+  if (form != MF_BATCH_PHASES && form != MF_BATCH_PERSISTENT) return fail(MF_ERR_ARG, "unknown batch form");
   if (count < 1 || !n || !depth || !cutoff) return fail(MF_ERR_ARG, "count must be >= 1 and arrays non-NULL");
   if (dtype != MF_F64 && dtype != MF_F32) return fail(MF_ERR_UNSUPPORTED, "batches support FP64 and FP32 (native leaves)");
   std::vector<const mf_algo*> al(count, nullptr);
@@ -281,6 +283,7 @@ mf_status mf_batch_create(int count, const int64_t* n, const mf_algo* const* alg
   if (!b) return fail(MF_ERR_NOMEM, "host allocation failed");
   b->count = count;
   b->dtype = dtype;
+  b->persistent = form == MF_BATCH_PERSISTENT;
   b->elem = dtype == MF_F64 ? 8 : 4;
   b->n.assign(n, n + count);
   const mf_status st = build_batch(b, al, depth, cutoff);
@@ -385,7 +388,7 @@ mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* cons
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->d_insts, b->h_insts, insts.size() * sizeof(BatchInst), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(b->copied, s);
-  if (kPersistentBatch) {
+  if (b->persistent) {
     if (e == hipSuccess) e = launch_fill_zero(b->d_ctr, b->nctr + 2, s);
     if (e == hipSuccess)
       e = launch_batch((int)b->elem, b->d_tasks, (int)b->tasks.size(), b->d_stages, b->d_gemms, b->d_insts,
@@ -407,7 +410,7 @@ mf_status mf_batch_aborted(const mf_batch* b, int* aborted) {
   if (!b || !aborted) return fail(MF_ERR_ARG, "NULL argument");
   int flag = 0;
   if (hipDeviceSynchronize() != hipSuccess) return fail(MF_ERR_HIP, "synchronisation failed");
-  if (!b->d_ctr || !kPersistentBatch) {  // the phase form has no waits to abort
+  if (!b->d_ctr || !b->persistent) {  // the phase form has no waits to abort
     *aborted = 0;
     return MF_OK;
   }

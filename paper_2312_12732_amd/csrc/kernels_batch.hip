@@ -65,6 +65,9 @@ __device__ __forceinline__ void run_combine(const BatchArgs& g, const BatchTask&
   a.m = st.m;
   a.vec_in = in.vec_in;
   a.vec_out = in.vec_out;
+  a.scale_c = 0;
+  a.alpha = T(1);
+  a.beta = T(0);
   const CombSet set = load_uniform(st.sets + tk.a);
   const bool full = set.full && in.vec_in && in.vec_out;
   auto chunk = [&](auto body, int vec) {
@@ -111,61 +114,82 @@ __device__ __forceinline__ void run_gemm(const BatchArgs& g, const BatchTask& tk
   a.epis = gr.epis;
   a.group_beg = gr.group_beg;
   a.groups = gr.groups;
-  a.m = gr.m;
+  a.m = a.n = a.k = gr.m;
   a.tiles_m = gr.tiles;
   a.tiles_n = gr.tiles;
   a.vec_in = in.vec_in;
+  a.scale_c = 0;
+  a.alpha = T(1);
+  a.beta = T(0);
   gemm_tile<T, Tile128>(a, tk.a, tk.b, tk.c, lds);
 }
 
-// Persistent form: one launch, workgroups take tasks from a global ticket and
-// wait on per-instance stage counters.  Thread 0 does all the atomics, in ONE
-// region per iteration placed before the barrier: it publishes the previous
-// task's completion, then takes the next ticket.  (With the completion add at
-// the end of the body and the ticket fetch at the top, the compiler merged the
-// two thread-0 regions across the back-edge into a nested loop in which the
-// other lanes re-ran the barrier and the same task while lane 0 stayed masked
-// off: the launch never finished.)
+// Wave 0 of a workgroup claims its next task: it publishes the completion of
+// the previous one (done counter prev_done, -1 for none), takes a ticket and
+// waits until the task's prerequisite counter is reached.  Returns the task
+// index, g.ntasks when the list is exhausted, or -1 after an abort.  All 64
+// lanes run this with identical control flow: every branch and loop condition
+// is a value broadcast with readfirstlane (all lanes poll the same address),
+// and the one lane that issues an atomic does it in a region with no loop and
+// no barrier, so the wave never splits around the polling loop.
+__device__ __forceinline__ int claim_task(const BatchArgs& g, int prev_done, int lane) {
+  int* ticket = g.ctr + g.nctr;
+  int* abort_flag = ticket + 1;
+  int t = 0;
+  if (lane == 0) {
+    if (prev_done >= 0) __hip_atomic_fetch_add(&g.ctr[prev_done], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    t = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  t = __builtin_amdgcn_readfirstlane(t);
+  if (t >= g.ntasks) return g.ntasks;
+  if (__builtin_amdgcn_readfirstlane(load_relaxed(abort_flag)) != 0) return -1;
+  const BatchTask tk = load_uniform(g.tasks + t);
+  if (tk.wait_ctr < 0) return t;
+  bool ok = true;
+  for (int spins = 0;; ++spins) {
+    if (__builtin_amdgcn_readfirstlane(load_relaxed(&g.ctr[tk.wait_ctr])) >= tk.wait_val) break;
+    if (__builtin_amdgcn_readfirstlane(load_relaxed(abort_flag)) != 0 || spins >= kSpinLimit) {
+      ok = false;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(32);
+  }
+  if (ok) return t;
+  if (lane == 0) __hip_atomic_exchange(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return -1;
+}
+
+// Persistent form: one launch; workgroups take tasks in ticket order and wait
+// on per-instance stage counters.  Only wave 0 touches the counters
+// (claim_task); it hands the task index to the other waves through LDS across
+// one barrier.  The task loop's condition is that broadcast index, so the
+// loop, like every barrier in it, is wave-uniform.  (An earlier form let
+// thread 0 alone publish and fetch in separate regions; the compiler turned
+// the loop into a nested one that lane 0 left to fetch a ticket while lanes
+// 1-63 of wave 0 kept re-running the barrier and the old task: the launch
+// never finished.)
 template <class T>
 __global__ void __launch_bounds__(Tile128::NTHREADS, Tile128::WAVES_PER_SIMD) batch_persistent(BatchArgs g) {
   __shared__ T lds[Tile128::LDS_ELEMS];
   __shared__ int s_task;
-  __shared__ int s_ok;
-  int* ticket = g.ctr + g.nctr;
-  int* abort_flag = ticket + 1;
-  int prev_done = -1;  // wave-uniform
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = (int)(threadIdx.x & 63);
+  int prev_done = -1;
   for (;;) {
-    if (threadIdx.x == 0) {
-      if (prev_done >= 0) __hip_atomic_fetch_add(&g.ctr[prev_done], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      int t = atomicAdd(ticket, 1);
-      if (load_relaxed(abort_flag) != 0) t = g.ntasks;
-      s_task = t;
+    if (wave == 0) {
+      const int t = claim_task(g, prev_done, lane);
+      if (lane == 0) s_task = t;
     }
     __syncthreads();
     const int t = __builtin_amdgcn_readfirstlane(s_task);
-    if (t >= g.ntasks) break;
+    if (t < 0 || t >= g.ntasks) break;
     const BatchTask tk = load_uniform(g.tasks + t);
-    if (tk.wait_ctr >= 0) {
-      if (threadIdx.x == 0) {
-        int ok = 1;
-        for (int spins = 0; load_relaxed(&g.ctr[tk.wait_ctr]) < tk.wait_val; ++spins) {
-          if (spins >= kSpinLimit || load_relaxed(abort_flag) != 0) {
-            ok = 0;
-            atomicExch(abort_flag, 1);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(32);
-        }
-        s_ok = ok;
-      }
-      __syncthreads();
-      if (__builtin_amdgcn_readfirstlane(s_ok) == 0) break;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
+    if (tk.wait_ctr >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (tk.type == 0)
       run_combine<T, false>(g, tk);
     else
       run_gemm<T>(g, tk, lds);
+    // every wave's results reach agent scope before wave 0 publishes them
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     prev_done = tk.done_ctr;

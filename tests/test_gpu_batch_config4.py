@@ -156,3 +156,34 @@ def test_batch_runs_on_two_streams_in_a_row():
     for As, Bs, _, _, dC in ops:
         for A, B, C in zip(As, Bs, dC):
             assert np.array_equal(C.cpu().numpy(), om.classical_mm(A, B).astype(np.float64))
+
+
+def test_config4_persistent_form_equals_phase_form():
+    """The same 64-instance batch in one persistent launch (plans cycling
+    through classical, Strassen d1 and Winograd d1/d2: the combinations the
+    persistent kernel takes) gives bitwise the phase form's results, and
+    integer inputs give the exact product."""
+    sizes = config4_sizes()
+    wino = mf.mf_algo_builtin("winograd")
+    stras = mf.mf_algo_builtin("strassen")
+    plans = [(None, 0), (stras, 1), (wino, 1), (wino, 2)]
+    algos = [plans[i % len(plans)][0] for i in range(len(sizes))]
+    depths = [plans[i % len(plans)][1] for i in range(len(sizes))]
+    cut = [0] * len(sizes)
+    for code, tdt in ((mf.MF_F64, torch.float64), (mf.MF_F32, torch.float32)):
+        print(f"config4 persistent, dtype code {code}", flush=True)
+        pers = mf.mf_batch_create(sizes, algos, depths, cut, code, form=mf.MF_BATCH_PERSISTENT)
+        phase = mf.mf_batch_create(sizes, algos, depths, cut, code)
+        As = [mi.int_uniform(n, 8000 + i) for i, n in enumerate(sizes)]
+        Bs = [mi.int_uniform(n, 8500 + i) for i, n in enumerate(sizes)]
+        dA = [torch.from_numpy(a.astype(np.float64)).to("cuda:0", tdt) for a in As]
+        dB = [torch.from_numpy(x.astype(np.float64)).to("cuda:0", tdt) for x in Bs]
+        got = [torch.full_like(a, float("nan")) for a in dA]
+        want = [torch.full_like(a, float("nan")) for a in dA]
+        mf.mf_batch_run(pers, dA, dB, got)
+        mf.mf_batch_run(phase, dA, dB, want)
+        torch.cuda.synchronize()
+        assert not pers.aborted()
+        for i, (A, B) in enumerate(zip(As, Bs)):
+            assert torch.equal(got[i], want[i]), f"instance {i}"
+            assert_exact(got[i].double(), A, B, i)

@@ -96,7 +96,8 @@ mf_status mf_algo_from_uvw(int n0, int R, const double* U, const double* V, cons
 mf_status mf_algo_builtin(const char* name, mf_algo** out);
 
 /* Compose: apply `outer` first and `inner` to each of its products
- * (Kronecker construction of Section 2); split factor n0_outer*n0_inner,
+ * (Kronecker construction of Section 2); split factors multiply dimension by
+ * dimension (n0_outer*n0_inner for square algorithms, each at most 8),
  * R_outer*R_inner products.  The result is Brent-checked. */
 mf_status mf_algo_compose(const mf_algo* outer, const mf_algo* inner, mf_algo** out);
 
@@ -107,15 +108,57 @@ mf_status mf_algo_compose(const mf_algo* outer, const mf_algo* inner, mf_algo** 
 mf_status mf_algo_rebase(const mf_algo* a, const int64_t* X, const int64_t* Y, const int64_t* Z,
                          mf_algo** out);
 
-/* Shape and sparsity of an algorithm (any output pointer may be NULL). */
+/* Shape and sparsity of an algorithm (any output pointer may be NULL); *n0
+ * is 0 for a rectangular algorithm (see mf_algo_shape). */
 mf_status mf_algo_info(const mf_algo* a, int* n0, int* R, int* nnz_u, int* nnz_v, int* nnz_w);
 
 /* Copy the canonical coefficients (W rows index C row-major) into host arrays
- * of n0*n0*R doubles each (any pointer may be NULL). */
+ * of m0*k0*R (U), k0*n0*R (V) and m0*n0*R (W) doubles (n0*n0*R each for a
+ * square algorithm; any pointer may be NULL). */
 mf_status mf_algo_get_uvw(const mf_algo* a, double* U, double* V, double* W);
 
 /* Release an algorithm (NULL is ignored). */
 void mf_algo_free(mf_algo* a);
+
+/* ---- Rectangular algorithms ---------------------------------------------------
+ * An algorithm <m0,k0,n0;R> splits A (M x K) into m0 x k0 blocks, B (K x N)
+ * into k0 x n0 blocks and C (M x N) into m0 x n0 blocks, each numbered
+ * row-major (A_(i,k) has index i*k0 + k, B_(k,j) index k*n0 + j, C_(i,j)
+ * index i*n0 + j).  Equation "strassen" of Section 2 then reads
+ *     T_r = sum U[(i,k), r] A_(i,k),   S_r = sum V[(k,j), r] B_(k,j),
+ *     P_r = T_r S_r,                   C_(i,j) = sum_r W[(i,j), r] P_r,
+ * and the Brent equations sum_r U[(i,k),r] V[(k',j),r] W[(i',j'),r] =
+ * [i = i'][k = k'][j = j'] are checked for every index triple.  Square
+ * algorithms are the case m0 = k0 = n0.  Section 2 builds a 6 x 6 x 6
+ * product from non-square pieces by the Kronecker product of their factor
+ * matrices (mf_algo_compose); the direct sum (mf_algo_concat) builds
+ * rectangular algorithms from smaller ones, e.g. <2,2,3;11> from Strassen's
+ * <2,2,2;7> and the textbook <2,2,1;4>.  Every level of a rectangular
+ * algorithm needs a linear-combination kernel for m0*k0, k0*n0 and R inputs
+ * per set (4, 6, 7, 8, 9, 11, 12, 16, 17, 27, 36, 49, 64, 81; a composition
+ * runs as its factors when it has none of its own), else MF_ERR_UNSUPPORTED
+ * at planning. */
+
+/* U (m0*k0 x R), V (k0*n0 x R), W (m0*n0 x R): host arrays, row-major, W rows
+ * indexing C row-major.  1 <= m0, k0, n0 <= 8, 1 <= R <= 4096; MF_ERR_BRENT
+ * if the Brent equations fail. */
+mf_status mf_algo_from_uvw_rect(int m0, int k0, int n0, int R, const double* U, const double* V,
+                                const double* W, mf_algo** out);
+
+/* The textbook partitioned product <m0,k0,n0; m0*k0*n0>: one product
+ * A_(i,k) B_(k,j) per (i, j, k), added into C_(i,j) (the definition of
+ * Section 2, partitioned). */
+mf_status mf_algo_classical(int m0, int k0, int n0, mf_algo** out);
+
+/* Direct sum of two algorithms along one dimension, the products of `a`
+ * first: axis 0 stacks the rows of A and C (a's m0 rows of blocks, then
+ * b's), axis 1 splits the inner dimension (C = A_a B_a + A_b B_b), axis 2
+ * places the columns of B and C side by side.  The other two split factors
+ * must agree (MF_ERR_ARG).  The result is Brent-checked. */
+mf_status mf_algo_concat(const mf_algo* a, const mf_algo* b, int axis, mf_algo** out);
+
+/* Split factors and rank (any output pointer may be NULL). */
+mf_status mf_algo_shape(const mf_algo* a, int* m0, int* k0, int* n0, int* R);
 
 /* C = A B with up to `depth` levels of `algo` (equation "strassen" of
  * Section 2 applied recursively: T_r, S_r from the blocks of the level above,
@@ -138,6 +181,24 @@ mf_status mf_fastmm(const mf_algo* algo, int depth, int cutoff, const void* A, c
  * mf_fastmm.  BF16 leaves stage the operands in workspace from the library's
  * pool. */
 mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int dtype, mf_stream stream);
+
+/* The general product C = alpha A B + beta C (Section 3 states the
+ * operation as C = alpha A B) for row-major A (M x K, leading dimension
+ * lda >= K), B (K x N, ldb >= N) and C (M x N, ldc >= N), with up to `depth`
+ * levels of `algo` (square or rectangular; NULL with depth 0 for the
+ * classical product).  A level is taken while levels remain and every
+ * dimension the algorithm splits exceeds `cutoff` and the 128 leaf tile;
+ * dimensions the splits do not divide are padded virtually with zeros.  The
+ * scaling is applied where results are written into C (the last
+ * post-addition, or the GEMM epilogue of a classical product); beta = 0 does
+ * not read C.  dtype MF_F64 or MF_F32 (leaves in the storage type; reduced
+ * precision leaves are available through mf_fastmm).  M or N = 0: nothing to
+ * do; K = 0: MF_ERR_SHAPE.  C must not overlap A or B (MF_ERR_ARG, by the
+ * byte ranges the three views span).  Workspace from the library's pool, as
+ * for mf_fastmm. */
+mf_status mf_gemm(const mf_algo* algo, int depth, int cutoff, int64_t M, int64_t N, int64_t K, double alpha,
+                  const void* A, int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
+                  int dtype, mf_stream stream);
 
 /* Bytes of device workspace mf_fastmm_ws needs for this request (0 for a
  * classical product with leaves in the storage type; BF16 leaves stage every
@@ -205,14 +266,35 @@ mf_status mf_fastmm_noalloc(const mf_algo* algo, int depth, int cutoff, const vo
  * for the same arguments, so its result is bitwise that of the standalone
  * call.  Supported algorithm shapes: combinations of 4, 7, 8, 9 or 16
  * inputs, and of 27 (at most 9 outputs), 49 or 64 (at most 16 outputs)
- * inputs; other shapes give MF_ERR_UNSUPPORTED.  A batch plan is immutable;
- * its runs are ordered (see mf_batch_run). */
+ * inputs; other shapes give MF_ERR_UNSUPPORTED.  The persistent form
+ * (mf_batch_create_form) runs the same task list in one launch.  A batch
+ * plan is immutable; its runs are ordered (see mf_batch_run). */
 typedef struct mf_batch mf_batch;
 
 /* Plan a batch (host only; device state is made on the first run).  The
- * algorithm handles must outlive the batch.  1 <= n[i] <= 65536. */
+ * algorithm handles must outlive the batch.  1 <= n[i] <= 65536.  The batch
+ * runs in the phase form (MF_BATCH_PHASES below). */
 mf_status mf_batch_create(int count, const int64_t* n, const mf_algo* const* algos, const int* depth,
                           const int* cutoff, int dtype, mf_batch** out);
+
+/* Execution form of a batch. */
+enum {
+  MF_BATCH_PHASES = 0,     /* one launch per phase, one workgroup per task; no waits */
+  MF_BATCH_PERSISTENT = 1  /* the whole task list in ONE launch of about two workgroups per compute
+                              unit: each takes the next task from a global ticket, waits until the
+                              per-instance counter of the stage it depends on is complete, runs the
+                              task and counts it done.  A task waits only on tasks with smaller
+                              tickets, held by running workgroups, so the schedule cannot deadlock;
+                              every wait is bounded (a few seconds), after which the run aborts
+                              (mf_batch_aborted) instead of hanging.  Supports combinations of 4, 7,
+                              8, 9 or 16 inputs (MF_ERR_UNSUPPORTED otherwise). */
+};
+
+/* As mf_batch_create with the execution form `form` (MF_ERR_ARG if unknown).
+ * Both forms run the same tasks on the same plans, so their results are
+ * bitwise equal. */
+mf_status mf_batch_create_form(int count, const int64_t* n, const mf_algo* const* algos, const int* depth,
+                               const int* cutoff, int dtype, int form, mf_batch** out);
 
 /* Device workspace bytes a run needs (0 if every instance is classical). */
 mf_status mf_batch_workspace_bytes(const mf_batch* b, size_t* bytes);
@@ -228,8 +310,9 @@ mf_status mf_batch_workspace_bytes(const mf_batch* b, size_t* bytes);
 mf_status mf_batch_run(const mf_batch* b, const void* const* A, const void* const* B, void* const* C,
                        void* workspace, size_t ws_bytes, mf_stream stream);
 
-/* Waits for the device and reports whether the last run aborted; a run of
- * the phase form never aborts (it has no waits), so *aborted is 0. */
+/* Waits for the device and reports whether the last run aborted (a wait of
+ * the persistent form exceeded its bound; the results of that run are then
+ * incomplete); a run of the phase form never aborts, so *aborted is 0. */
 mf_status mf_batch_aborted(const mf_batch* b, int* aborted);
 
 /* The task graph, for host-side schedule checks: *ntasks tasks and *nctr
@@ -257,7 +340,8 @@ void mf_batch_free(mf_batch* b);
  * A depth whose levels the plan would not take for that size (see
  * mf_fastmm) repeats a shallower plan and is skipped (time -1).  Each
  * measurement plans a batch of copies = ceil(work_flops / (2 n^3)) products
- * (at most max_copies, and at most 8 GiB of operands), fills distinct
+ * (at most max_copies, at most 8 GiB of operands, and for a fast candidate
+ * at most 8 GiB of workspace), fills distinct
  * operands on the device with the counter-based generator, runs it once
  * untimed and then `reps` times between two HIP events on `stream`.
  * Outputs: out_choice[i] = index of the fastest candidate for n[i];

@@ -1,6 +1,7 @@
-// Algebra of bilinear algorithms <p,p,p;R> on the host: Brent check,
-// composition (Kronecker construction, Section 2 of the paper), re-basis and
-// the built-in coefficient tables.
+// Algebra of bilinear algorithms <m0,k0,n0;R> on the host: Brent check,
+// composition (Kronecker construction, Section 2 of the paper), direct sums,
+// re-basis of square algorithms and the built-in coefficient tables.
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -20,22 +21,23 @@ bool all_small_integers(const std::vector<double>& x) {
 }  // namespace
 
 int64_t brent_violations(const Algo& a) {
-  const int p = a.p, P2 = p * p, R = a.R;
+  const int m0 = a.m0, k0 = a.k0, n0 = a.n0, R = a.R;
+  const int NA = m0 * k0, NB = k0 * n0, NC = m0 * n0;
   const bool exact = all_small_integers(a.U) && all_small_integers(a.V) && all_small_integers(a.W);
   // Sparse columns of W per product keep the triple loop cheap.
   std::vector<std::vector<std::pair<int, double>>> wcol(R);
   double scale = 1.0;
   for (int r = 0; r < R; ++r)
-    for (int c = 0; c < P2; ++c)
+    for (int c = 0; c < NC; ++c)
       if (a.w(c, r) != 0.0) {
         wcol[r].push_back({c, a.w(c, r)});
         scale = std::fmax(scale, std::fabs(a.w(c, r)));
       }
   int64_t bad = 0;
-  std::vector<int64_t> acc_i(P2);
-  std::vector<double> acc_d(P2);
-  for (int x = 0; x < P2; ++x) {      // A block (i, k)
-    for (int y = 0; y < P2; ++y) {    // B block (k2, j)
+  std::vector<int64_t> acc_i(NC);
+  std::vector<double> acc_d(NC);
+  for (int x = 0; x < NA; ++x) {      // A block (i, k)
+    for (int y = 0; y < NB; ++y) {    // B block (k2, j)
       std::fill(acc_i.begin(), acc_i.end(), 0);
       std::fill(acc_d.begin(), acc_d.end(), 0.0);
       for (int r = 0; r < R; ++r) {
@@ -48,9 +50,9 @@ int64_t brent_violations(const Algo& a) {
             acc_d[cw.first] += uv * cw.second;
         }
       }
-      const int i = x / p, k = x % p, k2 = y / p, j = y % p;
-      for (int c = 0; c < P2; ++c) {
-        const int want = (k == k2 && c == i * p + j) ? 1 : 0;
+      const int i = x / k0, k = x % k0, k2 = y / n0, j = y % n0;
+      for (int c = 0; c < NC; ++c) {
+        const int want = (k == k2 && c == i * n0 + j) ? 1 : 0;
         if (exact) {
           if (acc_i[c] != want) ++bad;
         } else if (std::fabs(acc_d[c] - want) > 1e-9 * scale * R) {
@@ -62,10 +64,31 @@ int64_t brent_violations(const Algo& a) {
   return bad;
 }
 
+namespace {
+
+// Kronecker product of two factor matrices X1 (r1 x c1 grid of blocks) and X2
+// (r2 x c2 grid): block (I, J) of the (r1 r2) x (c1 c2) grid lies in block
+// (I / r2, J / c2) of the outer grid at position (I % r2, J % c2) inside it;
+// product r = q1 * R2 + q2 has the product of the two coefficients.
+std::vector<double> kron_rows(const std::vector<double>& X1, int r1, int c1, int R1, const std::vector<double>& X2,
+                              int r2, int c2, int R2) {
+  const int rows = r1 * r2, cols = c1 * c2, R = R1 * R2;
+  std::vector<double> out((size_t)rows * cols * R, 0.0);
+  for (int I = 0; I < rows; ++I)
+    for (int J = 0; J < cols; ++J) {
+      const size_t row = (size_t)I * cols + J;
+      const int ko = (I / r2) * c1 + (J / c2);
+      const int ki = (I % r2) * c2 + (J % c2);
+      for (int q1 = 0; q1 < R1; ++q1)
+        for (int q2 = 0; q2 < R2; ++q2)
+          out[row * R + (size_t)q1 * R2 + q2] = X1[(size_t)ko * R1 + q1] * X2[(size_t)ki * R2 + q2];
+    }
+  return out;
+}
+
+}  // namespace
+
 Algo compose(const Algo& outer, const Algo& inner) {
-  // Block (I, J) of the fine grid lies in block (I / p2, J / p2) of the outer
-  // grid at position (I % p2, J % p2) inside it; product r = r1 * R2 + r2 has
-  // the product of the outer and inner coefficients.
   Algo c;
   auto flat = [](const Algo& a) {
     if (!a.factors.empty()) return a.factors;
@@ -75,27 +98,56 @@ Algo compose(const Algo& outer, const Algo& inner) {
   };
   c.factors = flat(outer);
   for (const Algo& f : flat(inner)) c.factors.push_back(f);
-  const int p1 = outer.p, p2 = inner.p, R1 = outer.R, R2 = inner.R;
-  c.p = p1 * p2;
-  c.R = R1 * R2;
-  const int P2 = c.p * c.p;
-  c.U.assign((size_t)P2 * c.R, 0.0);
-  c.V.assign((size_t)P2 * c.R, 0.0);
-  c.W.assign((size_t)P2 * c.R, 0.0);
-  for (int I = 0; I < c.p; ++I)
-    for (int J = 0; J < c.p; ++J) {
-      const int row = I * c.p + J;
-      const int ko = (I / p2) * p1 + (J / p2);
-      const int ki = (I % p2) * p2 + (J % p2);
-      for (int r1 = 0; r1 < R1; ++r1)
-        for (int r2 = 0; r2 < R2; ++r2) {
-          const size_t at = (size_t)row * c.R + (size_t)r1 * R2 + r2;
-          c.U[at] = outer.u(ko, r1) * inner.u(ki, r2);
-          c.V[at] = outer.v(ko, r1) * inner.v(ki, r2);
-          c.W[at] = outer.w(ko, r1) * inner.w(ki, r2);
-        }
-    }
+  const Algo &o = outer, &i = inner;
+  c.set_shape(o.m0 * i.m0, o.k0 * i.k0, o.n0 * i.n0);
+  c.R = o.R * i.R;
+  c.U = kron_rows(o.U, o.m0, o.k0, o.R, i.U, i.m0, i.k0, i.R);
+  c.V = kron_rows(o.V, o.k0, o.n0, o.R, i.V, i.k0, i.n0, i.R);
+  c.W = kron_rows(o.W, o.m0, o.n0, o.R, i.W, i.m0, i.n0, i.R);
   return c;
+}
+
+bool concat(const Algo& a, const Algo& b, int axis, Algo* out) {
+  // (rows, cols) of the block grid of each factor matrix of an algorithm
+  struct Grid {
+    int r, c;
+  };
+  auto grids = [](const Algo& x) {
+    return std::array<Grid, 3>{Grid{x.m0, x.k0}, Grid{x.k0, x.n0}, Grid{x.m0, x.n0}};
+  };
+  Algo c;
+  if (axis == 0 && a.k0 == b.k0 && a.n0 == b.n0)
+    c.set_shape(a.m0 + b.m0, a.k0, a.n0);
+  else if (axis == 1 && a.m0 == b.m0 && a.n0 == b.n0)
+    c.set_shape(a.m0, a.k0 + b.k0, a.n0);
+  else if (axis == 2 && a.m0 == b.m0 && a.k0 == b.k0)
+    c.set_shape(a.m0, a.k0, a.n0 + b.n0);
+  else
+    return false;
+  c.R = a.R + b.R;
+  const auto ga = grids(a), gb = grids(b), gc = grids(c);
+  // Which grid dimension of U (A: m, k), V (B: k, n), W (C: m, n) the axis
+  // extends: -1 none (both parts use the whole grid), 0 rows, 1 columns.
+  const int ext[3][3] = {{0, -1, 0}, {1, 0, -1}, {-1, 1, 1}};  // [axis][matrix]
+  std::vector<double>* dst[3] = {&c.U, &c.V, &c.W};
+  const std::vector<double>* src_a[3] = {&a.U, &a.V, &a.W};
+  const std::vector<double>* src_b[3] = {&b.U, &b.V, &b.W};
+  for (int x = 0; x < 3; ++x) {
+    dst[x]->assign((size_t)gc[x].r * gc[x].c * c.R, 0.0);
+    const int e = ext[axis][x];
+    for (int part = 0; part < 2; ++part) {
+      const Grid g = part == 0 ? ga[x] : gb[x];
+      const std::vector<double>& X = part == 0 ? *src_a[x] : *src_b[x];
+      const int R = part == 0 ? a.R : b.R, r0 = part == 0 ? 0 : a.R;
+      const int row0 = (part == 1 && e == 0) ? ga[x].r : 0, col0 = (part == 1 && e == 1) ? ga[x].c : 0;
+      for (int i = 0; i < g.r; ++i)
+        for (int j = 0; j < g.c; ++j)
+          for (int q = 0; q < R; ++q)
+            (*dst[x])[((size_t)(row0 + i) * gc[x].c + col0 + j) * c.R + r0 + q] = X[((size_t)i * g.c + j) * R + q];
+    }
+  }
+  *out = c;
+  return true;
 }
 
 Algo power(const Algo& a, int d) {
@@ -162,11 +214,12 @@ void sandwich(const int64_t* L, bool LT, const double* X, const int64_t* Rm, boo
 }  // namespace
 
 bool rebase(const Algo& a, const int64_t* X, const int64_t* Y, const int64_t* Z, Algo* out) {
+  if (!a.square()) return false;
   const int p = a.p, P2 = p * p;
   std::vector<int64_t> Xi, Yi, Zi;
   if (!int_inverse(X, p, &Xi) || !int_inverse(Y, p, &Yi) || !int_inverse(Z, p, &Zi)) return false;
   Algo b;
-  b.p = p;
+  b.set_shape(p, p, p);
   b.R = a.R;
   b.U.assign((size_t)P2 * a.R, 0.0);
   b.V.assign((size_t)P2 * a.R, 0.0);
@@ -194,7 +247,7 @@ namespace {
 
 Algo from_rows(int p, int R, const int* u, const int* v, const int* w) {
   Algo a;
-  a.p = p;
+  a.set_shape(p, p, p);
   a.R = R;
   const int n = p * p * R;
   a.U.assign(u, u + n);
@@ -203,26 +256,27 @@ Algo from_rows(int p, int R, const int* u, const int* v, const int* w) {
   return a;
 }
 
-Algo classical(int p) {
+}  // namespace
+
+// One product A_(i,k) B_(k,j) per (i, j, k), in that loop order, added into
+// C_(i,j) (the definition of Section 2, partitioned).
+Algo classical_algo(int m0, int k0, int n0) {
   Algo a;
-  a.p = p;
-  a.R = p * p * p;
-  const int P2 = p * p;
-  a.U.assign((size_t)P2 * a.R, 0.0);
-  a.V.assign((size_t)P2 * a.R, 0.0);
-  a.W.assign((size_t)P2 * a.R, 0.0);
+  a.set_shape(m0, k0, n0);
+  a.R = m0 * k0 * n0;
+  a.U.assign((size_t)m0 * k0 * a.R, 0.0);
+  a.V.assign((size_t)k0 * n0 * a.R, 0.0);
+  a.W.assign((size_t)m0 * n0 * a.R, 0.0);
   int r = 0;
-  for (int i = 0; i < p; ++i)
-    for (int j = 0; j < p; ++j)
-      for (int k = 0; k < p; ++k, ++r) {
-        a.U[(size_t)(i * p + k) * a.R + r] = 1.0;
-        a.V[(size_t)(k * p + j) * a.R + r] = 1.0;
-        a.W[(size_t)(i * p + j) * a.R + r] = 1.0;
+  for (int i = 0; i < m0; ++i)
+    for (int j = 0; j < n0; ++j)
+      for (int k = 0; k < k0; ++k, ++r) {
+        a.U[(size_t)(i * k0 + k) * a.R + r] = 1.0;
+        a.V[(size_t)(k * n0 + j) * a.R + r] = 1.0;
+        a.W[(size_t)(i * n0 + j) * a.R + r] = 1.0;
       }
   return a;
 }
-
-}  // namespace
 
 bool builtin(const std::string& name, Algo* out) {
   if (name == "strassen") {
@@ -279,11 +333,11 @@ bool builtin(const std::string& name, Algo* out) {
     return true;
   }
   if (name == "classical2") {
-    *out = classical(2);
+    *out = classical_algo(2, 2, 2);
     return true;
   }
   if (name == "classical3") {
-    *out = classical(3);
+    *out = classical_algo(3, 3, 3);
     return true;
   }
   return false;

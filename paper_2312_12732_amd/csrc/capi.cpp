@@ -97,12 +97,16 @@ PhaseTiming& timing() {
 // Enqueues the phases of one product on stream s.  desc: device address of a
 // copy of the plan's descriptor image; ws: the plan's workspace.
 mf_status run_at(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws, hipStream_t s,
-                 bool may_time) {
+                 bool may_time, double alpha, double beta) {
   // Rows start on 16-byte boundaries when the bases do and a row is a whole
   // number of 16-byte units.
-  const bool rows16 = (pl.n * (int64_t)pl.elem) % 16 == 0;
-  const bool vec_in = rows16 && aligned16(A) && aligned16(B);
-  const bool vec_c = rows16 && aligned16(C);
+  const Shape& sh = pl.shape;
+  const int64_t eb = (int64_t)pl.elem;
+  const bool vec_in = (sh.lda * eb) % 16 == 0 && (sh.ldb * eb) % 16 == 0 && aligned16(A) && aligned16(B);
+  const bool vec_c = (sh.ldc * eb) % 16 == 0 && aligned16(C);
+  CScale sc;
+  sc.alpha = alpha;
+  sc.beta = beta;
   const int leaf = (pl.dtype >> 8) & 0xff;
   // Timing events of this call; destroyed on every early return, handed to
   // the timing list once the whole call has been enqueued.
@@ -133,19 +137,19 @@ mf_status run_at(const Plan& pl, const char* desc, const void* A, const void* B,
     hipError_t e = hipSuccess;
     if (ph == 0) {
       for (const CombineStage& st : pl.pre)
-        if (e == hipSuccess) e = launch_combine(st, desc, (int)pl.elem, A, B, C, ws, vec_in, vec_c, s);
+        if (e == hipSuccess) e = launch_combine(st, desc, (int)pl.elem, A, B, C, ws, vec_in, vec_c, sc, s);
       // BF16 leaves: the last pre-addition level, fused with the staging
       if (e == hipSuccess && (leaf == 2 || leaf == 3))
         e = launch_stage_bf16(pl, desc, leaf == 3, A, B, C, ws, vec_in, s);
     } else if (ph == 2) {
       for (const CombineStage& st : pl.post)
-        if (e == hipSuccess) e = launch_combine(st, desc, (int)pl.elem, A, B, C, ws, vec_in, vec_c, s);
+        if (e == hipSuccess) e = launch_combine(st, desc, (int)pl.elem, A, B, C, ws, vec_in, vec_c, sc, s);
     } else if (pl.elem == 8)
-      e = launch_gemm_f64(pl, desc, A, B, C, ws, vec_in, s);
+      e = launch_gemm_f64(pl, desc, A, B, C, ws, vec_in, sc, s);
     else if (leaf == 2 || leaf == 3)
       e = launch_gemm_bf16(pl, desc, leaf == 3, A, B, C, ws, vec_in, s);
     else
-      e = launch_gemm_f32(pl, desc, A, B, C, ws, vec_in, s);
+      e = launch_gemm_f32(pl, desc, A, B, C, ws, vec_in, sc, s);
     if (e != hipSuccess) return fail(MF_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   }
   if (timed) {
@@ -160,10 +164,11 @@ mf_status run_at(const Plan& pl, const char* desc, const void* A, const void* B,
 namespace {
 
 // run_at() with the plan's own device copy of its descriptors.
-mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, hipStream_t s) {
+mf_status run(const Plan& pl, const void* A, const void* B, void* C, void* ws, hipStream_t s, double alpha = 1.0,
+              double beta = 0.0) {
   mf_status st = ensure_device(pl);
   if (st != MF_OK) return st;
-  return run_at(pl, pl.desc(), A, B, C, ws, s);
+  return run_at(pl, pl.desc(), A, B, C, ws, s, true, alpha, beta);
 }
 
 // One pool per device, made on first use and kept until the process ends.
@@ -210,7 +215,8 @@ hipError_t workspace_free(void* p, hipStream_t s) { return hipFreeAsync(p, s); }
 namespace {
 
 // run() with the workspace taken from the library's pool for the call.
-mf_status run_with_pool(const Plan& pl, const void* A, const void* B, void* C, hipStream_t s) {
+mf_status run_with_pool(const Plan& pl, const void* A, const void* B, void* C, hipStream_t s, double alpha = 1.0,
+                        double beta = 0.0) {
   void* ws = nullptr;
   if (pl.ws_bytes > 0) {
     hipError_t e = workspace_alloc(&ws, pl.ws_bytes, s);
@@ -219,7 +225,7 @@ mf_status run_with_pool(const Plan& pl, const void* A, const void* B, void* C, h
       return fail(MF_ERR_NOMEM, "workspace allocation of " + std::to_string(pl.ws_bytes) + " bytes failed");
     }
   }
-  mf_status st = run(pl, A, B, C, ws, s);
+  mf_status st = run(pl, A, B, C, ws, s, alpha, beta);
   if (ws) {
     hipError_t e = workspace_free(ws, s);
     if (e != hipSuccess && st == MF_OK) st = fail(MF_ERR_HIP, "workspace release failed");
@@ -252,7 +258,7 @@ mf_status mf_algo_from_uvw(int n0, int R, const double* U, const double* V, cons
     if (!std::isfinite(U[i]) || !std::isfinite(V[i]) || !std::isfinite(W[i]))
       return fail(MF_ERR_ARG, "coefficients must be finite");
   Algo a;
-  a.p = n0;
+  a.set_shape(n0, n0, n0);
   a.R = R;
   a.U.assign(U, U + cnt);
   a.V.assign(V, V + cnt);
@@ -278,7 +284,8 @@ mf_status mf_algo_compose(const mf_algo* outer, const mf_algo* inner, mf_algo** 
   clear_error();
   if (!outer || !inner || !out) return fail(MF_ERR_ARG, "NULL argument");
   *out = nullptr;
-  if (outer->a.p * inner->a.p > 8) return fail(MF_ERR_ARG, "composed split factor must be <= 8");
+  if (outer->a.m0 * inner->a.m0 > 8 || outer->a.k0 * inner->a.k0 > 8 || outer->a.n0 * inner->a.n0 > 8)
+    return fail(MF_ERR_ARG, "composed split factors must be <= 8");
   if ((int64_t)outer->a.R * inner->a.R > 4096) return fail(MF_ERR_ARG, "composed R must be <= 4096");
   return new_handle(compose(outer->a, inner->a), out);
 }
@@ -287,6 +294,7 @@ mf_status mf_algo_rebase(const mf_algo* a, const int64_t* X, const int64_t* Y, c
   clear_error();
   if (!a || !X || !Y || !Z || !out) return fail(MF_ERR_ARG, "NULL argument");
   *out = nullptr;
+  if (!a->a.square()) return fail(MF_ERR_UNSUPPORTED, "re-basis is defined for square algorithms");
   Algo b;
   if (!rebase(a->a, X, Y, Z, &b)) return fail(MF_ERR_ARG, "X, Y and Z must be unimodular integer matrices");
   return new_handle(b, out);
@@ -311,10 +319,9 @@ mf_status mf_algo_info(const mf_algo* a, int* n0, int* R, int* nnz_u, int* nnz_v
 mf_status mf_algo_get_uvw(const mf_algo* a, double* U, double* V, double* W) {
   clear_error();
   if (!a) return fail(MF_ERR_ARG, "algo is NULL");
-  const size_t cnt = a->a.U.size();
-  if (U) memcpy(U, a->a.U.data(), cnt * sizeof(double));
-  if (V) memcpy(V, a->a.V.data(), cnt * sizeof(double));
-  if (W) memcpy(W, a->a.W.data(), cnt * sizeof(double));
+  if (U) memcpy(U, a->a.U.data(), a->a.U.size() * sizeof(double));
+  if (V) memcpy(V, a->a.V.data(), a->a.V.size() * sizeof(double));
+  if (W) memcpy(W, a->a.W.data(), a->a.W.size() * sizeof(double));
   return MF_OK;
 }
 
@@ -370,7 +377,7 @@ mf_status mf_plan_query(const mf_algo* algo, int depth, int cutoff, int64_t n, i
   out->post_stages = (int)pl->post.size();
   out->leaf_m = pl->m;
   out->products = (int64_t)pl->prods.size();
-  out->gemm_flops = (double)pl->prods.size() * 2.0 * (double)pl->m * (double)pl->m * (double)pl->m;
+  out->gemm_flops = (double)pl->prods.size() * 2.0 * (double)pl->m * (double)pl->leaf_n * (double)pl->leaf_k;
   out->pre_bytes = stage_bytes(pl->pre);
   out->post_bytes = stage_bytes(pl->post);
   out->ws_bytes = pl->ws_bytes;
@@ -416,6 +423,91 @@ mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int 
   st = get_plan(nullptr, 0, 0, n, dtype, kStandaloneMinWorkgroups, &pl);
   if (st != MF_OK) return st;
   return run_with_pool(*pl, A, B, C, static_cast<hipStream_t>(stream));
+}
+
+mf_status mf_algo_from_uvw_rect(int m0, int k0, int n0, int R, const double* U, const double* V, const double* W,
+                                mf_algo** out) {
+  clear_error();
+  if (!out) return fail(MF_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (m0 < 1 || k0 < 1 || n0 < 1 || m0 > 8 || k0 > 8 || n0 > 8) return fail(MF_ERR_ARG, "m0, k0, n0 must be in [1, 8]");
+  if (R < 1 || R > 4096) return fail(MF_ERR_ARG, "R must be in [1, 4096]");
+  if (!U || !V || !W) return fail(MF_ERR_ARG, "U, V and W must be non-NULL");
+  Algo a;
+  a.set_shape(m0, k0, n0);
+  a.R = R;
+  a.U.assign(U, U + (size_t)m0 * k0 * R);
+  a.V.assign(V, V + (size_t)k0 * n0 * R);
+  a.W.assign(W, W + (size_t)m0 * n0 * R);
+  for (const std::vector<double>* x : {&a.U, &a.V, &a.W})
+    for (double v : *x)
+      if (!std::isfinite(v)) return fail(MF_ERR_ARG, "coefficients must be finite");
+  return new_handle(a, out);
+}
+
+mf_status mf_algo_classical(int m0, int k0, int n0, mf_algo** out) {
+  clear_error();
+  if (!out) return fail(MF_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (m0 < 1 || k0 < 1 || n0 < 1 || m0 > 8 || k0 > 8 || n0 > 8) return fail(MF_ERR_ARG, "m0, k0, n0 must be in [1, 8]");
+  return new_handle(classical_algo(m0, k0, n0), out);
+}
+
+mf_status mf_algo_concat(const mf_algo* a, const mf_algo* b, int axis, mf_algo** out) {
+  clear_error();
+  if (!a || !b || !out) return fail(MF_ERR_ARG, "NULL argument");
+  *out = nullptr;
+  if (axis < 0 || axis > 2) return fail(MF_ERR_ARG, "axis must be 0 (m), 1 (k) or 2 (n)");
+  if ((int64_t)a->a.R + b->a.R > 4096) return fail(MF_ERR_ARG, "R must be <= 4096");
+  Algo c;
+  if (!concat(a->a, b->a, axis, &c)) return fail(MF_ERR_ARG, "the other two dimensions of the algorithms differ");
+  if (c.m0 > 8 || c.k0 > 8 || c.n0 > 8) return fail(MF_ERR_ARG, "split factors must be <= 8");
+  return new_handle(c, out);
+}
+
+mf_status mf_algo_shape(const mf_algo* a, int* m0, int* k0, int* n0, int* R) {
+  clear_error();
+  if (!a) return fail(MF_ERR_ARG, "algo is NULL");
+  if (m0) *m0 = a->a.m0;
+  if (k0) *k0 = a->a.k0;
+  if (n0) *n0 = a->a.n0;
+  if (R) *R = a->a.R;
+  return MF_OK;
+}
+
+mf_status mf_gemm(const mf_algo* algo, int depth, int cutoff, int64_t M, int64_t N, int64_t K, double alpha,
+                  const void* A, int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc, int dtype,
+                  mf_stream stream) {
+  clear_error();
+  if (depth > 0 && !algo) return fail(MF_ERR_ARG, "algo is NULL with depth > 0");
+  if (depth < 0 || cutoff < 0) return fail(MF_ERR_ARG, "depth and cutoff must be >= 0");
+  if (M < 0 || N < 0 || K < 0) return fail(MF_ERR_ARG, "M, N, K must be >= 0");
+  if (dtype != MF_F64 && dtype != MF_F32)
+    return fail(MF_ERR_UNSUPPORTED, "mf_gemm takes MF_F64 or MF_F32 with leaves in the storage type");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(MF_ERR_ARG, "alpha and beta must be finite");
+  if (M == 0 || N == 0) return MF_OK;
+  if (K == 0) return fail(MF_ERR_SHAPE, "K must be >= 1");
+  if (M > kMaxN || N > kMaxN || K > kMaxN) return fail(MF_ERR_SHAPE, "dimensions exceed the supported maximum (2^20)");
+  if (lda < K || ldb < N || ldc < N) return fail(MF_ERR_ARG, "leading dimensions must be >= the row lengths");
+  if (lda > INT32_MAX || ldb > INT32_MAX || ldc > INT32_MAX) return fail(MF_ERR_SHAPE, "leading dimensions exceed 2^31 - 1");
+  if (!A || !B || !C) return fail(MF_ERR_ARG, "A, B and C must be non-NULL");
+  const size_t elem = dtype == MF_F64 ? 8 : 4;
+  if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(C)) & (elem - 1))
+    return fail(MF_ERR_ARG, "A, B and C must be aligned to the element size");
+  const size_t ba = ((size_t)(M - 1) * lda + K) * elem, bb = ((size_t)(K - 1) * ldb + N) * elem,
+               bc = ((size_t)(M - 1) * ldc + N) * elem;
+  if (overlaps(C, bc, A, ba) || overlaps(C, bc, B, bb)) return fail(MF_ERR_ARG, "C overlaps A or B");
+  Shape sh;
+  sh.M = M;
+  sh.N = N;
+  sh.K = K;
+  sh.lda = lda;
+  sh.ldb = ldb;
+  sh.ldc = ldc;
+  std::shared_ptr<const Plan> pl;
+  mf_status st = get_plan(depth > 0 ? algo : nullptr, depth, cutoff, sh, dtype, kStandaloneMinWorkgroups, &pl);
+  if (st != MF_OK) return st;
+  return run_with_pool(*pl, A, B, C, static_cast<hipStream_t>(stream), alpha, beta);
 }
 
 mf_status mf_phase_timing(int enable) {

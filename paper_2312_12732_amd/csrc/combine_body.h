@@ -20,9 +20,11 @@ struct CombArgs {
   const CombIn* ins;     // NIN per set
   const CombOut* outs;
   const double* coef;    // NIN per output
-  int m;
+  int m;                 // block size of a square stage (Kronecker-factored and batched stages)
   int vec_in;            // input views with src A/B/C have 16-byte aligned rows
   int vec_out;           // output views with dst C have 16-byte aligned rows
+  int scale_c;           // outputs into C are alpha (sum) + beta C
+  T alpha, beta;         // (beta = 0: C is not read)
 };
 
 template <class T>
@@ -44,6 +46,27 @@ __device__ __forceinline__ T* comb_dst(const CombArgs<T>& g, int dst) {
 template <class V>
 __device__ __forceinline__ void store_out(V* p, const V& v) {
   *p = v;
+}
+
+// An output into C under scaling: acc becomes alpha acc + beta C for the
+// `valid` leading elements at p (C is read only when beta != 0; vec: the
+// VEC elements at p can be read as one vector).
+template <class T, int VEC, class TV>
+__device__ __forceinline__ void scale_into_c(const CombArgs<T>& g, const T* p, bool vec, int valid, TV& acc) {
+  if (g.beta == T(0)) {
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) acc[q] = g.alpha * acc[q];
+    return;
+  }
+  TV old;
+  if (vec && valid >= VEC) {
+    old = *reinterpret_cast<const TV*>(p);
+  } else {
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) old[q] = q < valid ? p[q] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) acc[q] = fma_t(g.beta, old[q], g.alpha * acc[q]);
 }
 
 template <class T, int NIN, int VEC, bool FULL>
@@ -89,6 +112,10 @@ __device__ __forceinline__ void combine_body(const CombArgs<T>& g, const CombSet
     }
     if (!started) acc = (tv)(T(0));
     T* p = comb_dst(g, po.dst) + po.off + (int64_t)i * po.ld + j;
+    if (g.scale_c && po.dst == SRC_C) {
+      if (i >= po.vr) continue;
+      scale_into_c<T, VEC>(g, p, FULL || g.vec_out, po.vc - j, acc);
+    }
     if (FULL) {
       store_out(reinterpret_cast<tv*>(p), acc);
     } else {
@@ -166,6 +193,10 @@ __device__ __forceinline__ void combine_acc_body(const CombArgs<T>& g, const Com
     if (o >= nout) continue;
     const CombOut po = load_uniform(g.outs + set.out_beg + o);
     T* p = comb_dst(g, po.dst) + po.off + (int64_t)i * po.ld + j;
+    if (g.scale_c && po.dst == SRC_C) {
+      if (i >= po.vr) continue;
+      scale_into_c<T, VEC>(g, p, FULL || g.vec_out, po.vc - j, acc[o]);
+    }
     if (FULL) {
       store_out(reinterpret_cast<tv*>(p), acc[o]);
     } else {

@@ -18,10 +18,13 @@ struct GemmArgs {
   const EpiDesc* epis;
   const int32_t* group_beg;  // products of group g: [group_beg[g], group_beg[g+1])
   int groups;
-  int m;        // M = N = K of every leaf product
-  int tiles_m;  // output tiles along rows (m / BM) and columns (m / BN)
+  int m;        // rows M of every leaf product
+  int n, k;     // its columns N and inner size K (both m for square plans)
+  int tiles_m;  // output tiles along rows (m / BM) and columns (n / BN)
   int tiles_n;
   int vec_in;   // A and B rows are 16-byte aligned
+  int scale_c;  // outputs into C are alpha (sum) + beta C (beta = 0: C is not read)
+  T alpha, beta;
 };
 
 // Load a descriptor that every lane of the wave reads at the same address and
@@ -87,13 +90,15 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // Post-addition of one output element: first == 1 stores coef * v, 0 adds
-// coef * v (fused multiply-add), 2 stores zero.
+// coef * v (fused multiply-add), 2 stores zero.  beta != 0 (an output into C
+// under scaling, with alpha already in coef): the first store and the zero
+// store also add beta times the old value.
 template <class T>
-__device__ __forceinline__ void epi_apply(T* p, int first, T coef, T v) {
+__device__ __forceinline__ void epi_apply(T* p, int first, T coef, T v, T beta = T(0)) {
   if (first == 1)
-    *p = coef * v;
+    *p = beta != T(0) ? fma_t(coef, v, beta * *p) : coef * v;
   else if (first == 2)
-    *p = T(0);
+    *p = beta != T(0) ? beta * *p : T(0);
   else
     *p = fma_t(coef, v, *p);
 }

@@ -279,7 +279,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
   const int wm = (wave / WAVES_N) * (16 * WM_T), wn = (wave % WAVES_N) * (16 * WN_T);
   const int lr = lane & 15, lk = lane >> 4;
   const int i0 = ti * BM, j0 = tj * BN;
-  const int KT = g.m / Cfg::BK;
+  const int KT = g.k / Cfg::BK;
   const int r_beg = load_uniform(g.group_beg + grp), r_end = load_uniform(g.group_beg + grp + 1);
 
   for (int r = r_beg; r < r_end; ++r) {
@@ -295,7 +295,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
 #pragma unroll
       for (int ni = 0; ni < WN_T; ++ni) acc[mi][ni] = v4{T(0), T(0), T(0), T(0)};
 
-    const bool interior = FULL || (vec_a && vec_b && i0 + BM <= pd.a_vr && pd.a_vc >= g.m && pd.b_vr >= g.m &&
+    const bool interior = FULL || (vec_a && vec_b && i0 + BM <= pd.a_vr && pd.a_vc >= g.k && pd.b_vr >= g.k &&
                                    j0 + BN <= pd.b_vc);
     if (interior)
       k_loop<T, Cfg, false>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
@@ -309,7 +309,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
       const EpiDesc ed = load_uniform(g.epis + e);
       T* pc = dst_ptr(g, ed.c_src) + ed.c_off;
       const bool full = FULL || ((i0 + BM <= ed.c_vr) && (j0 + BN <= ed.c_vc));
-      const T coef = (T)ed.coef;
+      const bool to_c = g.scale_c && ed.c_src == SRC_C;
+      const T coef = to_c ? (T)ed.coef * g.alpha : (T)ed.coef;
+      const T beta = to_c ? g.beta : T(0);
 #pragma unroll
       for (int mi = 0; mi < WM_T; ++mi)
 #pragma unroll
@@ -319,7 +321,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
             const int row = i0 + wm + 16 * mi + Mfma<T>::row(lk, v);
             const int col = j0 + wn + 16 * ni + lr;
             if (full || (row < ed.c_vr && col < ed.c_vc))
-              epi_apply<T>(pc + (size_t)row * ed.ldc + col, ed.first, coef, acc[mi][ni][v]);
+              epi_apply<T>(pc + (size_t)row * ed.ldc + col, ed.first, coef, acc[mi][ni][v], beta);
           }
     }
   }

@@ -350,7 +350,10 @@ GemmArgs<float> bf_args(const Plan& pl, const char* desc, const void* A, const v
   g.epis = img_at<EpiDesc>(desc, pl.img_epis);
   g.group_beg = img_at<int32_t>(desc, pl.img_group_beg);
   g.groups = pl.groups;
-  g.m = (int)pl.m;
+  g.m = g.n = g.k = (int)pl.m;
+  g.scale_c = 0;
+  g.alpha = 1.0f;
+  g.beta = 0.0f;
   g.vec_in = 0;
   return g;
 }

@@ -15,11 +15,10 @@ namespace mf {
 // rows take a branch-free path.
 template <class T, int NIN, int VEC>
 __global__ void __launch_bounds__(256) combine(CombArgs<T> g) {
-  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
-  const int64_t mm = (int64_t)g.m * g.m;
-  if (e >= mm) return;
-  const int i = (int)(e / g.m), j = (int)(e % g.m);
   const CombSet set = load_uniform(g.sets + blockIdx.y);
+  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  if (e >= (int64_t)set.rows * set.cols) return;
+  const int i = (int)(e / set.cols), j = (int)(e % set.cols);
   if (set.full && g.vec_in && g.vec_out)
     combine_body<T, NIN, VEC, true>(g, set, i, j);
   else
@@ -30,11 +29,10 @@ __global__ void __launch_bounds__(256) combine(CombArgs<T> g) {
 // per set).
 template <class T, int NIN, int NOUT, int VEC>
 __global__ void __launch_bounds__(256) combine_acc(CombArgs<T> g) {
-  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
-  const int64_t mm = (int64_t)g.m * g.m;
-  if (e >= mm) return;
-  const int i = (int)(e / g.m), j = (int)(e % g.m);
   const CombSet set = load_uniform(g.sets + blockIdx.y);
+  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  if (e >= (int64_t)set.rows * set.cols) return;
+  const int i = (int)(e / set.cols), j = (int)(e % set.cols);
   if (set.full && g.vec_in && g.vec_out)
     combine_acc_body<T, NIN, NOUT, VEC, true>(g, set, i, j);
   else
@@ -77,15 +75,16 @@ __device__ __forceinline__ void kron_store(const CombArgs<T>& g, const CombOut& 
   if (i >= po.vr) return;  // also every output that is not stored (empty extent)
   T* p = comb_dst(g, po.dst) + po.off + (int64_t)i * po.ld + j;
   const bool vec = po.dst == SRC_WS || g.vec_out;
-  if (vec && j + VEC <= po.vc) {
-    tv y;
+  tv y;
 #pragma unroll
-    for (int q = 0; q < VEC; ++q) y[q] = x[q];
+  for (int q = 0; q < VEC; ++q) y[q] = x[q];
+  if (g.scale_c && po.dst == SRC_C) scale_into_c<T, VEC>(g, p, vec, po.vc - j, y);
+  if (vec && j + VEC <= po.vc) {
     *reinterpret_cast<tv*>(p) = y;
   } else {
 #pragma unroll
     for (int q = 0; q < VEC; ++q)
-      if (j + q < po.vc) p[q] = x[q];
+      if (j + q < po.vc) p[q] = y[q];
   }
 }
 
@@ -212,7 +211,7 @@ __global__ void __launch_bounds__(256) kron3_post(CombArgs<T> g) {
 
 template <class T>
 static hipError_t launch_combine_t(const CombineStage& cs, const char* desc, const void* A, const void* B, void* C,
-                                   void* ws, bool vec_in, bool vec_out, hipStream_t s) {
+                                   void* ws, bool vec_in, bool vec_out, const CScale& sc, hipStream_t s) {
   if (cs.sets.empty()) return hipSuccess;
   CombArgs<T> g;
   g.A = static_cast<const T*>(A);
@@ -226,7 +225,11 @@ static hipError_t launch_combine_t(const CombineStage& cs, const char* desc, con
   g.m = (int)cs.m;
   g.vec_in = vec_in ? 1 : 0;
   g.vec_out = vec_out ? 1 : 0;
-  const int64_t mm = cs.m * cs.m;
+  g.scale_c = sc.plain() ? 0 : 1;
+  g.alpha = (T)sc.alpha;
+  g.beta = (T)sc.beta;
+  // every set's block size is a multiple of the leaf tile, so of every VEC
+  const int64_t mm = cs.kron3 ? cs.m * cs.m : cs.elems_max;
   auto grid = [&](int vec) { return dim3((unsigned)((mm / vec + 255) / 256), (unsigned)cs.sets.size(), 1); };
   if (cs.kron3) {
     constexpr int V = sizeof(T) == 8 ? 1 : 2;
@@ -260,10 +263,14 @@ static hipError_t launch_combine_t(const CombineStage& cs, const char* desc, con
 #define MF_COMB_CASE(N, V) \
   case N: hipLaunchKernelGGL((combine<T, N, V>), grid(V), dim3(256), 0, s, g); break;
     MF_COMB_CASE(4, 4)
+    MF_COMB_CASE(6, 4)
     MF_COMB_CASE(7, 4)
     MF_COMB_CASE(8, 4)
     MF_COMB_CASE(9, 4)
+    MF_COMB_CASE(11, 4)
+    MF_COMB_CASE(12, 4)
     MF_COMB_CASE(16, 4)
+    MF_COMB_CASE(17, 2)
     MF_COMB_CASE(27, 1)
     MF_COMB_CASE(36, 1)
     MF_COMB_CASE(49, 1)
@@ -278,15 +285,17 @@ static hipError_t launch_combine_t(const CombineStage& cs, const char* desc, con
 
 bool combine_supported(int nin) {
   switch (nin) {
-    case 4: case 7: case 8: case 9: case 16: case 27: case 36: case 49: case 64: case 81: return true;
+    case 4: case 6: case 7: case 8: case 9: case 11: case 12: case 16: case 17: case 27: case 36: case 49: case 64:
+    case 81:
+      return true;
     default: return false;
   }
 }
 
 hipError_t launch_combine(const CombineStage& cs, const char* desc, int elem, const void* A, const void* B, void* C,
-                          void* ws, bool vec_in, bool vec_out, hipStream_t s) {
-  return elem == 8 ? launch_combine_t<double>(cs, desc, A, B, C, ws, vec_in, vec_out, s)
-                   : launch_combine_t<float>(cs, desc, A, B, C, ws, vec_in, vec_out, s);
+                          void* ws, bool vec_in, bool vec_out, const CScale& sc, hipStream_t s) {
+  return elem == 8 ? launch_combine_t<double>(cs, desc, A, B, C, ws, vec_in, vec_out, sc, s)
+                   : launch_combine_t<float>(cs, desc, A, B, C, ws, vec_in, vec_out, sc, s);
 }
 
 }  // namespace mf

@@ -27,21 +27,21 @@ __global__ void __launch_bounds__(Cfg::NTHREADS, Cfg::WAVES_PER_SIMD) gemm_group
 // m x m block with 16-byte aligned rows (then the kernel without the masked
 // paths runs; true for sizes the splits divide into whole tiles).
 static bool plan_full(const Plan& pl, size_t elem, bool vec_in) {
-  const int64_t m = pl.m;
+  const int64_t m = pl.m, n = pl.leaf_n, k = pl.leaf_k;
   for (const ProdDesc& pd : pl.prods) {
     const bool va = pd.a_src == SRC_WS || vec_in, vb = pd.b_src == SRC_WS || vec_in;
-    if (!va || !vb || pd.a_vr < m || pd.a_vc < m || pd.b_vr < m || pd.b_vc < m) return false;
+    if (!va || !vb || pd.a_vr < m || pd.a_vc < k || pd.b_vr < k || pd.b_vc < n) return false;
     if ((pd.lda * elem) % 16 || (pd.ldb * elem) % 16 || (pd.a_off * elem) % 16 || (pd.b_off * elem) % 16) return false;
   }
   for (const EpiDesc& ed : pl.epis)
-    if (ed.c_vr < m || ed.c_vc < m) return false;
+    if (ed.c_vr < m || ed.c_vc < n) return false;
   return true;
 }
 
 template <class T, class Cfg>
-static hipError_t launch_cfg(GemmArgs<T> g, int64_t m, bool full, hipStream_t s) {
-  g.tiles_m = (int)(m / Cfg::BM);
-  g.tiles_n = (int)(m / Cfg::BN);
+static hipError_t launch_cfg(GemmArgs<T> g, bool full, hipStream_t s) {
+  g.tiles_m = g.m / Cfg::BM;
+  g.tiles_n = g.n / Cfg::BN;
   const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n * (unsigned)g.groups;
   if (full)
     hipLaunchKernelGGL((gemm_grouped<T, Cfg, true>), dim3(grid), dim3(Cfg::NTHREADS), 0, s, g);
@@ -52,7 +52,7 @@ static hipError_t launch_cfg(GemmArgs<T> g, int64_t m, bool full, hipStream_t s)
 
 template <class T>
 static hipError_t launch_gemm_t(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws,
-                                bool vec_in, hipStream_t s) {
+                                bool vec_in, const CScale& sc, hipStream_t s) {
   GemmArgs<T> g;
   g.A = static_cast<const T*>(A);
   g.B = static_cast<const T*>(B);
@@ -63,18 +63,23 @@ static hipError_t launch_gemm_t(const Plan& pl, const char* desc, const void* A,
   g.group_beg = img_at<int32_t>(desc, pl.img_group_beg);
   g.groups = pl.groups;
   g.m = (int)pl.m;
+  g.n = (int)pl.leaf_n;
+  g.k = (int)pl.leaf_k;
   g.vec_in = vec_in ? 1 : 0;
-  return launch_cfg<T, Tile128>(g, pl.m, plan_full(pl, sizeof(T), vec_in), s);
+  g.scale_c = sc.plain() ? 0 : 1;
+  g.alpha = (T)sc.alpha;
+  g.beta = (T)sc.beta;
+  return launch_cfg<T, Tile128>(g, plan_full(pl, sizeof(T), vec_in), s);
 }
 
 hipError_t launch_gemm_f64(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws,
-                           bool vec_in, hipStream_t s) {
-  return launch_gemm_t<double>(pl, desc, A, B, C, ws, vec_in, s);
+                           bool vec_in, const CScale& sc, hipStream_t s) {
+  return launch_gemm_t<double>(pl, desc, A, B, C, ws, vec_in, sc, s);
 }
 
 hipError_t launch_gemm_f32(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws,
-                           bool vec_in, hipStream_t s) {
-  return launch_gemm_t<float>(pl, desc, A, B, C, ws, vec_in, s);
+                           bool vec_in, const CScale& sc, hipStream_t s) {
+  return launch_gemm_t<float>(pl, desc, A, B, C, ws, vec_in, sc, s);
 }
 
 }  // namespace mf

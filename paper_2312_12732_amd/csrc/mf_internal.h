@@ -19,10 +19,13 @@ namespace mf {
 // Algorithms
 // ---------------------------------------------------------------------------
 
-// A canonical <p,p,p;R> algorithm: U, V, W are p^2 x R, row-major, with row c
-// of W belonging to C_c (blocks numbered row-major).
+// A canonical <m0,k0,n0;R> algorithm: A is split into m0 x k0 blocks, B into
+// k0 x n0 and C into m0 x n0, each numbered row-major; U is (m0 k0) x R, V is
+// (k0 n0) x R and W is (m0 n0) x R, row-major, with row c of W belonging to
+// C_c.  A square algorithm <p,p,p;R> has p = m0 = k0 = n0; p is 0 otherwise.
 struct Algo {
   int p = 0;
+  int m0 = 0, k0 = 0, n0 = 0;
   int R = 0;
   std::vector<double> U, V, W;
   // A Kronecker composition (compose, power) keeps its factors, outermost
@@ -31,15 +34,27 @@ struct Algo {
   double u(int k, int r) const { return U[(size_t)k * R + r]; }
   double v(int k, int r) const { return V[(size_t)k * R + r]; }
   double w(int k, int r) const { return W[(size_t)k * R + r]; }
+  bool square() const { return m0 == k0 && k0 == n0; }
+  void set_shape(int m, int k, int n) {
+    m0 = m;
+    k0 = k;
+    n0 = n;
+    p = square() ? m : 0;
+  }
 };
 
 // Number of failing Brent equations (exact for integer coefficients).
 int64_t brent_violations(const Algo& a);
 Algo compose(const Algo& outer, const Algo& inner);
 Algo power(const Algo& a, int d);
+// Direct sum along one dimension (axis 0: rows of A and C, 1: the inner
+// dimension, 2: columns of B and C); false if the other dimensions differ.
+bool concat(const Algo& a, const Algo& b, int axis, Algo* out);
 // Re-base by unimodular X, Y, Z (p x p, row-major); false if not unimodular.
 bool rebase(const Algo& a, const int64_t* X, const int64_t* Y, const int64_t* Z, Algo* out);
 bool builtin(const std::string& name, Algo* out);
+// The textbook partitioned product <m0,k0,n0; m0 k0 n0>.
+Algo classical_algo(int m0, int k0, int n0);
 
 }  // namespace mf
 
@@ -103,16 +118,18 @@ struct CombOut {
 };
 
 // One operand set of a linear-combination stage: `nin` input views starting
-// at ins[in_beg] and the outputs [out_beg, out_end).  full: every view covers
-// its whole m x m block (no virtual padding).
+// at ins[in_beg] and the outputs [out_beg, out_end), all of rows x cols
+// elements.  full: every view covers its whole block (no virtual padding).
 struct CombSet {
   int32_t in_beg;
   int32_t out_beg, out_end;
   int32_t full;
+  int32_t rows, cols;
 };
 
-// A linear-combination launch over m x m blocks: one operand set per
-// blockIdx.y.
+// A linear-combination launch: one operand set per blockIdx.y, each over
+// blocks of its own shape (m x m for the Kronecker-factored and batched
+// stages, which are square).
 struct CombineStage {
   // kron3 = 1: a level of a three-factor Kronecker composition of <2,2,2;7>
   // algorithms (<8,8,8;343>).  Each set then lists its inputs and outputs in
@@ -126,7 +143,8 @@ struct CombineStage {
   int kpost = 0;
   int nin = 0;
   int nout_max = 0;  // most outputs of any set
-  int64_t m = 0;
+  int64_t m = 0;         // block size of a square stage
+  int64_t elems_max = 0;  // largest rows x cols of any set
   std::vector<CombSet> sets;
   std::vector<CombIn> ins;
   std::vector<CombOut> outs;
@@ -174,10 +192,22 @@ struct StageOut {
 //  - post-addition stages, one launch per outer level, innermost first,
 //    combining R child results into the p^2 blocks of their parent (C at the
 //    top).  With levels_outer = 0 the epilogue writes C directly.
+// Shape of one product C (M x N) = A (M x K) B (K x N): row-major with
+// leading dimensions lda, ldb, ldc (elements).
+struct Shape {
+  int64_t M = 0, N = 0, K = 0;
+  int64_t lda = 0, ldb = 0, ldc = 0;
+  static Shape sq(int64_t n) { return Shape{n, n, n, n, n, n}; }
+  bool square() const { return M == N && N == K && lda == M && ldb == M && ldc == M; }
+};
+
 struct Plan {
-  int64_t n = 0;        // true size
-  int64_t npad = 0;     // padded size = P * m
-  int64_t m = 0;        // leaf size (multiple of the GEMM tile)
+  Shape shape;          // the request
+  bool square = true;   // shape.square() and only square algorithm levels
+  int64_t n = 0;        // true size (M)
+  int64_t npad = 0;     // padded size = P * m (square plans)
+  int64_t m = 0;        // leaf rows (multiple of the GEMM tile); every leaf size of a square plan
+  int64_t leaf_n = 0, leaf_k = 0;  // leaf columns and inner size
   int64_t m_outer = 0;  // size of a group's output block (P_inner * m)
   int levels = 0, levels_outer = 0;
   int P = 1, P_outer = 1;
@@ -281,8 +311,12 @@ struct BatchTask {
 // so an instance's result is bitwise that of the standalone call.
 // Returns an mf_status and sets the thread's error message on failure.
 constexpr int64_t kStandaloneMinWorkgroups = int64_t(1) << 62;
-mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg,
+mf_status get_plan(const mf_algo* algo, int depth, int cutoff, const Shape& shape, int dtype, int64_t min_wg,
                    std::shared_ptr<const Plan>* out);
+inline mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg,
+                          std::shared_ptr<const Plan>* out) {
+  return get_plan(algo, depth, cutoff, Shape::sq(n), dtype, min_wg, out);
+}
 
 // Copies the plan's descriptor image to the device once (host-only queries
 // such as the workspace size never touch the device); afterwards pl.desc()
@@ -295,9 +329,15 @@ void drop_plans(uint64_t algo_id);
 // Leaf tile granularity: every leaf size is a multiple of this.
 constexpr int kLeafTile = 128;
 
-// Number of recursion levels the plan of an n x n product takes for an
-// algorithm of block size p and rank R at the requested depth and cutoff.
-int levels_for(int64_t n, int p, int R, int depth, int cutoff);
+// Number of recursion levels the plan of a product of this shape takes for
+// an algorithm with splits (m0, k0, n0) and rank R at the requested depth and
+// cutoff: one more while levels remain, every dimension the algorithm splits
+// exceeds the cutoff and the leaf tile, and the leaf count stays within the
+// limit (sizes rounded up at each split).
+int levels_for(int64_t M, int64_t K, int64_t N, int m0, int k0, int n0, int R, int depth, int cutoff);
+inline int levels_for(int64_t n, int p, int R, int depth, int cutoff) {
+  return levels_for(n, n, n, p, p, p, R, depth, cutoff);
+}
 
 // ---------------------------------------------------------------------------
 // Launchers (kernels.hip)
@@ -306,15 +346,22 @@ int levels_for(int64_t n, int p, int R, int depth, int cutoff);
 // Kernel launchers.  vec_in / vec_out: rows of A and B / of C start on
 // 16-byte boundaries.
 constexpr int kPhases = 3;  // pre-addition, grouped GEMM, outer post-addition
+// Scaling of the results written into C: C = alpha (sum) + beta C (beta = 0:
+// C is not read).  Outputs into the workspace are never scaled.
+struct CScale {
+  double alpha = 1.0, beta = 0.0;
+  bool plain() const { return alpha == 1.0 && beta == 0.0; }
+};
 // desc: device address of a copy of the plan's descriptor image.
 hipError_t launch_combine(const CombineStage& cs, const char* desc, int elem, const void* A, const void* B, void* C,
-                          void* ws, bool vec_in, bool vec_out, hipStream_t s);
+                          void* ws, bool vec_in, bool vec_out, const CScale& sc, hipStream_t s);
 hipError_t launch_gemm_f64(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws,
-                           bool vec_in, hipStream_t s);
+                           bool vec_in, const CScale& sc, hipStream_t s);
 hipError_t launch_gemm_f32(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws,
-                           bool vec_in, hipStream_t s);
+                           bool vec_in, const CScale& sc, hipStream_t s);
 // BF16 leaves: the staging launch (the last pre-addition level fused with the
-// conversion to BF16 planes), then the grouped GEMM on the staged planes.
+// conversion to BF16 planes), then the grouped GEMM on the staged planes
+// (square plans only; results are written unscaled, see capi).
 hipError_t launch_stage_bf16(const Plan& pl, const char* desc, bool x3, const void* A, const void* B, void* C,
                              void* ws, bool vec_in, hipStream_t s);
 hipError_t launch_gemm_bf16(const Plan& pl, const char* desc, bool x3, const void* A, const void* B, void* C,
@@ -349,8 +396,9 @@ mf_status plan_for(const mf_algo* algo, int depth, int cutoff, int64_t n, int dt
 // Enqueues the phases of one product on stream s.  desc: device address of
 // a copy of the plan's descriptor image; ws: the plan's workspace.  may_time:
 // whether the call may record phase-timing events (creating them).
+// alpha, beta: C = alpha A B + beta C (beta = 0: C is not read).
 mf_status run_at(const Plan& pl, const char* desc, const void* A, const void* B, void* C, void* ws, hipStream_t s,
-                 bool may_time = true);
+                 bool may_time = true, double alpha = 1.0, double beta = 0.0);
 // Byte ranges [x, x + xb) and [y, y + yb) intersect.
 bool overlaps(const void* x, size_t xb, const void* y, size_t yb);
 constexpr int kMaxDevices = 64;

@@ -46,12 +46,13 @@ struct Blk {
   int32_t stage_set = -1, stage_coef = -1;
 };
 
-// Quarter k (row-major in the p x p split) of block b, of size s.
-Blk quarter(const Blk& b, int k, int p, int64_t s) {
+// Part k (row-major in a split into pc columns of parts) of block b; every
+// part is sr x sc.
+Blk quarter(const Blk& b, int k, int pc, int64_t sr, int64_t sc) {
   Blk q = b;
-  const int64_t r0 = (int64_t)(k / p) * s, c0 = (int64_t)(k % p) * s;
-  q.vr = (int32_t)std::max<int64_t>(0, std::min<int64_t>(s, b.vr - r0));
-  q.vc = (int32_t)std::max<int64_t>(0, std::min<int64_t>(s, b.vc - c0));
+  const int64_t r0 = (int64_t)(k / pc) * sr, c0 = (int64_t)(k % pc) * sc;
+  q.vr = (int32_t)std::max<int64_t>(0, std::min<int64_t>(sr, b.vr - r0));
+  q.vc = (int32_t)std::max<int64_t>(0, std::min<int64_t>(sc, b.vc - c0));
   q.zero = b.zero || q.vr == 0 || q.vc == 0;
   if (q.zero) {
     q.vr = q.vc = 0;
@@ -61,6 +62,7 @@ Blk quarter(const Blk& b, int k, int p, int64_t s) {
   }
   return q;
 }
+Blk quarter(const Blk& b, int k, int p, int64_t s) { return quarter(b, k, p, s, s); }
 
 CombIn as_input(const Blk& b) {
   CombIn in{};
@@ -102,15 +104,19 @@ void kron3_coef(const Algo& a, char which, double scale, std::vector<double>* ou
       }
 }
 
-void finish_set(CombineStage* st, CombSet set) {
+// Appends a set whose blocks are rows x cols.
+void finish_set(CombineStage* st, CombSet set, int64_t rows, int64_t cols) {
+  set.rows = (int32_t)rows;
+  set.cols = (int32_t)cols;
   bool full = true;
   for (int k = 0; k < st->nin; ++k) {
     const CombIn& v = st->ins[(size_t)set.in_beg + k];
-    full = full && v.vr == st->m && v.vc == st->m;
+    full = full && v.vr == rows && v.vc == cols;
   }
-  for (int o = set.out_beg; o < set.out_end; ++o) full = full && st->outs[o].vr == st->m && st->outs[o].vc == st->m;
+  for (int o = set.out_beg; o < set.out_end; ++o) full = full && st->outs[o].vr == rows && st->outs[o].vc == cols;
   set.full = full ? 1 : 0;
   st->nout_max = std::max(st->nout_max, set.out_end - set.out_beg);
+  st->elems_max = std::max(st->elems_max, rows * cols);
   st->sets.push_back(set);
 }
 
@@ -155,28 +161,35 @@ int32_t add_stage_set(Plan* pl, int side, const std::vector<Blk>& q) {
   return (int32_t)pl->bf_sets.size() - 1;
 }
 
-mf_status build_classical(int64_t n, Plan* pl) {
+mf_status build_classical(const Shape& sh, Plan* pl) {
   pl->P = pl->P_outer = 1;
   pl->R = pl->groups = 1;
-  pl->m = pl->m_outer = round_up(n, kLeafTile);
+  pl->m = pl->m_outer = round_up(sh.M, kLeafTile);
+  pl->leaf_n = round_up(sh.N, kLeafTile);
+  pl->leaf_k = round_up(sh.K, kLeafTile);
   pl->npad = pl->m;
   ProdDesc pd{};
   pd.a_src = SRC_A;
   pd.b_src = SRC_B;
-  pd.lda = pd.ldb = (int32_t)n;
-  pd.a_vr = pd.a_vc = pd.b_vr = pd.b_vc = (int32_t)n;
+  pd.lda = (int32_t)sh.lda;
+  pd.ldb = (int32_t)sh.ldb;
+  pd.a_vr = (int32_t)sh.M;
+  pd.a_vc = pd.b_vr = (int32_t)sh.K;
+  pd.b_vc = (int32_t)sh.N;
   pd.epi_beg = 0;
   pd.epi_end = 1;
   pl->prods.push_back(pd);
   EpiDesc ed{};
   ed.c_src = SRC_C;
-  ed.ldc = (int32_t)n;
-  ed.c_vr = ed.c_vc = (int32_t)n;
+  ed.ldc = (int32_t)sh.ldc;
+  ed.c_vr = (int32_t)sh.M;
+  ed.c_vc = (int32_t)sh.N;
   ed.first = 1;
   ed.coef = 1.0;
   pl->epis.push_back(ed);
   pl->group_beg = {0, 1};
-  if (bf16_leaves(pl->dtype)) {  // each operand is a set of one input
+  if (bf16_leaves(pl->dtype)) {  // each operand is a set of one input (square plans only)
+    const int64_t n = sh.M;
     Blk ops[2];
     pl->bf_nin = 1;
     for (int side = 0; side < 2; ++side) {
@@ -194,21 +207,28 @@ mf_status build_classical(int64_t n, Plan* pl) {
   return MF_OK;
 }
 
+// Whether linear-combination kernels exist for one level of an algorithm:
+// m0 k0 inputs per A-side pre-addition set, k0 n0 per B-side set and R per
+// post-addition set.
+bool level_supported(const Algo& a) {
+  return combine_supported(a.m0 * a.k0) && combine_supported(a.k0 * a.n0) && combine_supported(a.R);
+}
+
 // The algorithm of every recursion level, outermost first.  An algorithm
 // runs as one level of its own when linear-combination kernels exist for its
-// shape (p^2 inputs per pre-addition set, R per post-addition set) or when it
-// is a three-factor composition of <2,2,2;7> algorithms (factor-by-factor
-// kernels).  A Kronecker composition without such kernels (for example a 2 x 3
-// split, <6,6,6;189>) runs as its factors, one level each, outer factor first:
-// the same algorithm (the composed coefficients are the factors' products),
-// evaluated level by level.  One level of the algorithm is taken while levels
-// remain, the current size exceeds the cutoff and the leaf tile, and the leaf
-// count stays within the limit; a level taken is taken whole (all of its
-// factors).  Returns false if some level has no kernel.
-bool level_sequence(const Algo& a, int depth, int cutoff, int64_t n, std::vector<const Algo*>* seq) {
+// shape or when it is a three-factor composition of <2,2,2;7> algorithms
+// (factor-by-factor kernels).  A Kronecker composition without such kernels
+// (for example a 2 x 3 split, <6,6,6;189>) runs as its factors, one level
+// each, outer factor first: the same algorithm (the composed coefficients are
+// the factors' products), evaluated level by level.  One level of the
+// algorithm is taken while levels remain, every dimension it splits exceeds
+// the cutoff and the leaf tile, and the leaf count stays within the limit; a
+// level taken is taken whole (all of its factors).  Returns false if some
+// level has no kernel.
+bool level_sequence(const Algo& a, int depth, int cutoff, const Shape& sh, std::vector<const Algo*>* seq) {
   seq->clear();
   std::vector<const Algo*> unit;
-  const bool direct = is_kron3(a) || (combine_supported(a.p * a.p) && combine_supported(a.R));
+  const bool direct = is_kron3(a) || level_supported(a);
   if (direct || a.factors.empty()) {
     unit.push_back(&a);
   } else {
@@ -216,36 +236,49 @@ bool level_sequence(const Algo& a, int depth, int cutoff, int64_t n, std::vector
   }
   for (const Algo* f : unit)
     if (f != &a || !is_kron3(a))
-      if (!combine_supported(f->p * f->p) || !combine_supported(f->R)) return false;
-  const int L = levels_for(n, a.p, a.R, depth, cutoff);
+      if (!level_supported(*f)) return false;
+  const int L = levels_for(sh.M, sh.K, sh.N, a.m0, a.k0, a.n0, a.R, depth, cutoff);
   for (int d = 0; d < L; ++d) seq->insert(seq->end(), unit.begin(), unit.end());
   return true;
 }
 
-mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg, Plan* pl) {
-  pl->n = n;
+mf_status build(const Algo* algo, int depth, int cutoff, const Shape& sh, int dtype, int64_t min_wg, Plan* pl) {
+  pl->shape = sh;
+  pl->n = sh.M;
   pl->dtype = dtype;
   pl->elem = (dtype & 0xff) == MF_F64 ? 8 : 4;
   std::vector<const Algo*> seq;
-  if (algo && !level_sequence(*algo, depth, cutoff, n, &seq))
+  if (algo && !level_sequence(*algo, depth, cutoff, sh, &seq))
     return fail(MF_ERR_UNSUPPORTED, "no linear-combination kernel for this algorithm shape");
   const int L = (int)seq.size();
   pl->levels = L;
-  if (L == 0) return build_classical(n, pl);
+  bool sq_levels = true;
+  for (const Algo* f : seq) sq_levels = sq_levels && f->square();
+  pl->square = sh.square() && sq_levels;
+  if (bf16_leaves(dtype) && !pl->square)
+    return fail(MF_ERR_UNSUPPORTED, "BF16 leaves need square operands and a square algorithm");
+  if (L == 0) return build_classical(sh, pl);
 
   const bool kron3 = is_kron3(*seq[0]);
-  int64_t P = 1;
-  for (const Algo* f : seq) P *= f->p;
-  pl->P = (int)P;
+  int64_t Pm = 1, Pk = 1, Pn = 1;
+  for (const Algo* f : seq) {
+    Pm *= f->m0;
+    Pk *= f->k0;
+    Pn *= f->n0;
+  }
+  pl->P = (int)Pm;
   if (bf16_leaves(dtype)) {
     const int p2_last = seq.back()->p * seq.back()->p;
     if (!stage_supported(p2_last)) return fail(MF_ERR_UNSUPPORTED, "no BF16 staging kernel for this algorithm shape");
     pl->bf_nin = p2_last;
   }
-  pl->m = round_up((n + P - 1) / P, kLeafTile);
-  pl->npad = pl->m * P;
-  const int64_t m = pl->m;
-  const int64_t positions = (m / kLeafTile) * (m / kLeafTile);
+  // leaf sizes: rows, columns and inner size, each a multiple of the tile
+  pl->m = round_up((sh.M + Pm - 1) / Pm, kLeafTile);
+  pl->leaf_n = round_up((sh.N + Pn - 1) / Pn, kLeafTile);
+  pl->leaf_k = round_up((sh.K + Pk - 1) / Pk, kLeafTile);
+  pl->npad = pl->m * Pm;
+  const int64_t m = pl->m, mn = pl->leaf_n, mk = pl->leaf_k;
+  const int64_t positions = (m / kLeafTile) * (mn / kLeafTile);
 
   // Outer levels split off as groups (with post-addition stages) until the
   // grouped GEMM has enough workgroups; the inner levels run as one composed
@@ -260,14 +293,16 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
     Fi = *seq[(size_t)L - 1];
     for (int l = L - 2; l >= Lo; --l) Fi = compose(*seq[(size_t)l], Fi);
   }
-  const int Pi = Li > 0 ? Fi.p : 1, Ri = Li > 0 ? Fi.R : 1;
+  // C grid of the levels fused into the epilogue
+  const int Pim = Li > 0 ? Fi.m0 : 1, Pin = Li > 0 ? Fi.n0 : 1, Ri = Li > 0 ? Fi.R : 1;
   int64_t P_outer = 1, R_all = 1;
-  for (int l = 0; l < Lo; ++l) P_outer *= seq[(size_t)l]->p;
+  for (int l = 0; l < Lo; ++l) P_outer *= seq[(size_t)l]->m0;
   for (const Algo* f : seq) R_all *= f->R;
   pl->P_outer = (int)P_outer;
   pl->R = (int)R_all;
   pl->groups = (int)outer_products;
-  pl->m_outer = (int64_t)Pi * m;
+  pl->m_outer = (int64_t)Pim * m;
+  const int64_t mo_r = (int64_t)Pim * m, mo_c = (int64_t)Pin * mn;  // a group's output block
   int64_t ws = 0;  // workspace elements allocated so far
   auto alloc = [&](int64_t elems) {
     const int64_t off = ws;
@@ -275,9 +310,12 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
     return off;
   };
 
-  // ---- pre-addition stages, level by level, both operands in each launch.
-  // BF16 leaves fuse the last level into the staging kernel: its linear
-  // combinations become term lists instead of FP32 workspace blocks.
+  // ---- pre-addition stages, level by level.  Side 0 splits A (rows M,
+  // columns K) into m0 x k0 parts, side 1 splits B (K x N) into k0 x n0 parts;
+  // both sides go into one launch when their sets have the same number of
+  // inputs, else one launch each.  BF16 leaves fuse the last level into the
+  // staging kernel: its linear combinations become term lists instead of
+  // FP32 workspace blocks.
   std::vector<Blk> leaves[2];
   {
     std::vector<Blk> cur[2];
@@ -285,30 +323,38 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
       Blk top;
       top.src = side == 0 ? SRC_A : SRC_B;
       top.off = 0;
-      top.ld = (int32_t)n;
-      top.vr = top.vc = (int32_t)n;
+      top.ld = (int32_t)(side == 0 ? sh.lda : sh.ldb);
+      top.vr = (int32_t)(side == 0 ? sh.M : sh.K);
+      top.vc = (int32_t)(side == 0 ? sh.K : sh.N);
       top.scale = 1.0;
       top.zero = false;
       cur[side] = {top};
     }
-    int64_t size = pl->npad;
+    // current block sizes of each side: rows, columns
+    int64_t size[2][2] = {{m * Pm, mk * Pk}, {mk * Pk, mn * Pn}};
     for (int lev = 1; lev <= L; ++lev) {
       const Algo& al = *seq[(size_t)lev - 1];
-      const int p = al.p, p2 = p * p, R = al.R;
-      const int64_t sz = size / p;
-      CombineStage st;
-      st.nin = p2;
-      st.m = sz;
-      st.kron3 = kron3 ? 1 : 0;
+      const int R = al.R;
+      const int pr[2] = {al.m0, al.k0}, pc[2] = {al.k0, al.n0};
+      const bool one_launch = pr[0] * pc[0] == pr[1] * pc[1];
+      CombineStage stage[2];
       std::vector<Blk> next[2];
       for (int side = 0; side < 2; ++side) {
+        CombineStage& st = stage[one_launch ? 0 : side];
+        const int np = pr[side] * pc[side];
+        const int64_t sr = size[side][0] / pr[side], sc = size[side][1] / pc[side];
+        st.nin = np;
+        st.m = sr == sc ? sr : 0;
+        st.kron3 = kron3 ? 1 : 0;
         const std::vector<double>& X = side == 0 ? al.U : al.V;
         for (const Blk& b : cur[side]) {
-          std::vector<Blk> q(p2);
-          for (int k = 0; k < p2; ++k) q[k] = quarter(b, k, p, sz);
+          std::vector<Blk> q(np);
+          for (int k = 0; k < np; ++k) q[k] = quarter(b, k, pc[side], sr, sc);
           if (lev == L && bf16_leaves(pl->dtype)) {
-            // last level fused with the BF16 staging: every nonzero child is
-            // an output of this block's staging set (aliased ones included)
+            // last level fused with the BF16 staging (square plans): every
+            // nonzero child is an output of this block's staging set
+            // (aliased ones included)
+            const int64_t sz = sr;
             if (b.zero) {
               next[side].resize(next[side].size() + (size_t)R);
               continue;
@@ -318,7 +364,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
               Blk child;
               const int32_t coef_off = (int32_t)pl->bf_coef.size();
               bool any = false;
-              for (int k = 0; k < p2; ++k) {
+              for (int k = 0; k < np; ++k) {
                 const double x = q[k].zero ? 0.0 : X[(size_t)k * R + r] * b.scale;
                 any = any || x != 0.0;
                 pl->bf_coef.push_back((float)x);
@@ -348,7 +394,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
           bool stored = false;
           for (int r = 0; r < R; ++r) {
             int nnz = 0, last = -1;
-            for (int k = 0; k < p2; ++k)
+            for (int k = 0; k < np; ++k)
               if (X[(size_t)k * R + r] != 0.0 && !q[k].zero) {
                 ++nnz;
                 last = k;
@@ -361,22 +407,24 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
               child.scale = b.scale * X[(size_t)last * R + r];
             } else {
               CombOut co{};
-              co.off = alloc(sz * sz);
+              co.off = alloc(sr * sc);
               co.dst = SRC_WS;
-              co.ld = (int32_t)sz;
-              co.vr = co.vc = (int32_t)sz;
+              co.ld = (int32_t)sc;
+              co.vr = (int32_t)sr;
+              co.vc = (int32_t)sc;
               if (kron3) {
                 co.coef_off = kcoef;
               } else {
                 co.coef_off = (int32_t)st.coef.size();
-                for (int k = 0; k < p2; ++k) st.coef.push_back(q[k].zero ? 0.0 : X[(size_t)k * R + r] * b.scale);
+                for (int k = 0; k < np; ++k) st.coef.push_back(q[k].zero ? 0.0 : X[(size_t)k * R + r] * b.scale);
               }
               st.outs.push_back(co);
               stored = true;
               child.src = SRC_WS;
               child.off = co.off;
-              child.ld = (int32_t)sz;
-              child.vr = child.vc = (int32_t)sz;
+              child.ld = (int32_t)sc;
+              child.vr = (int32_t)sr;
+              child.vc = (int32_t)sc;
               child.scale = 1.0;
               child.zero = false;
             }
@@ -401,15 +449,17 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
             st.outs.resize((size_t)set.out_beg);
             st.coef.resize((size_t)kcoef);
           } else if (set.out_end > set.out_beg) {
-            for (int k = 0; k < p2; ++k) st.ins.push_back(as_input(q[kron3 ? kron3_block(k) : k]));
-            finish_set(&st, set);
+            for (int k = 0; k < np; ++k) st.ins.push_back(as_input(q[kron3 ? kron3_block(k) : k]));
+            finish_set(&st, set, sr, sc);
           }
         }
+        size[side][0] = sr;
+        size[side][1] = sc;
       }
-      if (!st.sets.empty()) pl->pre.push_back(std::move(st));
+      for (int k = 0; k < (one_launch ? 1 : 2); ++k)
+        if (!stage[k].sets.empty()) pl->pre.push_back(std::move(stage[k]));
       cur[0].swap(next[0]);
       cur[1].swap(next[1]);
-      size = sz;
     }
     leaves[0].swap(cur[0]);
     leaves[1].swap(cur[1]);
@@ -417,32 +467,32 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
 
   // ---- group output buffers (sub-problem results of the outer levels)
   const int G = pl->groups;
-  const int64_t mo = pl->m_outer;
   std::vector<int64_t> gbuf(G, 0);
   if (Lo > 0)
-    for (int g = 0; g < G; ++g) gbuf[g] = alloc(mo * mo);
+    for (int g = 0; g < G; ++g) gbuf[g] = alloc(mo_r * mo_c);
 
   // ---- grouped leaf products with the inner post-addition in the epilogue
   std::vector<char> group_empty(G, 1);
   std::vector<Blk> ops_a, ops_b;  // BF16 leaves: the leaf blocks in product order
   for (int g = 0; g < G; ++g) {
     pl->group_beg.push_back((int32_t)pl->prods.size());
-    const int nout = Pi * Pi;
+    const int nout = Pim * Pin;
     std::vector<char> written(nout, 0);
     auto out_view = [&](int c, EpiDesc* ed) {
-      const int64_t r0 = (int64_t)(c / Pi) * m, c0 = (int64_t)(c % Pi) * m;
+      const int64_t r0 = (int64_t)(c / Pin) * m, c0 = (int64_t)(c % Pin) * mn;
       if (Lo == 0) {
         ed->c_src = SRC_C;
-        ed->ldc = (int32_t)n;
-        ed->c_vr = (int32_t)std::max<int64_t>(0, std::min<int64_t>(m, n - r0));
-        ed->c_vc = (int32_t)std::max<int64_t>(0, std::min<int64_t>(m, n - c0));
+        ed->ldc = (int32_t)sh.ldc;
+        ed->c_vr = (int32_t)std::max<int64_t>(0, std::min<int64_t>(m, sh.M - r0));
+        ed->c_vc = (int32_t)std::max<int64_t>(0, std::min<int64_t>(mn, sh.N - c0));
         if (ed->c_vr == 0 || ed->c_vc == 0) ed->c_vr = ed->c_vc = 0;
-        ed->c_off = ed->c_vr > 0 ? r0 * n + c0 : 0;
+        ed->c_off = ed->c_vr > 0 ? r0 * sh.ldc + c0 : 0;
       } else {
         ed->c_src = SRC_WS;
-        ed->ldc = (int32_t)mo;
-        ed->c_vr = ed->c_vc = (int32_t)m;
-        ed->c_off = gbuf[g] + r0 * mo + c0;
+        ed->ldc = (int32_t)mo_c;
+        ed->c_vr = (int32_t)m;
+        ed->c_vc = (int32_t)mn;
+        ed->c_off = gbuf[g] + r0 * mo_c + c0;
       }
     };
     const int group_first = (int)pl->prods.size();
@@ -507,26 +557,28 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
   if (pl->prods.empty()) return fail(MF_ERR_SHAPE, "plan has no products");
 
   // ---- post-addition stages, innermost outer level first:
-  // parent_c = sum_r W[c, r] child_r for each of the p^2 blocks c of a parent.
+  // parent_c = sum_r W[c, r] child_r for each of the m0 x n0 blocks c of a
+  // parent.
   if (Lo > 0) {
     std::vector<Blk> child(G);
     for (int g = 0; g < G; ++g) {
       child[g].src = SRC_WS;
       child[g].off = gbuf[g];
-      child[g].ld = (int32_t)mo;
-      child[g].vr = child[g].vc = (int32_t)mo;
+      child[g].ld = (int32_t)mo_c;
+      child[g].vr = (int32_t)mo_r;
+      child[g].vc = (int32_t)mo_c;
       child[g].zero = group_empty[g] != 0;
     }
-    int64_t csz = mo;  // size of a child result
+    int64_t cr = mo_r, cc = mo_c;  // size of a child result
     for (int lev = Lo; lev >= 1; --lev) {
       const Algo& al = *seq[(size_t)lev - 1];
-      const int p = al.p, p2 = p * p, R = al.R;
+      const int R = al.R, pm = al.m0, pn = al.n0;
       int nparent = 1;
       for (int l = 0; l < lev - 1; ++l) nparent *= seq[(size_t)l]->R;
-      const int64_t psz = csz * p;
+      const int64_t pr = cr * pm, pcol = cc * pn;
       CombineStage st;
       st.nin = R;
-      st.m = csz;
+      st.m = cr == cc ? cr : 0;
       st.kron3 = kron3 ? 1 : 0;
       st.kpost = 1;
       std::vector<Blk> parents(nparent);
@@ -535,14 +587,16 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
         if (lev == 1) {
           par.src = SRC_C;
           par.off = 0;
-          par.ld = (int32_t)n;
-          par.vr = par.vc = (int32_t)n;
+          par.ld = (int32_t)sh.ldc;
+          par.vr = (int32_t)sh.M;
+          par.vc = (int32_t)sh.N;
           par.zero = false;
         } else {
           par.src = SRC_WS;
-          par.off = alloc(psz * psz);
-          par.ld = (int32_t)psz;
-          par.vr = par.vc = (int32_t)psz;
+          par.off = alloc(pr * pcol);
+          par.ld = (int32_t)pcol;
+          par.vr = (int32_t)pr;
+          par.vc = (int32_t)pcol;
           par.zero = false;
         }
         parents[q] = par;
@@ -558,14 +612,14 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
           kron3_coef(al, 'w', 1.0, &st.coef);
           for (int r = 0; r < R; ++r) {
             const Blk& cb = child[(size_t)q * R + r];
-            if (!cb.zero && (cb.src != SRC_WS || cb.ld != csz || cb.vr != csz || cb.vc != csz))
+            if (!cb.zero && (cb.src != SRC_WS || cb.ld != cc || cb.vr != cr || cb.vc != cc))
               return fail(MF_ERR_UNSUPPORTED, "Kronecker post-addition needs whole workspace blocks");
             st.coef.push_back(cb.zero ? -1.0 : (double)cb.off);
           }
         }
-        for (int t = 0; t < p2; ++t) {
+        for (int t = 0; t < pm * pn; ++t) {
           const int c = kron3 ? kron3_block(t) : t;
-          const Blk qb = quarter(par, c, p, csz);
+          const Blk qb = quarter(par, c, pn, cr, cc);
           CombOut co{};
           if (qb.zero) {
             if (!kron3) continue;
@@ -588,11 +642,12 @@ mf_status build(const Algo* algo, int depth, int cutoff, int64_t n, int dtype, i
           st.outs.push_back(co);
         }
         set.out_end = (int32_t)st.outs.size();
-        finish_set(&st, set);
+        finish_set(&st, set, cr, cc);
       }
       pl->post.push_back(std::move(st));
       child.swap(parents);
-      csz = psz;
+      cr = pr;
+      cc = pcol;
     }
   }
   pl->ws_bytes = (size_t)ws * pl->elem;
@@ -657,10 +712,10 @@ mf_status upload(const Plan* pl) {
 struct Key {
   uint64_t algo;
   int levels, dtype, device;
-  int64_t n, min_wg;
+  int64_t M, N, K, lda, ldb, ldc, min_wg;
   bool operator<(const Key& o) const {
-    return std::tie(algo, levels, dtype, device, n, min_wg) <
-           std::tie(o.algo, o.levels, o.dtype, o.device, o.n, o.min_wg);
+    return std::tie(algo, levels, dtype, device, M, N, K, lda, ldb, ldc, min_wg) <
+           std::tie(o.algo, o.levels, o.dtype, o.device, o.M, o.N, o.K, o.lda, o.ldb, o.ldc, o.min_wg);
   }
 };
 
@@ -683,25 +738,35 @@ std::map<Key, std::shared_ptr<const Plan>>& cache() {
 
 }  // namespace
 
-// Levels taken for an n x n product: a level is taken while levels remain,
-// the current size exceeds the cutoff and the leaf tile (smaller leaves only
-// add padding on this GEMM), and the leaf count stays within the limit
-// (sizes rounded up at each split).
-int levels_for(int64_t n, int p, int R, int depth, int cutoff) {
+// Levels taken for a product: a level is taken while levels remain, every
+// dimension the algorithm splits exceeds the cutoff and the leaf tile
+// (smaller leaves only add padding on this GEMM), and the leaf count stays
+// within the limit (sizes rounded up at each split).
+int levels_for(int64_t M, int64_t K, int64_t N, int m0, int k0, int n0, int R, int depth, int cutoff) {
   int d = 0;
-  int64_t size = n, leaves = 1;
-  while (d < depth && size > cutoff && size > kLeafTile && p > 1 && leaves * R <= kMaxLeafProducts) {
-    size = (size + p - 1) / p;
+  int64_t size[3] = {M, K, N};
+  const int split[3] = {m0, k0, n0};
+  if (m0 < 1 || k0 < 1 || n0 < 1 || (m0 == 1 && k0 == 1 && n0 == 1)) return 0;
+  int64_t leaves = 1;
+  auto fits = [&]() {
+    for (int x = 0; x < 3; ++x)
+      if (split[x] > 1 && (size[x] <= cutoff || size[x] <= kLeafTile)) return false;
+    return true;
+  };
+  while (d < depth && fits() && leaves * R <= kMaxLeafProducts) {
+    for (int x = 0; x < 3; ++x) size[x] = (size[x] + split[x] - 1) / split[x];
     leaves *= R;
     ++d;
   }
   return d;
 }
 
-mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, int64_t min_wg,
+mf_status get_plan(const mf_algo* algo, int depth, int cutoff, const Shape& sh, int dtype, int64_t min_wg,
                    std::shared_ptr<const Plan>* out) {
-  const int levels = algo ? levels_for(n, algo->a.p, algo->a.R, depth, cutoff) : 0;
-  const Key key{levels == 0 ? 0 : algo->id, levels, dtype, current_device(), n, levels == 0 ? 0 : min_wg};
+  const int levels =
+      algo ? levels_for(sh.M, sh.K, sh.N, algo->a.m0, algo->a.k0, algo->a.n0, algo->a.R, depth, cutoff) : 0;
+  const Key key{levels == 0 ? 0 : algo->id, levels, dtype, current_device(), sh.M, sh.N, sh.K, sh.lda, sh.ldb,
+                sh.ldc, levels == 0 ? 0 : min_wg};
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = cache().find(key);
@@ -711,7 +776,7 @@ mf_status get_plan(const mf_algo* algo, int depth, int cutoff, int64_t n, int dt
     }
   }
   auto pl = std::make_shared<Plan>();
-  const mf_status st = build(levels == 0 ? nullptr : &algo->a, depth, cutoff, n, dtype, min_wg, pl.get());
+  const mf_status st = build(levels == 0 ? nullptr : &algo->a, depth, cutoff, sh, dtype, min_wg, pl.get());
   if (st != MF_OK) return st;
   make_image(pl.get());
   std::lock_guard<std::mutex> lk(g_mu);

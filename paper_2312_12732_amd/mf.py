@@ -30,6 +30,8 @@ MF_ERR_UNSUPPORTED = -6
 STATUS_NAMES = {0: "MF_OK", -1: "MF_ERR_ARG", -2: "MF_ERR_BRENT", -3: "MF_ERR_SHAPE", -4: "MF_ERR_NOMEM",
                 -5: "MF_ERR_HIP", -6: "MF_ERR_UNSUPPORTED"}
 
+MF_BATCH_PHASES = 0
+MF_BATCH_PERSISTENT = 1
 MF_F64 = 1
 MF_F32 = 2
 MF_LEAF_NATIVE = 0 << 8
@@ -42,11 +44,12 @@ MF_W_DEEPMIND_CT = 1
 EXPORTED = ["mf_algo_from_uvw", "mf_algo_builtin", "mf_algo_compose", "mf_algo_rebase", "mf_algo_info",
             "mf_algo_get_uvw", "mf_algo_free", "mf_fastmm", "mf_classical_mm", "mf_workspace_bytes",
             "mf_fastmm_ws", "mf_fastmm_noalloc", "mf_last_error", "mf_phase_timing", "mf_phase_timing_read",
-            "mf_batch_create", "mf_batch_workspace_bytes", "mf_batch_run", "mf_batch_aborted", "mf_batch_tasks",
-            "mf_batch_free", "mf_server_create", "mf_server_need_bytes", "mf_server_submit", "mf_server_replay",
+            "mf_batch_create", "mf_batch_create_form", "mf_batch_workspace_bytes", "mf_batch_run",
+            "mf_batch_aborted", "mf_batch_tasks", "mf_batch_free", "mf_server_create", "mf_server_need_bytes", "mf_server_submit", "mf_server_replay",
             "mf_server_drain", "mf_server_stats", "mf_server_free", "mf_admission_simulate", "mf_fill_uniform",
             "mf_autotune_batch", "mf_plan_query", "mf_batch_phases", "mf_server_device_ms",
-            "mf_server_submit_operands", "mf_server_device_interval"]
+            "mf_server_submit_operands", "mf_server_device_interval", "mf_algo_from_uvw_rect",
+            "mf_algo_classical", "mf_algo_concat", "mf_algo_shape", "mf_gemm"]
 
 
 class ServerConfig(ctypes.Structure):
@@ -90,9 +93,15 @@ def _load():
         "mf_workspace_bytes": ([P, I, I, I64, I, ctypes.POINTER(ctypes.c_size_t)], I),
         "mf_fastmm_ws": ([P, I, I, P, P, P, I64, I, P, ctypes.c_size_t, P], I),
         "mf_fastmm_noalloc": ([P, I, I, P, P, P, I64, I, P], I),
+        "mf_algo_from_uvw_rect": ([I, I, I, I, DP, DP, DP, AP], I),
+        "mf_algo_classical": ([I, I, I, AP], I),
+        "mf_algo_concat": ([P, P, I, AP], I),
+        "mf_algo_shape": ([P] + [ctypes.POINTER(I)] * 4, I),
+        "mf_gemm": ([P, I, I, I64, I64, I64, ctypes.c_double, P, I64, P, I64, ctypes.c_double, P, I64, I, P], I),
         "mf_last_error": ([], ctypes.c_char_p),
         "mf_phase_timing": ([I], I),
         "mf_batch_create": ([I, LP, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(I), I, AP], I),
+        "mf_batch_create_form": ([I, LP, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(I), I, I, AP], I),
         "mf_batch_workspace_bytes": ([P, ctypes.POINTER(ctypes.c_size_t)], I),
         "mf_batch_run": ([P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), P, ctypes.c_size_t, P], I),
         "mf_batch_aborted": ([P, ctypes.POINTER(I)], I),
@@ -159,10 +168,17 @@ class Algo:
         n0, R, nu, nv, nw = (v.value for v in vals)
         return {"n0": n0, "R": R, "nnz_u": nu, "nnz_v": nv, "nnz_w": nw}
 
+    def shape(self):
+        """(m0, k0, n0, R)."""
+        vals = [ctypes.c_int() for _ in range(4)]
+        _check(lib.mf_algo_shape(self._h, *[ctypes.byref(v) for v in vals]))
+        return tuple(v.value for v in vals)
+
     def uvw(self):
-        inf = self.info()
-        shape = (inf["n0"] ** 2, inf["R"])
-        U, V, W = (np.zeros(shape, dtype=np.float64) for _ in range(3))
+        m0, k0, n0, R = self.shape()
+        U = np.zeros((m0 * k0, R), dtype=np.float64)
+        V = np.zeros((k0 * n0, R), dtype=np.float64)
+        W = np.zeros((m0 * n0, R), dtype=np.float64)
         _check(lib.mf_algo_get_uvw(self._h, _dptr(U), _dptr(V), _dptr(W)))
         return U, V, W
 
@@ -175,6 +191,35 @@ def mf_algo_from_uvw(n0: int, U, V, W, w_convention: int = MF_W_ROWMAJOR_C) -> A
         raise ValueError("U, V, W must be 2-d arrays of equal shape")
     out = ctypes.c_void_p()
     _check(lib.mf_algo_from_uvw(n0, U.shape[1], _dptr(U), _dptr(V), _dptr(W), w_convention, ctypes.byref(out)))
+    return Algo(out.value)
+
+
+def mf_algo_from_uvw_rect(m0: int, k0: int, n0: int, U, V, W) -> Algo:
+    """<m0,k0,n0;R> from U (m0 k0 x R), V (k0 n0 x R), W (m0 n0 x R)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    R = U.shape[1]
+    if U.shape != (m0 * k0, R) or V.shape != (k0 * n0, R) or W.shape != (m0 * n0, R):
+        raise ValueError("U, V, W shapes do not match <m0,k0,n0;R>")
+    out = ctypes.c_void_p()
+    _check(lib.mf_algo_from_uvw_rect(m0, k0, n0, R, _dptr(U), _dptr(V), _dptr(W), ctypes.byref(out)))
+    return Algo(out.value)
+
+
+def mf_algo_classical(m0: int, k0: int, n0: int) -> Algo:
+    out = ctypes.c_void_p()
+    _check(lib.mf_algo_classical(m0, k0, n0, ctypes.byref(out)))
+    return Algo(out.value)
+
+
+AXIS = {"m": 0, "k": 1, "n": 2}
+
+
+def mf_algo_concat(a: Algo, b: Algo, axis) -> Algo:
+    """Direct sum along axis 'm' (0), 'k' (1) or 'n' (2)."""
+    out = ctypes.c_void_p()
+    _check(lib.mf_algo_concat(a.handle, b.handle, AXIS.get(axis, axis), ctypes.byref(out)))
     return Algo(out.value)
 
 
@@ -252,6 +297,27 @@ def mf_fastmm_noalloc(algo: Algo, depth: int, cutoff: int, A, B, C, leaf: int = 
     _check(lib.mf_fastmm_noalloc(algo.handle, depth, cutoff, ctypes.c_void_p(A.data_ptr()),
                                  ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(C.data_ptr()), A.shape[0],
                                  _dtype_code(A, leaf), _stream(stream)))
+    return C
+
+
+def mf_gemm(algo, depth: int, cutoff: int, A, B, C, alpha: float = 1.0, beta: float = 0.0, stream=None):
+    """C = alpha A B + beta C for 2-d device tensors with unit column stride
+    (row-major views; the row strides are the leading dimensions)."""
+    import torch
+    for name, t in (("A", A), ("B", B), ("C", C)):
+        if not t.is_cuda or t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+            raise ValueError(f"{name} must be a 2-d device tensor with unit column stride")
+    if not (A.dtype == B.dtype == C.dtype) or A.dtype not in (torch.float64, torch.float32):
+        raise ValueError("A, B, C must share dtype float64 or float32")
+    M, K = A.shape
+    K2, N = B.shape
+    if K2 != K or tuple(C.shape) != (M, N):
+        raise ValueError("shapes do not match C (M x N) = A (M x K) B (K x N)")
+    code = MF_F64 if A.dtype == torch.float64 else MF_F32
+    ld = lambda t: max(t.stride(0), t.shape[1])  # noqa: E731
+    _check(lib.mf_gemm(algo.handle if algo is not None else None, depth, cutoff, M, N, K, float(alpha),
+                       ctypes.c_void_p(A.data_ptr()), ld(A), ctypes.c_void_p(B.data_ptr()), ld(B), float(beta),
+                       ctypes.c_void_p(C.data_ptr()), ld(C), code, _stream(stream)))
     return C
 
 
@@ -333,15 +399,16 @@ class Batch:
         return bool(flag.value)
 
 
-def mf_batch_create(sizes, algos, depths, cutoffs, dtype_code: int = MF_F64) -> Batch:
-    """Plan a batch: algos[i] may be None where depths[i] == 0."""
+def mf_batch_create(sizes, algos, depths, cutoffs, dtype_code: int = MF_F64, form: int = MF_BATCH_PHASES) -> Batch:
+    """Plan a batch: algos[i] may be None where depths[i] == 0; form is
+    MF_BATCH_PHASES (one launch per phase) or MF_BATCH_PERSISTENT (one launch)."""
     count = len(sizes)
     n_arr = (ctypes.c_int64 * count)(*sizes)
     a_arr = (ctypes.c_void_p * count)(*[(a.handle.value if a is not None else None) for a in algos])
     d_arr = (ctypes.c_int * count)(*depths)
     c_arr = (ctypes.c_int * count)(*cutoffs)
     out = ctypes.c_void_p()
-    _check(lib.mf_batch_create(count, n_arr, a_arr, d_arr, c_arr, dtype_code, ctypes.byref(out)))
+    _check(lib.mf_batch_create_form(count, n_arr, a_arr, d_arr, c_arr, dtype_code, form, ctypes.byref(out)))
     return Batch(out.value, [a for a in algos if a is not None], sizes, dtype_code)
 
 

@@ -456,3 +456,33 @@ def test_mixed_factor_matches_oracle_composition():
     o_c3 = oa.classical_algo(3)
     for (outer, inner), (o_out, o_in) in (((s, c3), (o_s, o_c3)), ((c3, s), (o_c3, o_s))):
         assert same(mf.mf_algo_compose(outer, inner), oa.compose(o_out, o_in))
+
+
+def test_batch_form_argument_checked_on_host():
+    """The persistent form takes only the narrow combinations, and an unknown
+    form is rejected; both at planning time, without a device."""
+    w = mf.mf_algo_builtin("winograd")
+    w2 = mf.mf_algo_compose(w, w)
+    b = mf.mf_batch_create([256, 512], [w, w], [1, 2], [0, 0], mf.MF_F64, form=mf.MF_BATCH_PERSISTENT)
+    assert b.workspace_bytes() > 0
+    with pytest.raises(mf.MFError) as ei:
+        mf.mf_batch_create([1024], [w2], [1], [0], mf.MF_F64, form=mf.MF_BATCH_PERSISTENT)
+    assert ei.value.status == mf.MF_ERR_UNSUPPORTED
+    # the phase form takes the wide <4,4,4;49> post-addition
+    mf.mf_batch_create([1024], [w2], [1], [0], mf.MF_F64)
+    with pytest.raises(mf.MFError) as ei:
+        mf.mf_batch_create([256], [w], [1], [0], mf.MF_F64, form=7)
+    assert ei.value.status == mf.MF_ERR_ARG
+
+
+def test_noalloc_rejects_beyond_scratch_on_host():
+    """A request whose workspace exceeds the fixed scratch array is rejected
+    before anything touches a device (pointers are never dereferenced)."""
+    w = mf.mf_algo_builtin("winograd")
+    n = 4096
+    assert mf.mf_workspace_bytes(w, 1, 0, n) > (256 << 20)
+    A, B, C = 1 << 20, 2 << 40, 3 << 40
+    st = mf.lib.mf_fastmm_noalloc(w.handle, 1, 0, ctypes.c_void_p(A), ctypes.c_void_p(B), ctypes.c_void_p(C), n,
+                                  mf.MF_F64, None)
+    assert st == mf.MF_ERR_SHAPE
+    assert "scratch" in mf.lib.mf_last_error().decode()

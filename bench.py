@@ -6,7 +6,7 @@ the fast FP64 product (Strassen-Winograd, depth 3) at n = 8192, next to the
 library's own classical FP64 MFMA GEMM, with inputs resident in HBM.  One
 step is one whole product C = A B: pre-additions, the grouped GEMM of the 343
 leaf products, post-additions.  The default schedule runs depth 3 as one
-level of the algorithm's Kronecker cube <8,8,8;343> (--schedule fused);
+level of the algorithm's Kronecker cube <8,8,8;343> (--schedule kron);
 --schedule levels runs three levels of <2,2,2;7>, and --depth 2 the square
 <4,4,4;49>.
 
@@ -66,10 +66,12 @@ def parse():
     ap.add_argument("--algo", default="winograd")
     ap.add_argument("--depth", type=int, default=3)
     ap.add_argument("--cutoff", type=int, default=0)
-    ap.add_argument("--schedule", choices=("fused", "levels"), default="fused",
-                    help="fused: the depth-d power of the algorithm (Kronecker construction) as one level; "
+    ap.add_argument("--schedule", choices=("kron", "levels"), default="kron",
+                    help="kron: the depth-d power of the algorithm (Kronecker construction) as one level; "
                          "levels: d levels of the algorithm")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", dest="variants", action="store_false",
+                    help="square workload: skip the depth-1/2 and fused-schedule variants")
     ap.add_argument("--workload", choices=("square", "batched", "serving", "precision", "algorithms", "copy"),
                     default="square")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per arrival rate")
@@ -172,7 +174,7 @@ def run_square(args):
     algo = mf.mf_algo_builtin(args.algo)
     # schedule: d levels of the algorithm, or its d-th Kronecker power run as one level
     exec_algo, exec_depth = algo, args.depth
-    if args.schedule == "fused" and args.depth > 1:
+    if args.schedule == "kron" and args.depth > 1:
         for _ in range(args.depth - 1):
             exec_algo = mf.mf_algo_compose(exec_algo, algo)
         exec_depth = 1
@@ -231,7 +233,35 @@ def run_square(args):
         cb, err = cpu_baseline(args, A_host, B_host, C_host)
         out["cpu_baseline"] = cb
         out["rel_err"] = float(f"{err:.3e}")
+    if args.variants:
+        out["variants"] = square_variants(args, mf, timed, algo, A, B, A_host, B_host, classical_ms)
     print(json.dumps(out), flush=True)
+
+
+def square_variants(args, mf, timed, algo, A, B, A_host, B_host, classical_ms):
+    """The same product at depth 1 and 2 (stored schedule level by level, the
+    fused-operand schedule at depth 1, depth 2 as one level of the squared
+    algorithm): ms, speedup over the classical GEMM and the error on 64
+    sampled rows against the oracle's definition rows."""
+    import numpy as np
+    import torch
+
+    from oracle import matmul as om
+
+    n = args.n
+    rows = np.sort(np.random.default_rng(6).choice(n, size=64, replace=False))
+    ref = om.rows_reference(A_host, B_host, rows)
+    sq = mf.mf_algo_compose(algo, algo)
+    C2 = torch.empty_like(A)
+    out = {}
+    for key, al, d, sched in (("d1", algo, 1, 0), ("d1_fused", algo, 1, mf.MF_SCHED_FUSED), ("d2_levels", algo, 2, 0),
+                              ("d2_squared", sq, 1, 0)):
+        ms = timed(lambda: mf.mf_fastmm(al, d, args.cutoff, A, B, C2, leaf=sched), max(3, args.steps // 2), 2)
+        got = C2[torch.from_numpy(rows).to(A.device)].cpu().numpy()
+        out[key] = {"ms": round(ms, 4), "gflops": round(2.0 * n ** 3 / (ms * 1e-3) / 1e9, 1),
+                    "speedup_vs_classical": round(classical_ms / ms, 4),
+                    "rel_err": float(f"{om.rel_fro_error(got, ref):.3e}")}
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -687,6 +717,11 @@ def run_algorithms(args):
     cases += [("<4,4,4;49> d1", c444, 1), ("<8,8,8;343> d1 (Kronecker-fused depth 3)", c888, 1),
               ("rebased strassen d1", rebased, 1), ("rebased strassen d2", rebased, 2),
               ("<3,3,3;27> d1 (control)", c3, 1)]
+    # the fused-operand schedule: pre-additions in the GEMM operand load,
+    # post-additions in its epilogue (one level)
+    cases += [("strassen d1 fused", stras, 1, mf.MF_SCHED_FUSED), ("winograd d1 fused", wino, 1, mf.MF_SCHED_FUSED),
+              ("<4,4,4;49> d1 fused", c444, 1, mf.MF_SCHED_FUSED)]
+    cases = [c if len(c) == 4 else (*c, 0) for c in cases]
     results = []
     for n in (4096, 8192):
         Ah, Bh = mi.uniform(n, 10), mi.uniform(n, 11)
@@ -694,12 +729,12 @@ def run_algorithms(args):
         C = torch.empty_like(A)
         rows = sampled_rows(n, 4)
         ref = om.rows_reference(Ah, Bh, rows)
-        for name, al, d in cases:
+        for name, al, d, sched in cases:
             if al is None:
                 ms, ph = phase_run(mf, timed, lambda: mf.mf_classical_mm(A, B, C), args.steps, 2)
             else:
-                ms, ph = phase_run(mf, timed, lambda: mf.mf_fastmm(al, d, 0, A, B, C), args.steps, 2)
-            q = mf.mf_plan_query(al, d, 0, n)
+                ms, ph = phase_run(mf, timed, lambda: mf.mf_fastmm(al, d, 0, A, B, C, leaf=sched), args.steps, 2)
+            q = mf.mf_plan_query(al, d, 0, n, mf.MF_F64 | sched)
             Cr = C[torch.from_numpy(rows).to(dev)].cpu().numpy()
             gemm_tf = q["gemm_flops"] / (ph[1] * 1e-3) / 1e12
             rec = {"n": n, "case": name, "ms": round(ms, 4), "gflops": round(2.0 * n ** 3 / (ms * 1e-3) / 1e9, 1),
@@ -725,8 +760,9 @@ def run_algorithms(args):
         "data": "synthetic",
         "config": {"workload": "algorithms: FP64 n 4096 and 8192, uniform[-1,1] (seeds 10, 11); Strassen (paper "
                                "form), Strassen-Winograd d1-3, <4,4,4;49> = Winograd composed with itself, Strassen "
-                               "re-based by unimodular X, Y, Z (seeds 7, 8, 9), classical <3,3,3;27> control; error "
-                               "on 64 sampled rows vs the oracle", "best_at_8192": best["case"]},
+                               "re-based by unimodular X, Y, Z (seeds 7, 8, 9), classical <3,3,3;27> control, and the "
+                               "fused-operand schedule at depth 1; error on 64 sampled rows vs the oracle",
+                   "best_at_8192": best["case"]},
         "results": results,
         "roofline": {"bound": "mfma", "achieved": best["gemm_tflops"], "peak": FP64_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": best["gemm_frac"], "traffic": None,

@@ -69,7 +69,19 @@ enum {
   MF_LEAF_NATIVE = 0 << 8,  /* leaves in the storage type (FP64 or FP32 MFMA) */
   MF_LEAF_F32 = 1 << 8,     /* FP32 MFMA leaves (FP32 storage only) */
   MF_LEAF_BF16 = 2 << 8,    /* BF16 MFMA, FP32 accumulation (FP32 storage only) */
-  MF_LEAF_BF16X3 = 3 << 8   /* split-BF16 x3 compensated products, FP32 accumulation (FP32 storage only) */
+  MF_LEAF_BF16X3 = 3 << 8,  /* split-BF16 x3 compensated products, FP32 accumulation (FP32 storage only) */
+  /* Schedule (third byte).  Default: the pre-additions run as linear-
+   * combination launches that store each combined operand, every leaf
+   * product is stored, and the post-additions run as launches after the
+   * GEMM.  MF_SCHED_FUSED: one level of the algorithm (compose it for a
+   * deeper split) with the pre-additions done inside the GEMM's operand load
+   * (each operand tile summed from its <= 16 block terms in registers before
+   * the LDS store) and the post-additions in the GEMM epilogue (a workgroup
+   * runs every product at its tile position of all C blocks, in product
+   * order: the first product feeding a block stores, later ones add), so no
+   * workspace and no addition launches.  Leaves in the storage type only
+   * (MF_ERR_UNSUPPORTED otherwise, and for more levels or more terms). */
+  MF_SCHED_FUSED = 1 << 16
 };
 
 /* Row convention of W handed to mf_algo_from_uvw. */

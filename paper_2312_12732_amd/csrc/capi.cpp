@@ -56,7 +56,7 @@ mf_status check_request(const mf_algo* algo, bool need_algo, int depth, int cuto
   if (n < 0) return fail(MF_ERR_ARG, "n must be >= 0");
   if (n > kMaxN) return fail(MF_ERR_SHAPE, "n exceeds the supported maximum (2^20)");
   const int storage = dtype & 0xff, leaf = (dtype >> 8) & 0xff;
-  if ((dtype & ~0xffff) != 0 || (storage != MF_F64 && storage != MF_F32) || leaf > 3)
+  if ((dtype & ~(0xffff | MF_SCHED_FUSED)) != 0 || (storage != MF_F64 && storage != MF_F32) || leaf > 3)
     return fail(MF_ERR_ARG, "unknown dtype code");
   if (storage == MF_F64 && leaf != 0)
     return fail(MF_ERR_UNSUPPORTED, "reduced-precision leaves need FP32 storage");
@@ -482,7 +482,8 @@ mf_status mf_gemm(const mf_algo* algo, int depth, int cutoff, int64_t M, int64_t
   if (depth > 0 && !algo) return fail(MF_ERR_ARG, "algo is NULL with depth > 0");
   if (depth < 0 || cutoff < 0) return fail(MF_ERR_ARG, "depth and cutoff must be >= 0");
   if (M < 0 || N < 0 || K < 0) return fail(MF_ERR_ARG, "M, N, K must be >= 0");
-  if (dtype != MF_F64 && dtype != MF_F32)
+  const int base = dtype & ~MF_SCHED_FUSED;
+  if ((base != MF_F64 && base != MF_F32))
     return fail(MF_ERR_UNSUPPORTED, "mf_gemm takes MF_F64 or MF_F32 with leaves in the storage type");
   if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(MF_ERR_ARG, "alpha and beta must be finite");
   if (M == 0 || N == 0) return MF_OK;
@@ -491,7 +492,7 @@ mf_status mf_gemm(const mf_algo* algo, int depth, int cutoff, int64_t M, int64_t
   if (lda < K || ldb < N || ldc < N) return fail(MF_ERR_ARG, "leading dimensions must be >= the row lengths");
   if (lda > INT32_MAX || ldb > INT32_MAX || ldc > INT32_MAX) return fail(MF_ERR_SHAPE, "leading dimensions exceed 2^31 - 1");
   if (!A || !B || !C) return fail(MF_ERR_ARG, "A, B and C must be non-NULL");
-  const size_t elem = dtype == MF_F64 ? 8 : 4;
+  const size_t elem = base == MF_F64 ? 8 : 4;
   if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(C)) & (elem - 1))
     return fail(MF_ERR_ARG, "A, B and C must be aligned to the element size");
   const size_t ba = ((size_t)(M - 1) * lda + K) * elem, bb = ((size_t)(K - 1) * ldb + N) * elem,

@@ -17,6 +17,7 @@ struct GemmArgs {
   const ProdDesc* prods;
   const EpiDesc* epis;
   const int32_t* group_beg;  // products of group g: [group_beg[g], group_beg[g+1])
+  const TermDesc* terms;     // fused-operand plans: operand terms
   int groups;
   int m;        // rows M of every leaf product
   int n, k;     // its columns N and inner size K (both m for square plans)

@@ -155,10 +155,8 @@ __device__ __forceinline__ void load_tiles_interior(const T* __restrict__ pa, in
 }
 
 template <class T, class Cfg>
-__device__ __forceinline__ void load_tiles_masked(const T* __restrict__ pa, int lda, int a_vr, int a_vc,
-                                                  const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0,
-                                                  int j0, int k0, int t, typename Mfma<T>::v2 (&ra)[Cfg::LPT_A],
-                                                  typename Mfma<T>::v2 (&rb)[Cfg::LPT_B]) {
+__device__ __forceinline__ void load_a_masked(const T* __restrict__ pa, int lda, int a_vr, int a_vc, int i0, int k0,
+                                              int t, typename Mfma<T>::v2 (&ra)[Cfg::LPT_A]) {
   typedef typename Mfma<T>::v2 v2;
 #pragma unroll
   for (int q = 0; q < Cfg::LPT_A; ++q) {
@@ -172,6 +170,12 @@ __device__ __forceinline__ void load_tiles_masked(const T* __restrict__ pa, int 
     }
     ra[q] = v;
   }
+}
+
+template <class T, class Cfg>
+__device__ __forceinline__ void load_b_masked(const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int j0, int k0,
+                                              int t, typename Mfma<T>::v2 (&rb)[Cfg::LPT_B]) {
+  typedef typename Mfma<T>::v2 v2;
 #pragma unroll
   for (int q = 0; q < Cfg::LPT_B; ++q) {
     int kr, cp;
@@ -184,6 +188,15 @@ __device__ __forceinline__ void load_tiles_masked(const T* __restrict__ pa, int 
     }
     rb[q] = v;
   }
+}
+
+template <class T, class Cfg>
+__device__ __forceinline__ void load_tiles_masked(const T* __restrict__ pa, int lda, int a_vr, int a_vc,
+                                                  const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0,
+                                                  int j0, int k0, int t, typename Mfma<T>::v2 (&ra)[Cfg::LPT_A],
+                                                  typename Mfma<T>::v2 (&rb)[Cfg::LPT_B]) {
+  load_a_masked<T, Cfg>(pa, lda, a_vr, a_vc, i0, k0, t, ra);
+  load_b_masked<T, Cfg>(pb, ldb, b_vr, b_vc, j0, k0, t, rb);
 }
 
 template <class T, class Cfg>
@@ -265,6 +278,34 @@ __device__ __forceinline__ void k_loop(T* lds, const T* __restrict__ pa, int lda
   }
 }
 
+// Epilogue of one product: post-addition of the accumulator tile into every
+// output block the product feeds (first feeder stores, later ones add).
+template <class T, class Cfg, bool FULL>
+__device__ __forceinline__ void product_epilogue(const GemmArgs<T>& g, const ProdDesc& pd, int i0, int j0, int wm,
+                                                 int wn, int lr, int lk,
+                                                 const typename Mfma<T>::v4 (&acc)[Cfg::WM_T][Cfg::WN_T]) {
+  constexpr int BM = Cfg::BM, BN = Cfg::BN, WM_T = Cfg::WM_T, WN_T = Cfg::WN_T;
+  for (int e = pd.epi_beg; e < pd.epi_end; ++e) {
+    const EpiDesc ed = load_uniform(g.epis + e);
+    T* pc = dst_ptr(g, ed.c_src) + ed.c_off;
+    const bool full = FULL || ((i0 + BM <= ed.c_vr) && (j0 + BN <= ed.c_vc));
+    const bool to_c = g.scale_c && ed.c_src == SRC_C;
+    const T coef = to_c ? (T)ed.coef * g.alpha : (T)ed.coef;
+    const T beta = to_c ? g.beta : T(0);
+#pragma unroll
+    for (int mi = 0; mi < WM_T; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < WN_T; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = i0 + wm + 16 * mi + Mfma<T>::row(lk, v);
+          const int col = j0 + wn + 16 * ni + lr;
+          if (full || (row < ed.c_vr && col < ed.c_vc))
+            epi_apply<T>(pc + (size_t)row * ed.ldc + col, ed.first, coef, acc[mi][ni][v], beta);
+        }
+  }
+}
+
 // One work item of the grouped GEMM: tile (ti, tj) of every product of group
 // grp, in product order, each followed by its epilogue post-additions.
 // FULL: the host has checked that every operand view and every epilogue
@@ -304,26 +345,160 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
       k_loop<T, Cfg, true>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
                       lk, acc);
 
-    // Epilogue: post-addition into every output block this product feeds.
-    for (int e = pd.epi_beg; e < pd.epi_end; ++e) {
-      const EpiDesc ed = load_uniform(g.epis + e);
-      T* pc = dst_ptr(g, ed.c_src) + ed.c_off;
-      const bool full = FULL || ((i0 + BM <= ed.c_vr) && (j0 + BN <= ed.c_vc));
-      const bool to_c = g.scale_c && ed.c_src == SRC_C;
-      const T coef = to_c ? (T)ed.coef * g.alpha : (T)ed.coef;
-      const T beta = to_c ? g.beta : T(0);
+    product_epilogue<T, Cfg, FULL>(g, pd, i0, j0, wm, wn, lr, lk, acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused operands: one level's pre-addition done in the operand load.  The A
+// operand tile of a product is sum_t c_t X_t over its terms (views of
+// quarters of A); every term's tile of the next K step is loaded into
+// registers while the current step's MFMAs run, and the terms are summed just
+// before the LDS store, in term order (the first term scaled, or copied for
+// a coefficient of 1, then fused multiply-adds) as the combination kernels
+// do, so the operand equals the materialised one bit for bit.  So for B.
+// ---------------------------------------------------------------------------
+
+template <class T, int NT>
+struct FusedOperand {
+  int n;            // terms, 1..NT
+  int64_t off[NT];  // view origins (elements from the source base)
+  T coef[NT];
+  int vr[NT], vc[NT];
+};
+
+template <class T, int NT>
+__device__ __forceinline__ FusedOperand<T, NT> fused_operand(const TermDesc* terms, int beg, int n) {
+  FusedOperand<T, NT> f;
+  f.n = n;
 #pragma unroll
-      for (int mi = 0; mi < WM_T; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < WN_T; ++ni)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = i0 + wm + 16 * mi + Mfma<T>::row(lk, v);
-            const int col = j0 + wn + 16 * ni + lr;
-            if (full || (row < ed.c_vr && col < ed.c_vc))
-              epi_apply<T>(pc + (size_t)row * ed.ldc + col, ed.first, coef, acc[mi][ni][v], beta);
-          }
+  for (int u = 0; u < NT; ++u) {
+    f.off[u] = 0;
+    f.coef[u] = T(0);
+    f.vr[u] = f.vc[u] = 0;
+    if (u < n) {
+      const TermDesc td = load_uniform(terms + beg + u);
+      f.off[u] = td.off;
+      f.coef[u] = (T)td.coef;
+      f.vr[u] = td.vr;
+      f.vc[u] = td.vc;
     }
+  }
+  return f;
+}
+
+template <class T, int NT, int L>
+__device__ __forceinline__ void sum_terms(const FusedOperand<T, NT>& f, const typename Mfma<T>::v2 (&x)[NT][L],
+                                          typename Mfma<T>::v2 (&r)[L]) {
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    r[q] = f.coef[0] == T(1) ? x[0][q] : f.coef[0] * x[0][q];
+#pragma unroll
+    for (int u = 1; u < NT; ++u)
+      if (u < f.n) {
+        r[q].x = fma_t(f.coef[u], x[u][q].x, r[q].x);
+        r[q].y = fma_t(f.coef[u], x[u][q].y, r[q].y);
+      }
+  }
+}
+
+template <class T, class Cfg, int NT, bool MASKED>
+__device__ __forceinline__ void k_loop_fused(T* lds, const T* __restrict__ pa, int lda, const FusedOperand<T, NT>& fa,
+                                             const T* __restrict__ pb, int ldb, const FusedOperand<T, NT>& fb, int i0,
+                                             int j0, int KT, int t, int wm, int wn, int lr, int lk,
+                                             typename Mfma<T>::v4 (&acc)[Cfg::WM_T][Cfg::WN_T]) {
+  typedef typename Mfma<T>::v2 v2;
+  constexpr int WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, BK = Cfg::BK;
+  v2 xa[NT][Cfg::LPT_A], xb[NT][Cfg::LPT_B];
+  v2 ra[Cfg::LPT_A], rb[Cfg::LPT_B];
+  LaneOffsets<Cfg> o;
+  if constexpr (!MASKED) o = lane_offsets<T, Cfg>(lda, ldb, t);
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      if (u < fa.n) {
+        if constexpr (MASKED) {
+          load_a_masked<T, Cfg>(pa + fa.off[u], lda, fa.vr[u], fa.vc[u], i0, k0, t, xa[u]);
+        } else {
+          const __amdgpu_buffer_rsrc_t sa = raw_rsrc(pa + fa.off[u] + (size_t)i0 * lda + k0);
+#pragma unroll
+          for (int q = 0; q < Cfg::LPT_A; ++q) xa[u][q] = buffer_pair<T>(sa, o.a[q]);
+        }
+      }
+      if (u < fb.n) {
+        if constexpr (MASKED) {
+          load_b_masked<T, Cfg>(pb + fb.off[u], ldb, fb.vr[u], fb.vc[u], j0, k0, t, xb[u]);
+        } else {
+          const __amdgpu_buffer_rsrc_t sb = raw_rsrc(pb + fb.off[u] + (size_t)k0 * ldb + j0);
+#pragma unroll
+          for (int q = 0; q < Cfg::LPT_B; ++q) xb[u][q] = buffer_pair<T>(sb, o.b[q]);
+        }
+      }
+    }
+  };
+  auto a_buf = [&](int b) { return lds + b * Cfg::LDS_A; };
+  auto b_buf = [&](int b) { return lds + 2 * Cfg::LDS_A + b * Cfg::LDS_B; };
+  load(0);
+  sum_terms<T, NT, Cfg::LPT_A>(fa, xa, ra);
+  sum_terms<T, NT, Cfg::LPT_B>(fb, xb, rb);
+  store_tiles<T, Cfg>(a_buf(0), b_buf(0), t, ra, rb);
+  __syncthreads();
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < KT;
+    if (more) load((kt + 1) * BK);
+    const T* As = a_buf(cur);
+    const T* Bs = b_buf(cur);
+    T f_a[2][WM_T], f_b[2][WN_T];
+    load_frags<T, Cfg>(As, Bs, 0, wm, wn, lr, lk, f_a[0], f_b[0]);
+#pragma unroll
+    for (int s = 0; s < BK / 4; ++s) {
+      if (s + 1 < BK / 4) load_frags<T, Cfg>(As, Bs, s + 1, wm, wn, lr, lk, f_a[(s + 1) & 1], f_b[(s + 1) & 1]);
+      mfma_step<T, Cfg>(f_a[s & 1], f_b[s & 1], acc);
+    }
+    if (more) {
+      sum_terms<T, NT, Cfg::LPT_A>(fa, xa, ra);
+      sum_terms<T, NT, Cfg::LPT_B>(fb, xb, rb);
+      store_tiles<T, Cfg>(a_buf(cur ^ 1), b_buf(cur ^ 1), t, ra, rb);
+    }
+    __syncthreads();
+  }
+}
+
+// A work item of a fused-operand plan (one group: all products of the level
+// at one tile position of every C block, in product order).  FULL: every
+// term covers its whole block with 16-byte aligned rows (host-checked).
+template <class T, class Cfg, int NT, bool FULL>
+__device__ __forceinline__ void gemm_tile_fused(const GemmArgs<T>& g, int grp, int ti, int tj, T* lds) {
+  typedef typename Mfma<T>::v4 v4;
+  constexpr int BM = Cfg::BM, BN = Cfg::BN, WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, WAVES_N = Cfg::WAVES_N;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = (wave / WAVES_N) * (16 * WM_T), wn = (wave % WAVES_N) * (16 * WN_T);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int i0 = ti * BM, j0 = tj * BN;
+  const int KT = g.k / Cfg::BK;
+  const int r_beg = load_uniform(g.group_beg + grp), r_end = load_uniform(g.group_beg + grp + 1);
+  for (int r = r_beg; r < r_end; ++r) {
+    const ProdDesc pd = load_uniform(g.prods + r);
+    const FusedOperand<T, NT> fa = fused_operand<T, NT>(g.terms, pd.a_term0, pd.a_terms);
+    const FusedOperand<T, NT> fb = fused_operand<T, NT>(g.terms, pd.b_term0, pd.b_terms);
+    v4 acc[WM_T][WN_T];
+#pragma unroll
+    for (int mi = 0; mi < WM_T; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < WN_T; ++ni) acc[mi][ni] = v4{T(0), T(0), T(0), T(0)};
+    bool interior = FULL || g.vec_in;
+    if (!FULL)
+      for (int u = 0; u < NT; ++u) {
+        if (u < fa.n) interior = interior && i0 + BM <= fa.vr[u] && fa.vc[u] >= g.k;
+        if (u < fb.n) interior = interior && fb.vr[u] >= g.k && j0 + BN <= fb.vc[u];
+      }
+    if (interior)
+      k_loop_fused<T, Cfg, NT, false>(lds, g.A, pd.lda, fa, g.B, pd.ldb, fb, i0, j0, KT, t, wm, wn, lr, lk, acc);
+    else if constexpr (!FULL)
+      k_loop_fused<T, Cfg, NT, true>(lds, g.A, pd.lda, fa, g.B, pd.ldb, fb, i0, j0, KT, t, wm, wn, lr, lk, acc);
+    product_epilogue<T, Cfg, FULL>(g, pd, i0, j0, wm, wn, lr, lk, acc);
   }
 }
 

@@ -113,6 +113,7 @@ __device__ __forceinline__ void run_gemm(const BatchArgs& g, const BatchTask& tk
   a.prods = gr.prods;
   a.epis = gr.epis;
   a.group_beg = gr.group_beg;
+  a.terms = nullptr;
   a.groups = gr.groups;
   a.m = a.n = a.k = gr.m;
   a.tiles_m = gr.tiles;

@@ -351,6 +351,7 @@ GemmArgs<float> bf_args(const Plan& pl, const char* desc, const void* A, const v
   g.group_beg = img_at<int32_t>(desc, pl.img_group_beg);
   g.groups = pl.groups;
   g.m = g.n = g.k = (int)pl.m;
+  g.terms = nullptr;
   g.scale_c = 0;
   g.alpha = 1.0f;
   g.beta = 0.0f;

@@ -23,6 +23,51 @@ __global__ void __launch_bounds__(Cfg::NTHREADS, Cfg::WAVES_PER_SIMD) gemm_group
   gemm_tile<T, Cfg, FULL>(g, grp, ti, tj, lds);
 }
 
+// Fused-operand plans: the same tile on a register budget of two waves per
+// SIMD (one workgroup per CU), so that the loads of every operand term stay
+// in flight during the MFMAs of the previous K step.
+using Tile128F = TileCfg<128, 128, 2, 4, 2>;
+
+template <class T, class Cfg, int NT, bool FULL>
+__global__ void __launch_bounds__(Cfg::NTHREADS, Cfg::WAVES_PER_SIMD) gemm_fused(GemmArgs<T> g) {
+  __shared__ T lds[Cfg::LDS_ELEMS];
+  int grp, ti, tj;
+  work_of(blockIdx.x, g.tiles_m, g.tiles_n, g.groups, &grp, &ti, &tj);
+  gemm_tile_fused<T, Cfg, NT, FULL>(g, grp, ti, tj, lds);
+}
+
+// Whether every term of a fused-operand plan covers its whole block with
+// 16-byte aligned rows and every epilogue output its whole block.
+static bool fused_full(const Plan& pl, size_t elem, bool vec_in) {
+  if (!vec_in || (pl.shape.lda * (int64_t)elem) % 16 || (pl.shape.ldb * (int64_t)elem) % 16) return false;
+  for (const ProdDesc& pd : pl.prods) {
+    for (int u = 0; u < pd.a_terms; ++u) {
+      const TermDesc& td = pl.terms[(size_t)pd.a_term0 + u];
+      if (td.vr < pl.m || td.vc < pl.leaf_k || (td.off * (int64_t)elem) % 16) return false;
+    }
+    for (int u = 0; u < pd.b_terms; ++u) {
+      const TermDesc& td = pl.terms[(size_t)pd.b_term0 + u];
+      if (td.vr < pl.leaf_k || td.vc < pl.leaf_n || (td.off * (int64_t)elem) % 16) return false;
+    }
+  }
+  for (const EpiDesc& ed : pl.epis)
+    if (ed.c_vr < pl.m || ed.c_vc < pl.leaf_n) return false;
+  return true;
+}
+
+template <class T, int NT>
+static hipError_t launch_fused(GemmArgs<T> g, bool full, hipStream_t s) {
+  using Cfg = Tile128F;
+  g.tiles_m = g.m / Cfg::BM;
+  g.tiles_n = g.n / Cfg::BN;
+  const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n * (unsigned)g.groups;
+  if (full)
+    hipLaunchKernelGGL((gemm_fused<T, Cfg, NT, true>), dim3(grid), dim3(Cfg::NTHREADS), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm_fused<T, Cfg, NT, false>), dim3(grid), dim3(Cfg::NTHREADS), 0, s, g);
+  return hipGetLastError();
+}
+
 // Whether every operand view and epilogue output of the plan covers its whole
 // m x m block with 16-byte aligned rows (then the kernel without the masked
 // paths runs; true for sizes the splits divide into whole tiles).
@@ -61,6 +106,7 @@ static hipError_t launch_gemm_t(const Plan& pl, const char* desc, const void* A,
   g.prods = img_at<ProdDesc>(desc, pl.img_prods);
   g.epis = img_at<EpiDesc>(desc, pl.img_epis);
   g.group_beg = img_at<int32_t>(desc, pl.img_group_beg);
+  g.terms = img_at<TermDesc>(desc, pl.img_terms);
   g.groups = pl.groups;
   g.m = (int)pl.m;
   g.n = (int)pl.leaf_n;
@@ -69,6 +115,12 @@ static hipError_t launch_gemm_t(const Plan& pl, const char* desc, const void* A,
   g.scale_c = sc.plain() ? 0 : 1;
   g.alpha = (T)sc.alpha;
   g.beta = (T)sc.beta;
+  if (pl.fused_terms > 0) {
+    const bool full = fused_full(pl, sizeof(T), vec_in);
+    if (pl.fused_terms <= 4) return launch_fused<T, 4>(g, full, s);
+    if (pl.fused_terms <= 16) return launch_fused<T, 16>(g, full, s);
+    return hipErrorInvalidValue;
+  }
   return launch_cfg<T, Tile128>(g, plan_full(pl, sizeof(T), vec_in), s);
 }
 

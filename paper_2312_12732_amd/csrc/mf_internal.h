@@ -83,6 +83,19 @@ struct ProdDesc {
   int32_t a_vr, a_vc;        // valid rows / columns of the A view
   int32_t b_vr, b_vc;        // valid rows / columns of the B view
   int32_t epi_beg, epi_end;  // range in the epilogue list
+  // Fused-operand plans: the A operand is sum_t coef_t X_t over a_terms
+  // views X_t = terms[a_term0 + t] of the A source (the pre-addition done in
+  // the operand load), and so for B; 0 terms: the single view above.
+  int32_t a_terms, b_terms;
+  int32_t a_term0, b_term0;
+};
+
+// One term of a fused operand: coef times the view of its product's source
+// at `off` with leading dimension lda (ldb), valid over vr x vc.
+struct TermDesc {
+  int64_t off;
+  double coef;
+  int32_t vr, vc;
 };
 
 // One post-addition term of the GEMM epilogue: output block (dst, offset,
@@ -217,6 +230,8 @@ struct Plan {
   size_t ws_bytes = 0;
   std::vector<ProdDesc> prods;   // ordered by group
   std::vector<EpiDesc> epis;
+  std::vector<TermDesc> terms;   // fused-operand plans: operand terms
+  int fused_terms = 0;           // most terms of any fused operand (0: not fused)
   std::vector<int32_t> group_beg;  // groups + 1 entries
   std::vector<CombineStage> pre, post;  // in launch order
   // BF16 leaves: every leaf operand is staged once as BF16 (two planes, hi
@@ -238,7 +253,7 @@ struct Plan {
   // when the plan is built; the kernels get the device address of a copy of
   // it (the plan's own, or one the caller's call placed elsewhere).
   std::vector<char> image;
-  size_t img_prods = 0, img_epis = 0, img_group_beg = 0;
+  size_t img_prods = 0, img_epis = 0, img_group_beg = 0, img_terms = 0;
   size_t img_bf_sets = 0, img_bf_ins = 0, img_bf_outs = 0, img_bf_coef = 0;
   // the plan's own device copy of the image (one allocation, owned by the
   // plan), made on first use

@@ -207,6 +207,121 @@ mf_status build_classical(const Shape& sh, Plan* pl) {
   return MF_OK;
 }
 
+// Fused-operand plan of one level of `al` (the schedule bit MF_SCHED_FUSED):
+// no pre-addition stage and no workspace.  Product r's operands are the term
+// lists of columns r of U and V over the blocks of A and B (the pre-addition
+// is done in the GEMM's operand load), and its epilogue adds W[c, r] times
+// the product into every block c of C it feeds; products run in index order
+// within one group, so each workgroup owns one tile position of every C
+// block and its read-modify-writes are ordered (the first product feeding a
+// block stores).
+mf_status build_fused(const Algo& al, const Shape& sh, Plan* pl) {
+  const int m0 = al.m0, k0 = al.k0, n0 = al.n0, R = al.R;
+  pl->levels = 1;
+  pl->levels_outer = 0;
+  pl->groups = 1;
+  pl->P = m0;
+  pl->P_outer = 1;
+  pl->R = R;
+  pl->m = round_up((sh.M + m0 - 1) / m0, kLeafTile);
+  pl->leaf_n = round_up((sh.N + n0 - 1) / n0, kLeafTile);
+  pl->leaf_k = round_up((sh.K + k0 - 1) / k0, kLeafTile);
+  pl->npad = pl->m * m0;
+  pl->m_outer = pl->m * m0;
+  const int64_t m = pl->m, mn = pl->leaf_n, mk = pl->leaf_k;
+  Blk top[2];
+  for (int side = 0; side < 2; ++side) {
+    top[side].src = side == 0 ? SRC_A : SRC_B;
+    top[side].ld = (int32_t)(side == 0 ? sh.lda : sh.ldb);
+    top[side].vr = (int32_t)(side == 0 ? sh.M : sh.K);
+    top[side].vc = (int32_t)(side == 0 ? sh.K : sh.N);
+    top[side].zero = false;
+  }
+  std::vector<Blk> qa(m0 * k0), qb(k0 * n0);
+  for (int k = 0; k < m0 * k0; ++k) qa[k] = quarter(top[0], k, k0, m, mk);
+  for (int k = 0; k < k0 * n0; ++k) qb[k] = quarter(top[1], k, n0, mk, mn);
+  auto terms_of = [&](const std::vector<double>& X, const std::vector<Blk>& q, int r, int32_t* beg) {
+    *beg = (int32_t)pl->terms.size();
+    int n = 0;
+    for (size_t k = 0; k < q.size(); ++k) {
+      const double x = X[k * R + r];
+      if (x == 0.0 || q[k].zero) continue;
+      pl->terms.push_back(TermDesc{q[k].off, x, q[k].vr, q[k].vc});
+      ++n;
+    }
+    return n;
+  };
+  const int nout = m0 * n0;
+  std::vector<char> written(nout, 0);
+  auto out_view = [&](int c, EpiDesc* ed) {
+    const int64_t r0 = (int64_t)(c / n0) * m, c0 = (int64_t)(c % n0) * mn;
+    ed->c_src = SRC_C;
+    ed->ldc = (int32_t)sh.ldc;
+    ed->c_vr = (int32_t)std::max<int64_t>(0, std::min<int64_t>(m, sh.M - r0));
+    ed->c_vc = (int32_t)std::max<int64_t>(0, std::min<int64_t>(mn, sh.N - c0));
+    if (ed->c_vr == 0 || ed->c_vc == 0) ed->c_vr = ed->c_vc = 0;
+    ed->c_off = ed->c_vr > 0 ? r0 * sh.ldc + c0 : 0;
+  };
+  pl->group_beg.push_back(0);
+  for (int r = 0; r < R; ++r) {
+    ProdDesc pd{};
+    const size_t terms_before = pl->terms.size();
+    pd.a_terms = terms_of(al.U, qa, r, &pd.a_term0);
+    pd.b_terms = terms_of(al.V, qb, r, &pd.b_term0);
+    if (pd.a_terms == 0 || pd.b_terms == 0) {  // a zero product
+      pl->terms.resize(terms_before);
+      continue;
+    }
+    pl->fused_terms = std::max(pl->fused_terms, std::max(pd.a_terms, pd.b_terms));
+    const TermDesc& ta = pl->terms[(size_t)pd.a_term0];
+    const TermDesc& tb = pl->terms[(size_t)pd.b_term0];
+    pd.a_src = SRC_A;
+    pd.a_off = ta.off;
+    pd.lda = (int32_t)sh.lda;
+    pd.a_vr = ta.vr;
+    pd.a_vc = ta.vc;
+    pd.b_src = SRC_B;
+    pd.b_off = tb.off;
+    pd.ldb = (int32_t)sh.ldb;
+    pd.b_vr = tb.vr;
+    pd.b_vc = tb.vc;
+    pd.epi_beg = (int32_t)pl->epis.size();
+    for (int c = 0; c < nout; ++c) {
+      const double w = al.w(c, r);
+      if (w == 0.0) continue;
+      EpiDesc ed{};
+      out_view(c, &ed);
+      if (ed.c_vr == 0) continue;
+      ed.first = written[c] ? 0 : 1;
+      ed.coef = w;
+      written[c] = 1;
+      pl->epis.push_back(ed);
+    }
+    pd.epi_end = (int32_t)pl->epis.size();
+    pl->prods.push_back(pd);
+  }
+  if (pl->prods.empty()) return fail(MF_ERR_SHAPE, "plan has no products");
+  // C blocks that no product feeds (only through padding) are zero: the first
+  // product stores zeros there
+  for (int c = 0; c < nout; ++c) {
+    if (written[c]) continue;
+    EpiDesc ed{};
+    out_view(c, &ed);
+    if (ed.c_vr == 0) continue;
+    ed.first = 2;
+    const int at = pl->prods[0].epi_end;
+    pl->epis.insert(pl->epis.begin() + at, ed);
+    pl->prods[0].epi_end += 1;
+    for (size_t qd = 1; qd < pl->prods.size(); ++qd) {
+      pl->prods[qd].epi_beg += 1;
+      pl->prods[qd].epi_end += 1;
+    }
+  }
+  pl->group_beg.push_back((int32_t)pl->prods.size());
+  pl->ws_bytes = 0;
+  return MF_OK;
+}
+
 // Whether linear-combination kernels exist for one level of an algorithm:
 // m0 k0 inputs per A-side pre-addition set, k0 n0 per B-side set and R per
 // post-addition set.
@@ -258,6 +373,17 @@ mf_status build(const Algo* algo, int depth, int cutoff, const Shape& sh, int dt
   if (bf16_leaves(dtype) && !pl->square)
     return fail(MF_ERR_UNSUPPORTED, "BF16 leaves need square operands and a square algorithm");
   if (L == 0) return build_classical(sh, pl);
+  if (dtype & MF_SCHED_FUSED) {
+    if (bf16_leaves(dtype)) return fail(MF_ERR_UNSUPPORTED, "fused operands take leaves in the storage type");
+    if (L != 1 || is_kron3(*seq[0]))
+      return fail(MF_ERR_UNSUPPORTED,
+                  "fused operands run one level of an algorithm with at most 16 terms per operand "
+                  "(compose the algorithm for a deeper split)");
+    const mf_status st = build_fused(*seq[0], sh, pl);
+    if (st == MF_OK && pl->fused_terms > 16)
+      return fail(MF_ERR_UNSUPPORTED, "fused operands take at most 16 terms per operand");
+    return st;
+  }
 
   const bool kron3 = is_kron3(*seq[0]);
   int64_t Pm = 1, Pk = 1, Pn = 1;
@@ -674,6 +800,7 @@ void make_image(Plan* pl) {
   place(pl->prods.data(), bytes_of(pl->prods), &pl->img_prods);
   place(pl->epis.data(), bytes_of(pl->epis), &pl->img_epis);
   place(pl->group_beg.data(), bytes_of(pl->group_beg), &pl->img_group_beg);
+  place(pl->terms.data(), bytes_of(pl->terms), &pl->img_terms);
   place(pl->bf_sets.data(), bytes_of(pl->bf_sets), &pl->img_bf_sets);
   place(pl->bf_ins.data(), bytes_of(pl->bf_ins), &pl->img_bf_ins);
   place(pl->bf_outs.data(), bytes_of(pl->bf_outs), &pl->img_bf_outs);

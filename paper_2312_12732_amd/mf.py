@@ -30,6 +30,7 @@ MF_ERR_UNSUPPORTED = -6
 STATUS_NAMES = {0: "MF_OK", -1: "MF_ERR_ARG", -2: "MF_ERR_BRENT", -3: "MF_ERR_SHAPE", -4: "MF_ERR_NOMEM",
                 -5: "MF_ERR_HIP", -6: "MF_ERR_UNSUPPORTED"}
 
+MF_SCHED_FUSED = 1 << 16
 MF_BATCH_PHASES = 0
 MF_BATCH_PERSISTENT = 1
 MF_F64 = 1
@@ -300,9 +301,11 @@ def mf_fastmm_noalloc(algo: Algo, depth: int, cutoff: int, A, B, C, leaf: int = 
     return C
 
 
-def mf_gemm(algo, depth: int, cutoff: int, A, B, C, alpha: float = 1.0, beta: float = 0.0, stream=None):
+def mf_gemm(algo, depth: int, cutoff: int, A, B, C, alpha: float = 1.0, beta: float = 0.0, stream=None,
+            schedule: int = 0):
     """C = alpha A B + beta C for 2-d device tensors with unit column stride
-    (row-major views; the row strides are the leading dimensions)."""
+    (row-major views; the row strides are the leading dimensions); schedule:
+    0 or MF_SCHED_FUSED."""
     import torch
     for name, t in (("A", A), ("B", B), ("C", C)):
         if not t.is_cuda or t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
@@ -313,7 +316,7 @@ def mf_gemm(algo, depth: int, cutoff: int, A, B, C, alpha: float = 1.0, beta: fl
     K2, N = B.shape
     if K2 != K or tuple(C.shape) != (M, N):
         raise ValueError("shapes do not match C (M x N) = A (M x K) B (K x N)")
-    code = MF_F64 if A.dtype == torch.float64 else MF_F32
+    code = (MF_F64 if A.dtype == torch.float64 else MF_F32) | schedule
     ld = lambda t: max(t.stride(0), t.shape[1])  # noqa: E731
     _check(lib.mf_gemm(algo.handle if algo is not None else None, depth, cutoff, M, N, K, float(alpha),
                        ctypes.c_void_p(A.data_ptr()), ld(A), ctypes.c_void_p(B.data_ptr()), ld(B), float(beta),

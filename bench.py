@@ -636,10 +636,12 @@ def run_precision(args):
         sets = {"uniform": (mi.uniform(n, 20), mi.uniform(n, 21)),
                 "scaled": (mi.scaled(n, 22, 24, 25), mi.scaled(n, 23, 26, 27))}
         rows = sampled_rows(n, 3)
-        refs, dev_in = {}, {}
+        refs, dens, dev_in = {}, {}, {}
         for name, (A, B) in sets.items():
             A32, B32 = A.astype(np.float32), B.astype(np.float32)
             refs[name] = om.rows_reference(A32.astype(np.float64), B32.astype(np.float64), rows)
+            # (|A| |B|) on the sampled rows: the componentwise error's denominator
+            dens[name] = om.rows_reference(np.abs(A32).astype(np.float64), np.abs(B32).astype(np.float64), rows)
             dev_in[name] = (torch.from_numpy(A32).to(dev), torch.from_numpy(B32).to(dev))
         del sets
         C = torch.empty(n, n, dtype=torch.float32, device=dev)
@@ -662,6 +664,9 @@ def run_precision(args):
                     torch.cuda.synchronize()
                     Cr = C[torch.from_numpy(rows).to(dev)].cpu().numpy().astype(np.float64)
                     rec[f"err_{name}"] = float(f"{om.rel_fro_error(Cr, refs[name]):.3e}")
+                    # componentwise: max_ij |C^ - C|_ij / (|A| |B|)_ij over the sampled rows
+                    cw = np.abs(Cr - refs[name]) / np.where(dens[name] > 0, dens[name], 1.0)
+                    rec[f"cerr_{name}"] = float(f"{cw.max():.3e}")
                 results.append(rec)
                 print(json.dumps({"progress": rec}), file=sys.stderr, flush=True)
         del dev_in, C
@@ -678,8 +683,9 @@ def run_precision(args):
                                "Kronecker-fused (<4,4,4;49>) and, for FP32 leaves, depth 3 Kronecker-fused "
                                "(<8,8,8;343>); FP32 storage and additions, leaves "
                                "FP32 / BF16 / split-BF16x3; uniform[-1,1] (seeds 20, 21) and scaled D1 A0 D2 "
-                               "(A: seeds 22, 24, 25; B: 23, 26, 27); error on 64 sampled rows vs the FP64 oracle "
-                               "on the FP32-rounded inputs",
+                               "(A: seeds 22, 24, 25; B: 23, 26, 27); errors on 64 sampled rows vs the FP64 oracle "
+                               "on the FP32-rounded inputs: normwise err = ||C^-C||_F/||C||_F, componentwise "
+                               "cerr = max |C^-C| / (|A||B|)",
                    "headline": f"n={head['n']} {head['leaf']} depth {head['depth']} {head['schedule']}"},
         "results": results,
         "roofline": {"bound": "mfma", "achieved": head["mfma_tflops"],
@@ -721,6 +727,17 @@ def run_algorithms(args):
     # post-additions in its epilogue (one level)
     cases += [("strassen d1 fused", stras, 1, mf.MF_SCHED_FUSED), ("winograd d1 fused", wino, 1, mf.MF_SCHED_FUSED),
               ("<4,4,4;49> d1 fused", c444, 1, mf.MF_SCHED_FUSED)]
+    # split factor 6 in both orders (Section 2: 2 then 3 differs from 3 then
+    # 2 in temporary space and error): Winograd with the textbook <3,3,3;27>,
+    # and the 187-product algorithm from the non-square pieces <2,3,3;17>
+    # and <3,2,2;11> (direct sums of Strassen and textbook blocks)
+    hk = mf.mf_algo_concat(stras, mf.mf_algo_classical(2, 2, 1), "n")
+    r233 = mf.mf_algo_concat(hk, mf.mf_algo_classical(2, 1, 3), "k")
+    r322 = mf.mf_algo_concat(stras, mf.mf_algo_classical(1, 2, 2), "m")
+    cases += [("winograd x classical3 <6,6,6;189> d1", mf.mf_algo_compose(wino, c3), 1),
+              ("classical3 x winograd <6,6,6;189> d1", mf.mf_algo_compose(c3, wino), 1),
+              ("<2,3,3;17> x <3,2,2;11> = <6,6,6;187> d1", mf.mf_algo_compose(r233, r322), 1),
+              ("<3,2,2;11> x <2,3,3;17> = <6,6,6;187> d1", mf.mf_algo_compose(r322, r233), 1)]
     cases = [c if len(c) == 4 else (*c, 0) for c in cases]
     results = []
     for n in (4096, 8192):
@@ -739,7 +756,7 @@ def run_algorithms(args):
             gemm_tf = q["gemm_flops"] / (ph[1] * 1e-3) / 1e12
             rec = {"n": n, "case": name, "ms": round(ms, 4), "gflops": round(2.0 * n ** 3 / (ms * 1e-3) / 1e9, 1),
                    "rel_err": float(f"{om.rel_fro_error(Cr, ref):.3e}"), "leaf_m": q["leaf_m"],
-                   "products": q["products"],
+                   "products": q["products"], "workspace_bytes": q["ws_bytes"],
                    "phases_ms": [round(x, 4) for x in ph],
                    "gemm_tflops": round(gemm_tf, 2), "gemm_frac": round(gemm_tf / FP64_MFMA_PEAK_TFLOPS, 4),
                    "pre_gbs": round(q["pre_bytes"] / (ph[0] * 1e-3) / 1e9, 1) if ph[0] > 0 else None,

@@ -449,30 +449,34 @@ __device__ __forceinline__ void k_loop_fused(T* lds, const T* __restrict__ pa, i
   };
   auto a_buf = [&](int b) { return lds + b * Cfg::LDS_A; };
   auto b_buf = [&](int b) { return lds + 2 * Cfg::LDS_A + b * Cfg::LDS_B; };
+  constexpr int S = BK / 4;
   load(0);
   sum_terms<T, NT, Cfg::LPT_A>(fa, xa, ra);
   sum_terms<T, NT, Cfg::LPT_B>(fb, xb, rb);
   store_tiles<T, Cfg>(a_buf(0), b_buf(0), t, ra, rb);
   __syncthreads();
+  T f_a[2][WM_T], f_b[2][WN_T];
+  load_frags<T, Cfg>(a_buf(0), b_buf(0), 0, wm, wn, lr, lk, f_a[0], f_b[0]);
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < KT;
     if (more) load((kt + 1) * BK);
     const T* As = a_buf(cur);
     const T* Bs = b_buf(cur);
-    T f_a[2][WM_T], f_b[2][WN_T];
-    load_frags<T, Cfg>(As, Bs, 0, wm, wn, lr, lk, f_a[0], f_b[0]);
 #pragma unroll
-    for (int s = 0; s < BK / 4; ++s) {
-      if (s + 1 < BK / 4) load_frags<T, Cfg>(As, Bs, s + 1, wm, wn, lr, lk, f_a[(s + 1) & 1], f_b[(s + 1) & 1]);
+    for (int s = 0; s < S - 1; ++s) {
+      load_frags<T, Cfg>(As, Bs, s + 1, wm, wn, lr, lk, f_a[(s + 1) & 1], f_b[(s + 1) & 1]);
       mfma_step<T, Cfg>(f_a[s & 1], f_b[s & 1], acc);
     }
+    // the barrier in the shadow of the last k-step's MFMAs, as in k_loop
     if (more) {
       sum_terms<T, NT, Cfg::LPT_A>(fa, xa, ra);
       sum_terms<T, NT, Cfg::LPT_B>(fb, xb, rb);
       store_tiles<T, Cfg>(a_buf(cur ^ 1), b_buf(cur ^ 1), t, ra, rb);
     }
     __syncthreads();
+    if (more) load_frags<T, Cfg>(a_buf(cur ^ 1), b_buf(cur ^ 1), 0, wm, wn, lr, lk, f_a[S & 1], f_b[S & 1]);
+    mfma_step<T, Cfg>(f_a[(S - 1) & 1], f_b[(S - 1) & 1], acc);
   }
 }
 

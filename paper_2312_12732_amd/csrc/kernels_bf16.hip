@@ -172,46 +172,54 @@ using Cfg128 = BfCfg<128, 128, 2, 2>;
 using CfgSq = BfCfg<256, 256, 2, 4>;
 using CfgW = BfCfg<256, 128, 4, 2>;
 
+// LDS ring of NBUF K-step buffers: three for the one-workgroup-per-CU tiles
+// (96 / 144 KiB), two for Cfg128, whose two workgroups per CU share the LDS.
+template <class C>
+constexpr int nbuf() {
+  return C::MIN_BLOCKS == 1 ? 3 : 2;
+}
+
 template <class C, bool X3>
 struct Lds {
-  __bf16 a[2][X3 ? 2 : 1][C::BM * KS];  // [buffer][hi|lo][block order, as staged]
-  __bf16 b[2][X3 ? 2 : 1][C::BN * KS];
+  static constexpr int NBUF = nbuf<C>();
+  __bf16 a[NBUF][X3 ? 2 : 1][C::BM * KS];  // [buffer][hi|lo][block order, as staged]
+  __bf16 b[NBUF][X3 ? 2 : 1][C::BN * KS];
 };
 
 constexpr int PLANES_MAX = 2;
 
 // The operand tiles of one K step are contiguous in the staged planes and
-// in LDS (same block order): thread t moves 16-byte pieces t + NT q.
+// in LDS (same block order): thread t moves 16-byte pieces t + NT q.  They go
+// straight from memory to LDS (buffer_load ... lds, 16 bytes per lane: lane
+// l of a wave lands at the wave's LDS base + 16 l, measured on the device),
+// so no registers hold them and no LDS store instructions run.
 template <class C, bool X3>
-__device__ __forceinline__ void load_stage(const __bf16* a, const __bf16* b, int64_t plane, int m, int i0, int j0,
-                                           int k0, int t, bf8 (&ra)[PLANES_MAX][C::A_LOADS],
-                                           bf8 (&rb)[PLANES_MAX][C::B_LOADS]) {
+__device__ __forceinline__ void dma_stage(Lds<C, X3>& L, int buf, const __bf16* a, const __bf16* b, int64_t plane,
+                                          int m, int i0, int j0, int k0, int t) {
   constexpr int P = X3 ? 2 : 1;
   const int64_t kb = (int64_t)(k0 / BK) * (m / 16);
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // the LDS base is per wave
 #pragma unroll
   for (int pl = 0; pl < P; ++pl) {
     const __amdgpu_buffer_rsrc_t sa = raw_rsrc(a + pl * plane + (kb + i0 / 16) * (16 * BK));
     const __amdgpu_buffer_rsrc_t sb = raw_rsrc(b + pl * plane + (kb + j0 / 16) * (16 * BK));
 #pragma unroll
     for (int q = 0; q < C::A_LOADS; ++q)
-      ra[pl][q] = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(sa, (t + C::NT * q) * 16, 0, 0));
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(sa, &L.a[buf][pl][(64 * w + C::NT * q) * 8], 16,
+                                               (t + C::NT * q) * 16, 0, 0, 0);
 #pragma unroll
     for (int q = 0; q < C::B_LOADS; ++q)
-      rb[pl][q] = __builtin_bit_cast(bf8, __builtin_amdgcn_raw_buffer_load_b128(sb, (t + C::NT * q) * 16, 0, 0));
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(sb, &L.b[buf][pl][(64 * w + C::NT * q) * 8], 16,
+                                               (t + C::NT * q) * 16, 0, 0, 0);
   }
 }
 
-template <class C, bool X3>
-__device__ __forceinline__ void store_stage(Lds<C, X3>& L, int buf, int t, const bf8 (&ra)[PLANES_MAX][C::A_LOADS],
-                                            const bf8 (&rb)[PLANES_MAX][C::B_LOADS]) {
-  constexpr int P = X3 ? 2 : 1;
-#pragma unroll
-  for (int pl = 0; pl < P; ++pl) {
-#pragma unroll
-    for (int q = 0; q < C::A_LOADS; ++q) *reinterpret_cast<bf8*>(&L.a[buf][pl][(t + C::NT * q) * 8]) = ra[pl][q];
-#pragma unroll
-    for (int q = 0; q < C::B_LOADS; ++q) *reinterpret_cast<bf8*>(&L.b[buf][pl][(t + C::NT * q) * 8]) = rb[pl][q];
-  }
+// Wait until at most N of this thread's memory loads are outstanding
+// (s_waitcnt vmcnt(N); N < 64), leaving LDS and export counters alone.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
 }
 
 // MFMA work of one K step from LDS buffer cur.
@@ -251,34 +259,36 @@ __device__ __forceinline__ void mma_step(const Lds<C, X3>& L, int cur, int wm, i
   }
 }
 
-// K loop: two register sets; the loads of step k+2 are issued at the start
-// of step k and written to LDS at the end of step k+1, so two steps of MFMA
-// work cover their latency (one step ahead measured 2-6% slower; a scheduling
-// fence that keeps the loads above the MFMAs measured slower than the
-// compiler's own order).  The leaf size is a multiple of 128, so the number of
-// steps (m / 32) is a multiple of 4; past the end the loads repeat the last
-// step (in bounds, never read back).
+// K loop over an LDS ring of NBUF buffers: the loads of step k + NBUF - 1 go
+// to LDS at the start of step k (into the buffer step k - 1 read, freed by the
+// barrier that ended it), so NBUF - 1 steps of MFMA work cover their latency;
+// each step ends by waiting for the next step's loads and a barrier.  (Staging
+// through registers instead - two register sets, loads two steps ahead and
+// stored to LDS one step ahead - measured the same: 0.47 of the BF16 peak at
+// n = 16384 classical either way.)
 template <class C, bool X3>
 __device__ __forceinline__ void k_loop(Lds<C, X3>& L, const __bf16* a, const __bf16* b, int64_t plane, int m, int i0,
                                        int j0, int t, int wm, int wn, int lr, int lk,
                                        f4 (&acc)[C::WTM][C::WTN]) {
+  constexpr int NB = Lds<C, X3>::NBUF, D = NB - 1;
+  constexpr int LPS = (X3 ? 2 : 1) * (C::A_LOADS + C::B_LOADS);  // loads per thread and step
   const int KT = m / BK;
-  bf8 ra0[PLANES_MAX][C::A_LOADS], rb0[PLANES_MAX][C::B_LOADS];
-  bf8 ra1[PLANES_MAX][C::A_LOADS], rb1[PLANES_MAX][C::B_LOADS];
-  load_stage<C, X3>(a, b, plane, m, i0, j0, 0, t, ra0, rb0);
-  load_stage<C, X3>(a, b, plane, m, i0, j0, BK, t, ra1, rb1);
-  store_stage<C, X3>(L, 0, t, ra0, rb0);
+  for (int d = 0; d < D; ++d)
+    if (d < KT) dma_stage<C, X3>(L, d, a, b, plane, m, i0, j0, d * BK, t);
+  if (D > 1 && KT > 1)
+    wait_vm<(D > 1 ? LPS : 0)>();  // step 0 landed, step 1 may still fly
+  else
+    wait_vm<0>();
   __syncthreads();
-  for (int kt = 0; kt < KT; kt += 2) {
-    // LDS buffer 0 holds step kt; set 1 holds step kt + 1 (in flight)
-    load_stage<C, X3>(a, b, plane, m, i0, j0, min(kt + 2, KT - 1) * BK, t, ra0, rb0);
-    mma_step<C, X3>(L, 0, wm, wn, lr, lk, acc);
-    store_stage<C, X3>(L, 1, t, ra1, rb1);
-    __syncthreads();
-    // LDS buffer 1 holds step kt + 1; set 0 holds step kt + 2 (in flight)
-    load_stage<C, X3>(a, b, plane, m, i0, j0, min(kt + 3, KT - 1) * BK, t, ra1, rb1);
-    mma_step<C, X3>(L, 1, wm, wn, lr, lk, acc);
-    store_stage<C, X3>(L, 0, t, ra0, rb0);
+  for (int kt = 0; kt < KT; ++kt) {
+    const bool ahead = kt + D < KT;
+    if (ahead) dma_stage<C, X3>(L, (kt + D) % NB, a, b, plane, m, i0, j0, (kt + D) * BK, t);
+    mma_step<C, X3>(L, kt % NB, wm, wn, lr, lk, acc);
+    // step kt + 1 must have landed; later steps may still fly
+    if (D > 1 && ahead)
+      wait_vm<(D > 1 ? LPS : 0)>();
+    else
+      wait_vm<0>();
     __syncthreads();
   }
 }

@@ -11,11 +11,17 @@
 // and return 4 values per lane:
 //   f64: element v of lane l is D[l / 16 + 4 v][l % 16]
 //   f32: element v of lane l is D[4 (l / 16) + v][l % 16].
-// Both LDS tiles are stored k-major (A transposed on the way in) so that the
-// 16 lanes of a fragment row read 16 consecutive elements.  The A tile is
-// loaded so that the lanes one LDS cycle serves write consecutive rows of one
-// k-row pair (a_slot), which keeps the transposing stores free of bank
-// conflicts.
+// Two ways to fill LDS:
+//   * FP64 interior tiles (k_loop_dma): both operands straight from memory to
+//     LDS (no registers, no LDS stores); A stays row-major with its 16-byte
+//     pieces swizzled per row, B k-major.
+//   * Edge tiles, FP32 and fused operands (k_loop, k_loop_fused): through
+//     registers; both LDS tiles k-major (A transposed on the way in) so that
+//     the 16 lanes of a fragment row read 16 consecutive elements.  The A tile
+//     is loaded so that the lanes one LDS cycle serves write consecutive rows
+//     of one k-row pair (a_slot), which keeps the transposing stores free of
+//     bank conflicts.
+// All paths feed the MFMA k slots in the same order (kslot).
 //
 // A work item owns one tile position of every output block of its group and
 // runs the group's products in order: the first product feeding a block
@@ -218,13 +224,134 @@ __device__ __forceinline__ void store_tiles(T* As, T* Bs, int t, const typename 
   }
 }
 
+// Wait until at most N of this thread's vector memory operations (loads into
+// LDS included) are outstanding: s_waitcnt vmcnt(N), LDS and export counters
+// left alone.
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
+}
+
+// k of MFMA k-step s (of the 4 in a K step of 16) in the lanes of row group
+// lk = l / 16: step s takes k = 8 (s / 2) + 2 lk + s % 2, so the two k of a
+// 16-byte piece (an element pair) feed consecutive k-steps.  Every path
+// (LDS-direct, register-staged, fused) uses this order, so products agree bit
+// for bit whichever path loaded their operands.
+__device__ __forceinline__ int kslot(int s, int lk) { return 8 * (s >> 1) + 2 * lk + (s & 1); }
+
 template <class T, class Cfg>
 __device__ __forceinline__ void load_frags(const T* As, const T* Bs, int s, int wm, int wn, int lr, int lk,
                                            T (&fa)[Cfg::WM_T], T (&fb)[Cfg::WN_T]) {
+  const int k = kslot(s, lk);
 #pragma unroll
-  for (int mi = 0; mi < Cfg::WM_T; ++mi) fa[mi] = As[(4 * s + lk) * Cfg::SA + wm + 16 * mi + lr];
+  for (int mi = 0; mi < Cfg::WM_T; ++mi) fa[mi] = As[k * Cfg::SA + wm + 16 * mi + lr];
 #pragma unroll
-  for (int ni = 0; ni < Cfg::WN_T; ++ni) fb[ni] = Bs[(4 * s + lk) * Cfg::SB + wn + 16 * ni + lr];
+  for (int ni = 0; ni < Cfg::WN_T; ++ni) fb[ni] = Bs[k * Cfg::SB + wn + 16 * ni + lr];
+}
+
+// One K step's A and B tiles of a wave, memory -> LDS (see k_loop_dma).
+// Kept out of the loop's lambdas: those are host-device functions, and the
+// builtin exists only on the device.
+template <class T, class Cfg, int A_INSTR, int B_INSTR>
+__device__ __forceinline__ void dma_tiles(T* As, T* Bs, const T* a0, const T* b0, const int (&oa)[A_INSTR],
+                                          const int (&ob)[B_INSTR], int w) {
+  constexpr int NW = Cfg::NTHREADS / 64;
+  const __amdgpu_buffer_rsrc_t sa = raw_rsrc(a0);
+  const __amdgpu_buffer_rsrc_t sb = raw_rsrc(b0);
+#pragma unroll
+  for (int q = 0; q < A_INSTR; ++q)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(sa, As + 8 * (w + NW * q) * Cfg::BK, 16, oa[q], 0, 0, 0);
+#pragma unroll
+  for (int q = 0; q < B_INSTR; ++q)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(sb, Bs + (w + NW * q) * Cfg::SB, 16, ob[q], 0, 0, 0);
+}
+
+// FP64 interior tiles with both operands moved straight from memory to LDS
+// (buffer_load ... lds, 16 bytes per lane, lane l of a wave landing at the
+// instruction's LDS base + 16 l), so no registers hold the next tile and no
+// LDS store instructions run.
+//   A tile: row-major, BM rows of 8 pieces (16 B = k pair); piece c of row r
+//     sits at position c ^ (r & 7).  One wave instruction moves 8 whole rows.
+//     A fragment read (ds_read_b128) of rows r..r+7 for one piece index then
+//     hits 8 distinct positions, i.e. every bank once.
+//   B tile: k-major rows of BN elements (row stride SB), one row per wave
+//     instruction.
+// The fragments of A for k-steps 2p and 2p + 1 come from one 16-byte read
+// (piece 4p + lk), matching kslot.
+template <class T, class Cfg>
+__device__ __forceinline__ void k_loop_dma(T* lds, const T* __restrict__ pa, int lda, const T* __restrict__ pb,
+                                           int ldb, int i0, int j0, int KT, int t, int wm, int wn, int lr, int lk,
+                                           typename Mfma<T>::v4 (&acc)[Cfg::WM_T][Cfg::WN_T]) {
+  typedef typename Mfma<T>::v2 v2;
+  constexpr int WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, BK = Cfg::BK;
+  constexpr int NW = Cfg::NTHREADS / 64;
+  constexpr int A_INSTR = Cfg::BM / (8 * NW), B_INSTR = BK / NW;
+  static_assert(sizeof(T) == 8 && BK == 16 && Cfg::BN == 128 && A_INSTR * 8 * NW == Cfg::BM && B_INSTR * NW == BK &&
+                    Cfg::BM * BK <= Cfg::LDS_A,
+                "one 16-byte piece per lane: 8 A rows or one 128-wide B row per wave instruction");
+  const int lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  int oa[A_INSTR], ob[B_INSTR];
+#pragma unroll
+  for (int q = 0; q < A_INSTR; ++q)
+    oa[q] = ((8 * (w + NW * q) + (lane >> 3)) * lda + 2 * ((lane & 7) ^ (lane >> 3))) * (int)sizeof(T);
+#pragma unroll
+  for (int q = 0; q < B_INSTR; ++q) ob[q] = ((w + NW * q) * ldb + 2 * lane) * (int)sizeof(T);
+  auto a_buf = [&](int b) { return lds + b * Cfg::LDS_A; };
+  auto b_buf = [&](int b) { return lds + 2 * Cfg::LDS_A + b * Cfg::LDS_B; };
+  auto issue = [&](int k0, int buf) {
+    dma_tiles<T, Cfg, A_INSTR, B_INSTR>(a_buf(buf), b_buf(buf), pa + (size_t)i0 * lda + k0,
+                                        pb + (size_t)k0 * ldb + j0, oa, ob, w);
+  };
+  auto read_a = [&](const T* As, int p, v2 (&f)[WM_T]) {
+    const int pos = (4 * p + lk) ^ (lr & 7);
+#pragma unroll
+    for (int mi = 0; mi < WM_T; ++mi) f[mi] = *reinterpret_cast<const v2*>(As + (wm + 16 * mi + lr) * BK + 2 * pos);
+  };
+  auto read_b = [&](const T* Bs, int s, T (&f)[WN_T]) {
+    const int k = kslot(s, lk);
+#pragma unroll
+    for (int ni = 0; ni < WN_T; ++ni) f[ni] = Bs[k * Cfg::SB + wn + 16 * ni + lr];
+  };
+  auto mma = [&](const v2 (&a)[WM_T], int h, const T (&b)[WN_T]) {
+#pragma unroll
+    for (int mi = 0; mi < WM_T; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < WN_T; ++ni) acc[mi][ni] = Mfma<T>::op(h ? a[mi].y : a[mi].x, b[ni], acc[mi][ni]);
+  };
+  issue(0, 0);
+  wait_vmcnt<0>();
+  __syncthreads();
+  v2 fa[2][WM_T];
+  T fb[2][WN_T];
+  read_a(a_buf(0), 0, fa[0]);
+  read_b(b_buf(0), 0, fb[0]);
+  for (int kt = 0; kt < KT; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < KT;
+    // buffer cur ^ 1 was last read before the previous barrier
+    if (more) issue((kt + 1) * BK, cur ^ 1);
+    const T* As = a_buf(cur);
+    const T* Bs = b_buf(cur);
+    read_b(Bs, 1, fb[1]);
+    mma(fa[0], 0, fb[0]);
+    read_a(As, 1, fa[1]);
+    read_b(Bs, 2, fb[0]);
+    mma(fa[0], 1, fb[1]);
+    read_b(Bs, 3, fb[1]);
+    mma(fa[1], 0, fb[0]);
+    // the next tile has landed and every read of buffer cur is done; the
+    // last k-step's fragments are in registers, so the barrier and the next
+    // step's first reads overlap its MFMAs
+    wait_vmcnt<0>();
+    __syncthreads();
+    if (more) {
+      read_a(a_buf(cur ^ 1), 0, fa[0]);
+      read_b(b_buf(cur ^ 1), 0, fb[0]);
+    }
+    mma(fa[1], 1, fb[1]);
+  }
 }
 
 template <class T, class Cfg>
@@ -349,12 +476,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
 
     const bool interior = FULL || (vec_a && vec_b && i0 + BM <= pd.a_vr && pd.a_vc >= g.k && pd.b_vr >= g.k &&
                                    j0 + BN <= pd.b_vc);
-    if (interior)
-      k_loop<T, Cfg, false>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
-                       lk, acc);
-    else if constexpr (!FULL)
+    if (interior) {
+      if constexpr (sizeof(T) == 8)
+        k_loop_dma<T, Cfg>(lds, pa, pd.lda, pb, pd.ldb, i0, j0, KT, t, wm, wn, lr, lk, acc);
+      else
+        k_loop<T, Cfg, false>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn,
+                              lr, lk, acc);
+    } else if constexpr (!FULL) {
       k_loop<T, Cfg, true>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
-                      lk, acc);
+                           lk, acc);
+    }
 
     product_epilogue<T, Cfg, FULL>(g, pd, i0, j0, wm, wn, lr, lk, acc);
   }

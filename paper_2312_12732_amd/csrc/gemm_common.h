@@ -51,18 +51,22 @@ __device__ __forceinline__ S load_uniform(const S* p) {
   return v;
 }
 
+// The base of an operand source or output destination.  Selected with
+// integer masks: a chain of selects over the fields is turned by the
+// compiler into a load at a computed offset, which forces a GemmArgs built
+// in a kernel (the batched kernels build one per task) into scratch memory.
 template <class T>
 __device__ __forceinline__ const T* src_ptr(const GemmArgs<T>& g, int src) {
-  const T* p = g.ws;
-  p = src == SRC_A ? g.A : p;
-  p = src == SRC_B ? g.B : p;
-  p = src == SRC_C ? g.C : p;
-  return p;
+  const uint64_t m_a = 0 - (uint64_t)(src == SRC_A), m_b = 0 - (uint64_t)(src == SRC_B);
+  const uint64_t m_c = 0 - (uint64_t)(src == SRC_C), m_w = ~(m_a | m_b | m_c);
+  return reinterpret_cast<const T*>((reinterpret_cast<uint64_t>(g.A) & m_a) | (reinterpret_cast<uint64_t>(g.B) & m_b) |
+                                    (reinterpret_cast<uint64_t>(g.C) & m_c) | (reinterpret_cast<uint64_t>(g.ws) & m_w));
 }
 
 template <class T>
 __device__ __forceinline__ T* dst_ptr(const GemmArgs<T>& g, int dst) {
-  return dst == SRC_C ? g.C : g.ws;
+  const uint64_t m_c = 0 - (uint64_t)(dst == SRC_C);
+  return reinterpret_cast<T*>((reinterpret_cast<uint64_t>(g.C) & m_c) | (reinterpret_cast<uint64_t>(g.ws) & ~m_c));
 }
 
 // Map a workgroup id to (group, tile position).  Workgroups are dealt

@@ -39,16 +39,36 @@ struct TileCfg {
   static constexpr int NTHREADS = 64 * WAVES_M * WAVES_N;
   static constexpr int WAVES_PER_SIMD = WAVES_PER_SIMD_;  // occupancy the register budget is sized for
   static constexpr int WM_T = BM / (16 * WAVES_M), WN_T = BN / (16 * WAVES_N);  // MFMA tiles per wave
-  static constexpr int SA = BM + 16, SB = BN + 16;  // LDS row strides (elements)
   static constexpr int LPT_A = BM * BK / 2 / NTHREADS;  // element-pair loads per thread and K step
   static constexpr int LPT_B = BK * BN / 2 / NTHREADS;
-  static constexpr int LDS_A = BK * SA, LDS_B = BK * SB;
-  static constexpr int LDS_ELEMS = 2 * (LDS_A + LDS_B);  // two buffers of A and B
   static_assert(LPT_A >= 1 && LPT_B >= 1 && BM * BK / 2 % NTHREADS == 0 && BK * BN / 2 % NTHREADS == 0,
                 "tile loads must divide evenly");
   static_assert(BM % kLeafTile == 0 && BN % kLeafTile == 0, "tiles are multiples of the leaf granularity");
 };
 using Tile128 = TileCfg<128, 128, 2, 4, 4>;
+
+// LDS geometry of one element type: two A buffers, then two B buffers.
+//   A, register-staged path: k-major, k row k at k * SA.
+//   A, LDS-direct path: row-major, BM rows of BK elements (same space).
+//   B, both paths: k-major rows of BN elements at b_row(k).
+// LDS has 32 four-byte banks and serves 128 bytes per cycle: an FP64
+// fragment read serves 16 lanes (one k row) per cycle, an FP32 one 32 lanes,
+// i.e. the k rows of row groups lk and lk + 1, which kslot puts 4 apart.  For
+// FP32 those rows start 16 banks apart: A stride BM + 4, and B stored as
+// pairs of k rows (a pair is what one LDS-direct instruction moves) 2 BN + 8
+// apart.
+template <class T, class Cfg>
+struct Geom {
+  static constexpr bool F64 = sizeof(T) == 8;
+  static constexpr int SA = Cfg::BM + (F64 ? 16 : 4);
+  static constexpr int SB = Cfg::BN + 16;       // FP64 B: k row stride
+  static constexpr int PAIR = 2 * Cfg::BN + 8;  // FP32 B: stride of a pair of k rows
+  static constexpr int LDS_A = Cfg::BK * SA;
+  static constexpr int LDS_B = F64 ? Cfg::BK * SB : Cfg::BK / 2 * PAIR;
+  static constexpr int ELEMS = 2 * (LDS_A + LDS_B);
+  static_assert(Cfg::BM * Cfg::BK <= LDS_A, "the row-major A tile fits an A buffer");
+  static __device__ __forceinline__ int b_row(int k) { return F64 ? k * SB : (k >> 1) * PAIR + (k & 1) * Cfg::BN; }
+};
 
 // Element pair idx of the A tile -> (row, kp): the pair A[row][kp..kp+1].
 // LDS has 32 four-byte banks and serves 128 bytes per cycle (16 lanes of a
@@ -92,8 +112,9 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
 };
 
-// Global -> register prefetch of one BM x BK tile of the A view and one
-// BK x BN tile of the B view, two consecutive elements per load.
+// Global -> register prefetch of one BM x BK tile of an A view and one
+// BK x BN tile of a B view, two consecutive elements per load (the fused-
+// operand path and edge tiles).
 //
 // Interior tiles (every element valid, rows 16-byte aligned): raw buffer loads
 // whose descriptors (tile origin at the current k0) live in scalar registers,
@@ -145,19 +166,6 @@ __device__ __forceinline__ typename Mfma<T>::v2 buffer_pair(__amdgpu_buffer_rsrc
     return __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
   else
     return __builtin_bit_cast(v2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-
-template <class T, class Cfg>
-__device__ __forceinline__ void load_tiles_interior(const T* __restrict__ pa, int lda, const T* __restrict__ pb,
-                                                    int ldb, int i0, int j0, int k0, const LaneOffsets<Cfg>& o,
-                                                    typename Mfma<T>::v2 (&ra)[Cfg::LPT_A],
-                                                    typename Mfma<T>::v2 (&rb)[Cfg::LPT_B]) {
-  const __amdgpu_buffer_rsrc_t sa = raw_rsrc(pa + (size_t)i0 * lda + k0);
-  const __amdgpu_buffer_rsrc_t sb = raw_rsrc(pb + (size_t)k0 * ldb + j0);
-#pragma unroll
-  for (int q = 0; q < Cfg::LPT_A; ++q) ra[q] = buffer_pair<T>(sa, o.a[q]);
-#pragma unroll
-  for (int q = 0; q < Cfg::LPT_B; ++q) rb[q] = buffer_pair<T>(sb, o.b[q]);
 }
 
 template <class T, class Cfg>
@@ -213,14 +221,14 @@ __device__ __forceinline__ void store_tiles(T* As, T* Bs, int t, const typename 
   for (int q = 0; q < Cfg::LPT_A; ++q) {
     int row, kp;
     a_slot<T, Cfg>(t + Cfg::NTHREADS * q, row, kp);
-    As[kp * Cfg::SA + row] = ra[q].x;
-    As[(kp + 1) * Cfg::SA + row] = ra[q].y;
+    As[kp * Geom<T, Cfg>::SA + row] = ra[q].x;
+    As[(kp + 1) * Geom<T, Cfg>::SA + row] = ra[q].y;
   }
 #pragma unroll
   for (int q = 0; q < Cfg::LPT_B; ++q) {
     int kr, cp;
     b_slot<T, Cfg>(t + Cfg::NTHREADS * q, kr, cp);
-    *reinterpret_cast<v2*>(Bs + kr * Cfg::SB + cp) = rb[q];
+    *reinterpret_cast<v2*>(Bs + Geom<T, Cfg>::b_row(kr) + cp) = rb[q];
   }
 }
 
@@ -234,123 +242,175 @@ __device__ __forceinline__ void wait_vmcnt() {
 }
 
 // k of MFMA k-step s (of the 4 in a K step of 16) in the lanes of row group
-// lk = l / 16: step s takes k = 8 (s / 2) + 2 lk + s % 2, so the two k of a
-// 16-byte piece (an element pair) feed consecutive k-steps.  Every path
-// (LDS-direct, register-staged, fused) uses this order, so products agree bit
-// for bit whichever path loaded their operands.
-__device__ __forceinline__ int kslot(int s, int lk) { return 8 * (s >> 1) + 2 * lk + (s & 1); }
+// lk = l / 16.  With P elements per 16-byte piece (2 in FP64, 4 in FP32),
+// step s takes element s % P of piece 4 (s / P) + lk of the k range, so the
+// elements of a piece feed consecutive k-steps and one 16-byte LDS read
+// serves P steps.  Every path (LDS-direct, register-staged, fused) uses this
+// order, so products agree bit for bit whichever path loaded their operands.
+template <class T>
+__device__ __forceinline__ int kslot(int s, int lk) {
+  constexpr int P = 16 / sizeof(T);
+  return P * (4 * (s / P) + lk) + s % P;
+}
 
 template <class T, class Cfg>
 __device__ __forceinline__ void load_frags(const T* As, const T* Bs, int s, int wm, int wn, int lr, int lk,
                                            T (&fa)[Cfg::WM_T], T (&fb)[Cfg::WN_T]) {
-  const int k = kslot(s, lk);
+  const int k = kslot<T>(s, lk);
 #pragma unroll
-  for (int mi = 0; mi < Cfg::WM_T; ++mi) fa[mi] = As[k * Cfg::SA + wm + 16 * mi + lr];
+  for (int mi = 0; mi < Cfg::WM_T; ++mi) fa[mi] = As[k * Geom<T, Cfg>::SA + wm + 16 * mi + lr];
 #pragma unroll
-  for (int ni = 0; ni < Cfg::WN_T; ++ni) fb[ni] = Bs[k * Cfg::SB + wn + 16 * ni + lr];
+  for (int ni = 0; ni < Cfg::WN_T; ++ni) fb[ni] = Bs[Geom<T, Cfg>::b_row(k) + wn + 16 * ni + lr];
 }
+
+// LDS-direct geometry of one element type: P elements per 16-byte piece,
+// RA rows of A and RB k rows of B per wave instruction (64 pieces), and the
+// swizzle of A pieces within a row: piece c of row r sits at position
+// c ^ swz(r), so that the 8 lanes one LDS cycle serves in a 16-byte fragment
+// read (rows r..r+7, one piece index) hit every bank once.
+template <class T, class Cfg>
+struct Dma {
+  static constexpr int P = 16 / sizeof(T);
+  static constexpr int NW = Cfg::NTHREADS / 64;
+  static constexpr int PPR = Cfg::BK / P;  // pieces per A row
+  static constexpr int RA = 64 / PPR, RB = 64 * P / Cfg::BN;
+  static constexpr int A_INSTR = Cfg::BM / (NW * RA), B_INSTR = Cfg::BK / (NW * RB);
+  static_assert(A_INSTR * NW * RA == Cfg::BM && B_INSTR * NW * RB == Cfg::BK && 4 % P == 0 && RA % 8 == 0,
+                "whole A rows and whole B k rows per wave instruction");
+  // FP64: a row is 128 bytes (all 32 banks) of 8 pieces, so 8 rows need 8
+  // distinct positions.  FP32: a row is 64 bytes of 4 pieces; rows r and
+  // r + 2 start in the same bank, so the position follows r / 2.
+  static __device__ __forceinline__ int swz(int r) { return P == 2 ? (r & 7) : ((r >> 1) & 3); }
+};
 
 // One K step's A and B tiles of a wave, memory -> LDS (see k_loop_dma).
 // Kept out of the loop's lambdas: those are host-device functions, and the
 // builtin exists only on the device.
-template <class T, class Cfg, int A_INSTR, int B_INSTR>
-__device__ __forceinline__ void dma_tiles(T* As, T* Bs, const T* a0, const T* b0, const int (&oa)[A_INSTR],
-                                          const int (&ob)[B_INSTR], int w) {
-  constexpr int NW = Cfg::NTHREADS / 64;
+// Lane byte offsets oa, ob address instruction 0; instruction q adds
+// q * sa_step (sb_step) bytes, a wave-uniform value passed as the scalar
+// offset, so each lane holds one offset per operand.
+template <class T, class Cfg>
+__device__ __forceinline__ void dma_tiles(T* As, T* Bs, const T* a0, const T* b0, int oa, int ob, int sa_step,
+                                          int sb_step, int w) {
+  typedef Dma<T, Cfg> D;
   const __amdgpu_buffer_rsrc_t sa = raw_rsrc(a0);
   const __amdgpu_buffer_rsrc_t sb = raw_rsrc(b0);
 #pragma unroll
-  for (int q = 0; q < A_INSTR; ++q)
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(sa, As + 8 * (w + NW * q) * Cfg::BK, 16, oa[q], 0, 0, 0);
+  for (int q = 0; q < D::A_INSTR; ++q)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(sa, As + D::RA * (w + D::NW * q) * Cfg::BK, 16, oa, q * sa_step, 0, 0);
 #pragma unroll
-  for (int q = 0; q < B_INSTR; ++q)
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(sb, Bs + (w + NW * q) * Cfg::SB, 16, ob[q], 0, 0, 0);
+  for (int q = 0; q < D::B_INSTR; ++q)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(sb, Bs + Geom<T, Cfg>::b_row(D::RB * (w + D::NW * q)), 16, ob,
+                                             q * sb_step, 0, 0);
 }
 
-// FP64 interior tiles with both operands moved straight from memory to LDS
+// Interior tiles with both operands moved straight from memory to LDS
 // (buffer_load ... lds, 16 bytes per lane, lane l of a wave landing at the
 // instruction's LDS base + 16 l), so no registers hold the next tile and no
 // LDS store instructions run.
-//   A tile: row-major, BM rows of 8 pieces (16 B = k pair); piece c of row r
-//     sits at position c ^ (r & 7).  One wave instruction moves 8 whole rows.
-//     A fragment read (ds_read_b128) of rows r..r+7 for one piece index then
-//     hits 8 distinct positions, i.e. every bank once.
-//   B tile: k-major rows of BN elements (row stride SB), one row per wave
-//     instruction.
-// The fragments of A for k-steps 2p and 2p + 1 come from one 16-byte read
-// (piece 4p + lk), matching kslot.
+//   A tile: row-major, BM rows of BK / P pieces, swizzled (Dma::swz).  A
+//     fragment read (ds_read_b128) of rows r..r+7 for one piece index hits
+//     every bank once; one read gives a lane the A values of P k-steps.
+//   B tile: k-major rows (Geom::b_row), RB rows per wave instruction.
+// Each K step issues the next tile's loads first (into the buffer every wave
+// finished reading before the previous barrier) and ends with the wait for
+// them and the barrier, placed before the last k-step's MFMAs so that the
+// wait and the next step's first fragment reads overlap MFMAs.
 template <class T, class Cfg>
 __device__ __forceinline__ void k_loop_dma(T* lds, const T* __restrict__ pa, int lda, const T* __restrict__ pb,
                                            int ldb, int i0, int j0, int KT, int t, int wm, int wn, int lr, int lk,
                                            typename Mfma<T>::v4 (&acc)[Cfg::WM_T][Cfg::WN_T]) {
-  typedef typename Mfma<T>::v2 v2;
-  constexpr int WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, BK = Cfg::BK;
-  constexpr int NW = Cfg::NTHREADS / 64;
-  constexpr int A_INSTR = Cfg::BM / (8 * NW), B_INSTR = BK / NW;
-  static_assert(sizeof(T) == 8 && BK == 16 && Cfg::BN == 128 && A_INSTR * 8 * NW == Cfg::BM && B_INSTR * NW == BK &&
-                    Cfg::BM * BK <= Cfg::LDS_A,
-                "one 16-byte piece per lane: 8 A rows or one 128-wide B row per wave instruction");
+  typedef Dma<T, Cfg> D;
+  typedef Geom<T, Cfg> G;
+  constexpr int P = D::P, WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, BK = Cfg::BK;
+  typedef T vp __attribute__((ext_vector_type(P)));
+  static_assert(BK == 16, "4 MFMA k-steps per K step");
   const int lane = t & 63;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-  int oa[A_INSTR], ob[B_INSTR];
-#pragma unroll
-  for (int q = 0; q < A_INSTR; ++q)
-    oa[q] = ((8 * (w + NW * q) + (lane >> 3)) * lda + 2 * ((lane & 7) ^ (lane >> 3))) * (int)sizeof(T);
-#pragma unroll
-  for (int q = 0; q < B_INSTR; ++q) ob[q] = ((w + NW * q) * ldb + 2 * lane) * (int)sizeof(T);
-  auto a_buf = [&](int b) { return lds + b * Cfg::LDS_A; };
-  auto b_buf = [&](int b) { return lds + 2 * Cfg::LDS_A + b * Cfg::LDS_B; };
+  const int rl = lane / D::PPR;  // A row within an instruction (whose first row is a multiple of 8)
+  const int oa = ((D::RA * w + rl) * lda + P * ((lane % D::PPR) ^ D::swz(rl))) * (int)sizeof(T);
+  const int ob = ((D::RB * w + lane / (64 / D::RB)) * ldb + P * (lane % (64 / D::RB))) * (int)sizeof(T);
+  const int sa_step = D::RA * D::NW * lda * (int)sizeof(T), sb_step = D::RB * D::NW * ldb * (int)sizeof(T);
+  auto a_buf = [&](int b) { return lds + b * G::LDS_A; };
+  auto b_buf = [&](int b) { return lds + 2 * G::LDS_A + b * G::LDS_B; };
   auto issue = [&](int k0, int buf) {
-    dma_tiles<T, Cfg, A_INSTR, B_INSTR>(a_buf(buf), b_buf(buf), pa + (size_t)i0 * lda + k0,
-                                        pb + (size_t)k0 * ldb + j0, oa, ob, w);
+    dma_tiles<T, Cfg>(a_buf(buf), b_buf(buf), pa + (size_t)i0 * lda + k0, pb + (size_t)k0 * ldb + j0, oa, ob, sa_step,
+                      sb_step, w);
   };
-  auto read_a = [&](const T* As, int p, v2 (&f)[WM_T]) {
-    const int pos = (4 * p + lk) ^ (lr & 7);
+  // the A values of k-steps P p .. P p + P - 1: piece 4 p + lk of each row
+  auto read_a = [&](const T* As, int p, vp (&f)[WM_T]) {
+    const int pos = (4 * p + lk) ^ D::swz(lr);
 #pragma unroll
-    for (int mi = 0; mi < WM_T; ++mi) f[mi] = *reinterpret_cast<const v2*>(As + (wm + 16 * mi + lr) * BK + 2 * pos);
+    for (int mi = 0; mi < WM_T; ++mi) f[mi] = *reinterpret_cast<const vp*>(As + (wm + 16 * mi + lr) * BK + P * pos);
   };
   auto read_b = [&](const T* Bs, int s, T (&f)[WN_T]) {
-    const int k = kslot(s, lk);
+    const int row = G::b_row(kslot<T>(s, lk));
 #pragma unroll
-    for (int ni = 0; ni < WN_T; ++ni) f[ni] = Bs[k * Cfg::SB + wn + 16 * ni + lr];
+    for (int ni = 0; ni < WN_T; ++ni) f[ni] = Bs[row + wn + 16 * ni + lr];
   };
-  auto mma = [&](const v2 (&a)[WM_T], int h, const T (&b)[WN_T]) {
+  auto mma = [&](const vp (&a)[WM_T], int e, const T (&b)[WN_T]) {
 #pragma unroll
     for (int mi = 0; mi < WM_T; ++mi)
 #pragma unroll
-      for (int ni = 0; ni < WN_T; ++ni) acc[mi][ni] = Mfma<T>::op(h ? a[mi].y : a[mi].x, b[ni], acc[mi][ni]);
+      for (int ni = 0; ni < WN_T; ++ni) acc[mi][ni] = Mfma<T>::op(a[mi][e], b[ni], acc[mi][ni]);
   };
   issue(0, 0);
   wait_vmcnt<0>();
   __syncthreads();
-  v2 fa[2][WM_T];
   T fb[2][WN_T];
-  read_a(a_buf(0), 0, fa[0]);
-  read_b(b_buf(0), 0, fb[0]);
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
-    const bool more = kt + 1 < KT;
-    // buffer cur ^ 1 was last read before the previous barrier
-    if (more) issue((kt + 1) * BK, cur ^ 1);
-    const T* As = a_buf(cur);
-    const T* Bs = b_buf(cur);
-    read_b(Bs, 1, fb[1]);
-    mma(fa[0], 0, fb[0]);
-    read_a(As, 1, fa[1]);
-    read_b(Bs, 2, fb[0]);
-    mma(fa[0], 1, fb[1]);
-    read_b(Bs, 3, fb[1]);
-    mma(fa[1], 0, fb[0]);
-    // the next tile has landed and every read of buffer cur is done; the
-    // last k-step's fragments are in registers, so the barrier and the next
-    // step's first reads overlap its MFMAs
-    wait_vmcnt<0>();
-    __syncthreads();
-    if (more) {
-      read_a(a_buf(cur ^ 1), 0, fa[0]);
-      read_b(b_buf(cur ^ 1), 0, fb[0]);
+  if constexpr (P == 2) {
+    // FP64: two A reads per K step (k-steps 0-1 and 2-3)
+    vp fa[2][WM_T];
+    read_a(a_buf(0), 0, fa[0]);
+    read_b(b_buf(0), 0, fb[0]);
+    for (int kt = 0; kt < KT; ++kt) {
+      const int cur = kt & 1;
+      const bool more = kt + 1 < KT;
+      if (more) issue((kt + 1) * BK, cur ^ 1);
+      const T* As = a_buf(cur);
+      const T* Bs = b_buf(cur);
+      read_b(Bs, 1, fb[1]);
+      mma(fa[0], 0, fb[0]);
+      read_a(As, 1, fa[1]);
+      read_b(Bs, 2, fb[0]);
+      mma(fa[0], 1, fb[1]);
+      read_b(Bs, 3, fb[1]);
+      mma(fa[1], 0, fb[0]);
+      wait_vmcnt<0>();
+      __syncthreads();
+      if (more) {
+        read_a(a_buf(cur ^ 1), 0, fa[0]);
+        read_b(b_buf(cur ^ 1), 0, fb[0]);
+      }
+      mma(fa[1], 1, fb[1]);
     }
-    mma(fa[1], 1, fb[1]);
+  } else {
+    // FP32: one A read per K step serves all four k-steps; the next step's
+    // is read after the barrier into a second set
+    vp fa[WM_T], fn[WM_T];
+    read_a(a_buf(0), 0, fa);
+    read_b(b_buf(0), 0, fb[0]);
+    for (int kt = 0; kt < KT; ++kt) {
+      const int cur = kt & 1;
+      const bool more = kt + 1 < KT;
+      if (more) issue((kt + 1) * BK, cur ^ 1);
+      const T* Bs = b_buf(cur);
+      read_b(Bs, 1, fb[1]);
+      mma(fa, 0, fb[0]);
+      read_b(Bs, 2, fb[0]);
+      mma(fa, 1, fb[1]);
+      read_b(Bs, 3, fb[1]);
+      mma(fa, 2, fb[0]);
+      wait_vmcnt<0>();
+      __syncthreads();
+      if (more) {
+        read_a(a_buf(cur ^ 1), 0, fn);
+        read_b(b_buf(cur ^ 1), 0, fb[0]);
+      }
+      mma(fa, 3, fb[1]);
+#pragma unroll
+      for (int mi = 0; mi < WM_T; ++mi) fa[mi] = fn[mi];
+    }
   }
 }
 
@@ -363,25 +423,19 @@ __device__ __forceinline__ void mfma_step(const T (&fa)[Cfg::WM_T], const T (&fb
     for (int ni = 0; ni < Cfg::WN_T; ++ni) acc[mi][ni] = Mfma<T>::op(fa[mi], fb[ni], acc[mi][ni]);
 }
 
-// acc = A_view(i0.., :) * B_view(:, j0..) over K = KT * BK.  lds holds the
-// two A buffers, then the two B buffers.
-template <class T, class Cfg, bool MASKED>
-__device__ __forceinline__ void k_loop(T* lds, const T* __restrict__ pa, int lda, int a_vr, int a_vc,
-                                       const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0, int j0, int KT,
-                                       int t, int wm, int wn, int lr, int lk,
-                                       typename Mfma<T>::v4 (&acc)[Cfg::WM_T][Cfg::WN_T]) {
+// Edge tiles: acc = A_view(i0.., :) * B_view(:, j0..) over K = KT * BK with
+// masked loads through registers (entries outside the views are zero).  lds
+// holds the two A buffers (k-major), then the two B buffers.
+template <class T, class Cfg>
+__device__ __forceinline__ void k_loop_masked(T* lds, const T* __restrict__ pa, int lda, int a_vr, int a_vc,
+                                              const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0, int j0,
+                                              int KT, int t, int wm, int wn, int lr, int lk,
+                                              typename Mfma<T>::v4 (&acc)[Cfg::WM_T][Cfg::WN_T]) {
   constexpr int WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, BK = Cfg::BK;
   typename Mfma<T>::v2 ra[Cfg::LPT_A], rb[Cfg::LPT_B];
-  LaneOffsets<Cfg> o;
-  if constexpr (!MASKED) o = lane_offsets<T, Cfg>(lda, ldb, t);
-  auto load = [&](int k0) {
-    if constexpr (MASKED)
-      load_tiles_masked<T, Cfg>(pa, lda, a_vr, a_vc, pb, ldb, b_vr, b_vc, i0, j0, k0, t, ra, rb);
-    else
-      load_tiles_interior<T, Cfg>(pa, lda, pb, ldb, i0, j0, k0, o, ra, rb);
-  };
-  auto a_buf = [&](int b) { return lds + b * Cfg::LDS_A; };
-  auto b_buf = [&](int b) { return lds + 2 * Cfg::LDS_A + b * Cfg::LDS_B; };
+  auto load = [&](int k0) { load_tiles_masked<T, Cfg>(pa, lda, a_vr, a_vc, pb, ldb, b_vr, b_vc, i0, j0, k0, t, ra, rb); };
+  auto a_buf = [&](int b) { return lds + b * Geom<T, Cfg>::LDS_A; };
+  auto b_buf = [&](int b) { return lds + 2 * Geom<T, Cfg>::LDS_A + b * Geom<T, Cfg>::LDS_B; };
   constexpr int S = BK / 4;  // MFMA k-steps per K step
   load(0);
   store_tiles<T, Cfg>(a_buf(0), b_buf(0), t, ra, rb);
@@ -407,8 +461,7 @@ __device__ __forceinline__ void k_loop(T* lds, const T* __restrict__ pa, int lda
     // barrier and the LDS latency after it overlap work in the MFMA pipe.
     // (Every read of buffer cur completed before the barrier, so the next
     // step may overwrite it; buffer cur ^ 1 was last read before the previous
-    // barrier.)  Issuing the global loads two steps ahead instead (after the
-    // store, same registers) measured 3% slower.
+    // barrier.)
     if (more) store_tiles<T, Cfg>(a_buf(cur ^ 1), b_buf(cur ^ 1), t, ra, rb);
     __syncthreads();
     if (more) load_frags<T, Cfg>(a_buf(cur ^ 1), b_buf(cur ^ 1), 0, wm, wn, lr, lk, fa[S & 1], fb[S & 1]);
@@ -476,16 +529,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
 
     const bool interior = FULL || (vec_a && vec_b && i0 + BM <= pd.a_vr && pd.a_vc >= g.k && pd.b_vr >= g.k &&
                                    j0 + BN <= pd.b_vc);
-    if (interior) {
-      if constexpr (sizeof(T) == 8)
-        k_loop_dma<T, Cfg>(lds, pa, pd.lda, pb, pd.ldb, i0, j0, KT, t, wm, wn, lr, lk, acc);
-      else
-        k_loop<T, Cfg, false>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn,
-                              lr, lk, acc);
-    } else if constexpr (!FULL) {
-      k_loop<T, Cfg, true>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn, lr,
-                           lk, acc);
-    }
+    if (interior)
+      k_loop_dma<T, Cfg>(lds, pa, pd.lda, pb, pd.ldb, i0, j0, KT, t, wm, wn, lr, lk, acc);
+    else if constexpr (!FULL)
+      k_loop_masked<T, Cfg>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn,
+                            lr, lk, acc);
 
     product_epilogue<T, Cfg, FULL>(g, pd, i0, j0, wm, wn, lr, lk, acc);
   }
@@ -578,8 +626,8 @@ __device__ __forceinline__ void k_loop_fused(T* lds, const T* __restrict__ pa, i
       }
     }
   };
-  auto a_buf = [&](int b) { return lds + b * Cfg::LDS_A; };
-  auto b_buf = [&](int b) { return lds + 2 * Cfg::LDS_A + b * Cfg::LDS_B; };
+  auto a_buf = [&](int b) { return lds + b * Geom<T, Cfg>::LDS_A; };
+  auto b_buf = [&](int b) { return lds + 2 * Geom<T, Cfg>::LDS_A + b * Geom<T, Cfg>::LDS_B; };
   constexpr int S = BK / 4;
   load(0);
   sum_terms<T, NT, Cfg::LPT_A>(fa, xa, ra);

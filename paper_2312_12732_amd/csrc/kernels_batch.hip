@@ -171,7 +171,7 @@ __device__ __forceinline__ int claim_task(const BatchArgs& g, int prev_done, int
 // never finished.)
 template <class T>
 __global__ void __launch_bounds__(Tile128::NTHREADS, Tile128::WAVES_PER_SIMD) batch_persistent(BatchArgs g) {
-  __shared__ T lds[Tile128::LDS_ELEMS];
+  __shared__ T lds[Geom<T, Tile128>::ELEMS];
   __shared__ int s_task;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = (int)(threadIdx.x & 63);
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(Tile128::NTHREADS) batch_combine_phase(BatchAr
 
 template <class T>
 __global__ void __launch_bounds__(Tile128::NTHREADS, Tile128::WAVES_PER_SIMD) batch_gemm_phase(BatchArgs g, int task0) {
-  __shared__ T lds[Tile128::LDS_ELEMS];
+  __shared__ T lds[Geom<T, Tile128>::ELEMS];
   const BatchTask tk = load_uniform(g.tasks + task0 + blockIdx.x);
   run_gemm<T>(g, tk, lds);
 }

@@ -17,7 +17,7 @@ namespace mf {
 
 template <class T, class Cfg, bool FULL>
 __global__ void __launch_bounds__(Cfg::NTHREADS, Cfg::WAVES_PER_SIMD) gemm_grouped(GemmArgs<T> g) {
-  __shared__ T lds[Cfg::LDS_ELEMS];  // [A buffer 0 | A buffer 1 | B buffer 0 | B buffer 1], k-major
+  __shared__ T lds[Geom<T, Cfg>::ELEMS];  // [A buffer 0 | A buffer 1 | B buffer 0 | B buffer 1]
   int grp, ti, tj;
   work_of(blockIdx.x, g.tiles_m, g.tiles_n, g.groups, &grp, &ti, &tj);
   gemm_tile<T, Cfg, FULL>(g, grp, ti, tj, lds);
@@ -30,7 +30,7 @@ using Tile128F = TileCfg<128, 128, 2, 4, 2>;
 
 template <class T, class Cfg, int NT, bool FULL>
 __global__ void __launch_bounds__(Cfg::NTHREADS, Cfg::WAVES_PER_SIMD) gemm_fused(GemmArgs<T> g) {
-  __shared__ T lds[Cfg::LDS_ELEMS];
+  __shared__ T lds[Geom<T, Cfg>::ELEMS];
   int grp, ti, tj;
   work_of(blockIdx.x, g.tiles_m, g.tiles_n, g.groups, &grp, &ti, &tj);
   gemm_tile_fused<T, Cfg, NT, FULL>(g, grp, ti, tj, lds);

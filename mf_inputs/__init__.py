@@ -224,10 +224,33 @@ _SPLITMIX_GAMMA = np.uint64(0x9E3779B97F4A7C15)
 
 def counter_uniform(count: int, seed: int, dtype=np.float64) -> np.ndarray:
     """Counter-based uniform[-1, 1) values (the serving runtime's operands)."""
+    return counter_uniform_at(np.arange(count, dtype=np.uint64), seed, dtype)
+
+
+def counter_uniform_at(index: np.ndarray, seed: int, dtype=np.float64) -> np.ndarray:
+    """Elements `index` (0-based) of counter_uniform(..., seed): element e is
+    the SplitMix64 output for counter e + 1, so any subset (say some rows of
+    a matrix) can be drawn without the rest.  Works in place on two integer
+    arrays (fresh large arrays are slow to fault in on some hosts)."""
+    z = np.array(index, dtype=np.uint64)
+    t = np.empty_like(z)
     with np.errstate(over="ignore"):
-        z = np.uint64(seed) + (np.arange(1, count + 1, dtype=np.uint64) * _SPLITMIX_GAMMA)
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-        z = z ^ (z >> np.uint64(31))
-    u = (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
-    return (2.0 * u - 1.0).astype(dtype)
+        z += np.uint64(1)
+        z *= _SPLITMIX_GAMMA
+        z += np.uint64(seed)
+        np.right_shift(z, np.uint64(30), out=t)
+        z ^= t
+        z *= np.uint64(0xBF58476D1CE4E5B9)
+        np.right_shift(z, np.uint64(27), out=t)
+        z ^= t
+        z *= np.uint64(0x94D049BB133111EB)
+        np.right_shift(z, np.uint64(31), out=t)
+        z ^= t
+        np.right_shift(z, np.uint64(11), out=z)
+    del t
+    u = z.astype(np.float64)
+    del z
+    u *= 2.0 ** -53
+    u *= 2.0
+    u -= 1.0
+    return u.astype(dtype, copy=False)

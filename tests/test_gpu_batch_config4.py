@@ -86,6 +86,64 @@ def test_config4_every_instance_against_oracle(name):
     print(f"config4 {name}: worst sampled rel err {worst:.3e}", flush=True)
 
 
+def sampled_block_operands(n, i, seed0, npdt, k=48):
+    """Rows `rows` of A and columns `cols` of B of instance i (the same
+    counter-generated values the device fills), drawn without the rest of
+    either matrix."""
+    g = np.random.default_rng(10_000 + i)
+    rows = np.sort(g.choice(n, size=min(n, k), replace=False))
+    cols = np.sort(g.choice(n, size=min(n, k), replace=False))
+    j = np.arange(n, dtype=np.uint64)
+    a_idx = rows.astype(np.uint64)[:, None] * np.uint64(n) + j[None, :]
+    b_idx = j[:, None] * np.uint64(n) + cols.astype(np.uint64)[None, :]
+    A_rows = mi.counter_uniform_at(a_idx, 2 * (seed0 + i), npdt).astype(np.float64)
+    B_cols = mi.counter_uniform_at(b_idx, 2 * (seed0 + i) + 1, npdt).astype(np.float64)
+    return rows, cols, A_rows, B_cols
+
+
+@pytest.mark.parametrize("name,form", [("f64", "phases"), ("f32", "phases"), ("f64", "persistent")])
+def test_config4_all_512_instances_sampled_blocks(name, form):
+    """All 512 instances of the batched workload, plans cycling through every
+    eligible algorithm: a 48 x 48 block of every C (random rows and columns)
+    against the oracle product of the same rows of A and columns of B."""
+    code, tdt, npdt, tol = {"f64": (mf.MF_F64, torch.float64, np.float64, 1e-11),
+                            "f32": (mf.MF_F32, torch.float32, np.float32, 2e-5)}[name]
+    sizes = mi.batch_sizes(512, 30)
+    if form == "phases":
+        plans = cycled_plans()
+        kw = {}
+    else:  # the combinations the persistent kernel takes
+        wino = mf.mf_algo_builtin("winograd")
+        plans = [(None, 0), (mf.mf_algo_builtin("strassen"), 1), (wino, 1), (wino, 2)]
+        kw = {"form": mf.MF_BATCH_PERSISTENT}
+    algos = [plans[i % len(plans)][0] for i in range(len(sizes))]
+    depths = [plans[i % len(plans)][1] for i in range(len(sizes))]
+    print(f"config4 all 512 {name} {form}", flush=True)
+    b = mf.mf_batch_create(sizes, algos, depths, [0] * len(sizes), code, **kw)
+    dA, dB, dC = [], [], []
+    for i, n in enumerate(sizes):
+        A = torch.empty(n, n, dtype=tdt, device="cuda:0")
+        B = torch.empty(n, n, dtype=tdt, device="cuda:0")
+        mf.mf_fill_uniform(A, 2 * (31 + i))
+        mf.mf_fill_uniform(B, 2 * (31 + i) + 1)
+        dA.append(A)
+        dB.append(B)
+        dC.append(torch.full_like(A, float("nan")))
+    mf.mf_batch_run(b, dA, dB, dC)
+    torch.cuda.synchronize()
+    assert not b.aborted()
+    worst = 0.0
+    for i, n in enumerate(sizes):
+        rows, cols, A_rows, B_cols = sampled_block_operands(n, i, 31, npdt)
+        blk = dC[i][torch.from_numpy(rows).cuda()][:, torch.from_numpy(cols).cuda()]
+        got = blk.cpu().numpy().astype(np.float64)
+        assert np.isfinite(got).all(), f"instance {i} (n={n}) has non-finite entries"
+        err = om.rel_fro_error(got, om.rows_reference(A_rows, B_cols, np.arange(len(rows))))
+        worst = max(worst, err)
+        assert err < tol, f"instance {i} n={n} depth {depths[i]}: rel err {err:.3e}"
+    print(f"config4 all 512 {name} {form}: worst sampled rel err {worst:.3e}", flush=True)
+
+
 def test_config4_fp64_integer_exact():
     """Integer-valued FP64 operands: every instance equals the exact product."""
     sizes = config4_sizes()

@@ -61,6 +61,57 @@ def test_mix_equals_alone_and_oracle():
     assert set(st["depth"].tolist()) >= {0, 1, 2}
 
 
+def block_operands(n, seed, npdt, k=48, pick=0):
+    """Rows of A and columns of B of a request (its counter-generated
+    operands: A from 2 seed, B from 2 seed + 1), drawn without the rest."""
+    g = np.random.default_rng(20_000 + pick)
+    rows = np.sort(g.choice(n, size=min(n, k), replace=False))
+    cols = np.sort(g.choice(n, size=min(n, k), replace=False))
+    j = np.arange(n, dtype=np.uint64)
+    A_rows = mi.counter_uniform_at(rows.astype(np.uint64)[:, None] * np.uint64(n) + j[None, :], 2 * seed, npdt)
+    B_cols = mi.counter_uniform_at(j[:, None] * np.uint64(n) + cols.astype(np.uint64)[None, :], 2 * seed + 1, npdt)
+    return rows, cols, A_rows.astype(np.float64), B_cols.astype(np.float64)
+
+
+def test_serving_workload_draw_mix_alone_and_oracle():
+    """300 requests of the serving workload's own draw (n log-uniform in
+    [256, 8192], 70% FP32, seed 40) with its depth policy, served 8 at a time:
+    every request with n <= 2048 and a 5% sample of the larger ones equal,
+    bit for bit, the same request served alone, and a 48 x 48 block of each
+    (random rows and columns) matches the oracle."""
+    reqs = mi.serving_requests(300, 40)
+    policy = dict(depth_min_n_f64=(2048, 4096, 0, 0), depth_min_n_f32=(2048, 4096, 0, 0))
+    g = np.random.default_rng(41)
+    check = [k for k, (n, _) in enumerate(reqs) if n <= 2048 or g.random() < 0.05]
+    assert len(check) > 150 and any(reqs[k][0] > 2048 for k in check)
+    seed = [3000 + k for k in range(len(reqs))]
+    outs = {k: torch.empty(reqs[k][0], reqs[k][0], dtype=tdtype(reqs[k][1])).pin_memory() for k in check}
+    print(f"serving draw: {len(reqs)} requests, {len(check)} checked", flush=True)
+    srv = mf.Server(8, 64 << 30, mf.mf_algo_builtin("winograd"), **policy)
+    for k, (n, dt) in enumerate(reqs):
+        srv.submit(n, code(dt), seed[k], outs.get(k))
+    srv.drain()
+    depth = srv.stats()["depth"]
+    srv.close()
+    assert set(depth.tolist()) >= {0, 1, 2}
+    alone = mf.Server(1, 64 << 30, mf.mf_algo_builtin("winograd"), **policy)
+    worst = {"f64": 0.0, "f32": 0.0}
+    for k in check:
+        n, dt = reqs[k]
+        out = torch.empty(n, n, dtype=tdtype(dt)).pin_memory()
+        alone.submit(n, code(dt), seed[k], out)
+        alone.drain()
+        assert torch.equal(out, outs[k]), (k, n, dt)
+        npdt = np.float64 if dt == "f64" else np.float32
+        rows, cols, A_rows, B_cols = block_operands(n, seed[k], npdt, pick=k)
+        got = outs[k].numpy()[np.ix_(rows, cols)].astype(np.float64)
+        err = om.rel_fro_error(got, om.rows_reference(A_rows, B_cols, np.arange(len(rows))))
+        worst[dt] = max(worst[dt], err)
+        assert err < (1e-11 if dt == "f64" else 2e-5), (k, n, dt, err)
+    alone.close()
+    print(f"serving draw: worst sampled rel err {worst}", flush=True)
+
+
 def test_requests_overlap_on_the_device():
     """Requests on different slots run at the same time on the device: on the
     device's own timeline (events recorded on each slot's stream, measured

@@ -93,6 +93,21 @@ def test_counter_generator_matches_published_splitmix():
     assert np.array_equal(f, v.astype(np.float32))
 
 
+def test_counter_generator_at_chosen_positions():
+    """counter_uniform_at draws any subset of the stream: equal to the scalar
+    SplitMix64 reference at large, unordered and repeated positions, and to
+    the full stream's slice."""
+    idx = np.array([5_000_000_123, 7, 0, 7, 2**33 + 1], dtype=np.uint64)
+    v = mi.counter_uniform_at(idx, 99)
+    for k, i in enumerate(idx.tolist()):
+        assert v[k] == 2.0 * ((splitmix_reference(99, i) >> 11) * 2.0 ** -53) - 1.0
+    full = mi.counter_uniform(3000, 4242, np.float32)
+    rows = np.array([[2999, 0], [17, 1500]], dtype=np.uint64)
+    got = mi.counter_uniform_at(rows, 4242, np.float32)
+    assert got.shape == (2, 2) and got.dtype == np.float32
+    assert np.array_equal(got, full[rows.astype(np.int64)])
+
+
 def test_arena_fragmentation_blocks_fifo_head_until_space_coalesces():
     # budget 3 MiB: A (offset 0), B (1 MiB) and C (2 MiB) fill it.  When B ends at t=1
     # only its 1 MiB hole is free, so the 2 MiB request D waits; when A ends at t=5

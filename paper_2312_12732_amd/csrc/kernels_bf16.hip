@@ -153,12 +153,12 @@ __global__ void __launch_bounds__(256)
 // waves per SIMD either way.
 //   Cfg128: 128 x 128, 2 x 2 waves of 64 x 64, two workgroups per CU (either
 //           form; leaves that the larger tiles do not divide);
-//   CfgSq:  256 x 256, 2 x 4 waves of 128 x 64, one workgroup per CU (BF16:
-//           a third less operand traffic from L2 per flop than two 256 x 128
-//           tiles, which bounds BF16 at these tile sizes; the x3 form's hi
-//           and lo fragments do not fit its wave tile);
-//   CfgW:   256 x 128, 4 x 2 waves of 64 x 64, one workgroup per CU
-//           (split-BF16x3).
+//   CfgSq:  256 x 256, 2 x 4 waves of 128 x 64, one workgroup per CU (either
+//           form).  The LDS bytes a wave reads per MFMA fall as its tile
+//           grows: for split-BF16x3 (hi and lo planes, 244 VGPRs, 64 KiB per
+//           K step) the 128 x 64 wave tile moved the GEMM from 0.52 to 0.64
+//           of the peak at n = 16384, against 256 x 128 tiles of 64 x 64
+//           waves, which kept LDS about 90% busy.
 template <int BM_, int BN_, int WM_, int WN_>
 struct BfCfg {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
@@ -170,15 +170,14 @@ struct BfCfg {
 };
 using Cfg128 = BfCfg<128, 128, 2, 2>;
 using CfgSq = BfCfg<256, 256, 2, 4>;
-using CfgW = BfCfg<256, 128, 4, 2>;
 
 // LDS ring of NBUF K-step buffers: four for the BF16 256 x 256 tile (128
-// KiB, fragment prefetch with the loads two steps ahead, k_loop_pf), three
-// for the split-BF16x3 tile (144 KiB), two for Cfg128, whose two workgroups
-// per CU share the LDS.
+// KiB, fragment prefetch with the loads two steps ahead, k_loop_pf), two for
+// split-BF16x3 on that tile (64 KiB per step, 128 KiB) and for Cfg128, whose
+// two workgroups per CU share the LDS.
 template <class C, bool X3>
 constexpr int nbuf() {
-  return C::MIN_BLOCKS == 1 ? (X3 ? 3 : 4) : 2;
+  return C::MIN_BLOCKS == 1 && !X3 ? 4 : 2;
 }
 
 template <class C, bool X3>
@@ -342,9 +341,9 @@ __device__ __forceinline__ void mma_frags(const Frags<C, X3>& F, f4 (&acc)[C::WT
 // were in registers before step k - 1's MFMAs), so the loads of step
 // k + NBUF - 1 go there; then the fragments of step k + 1 are read and the
 // MFMAs of step k issued.  BF16 at n = 16384: leaf GEMMs of depth 1-3 4-6%
-// faster than k_loop, classical unchanged.  With three buffers (split-BF16x3,
-// whose 48 KiB steps allow no fourth) the loads run only one step ahead and
-// the x3 GEMM was 3% slower, so it keeps k_loop.
+// faster than k_loop, classical unchanged.  (On a three-buffer ring, split-
+// BF16x3 on 256 x 128 tiles, the loads ran only one step ahead and the x3
+// GEMM was 3% slower.)
 template <class C, bool X3>
 __device__ __forceinline__ void k_loop_pf(Lds<C, X3>& L, const __bf16* a, const __bf16* b, int64_t plane, int m,
                                           int i0, int j0, int t, int wm, int wn, int lr, int lk,
@@ -512,11 +511,10 @@ hipError_t launch_gemm_bf16(const Plan& pl, const char* desc, bool x3, const voi
     const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n * (unsigned)g.groups;
     hipLaunchKernelGGL((bf::gemm_bf16_grouped<Cf, X>), dim3(grid), dim3(Cf::NT), 0, s, g, st, nprod, plane);
   };
-  // BF16: CfgSq; split-BF16x3: CfgW; Cfg128 for leaves the larger tiles do
-  // not divide
+  // CfgSq; Cfg128 for leaves the larger tile does not divide
   if (x3) {
-    if (pl.m % bf::CfgW::BM == 0)
-      launch(bf::CfgW{}, std::true_type{});
+    if (pl.m % bf::CfgSq::BM == 0)
+      launch(bf::CfgSq{}, std::true_type{});
     else
       launch(bf::Cfg128{}, std::true_type{});
   } else {

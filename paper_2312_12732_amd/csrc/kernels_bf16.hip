@@ -158,12 +158,16 @@ __global__ void __launch_bounds__(256)
 //           grows: for split-BF16x3 (hi and lo planes, 244 VGPRs, 64 KiB per
 //           K step) the 128 x 64 wave tile moved the GEMM from 0.52 to 0.64
 //           of the peak at n = 16384, against 256 x 128 tiles of 64 x 64
-//           waves, which kept LDS about 90% busy.
-template <int BM_, int BN_, int WM_, int WN_>
+//           waves, which kept LDS about 90% busy.  (BF16 on four 128 x 128
+//           waves, one per SIMD with 256 accumulator registers, halves those
+//           bytes again but measured 5-11% slower: one wave per SIMD leaves
+//           its stalls uncovered.)
+template <int BM_, int BN_, int WM_, int WN_, int WPE_ = 2>
 struct BfCfg {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
   static constexpr int NT = 64 * WM * WN;                       // threads per workgroup
-  static constexpr int MIN_BLOCKS = 512 / NT;                   // two waves per SIMD
+  static constexpr int WPE = WPE_;                              // waves per SIMD (register budget)
+  static constexpr int ONE_PER_CU = BM * BN >= 256 * 256;       // LDS holds one workgroup
   static constexpr int WTM = BM / WM / 16, WTN = BN / WN / 16;  // 16 x 16 tiles per wave
   static constexpr int A_LOADS = BM * BK / 8 / NT, B_LOADS = BN * BK / 8 / NT;
   static_assert(A_LOADS * 8 * NT == BM * BK && B_LOADS * 8 * NT == BN * BK, "whole 16-byte pieces");
@@ -177,7 +181,7 @@ using CfgSq = BfCfg<256, 256, 2, 4>;
 // two workgroups per CU share the LDS.
 template <class C, bool X3>
 constexpr int nbuf() {
-  return C::MIN_BLOCKS == 1 && !X3 ? 4 : 2;
+  return C::ONE_PER_CU && !X3 ? 4 : 2;
 }
 
 template <class C, bool X3>
@@ -383,7 +387,7 @@ __device__ __forceinline__ void k_loop_pf(Lds<C, X3>& L, const __bf16* a, const 
 constexpr int kBand = 4;
 
 template <class C, bool X3>
-__global__ void __launch_bounds__(C::NT, C::MIN_BLOCKS)
+__global__ void __launch_bounds__(C::NT, C::WPE)
     gemm_bf16_grouped(GemmArgs<float> g, const __bf16* __restrict__ staged, int nprod, int64_t plane) {
   __shared__ Lds<C, X3> L;
   constexpr int WTM = C::WTM, WTN = C::WTN;

@@ -198,7 +198,8 @@ mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int 
  * operation as C = alpha A B) for row-major A (M x K, leading dimension
  * lda >= K), B (K x N, ldb >= N) and C (M x N, ldc >= N), with up to `depth`
  * levels of `algo` (square or rectangular; NULL with depth 0 for the
- * classical product).  A level is taken while levels remain and every
+ * classical product).  M, N, K <= 2^20; lda, ldb <= 2^21 and ldc < 2^31
+ * (MF_ERR_SHAPE beyond).  A level is taken while levels remain and every
  * dimension the algorithm splits exceeds `cutoff` and the 128 leaf tile;
  * dimensions the splits do not divide are padded virtually with zeros.  The
  * scaling is applied where results are written into C (the last

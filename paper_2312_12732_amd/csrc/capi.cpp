@@ -26,6 +26,9 @@ void clear_error() { t_err.clear(); }
 namespace {
 
 constexpr int64_t kMaxN = 1 << 20;
+// Largest lda / ldb of mf_gemm: the GEMM addresses a 128-row operand tile
+// with 32-bit byte offsets from the tile origin (128 x 2^21 x 8 B = 2^31).
+constexpr int64_t kMaxLdAB = 1 << 21;
 
 mf_status new_handle(const Algo& a, mf_algo** out) {
   const int64_t bad = brent_violations(a);
@@ -490,7 +493,8 @@ mf_status mf_gemm(const mf_algo* algo, int depth, int cutoff, int64_t M, int64_t
   if (K == 0) return fail(MF_ERR_SHAPE, "K must be >= 1");
   if (M > kMaxN || N > kMaxN || K > kMaxN) return fail(MF_ERR_SHAPE, "dimensions exceed the supported maximum (2^20)");
   if (lda < K || ldb < N || ldc < N) return fail(MF_ERR_ARG, "leading dimensions must be >= the row lengths");
-  if (lda > INT32_MAX || ldb > INT32_MAX || ldc > INT32_MAX) return fail(MF_ERR_SHAPE, "leading dimensions exceed 2^31 - 1");
+  if (lda > kMaxLdAB || ldb > kMaxLdAB) return fail(MF_ERR_SHAPE, "lda and ldb must be at most 2^21");
+  if (ldc > INT32_MAX) return fail(MF_ERR_SHAPE, "ldc exceeds 2^31 - 1");
   if (!A || !B || !C) return fail(MF_ERR_ARG, "A, B and C must be non-NULL");
   const size_t elem = base == MF_F64 ? 8 : 4;
   if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B) | reinterpret_cast<uintptr_t>(C)) & (elem - 1))

@@ -108,3 +108,6 @@ def test_gemm_argument_checks_before_device_use():
     assert gemm_status(dtype=mf.MF_F32 | mf.MF_LEAF_BF16)[0] == mf.MF_ERR_UNSUPPORTED
     assert gemm_status(alpha=float("nan"))[0] == mf.MF_ERR_ARG
     assert gemm_status(A=(1 << 20) + 4)[0] == mf.MF_ERR_ARG  # misaligned
+    # operand tiles are addressed with 32-bit byte offsets: lda, ldb <= 2^21
+    assert gemm_status(lda=(1 << 21) + 1)[0] == mf.MF_ERR_SHAPE
+    assert gemm_status(ldb=(1 << 21) + 1)[0] == mf.MF_ERR_SHAPE

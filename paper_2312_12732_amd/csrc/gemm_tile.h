@@ -480,15 +480,19 @@ __device__ __forceinline__ void k_loop_masked(T* lds, const T* __restrict__ pa, 
 
 // Epilogue of one product: post-addition of the accumulator tile into every
 // output block the product feeds (first feeder stores, later ones add).
+// acc holds the tile whose origin is (s0, t0); only rows >= i0 and columns
+// >= j0 of it are written (an edge tile moved back into the views, see
+// gemm_tile, leaves the rows and columns before its own origin to the tiles
+// that own them).
 template <class T, class Cfg, bool FULL>
-__device__ __forceinline__ void product_epilogue(const GemmArgs<T>& g, const ProdDesc& pd, int i0, int j0, int wm,
-                                                 int wn, int lr, int lk,
+__device__ __forceinline__ void product_epilogue(const GemmArgs<T>& g, const ProdDesc& pd, int s0, int t0, int i0,
+                                                 int j0, int wm, int wn, int lr, int lk,
                                                  const typename Mfma<T>::v4 (&acc)[Cfg::WM_T][Cfg::WN_T]) {
   constexpr int BM = Cfg::BM, BN = Cfg::BN, WM_T = Cfg::WM_T, WN_T = Cfg::WN_T;
   for (int e = pd.epi_beg; e < pd.epi_end; ++e) {
     const EpiDesc ed = load_uniform(g.epis + e);
     T* pc = dst_ptr(g, ed.c_src) + ed.c_off;
-    const bool full = FULL || ((i0 + BM <= ed.c_vr) && (j0 + BN <= ed.c_vc));
+    const bool full = FULL || (s0 == i0 && t0 == j0 && i0 + BM <= ed.c_vr && j0 + BN <= ed.c_vc);
     const bool to_c = g.scale_c && ed.c_src == SRC_C;
     const T coef = to_c ? (T)ed.coef * g.alpha : (T)ed.coef;
     const T beta = to_c ? g.beta : T(0);
@@ -498,9 +502,9 @@ __device__ __forceinline__ void product_epilogue(const GemmArgs<T>& g, const Pro
       for (int ni = 0; ni < WN_T; ++ni)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = i0 + wm + 16 * mi + Mfma<T>::row(lk, v);
-          const int col = j0 + wn + 16 * ni + lr;
-          if (full || (row < ed.c_vr && col < ed.c_vc))
+          const int row = s0 + wm + 16 * mi + Mfma<T>::row(lk, v);
+          const int col = t0 + wn + 16 * ni + lr;
+          if (full || (row >= i0 && col >= j0 && row < ed.c_vr && col < ed.c_vc))
             epi_apply<T>(pc + (size_t)row * ed.ldc + col, ed.first, coef, acc[mi][ni][v], beta);
         }
   }
@@ -514,13 +518,12 @@ __device__ __forceinline__ void product_epilogue(const GemmArgs<T>& g, const Pro
 template <class T, class Cfg, bool FULL = false>
 __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti, int tj, T* lds) {
   typedef typename Mfma<T>::v4 v4;
-  constexpr int BM = Cfg::BM, BN = Cfg::BN, WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, WAVES_N = Cfg::WAVES_N;
+  constexpr int BM = Cfg::BM, BN = Cfg::BN, WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, WAVES_N = Cfg::WAVES_N, BK = Cfg::BK;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = (wave / WAVES_N) * (16 * WM_T), wn = (wave % WAVES_N) * (16 * WN_T);
   const int lr = lane & 15, lk = lane >> 4;
   const int i0 = ti * BM, j0 = tj * BN;
-  const int KT = g.k / Cfg::BK;
   const int r_beg = load_uniform(g.group_beg + grp), r_end = load_uniform(g.group_beg + grp + 1);
 
   for (int r = r_beg; r < r_end; ++r) {
@@ -529,6 +532,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
     const T* pb = src_ptr(g, pd.b_src) + pd.b_off;
     const bool vec_a = pd.a_src == SRC_WS || g.vec_in;
     const bool vec_b = pd.b_src == SRC_WS || g.vec_in;
+    // The K loop stops at the product's valid inner size: past the A view's
+    // valid columns or the B view's valid rows every term is zero.  (A plan
+    // pads K to whole tiles: a classical product of n = 64 (2q + 1) has
+    // K = n + 64, and its tiles would all miss the LDS-direct path.)
+    const int k_eff = FULL ? g.k : min(g.k, min(pd.a_vc, pd.b_vr));
+    const int KT = FULL ? g.k / BK : (k_eff + BK - 1) / BK;
 
     v4 acc[WM_T][WN_T];
 #pragma unroll
@@ -536,15 +545,39 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
 #pragma unroll
       for (int ni = 0; ni < WN_T; ++ni) acc[mi][ni] = v4{T(0), T(0), T(0), T(0)};
 
-    const bool interior = FULL || (vec_a && vec_b && i0 + BM <= pd.a_vr && pd.a_vc >= g.k && pd.b_vr >= g.k &&
-                                   j0 + BN <= pd.b_vc);
-    if (interior)
-      k_loop_dma<T, Cfg>(lds, pa, pd.lda, pb, pd.ldb, i0, j0, KT, t, wm, wn, lr, lk, acc);
-    else if constexpr (!FULL)
+    // An edge tile of a view at least one tile wide is computed as the whole
+    // tile that ends at the view's last row (column), so that it takes the
+    // LDS-direct path; its epilogue writes only the rows (columns) from i0
+    // (j0) on.  A moved B tile keeps 16-byte aligned rows.  Only where every
+    // output of the product ends inside the moved tile: an output larger
+    // than the operand views (a stored product of zero-padded views) takes
+    // zeros past them, which the masked path writes.
+    int s0 = i0, t0 = j0;
+    if constexpr (!FULL) {
+      if (i0 + BM > pd.a_vr && pd.a_vr >= BM) s0 = pd.a_vr - BM;
+      if (j0 + BN > pd.b_vc && pd.b_vc >= BN && (pd.b_vc * (int)sizeof(T)) % 16 == 0) t0 = pd.b_vc - BN;
+      if (s0 != i0 || t0 != j0)
+        for (int e = pd.epi_beg; e < pd.epi_end; ++e) {
+          const EpiDesc ed = load_uniform(g.epis + e);
+          if (ed.c_vr > s0 + BM || ed.c_vc > t0 + BN) {
+            s0 = i0;
+            t0 = j0;
+            break;
+          }
+        }
+    }
+    const bool interior =
+        FULL || (vec_a && vec_b && s0 + BM <= pd.a_vr && t0 + BN <= pd.b_vc && k_eff >= BK && k_eff % BK == 0);
+    if (interior) {
+      k_loop_dma<T, Cfg>(lds, pa, pd.lda, pb, pd.ldb, s0, t0, KT, t, wm, wn, lr, lk, acc);
+    } else if constexpr (!FULL) {
+      s0 = i0;
+      t0 = j0;
       k_loop_masked<T, Cfg>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn,
                             lr, lk, acc);
+    }
 
-    product_epilogue<T, Cfg, FULL>(g, pd, i0, j0, wm, wn, lr, lk, acc);
+    product_epilogue<T, Cfg, FULL>(g, pd, s0, t0, i0, j0, wm, wn, lr, lk, acc);
   }
 }
 
@@ -701,7 +734,7 @@ __device__ __forceinline__ void gemm_tile_fused(const GemmArgs<T>& g, int grp, i
       k_loop_fused<T, Cfg, NT, false>(lds, g.A, pd.lda, fa, g.B, pd.ldb, fb, i0, j0, KT, t, wm, wn, lr, lk, acc);
     else if constexpr (!FULL)
       k_loop_fused<T, Cfg, NT, true>(lds, g.A, pd.lda, fa, g.B, pd.ldb, fb, i0, j0, KT, t, wm, wn, lr, lk, acc);
-    product_epilogue<T, Cfg, FULL>(g, pd, i0, j0, wm, wn, lr, lk, acc);
+    product_epilogue<T, Cfg, FULL>(g, pd, i0, j0, i0, j0, wm, wn, lr, lk, acc);
   }
 }
 

@@ -123,6 +123,36 @@ def test_alpha_beta_int_exact(name, depth):
     assert np.array_equal(got, want.astype(np.float64))
 
 
+# A tile past a view's last row (column) is computed as the tile that ends at
+# the view's edge when the views are at least one tile wide, the inner size is
+# a whole number of K steps and the outputs end inside that tile; it writes only
+# the rows (columns) it owns.  With beta = 1 an element written twice, or not at
+# all, breaks the exact result.
+EDGE_CASES = [  # algorithm, depth, M, K, N, dtype
+    (None, 0, 200, 208, 336, "f64"),     # rows and columns move
+    (None, 0, 200, 208, 335, "f64"),     # odd N: B rows not 16-byte aligned, columns stay masked
+    (None, 0, 320, 320, 320, "f64"),     # square, both move
+    (None, 0, 1000, 1008, 1111, "f64"),  # rows move, odd N stays masked
+    (None, 0, 100, 96, 260, "f64"),      # fewer rows than a tile: masked; columns move
+    (None, 0, 192, 320, 448, "f32"),     # FP32: both move
+    (None, 0, 700, 200, 129, "f32"),     # K = 200 not a whole number of K steps: masked
+    ("winograd", 1, 400, 416, 464, "f64"),  # stored products of padded views: masked
+    ("hk223", 1, 520, 416, 780, "f64"),     # rectangular algorithm, products into C
+]
+
+
+@pytest.mark.parametrize("name,depth,M,K,N,dt", EDGE_CASES)
+def test_edge_tiles_int_exact(name, depth, M, K, N, dt):
+    print(f"edge tiles {name} depth {depth} {M}x{K}x{N} {dt}", flush=True)
+    A = mi.int_uniform_rect(M, K, 51 + M)
+    B = mi.int_uniform_rect(K, N, 52 + N)
+    C0 = mi.int_uniform_rect(M, N, 53)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    got = run_gemm(name, depth, A.astype(np.float64), B.astype(np.float64), C0.astype(np.float64), 1.0, 1.0, dt=tdt)
+    want = om.classical_mm(A, B) + C0
+    assert np.array_equal(got, want.astype(np.float64))
+
+
 @pytest.mark.parametrize("name,depth", [(None, 0), ("winograd", 2), ("six_233_322", 1)])
 def test_beta_zero_does_not_read_c(name, depth):
     M, K, N = (1536, 1536, 1536) if name == "six_233_322" else (700, 300, 500)

@@ -233,7 +233,9 @@ typedef struct {
   int pre_stages, post_stages;
   int64_t leaf_m;      /* leaf size, a multiple of the 128 GEMM tile */
   int64_t products;    /* R^levels leaf products */
-  double gemm_flops;   /* products * 2 leaf_m^3, as executed (padded) */
+  double gemm_flops;   /* MFMA work as executed: per product 2 leaf_m leaf_n K over whole tiles,
+                          K = the product's valid inner size rounded up to 16 (FP64 / FP32
+                          leaves) or the padded leaf K (BF16 leaves, fused operands) */
   double pre_bytes;    /* algorithmic bytes of all pre-addition stages */
   double post_bytes;   /* algorithmic bytes of all post-addition stages */
   size_t ws_bytes;     /* as mf_workspace_bytes */

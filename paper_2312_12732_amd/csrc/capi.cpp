@@ -1,5 +1,6 @@
 // C ABI of the mf library: argument validation, algorithm handles, plan
 // lookup, workspace and the launch sequence of one fast product.
+#include <algorithm>
 #include <array>
 #include <atomic>
 #include <cmath>
@@ -380,7 +381,18 @@ mf_status mf_plan_query(const mf_algo* algo, int depth, int cutoff, int64_t n, i
   out->post_stages = (int)pl->post.size();
   out->leaf_m = pl->m;
   out->products = (int64_t)pl->prods.size();
-  out->gemm_flops = (double)pl->prods.size() * 2.0 * (double)pl->m * (double)pl->leaf_n * (double)pl->leaf_k;
+  // MFMA work as executed: every output tile of every product, over the
+  // product's valid inner size in whole K steps of 16 (the FP64 / FP32
+  // kernel stops there; the BF16 and fused-operand kernels run the padded K)
+  const int leaf = (pl->dtype >> 8) & 0xff;
+  const bool padded_k = leaf == 2 || leaf == 3 || pl->fused_terms > 0;
+  double flops = 0.0;
+  for (const ProdDesc& pd : pl->prods) {
+    const int64_t k = padded_k ? pl->leaf_k
+                               : std::min<int64_t>(pl->leaf_k, std::min<int64_t>(pd.a_vc, pd.b_vr));
+    flops += 2.0 * (double)pl->m * (double)pl->leaf_n * (double)((k + 15) / 16 * 16);
+  }
+  out->gemm_flops = flops;
   out->pre_bytes = stage_bytes(pl->pre);
   out->post_bytes = stage_bytes(pl->post);
   out->ws_bytes = pl->ws_bytes;

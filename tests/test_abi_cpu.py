@@ -312,6 +312,20 @@ def test_plan_query_closed_forms():
     # materialised child is a whole 512 x 512 workspace block, zeros included, as the leaf GEMM reads it
     q = mf.mf_plan_query(w, 1, 0, 1000)
     assert q["leaf_m"] == 512 and q["pre_bytes"] == 2 * 8 * (1000 * 1000 + 4 * 512 * 512)
+    # padded leaves: whole 128 tiles in rows and columns, the valid inner size
+    # (rounded up to 16) in K for FP64 / FP32 leaves, the padded K for BF16 ones
+    q = mf.mf_plan_query(None, 0, 0, 1040)
+    assert q["leaf_m"] == 1152 and q["gemm_flops"] == 2.0 * 1152 * 1152 * 1040
+    q = mf.mf_plan_query(None, 0, 0, 1037)
+    assert q["gemm_flops"] == 2.0 * 1152 * 1152 * 1040
+    q = mf.mf_plan_query(None, 0, 0, 1040, mf.MF_F32 | mf.MF_LEAF_BF16)
+    assert q["gemm_flops"] == 2.0 * 1152 ** 3
+    # Winograd depth 1 at n = 1040: leaf 640, blocks split at 640, so A12 and A22
+    # have 400 valid columns and B21 and B22 400 valid rows.  M1 = A12 B21,
+    # M2 = (..) B22 and M3 = A22 (..) run K = 400; M0 = A11 B11 and the three
+    # products of two materialised (whole 640 x 640) blocks run K = 640.
+    q = mf.mf_plan_query(w, 1, 0, 1040)
+    assert q["leaf_m"] == 640 and q["gemm_flops"] == 2.0 * 640 * 640 * (4 * 640 + 3 * 400)
 
 
 def test_workspace_bytes_bf16_staging():

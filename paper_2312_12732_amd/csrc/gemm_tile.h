@@ -556,14 +556,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
     if constexpr (!FULL) {
       if (i0 + BM > pd.a_vr && pd.a_vr >= BM) s0 = pd.a_vr - BM;
       if (j0 + BN > pd.b_vc && pd.b_vc >= BN && (pd.b_vc * (int)sizeof(T)) % 16 == 0) t0 = pd.b_vc - BN;
+      // (a moved dimension must cover the outputs up to their end; the other
+      // one is covered by the tile itself)
       if (s0 != i0 || t0 != j0)
         for (int e = pd.epi_beg; e < pd.epi_end; ++e) {
           const EpiDesc ed = load_uniform(g.epis + e);
-          if (ed.c_vr > s0 + BM || ed.c_vc > t0 + BN) {
-            s0 = i0;
-            t0 = j0;
-            break;
-          }
+          if (s0 != i0 && ed.c_vr > s0 + BM) s0 = i0;
+          if (t0 != j0 && ed.c_vc > t0 + BN) t0 = j0;
         }
     }
     const bool interior =

@@ -61,7 +61,11 @@ template <class T, class Cfg>
 struct Geom {
   static constexpr bool F64 = sizeof(T) == 8;
   static constexpr int SA = Cfg::BM + (F64 ? 16 : 4);
-  static constexpr int SB = Cfg::BN + 16;       // FP64 B: k row stride
+  // FP64 B: k row stride.  BN + 8 puts adjacent k rows 16 banks apart: the
+  // K loop unrolled by two steps reads fragments of adjacent k rows in one
+  // ds_read2_b64, which at BN + 16 (rows in the same banks) cost 64 conflict
+  // cycles per K step and workgroup.
+  static constexpr int SB = Cfg::BN + 8;
   static constexpr int PAIR = 2 * Cfg::BN + 8;  // FP32 B: stride of a pair of k rows
   static constexpr int LDS_A = Cfg::BK * SA;
   static constexpr int LDS_B = F64 ? Cfg::BK * SB : Cfg::BK / 2 * PAIR;

@@ -231,9 +231,12 @@ typedef struct {
   int levels_outer;    /* levels whose post-additions run as separate stages */
   int groups;          /* products are grouped by the outer levels */
   int pre_stages, post_stages;
-  int64_t leaf_m;      /* leaf size, a multiple of the 128 GEMM tile */
+  int64_t leaf_m;      /* leaf rows: a multiple of 16 with FP64 / FP32 leaves (the GEMM covers
+                          them with whole 128 x 128 tiles), of 128 with BF16 leaves or fused
+                          operands */
   int64_t products;    /* R^levels leaf products */
-  double gemm_flops;   /* MFMA work as executed: per product 2 leaf_m leaf_n K over whole tiles,
+  double gemm_flops;   /* MFMA work as executed: per product 2 M' N' K, M' and N' the leaf
+                          rows and columns rounded up to whole 128 tiles,
                           K = the product's valid inner size rounded up to 16 (FP64 / FP32
                           leaves) or the padded leaf K (BF16 leaves, fused operands) */
   double pre_bytes;    /* algorithmic bytes of all pre-addition stages */

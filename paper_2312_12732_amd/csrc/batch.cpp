@@ -145,7 +145,7 @@ mf_status build_batch(mf_batch* b, const std::vector<const mf_algo*>& algos, con
       wait_val = count_stage(pl.pre[s]);
     }
     std::vector<BatchTask> gt;
-    const int tiles = (int)(pl.m / kLeafTile);
+    const int tiles = (int)((pl.m + kLeafTile - 1) / kLeafTile);
     for (int g = 0; g < pl.groups; ++g)
       for (int ti = 0; ti < tiles; ++ti)
         for (int tj = 0; tj < tiles; ++tj) {
@@ -210,7 +210,7 @@ mf_status upload_batch(const mf_batch* b) {
     const char* d = pl->desc();
     gemm_recs.push_back(GemmRec{img_at<ProdDesc>(d, pl->img_prods), img_at<EpiDesc>(d, pl->img_epis),
                                 img_at<int32_t>(d, pl->img_group_beg), pl->groups, (int32_t)pl->m,
-                                (int32_t)(pl->m / kLeafTile), 0});
+                                (int32_t)((pl->m + kLeafTile - 1) / kLeafTile), 0});
   }
   auto align = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t st_ = align(b->tasks.size() * sizeof(BatchTask));

@@ -381,16 +381,19 @@ mf_status mf_plan_query(const mf_algo* algo, int depth, int cutoff, int64_t n, i
   out->post_stages = (int)pl->post.size();
   out->leaf_m = pl->m;
   out->products = (int64_t)pl->prods.size();
-  // MFMA work as executed: every output tile of every product, over the
-  // product's valid inner size in whole K steps of 16 (the FP64 / FP32
-  // kernel stops there; the BF16 and fused-operand kernels run the padded K)
+  // MFMA work as executed: every 128 x 128 output tile of every product,
+  // over the product's valid inner size in whole K steps of 16 (the FP64 /
+  // FP32 kernel stops there; the BF16 and fused-operand kernels run the
+  // padded K)
   const int leaf = (pl->dtype >> 8) & 0xff;
   const bool padded_k = leaf == 2 || leaf == 3 || pl->fused_terms > 0;
+  const double tm = (double)((pl->m + kLeafTile - 1) / kLeafTile * kLeafTile);
+  const double tn = (double)((pl->leaf_n + kLeafTile - 1) / kLeafTile * kLeafTile);
   double flops = 0.0;
   for (const ProdDesc& pd : pl->prods) {
     const int64_t k = padded_k ? pl->leaf_k
                                : std::min<int64_t>(pl->leaf_k, std::min<int64_t>(pd.a_vc, pd.b_vr));
-    flops += 2.0 * (double)pl->m * (double)pl->leaf_n * (double)((k + 15) / 16 * 16);
+    flops += 2.0 * tm * tn * (double)((k + 15) / 16 * 16);
   }
   out->gemm_flops = flops;
   out->pre_bytes = stage_bytes(pl->pre);

@@ -50,7 +50,8 @@ using Tile128 = TileCfg<128, 128, 2, 4, 4>;
 // LDS geometry of one element type: two A buffers, then two B buffers.
 //   A, register-staged path: k-major, k row k at k * SA.
 //   A, LDS-direct path: row-major, BM rows of BK elements (same space).
-//   B, both paths: k-major rows of BN elements at b_row(k).
+//   B, both paths: k-major rows of BN elements, at b_row(k) on the
+//   LDS-direct path and at b_row_r(k) on the register-staged one.
 // LDS has 32 four-byte banks and serves 128 bytes per cycle: an FP64
 // fragment read serves 16 lanes (one k row) per cycle, an FP32 one 32 lanes,
 // i.e. the k rows of row groups lk and lk + 1, which kslot puts 4 apart.  For
@@ -61,17 +62,24 @@ template <class T, class Cfg>
 struct Geom {
   static constexpr bool F64 = sizeof(T) == 8;
   static constexpr int SA = Cfg::BM + (F64 ? 16 : 4);
-  // FP64 B: k row stride.  BN + 8 puts adjacent k rows 16 banks apart: the
-  // K loop unrolled by two steps reads fragments of adjacent k rows in one
-  // ds_read2_b64, which at BN + 16 (rows in the same banks) cost 64 conflict
-  // cycles per K step and workgroup.
+  // FP64 B: k row stride of the LDS-direct path.  BN + 8 puts adjacent k
+  // rows 16 banks apart: the K loop unrolled by two steps reads fragments of
+  // adjacent k rows in one ds_read2_b64, which at BN + 16 (rows in the same
+  // banks) cost 64 conflict cycles per K step and workgroup.  The register-
+  // staged path keeps BN + 16 (at BN + 8 its loop ran 8% slower: n = 1037
+  // classical, 0.220 against 0.203 ms).  A tile fills and reads its buffers
+  // in one loop, so the two layouts never meet.
   static constexpr int SB = Cfg::BN + 8;
+  static constexpr int SBR = Cfg::BN + 16;
   static constexpr int PAIR = 2 * Cfg::BN + 8;  // FP32 B: stride of a pair of k rows
   static constexpr int LDS_A = Cfg::BK * SA;
-  static constexpr int LDS_B = F64 ? Cfg::BK * SB : Cfg::BK / 2 * PAIR;
+  static constexpr int LDS_B = F64 ? Cfg::BK * SBR : Cfg::BK / 2 * PAIR;
   static constexpr int ELEMS = 2 * (LDS_A + LDS_B);
   static_assert(Cfg::BM * Cfg::BK <= LDS_A, "the row-major A tile fits an A buffer");
   static __device__ __forceinline__ int b_row(int k) { return F64 ? k * SB : (k >> 1) * PAIR + (k & 1) * Cfg::BN; }
+  static __device__ __forceinline__ int b_row_r(int k) {
+    return F64 ? k * SBR : (k >> 1) * PAIR + (k & 1) * Cfg::BN;
+  }
 };
 
 // Element pair idx of the A tile -> (row, kp): the pair A[row][kp..kp+1].
@@ -232,7 +240,7 @@ __device__ __forceinline__ void store_tiles(T* As, T* Bs, int t, const typename 
   for (int q = 0; q < Cfg::LPT_B; ++q) {
     int kr, cp;
     b_slot<T, Cfg>(t + Cfg::NTHREADS * q, kr, cp);
-    *reinterpret_cast<v2*>(Bs + Geom<T, Cfg>::b_row(kr) + cp) = rb[q];
+    *reinterpret_cast<v2*>(Bs + Geom<T, Cfg>::b_row_r(kr) + cp) = rb[q];
   }
 }
 
@@ -264,7 +272,7 @@ __device__ __forceinline__ void load_frags(const T* As, const T* Bs, int s, int 
 #pragma unroll
   for (int mi = 0; mi < Cfg::WM_T; ++mi) fa[mi] = As[k * Geom<T, Cfg>::SA + wm + 16 * mi + lr];
 #pragma unroll
-  for (int ni = 0; ni < Cfg::WN_T; ++ni) fb[ni] = Bs[Geom<T, Cfg>::b_row(k) + wn + 16 * ni + lr];
+  for (int ni = 0; ni < Cfg::WN_T; ++ni) fb[ni] = Bs[Geom<T, Cfg>::b_row_r(k) + wn + 16 * ni + lr];
 }
 
 // LDS-direct geometry of one element type: P elements per 16-byte piece,

@@ -228,7 +228,7 @@ static hipError_t launch_combine_t(const CombineStage& cs, const char* desc, con
   g.scale_c = sc.plain() ? 0 : 1;
   g.alpha = (T)sc.alpha;
   g.beta = (T)sc.beta;
-  // every set's block size is a multiple of the leaf tile, so of every VEC
+  // every set's block size is a multiple of the leaf step (16), so of every VEC
   const int64_t mm = cs.kron3 ? cs.m * cs.m : cs.elems_max;
   auto grid = [&](int vec) { return dim3((unsigned)((mm / vec + 255) / 256), (unsigned)cs.sets.size(), 1); };
   if (cs.kron3) {

@@ -74,11 +74,13 @@ static hipError_t launch_fused(GemmArgs<T> g, bool full, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Whether every operand view and epilogue output of the plan covers its whole
-// m x m block with 16-byte aligned rows (then the kernel without the masked
-// paths runs; true for sizes the splits divide into whole tiles).
+// Whether the leaves are whole tiles and every operand view and epilogue
+// output of the plan covers its whole m x m block with 16-byte aligned rows
+// (then the kernel without the masked paths runs; true for sizes the splits
+// divide into whole tiles).
 static bool plan_full(const Plan& pl, size_t elem, bool vec_in) {
   const int64_t m = pl.m, n = pl.leaf_n, k = pl.leaf_k;
+  if (m % kLeafTile || n % kLeafTile) return false;  // edge tiles: the general kernel
   for (const ProdDesc& pd : pl.prods) {
     const bool va = pd.a_src == SRC_WS || vec_in, vb = pd.b_src == SRC_WS || vec_in;
     if (!va || !vb || pd.a_vr < m || pd.a_vc < k || pd.b_vr < k || pd.b_vc < n) return false;
@@ -91,8 +93,8 @@ static bool plan_full(const Plan& pl, size_t elem, bool vec_in) {
 
 template <class T, class Cfg, bool FULL>
 static hipError_t launch_tiles(GemmArgs<T> g, hipStream_t s) {
-  g.tiles_m = g.m / Cfg::BM;
-  g.tiles_n = g.n / Cfg::BN;
+  g.tiles_m = (g.m + Cfg::BM - 1) / Cfg::BM;
+  g.tiles_n = (g.n + Cfg::BN - 1) / Cfg::BN;
   const unsigned grid = (unsigned)g.tiles_m * (unsigned)g.tiles_n * (unsigned)g.groups;
   hipLaunchKernelGGL((gemm_grouped<T, Cfg, FULL>), dim3(grid), dim3(Cfg::NTHREADS), 0, s, g);
   return hipGetLastError();

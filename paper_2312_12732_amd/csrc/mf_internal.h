@@ -343,6 +343,11 @@ void drop_plans(uint64_t algo_id);
 
 // Leaf tile granularity: every leaf size is a multiple of this.
 constexpr int kLeafTile = 128;
+// Leaf sizes of plans with FP64 / FP32 leaves and stored products are
+// multiples of kLeafStep (whole K steps of the GEMM, 16-byte rows); the GEMM
+// covers a leaf with ceil(size / 128) tiles, the last one moved inside the
+// block.  BF16 leaves and fused-operand plans use whole tiles (kLeafTile).
+constexpr int kLeafStep = 16;
 
 // Number of recursion levels the plan of a product of this shape takes for
 // an algorithm with splits (m0, k0, n0) and rank R at the requested depth and

@@ -120,10 +120,15 @@ void finish_set(CombineStage* st, CombSet set, int64_t rows, int64_t cols) {
   st->sets.push_back(set);
 }
 
+// Granule of the leaf sizes of a stored-product plan (see kLeafStep).
+int64_t leaf_granule(int dtype);
+
 bool bf16_leaves(int dtype) {
   const int leaf = (dtype >> 8) & 0xff;
   return leaf == 2 || leaf == 3;
 }
+
+int64_t leaf_granule(int dtype) { return bf16_leaves(dtype) ? kLeafTile : kLeafStep; }
 
 // BF16 leaves: reserve the staged operands (see Plan::bf_base) after
 // everything else in the workspace, and list the outputs of every staging
@@ -164,9 +169,10 @@ int32_t add_stage_set(Plan* pl, int side, const std::vector<Blk>& q) {
 mf_status build_classical(const Shape& sh, Plan* pl) {
   pl->P = pl->P_outer = 1;
   pl->R = pl->groups = 1;
-  pl->m = pl->m_outer = round_up(sh.M, kLeafTile);
-  pl->leaf_n = round_up(sh.N, kLeafTile);
-  pl->leaf_k = round_up(sh.K, kLeafTile);
+  const int64_t g = leaf_granule(pl->dtype);
+  pl->m = pl->m_outer = round_up(sh.M, g);
+  pl->leaf_n = round_up(sh.N, g);
+  pl->leaf_k = round_up(sh.K, g);
   pl->npad = pl->m;
   ProdDesc pd{};
   pd.a_src = SRC_A;
@@ -398,13 +404,14 @@ mf_status build(const Algo* algo, int depth, int cutoff, const Shape& sh, int dt
     if (!stage_supported(p2_last)) return fail(MF_ERR_UNSUPPORTED, "no BF16 staging kernel for this algorithm shape");
     pl->bf_nin = p2_last;
   }
-  // leaf sizes: rows, columns and inner size, each a multiple of the tile
-  pl->m = round_up((sh.M + Pm - 1) / Pm, kLeafTile);
-  pl->leaf_n = round_up((sh.N + Pn - 1) / Pn, kLeafTile);
-  pl->leaf_k = round_up((sh.K + Pk - 1) / Pk, kLeafTile);
+  // leaf sizes: rows, columns and inner size, each a multiple of the granule
+  const int64_t lg = leaf_granule(dtype);
+  pl->m = round_up((sh.M + Pm - 1) / Pm, lg);
+  pl->leaf_n = round_up((sh.N + Pn - 1) / Pn, lg);
+  pl->leaf_k = round_up((sh.K + Pk - 1) / Pk, lg);
   pl->npad = pl->m * Pm;
   const int64_t m = pl->m, mn = pl->leaf_n, mk = pl->leaf_k;
-  const int64_t positions = (m / kLeafTile) * (mn / kLeafTile);
+  const int64_t positions = ((m + kLeafTile - 1) / kLeafTile) * ((mn + kLeafTile - 1) / kLeafTile);
 
   // Outer levels split off as groups (with post-addition stages) until the
   // grouped GEMM has enough workgroups; the inner levels run as one composed

@@ -122,7 +122,8 @@ def expected_ws(n, depth, mat_u, mat_v, R=7, p=2, min_wg=1 << 62):
     """Closed form of the executor's workspace (elements of 8 bytes):
     level l of the pre-additions materialises mat_u + mat_v children of each
     of the R^(l-1) parents, each of size (n'/p^l)^2 (n' = p^d * m, m = n/p^d
-    rounded up to the 128 tile); when the (m/128)^2 tile positions times
+    rounded up to 16, the leaf step of FP64 / FP32 leaves); when the
+    ceil(m/128)^2 tile positions times
     R^lo groups first reach min_wg workgroups at lo outer levels (a
     standalone product takes every level: lo = d), every group keeps a result
     block of size (m p^(d-lo))^2 and every post-addition parent below the
@@ -132,13 +133,13 @@ def expected_ws(n, depth, mat_u, mat_v, R=7, p=2, min_wg=1 << 62):
         size, d = -(-size // p), d + 1
     depth = d
     P = p ** depth
-    m = 128 * -(-(-(-n // P)) // 128)
+    m = 16 * -(-(-(-n // P)) // 16)
     npad = P * m
     elems = 0
     for lev in range(1, depth + 1):
         s = npad // p ** lev
         elems += (mat_u + mat_v) * R ** (lev - 1) * s * s
-    pos = (m // 128) ** 2
+    pos = (-(-m // 128)) ** 2
     lo = 0
     while lo < depth and pos * R ** lo < min_wg:
         lo += 1
@@ -166,7 +167,7 @@ def test_workspace_bytes_closed_form():
     assert mf.mf_workspace_bytes(s, 3, 0, 8192) == 8 * (8 * 4096 ** 2 + 56 * 2048 ** 2 + 392 * 1024 ** 2
                                                          + 343 * 1024 ** 2 + 49 * 2048 ** 2 + 7 * 4096 ** 2)
     assert mf.mf_workspace_bytes(s, 3, 0, 8192) == expected_ws(8192, 3, 4, 4)
-    # ragged: n = 1000, leaf size rounded up to the 128 tile (500 -> 512)
+    # ragged: n = 1000, leaf size rounded up to 16 (500 -> 512)
     assert mf.mf_workspace_bytes(s, 1, 0, 1000) == expected_ws(1000, 1, 4, 4)
     assert mf.mf_workspace_bytes(s, 2, 0, 1000) == expected_ws(1000, 2, 4, 4)
     # classical (depth 0 or cutoff >= n) needs no workspace
@@ -175,7 +176,7 @@ def test_workspace_bytes_closed_form():
     # classical <3,3,3;27>: every column is a single block, no pre-addition;
     # 484 tile positions < 1024, so each product is its own group
     c3 = mf.mf_workspace_bytes(mf.mf_algo_builtin("classical3"), 1, 0, 8192)
-    assert c3 == expected_ws(8192, 1, 0, 0, R=27, p=3) == 27 * 2816 ** 2 * 8
+    assert c3 == expected_ws(8192, 1, 0, 0, R=27, p=3) == 27 * 2736 ** 2 * 8
     # Winograd: also 4 materialised columns in U and in V
     w = mf.mf_algo_builtin("winograd")
     assert mf.mf_workspace_bytes(w, 1, 0, 4096) == expected_ws(4096, 1, 4, 4)
@@ -192,7 +193,8 @@ def test_workspace_bytes_paper_size_24012():
     # matrix.  This executor materialises 4 + 4 blocks and stores the 7
     # products at depth 1.
     s = mf.mf_algo_builtin("strassen")
-    m = 128 * -(-12006 // 128)
+    m = 16 * -(-12006 // 16)
+    assert m == 12016
     assert mf.mf_workspace_bytes(s, 1, 0, 24012) == 8 * (8 + 7) * m * m
 
 
@@ -307,25 +309,28 @@ def test_plan_query_closed_forms():
         post = sum(8 * 7 ** lv * (7 + 4) * (n >> (lv + 1)) ** 2 for lv in range(lo))
         assert q["post_bytes"] == post
     c = mf.mf_plan_query(None, 0, 0, 1000)
-    assert c["levels"] == 0 and c["products"] == 1 and c["leaf_m"] == 1024 and c["pre_bytes"] == 0
+    assert c["levels"] == 0 and c["products"] == 1 and c["leaf_m"] == 1008 and c["pre_bytes"] == 0
     # virtual padding: the inputs count only their valid elements (n = 1000: quarters of 500 x 500), while a
     # materialised child is a whole 512 x 512 workspace block, zeros included, as the leaf GEMM reads it
     q = mf.mf_plan_query(w, 1, 0, 1000)
     assert q["leaf_m"] == 512 and q["pre_bytes"] == 2 * 8 * (1000 * 1000 + 4 * 512 * 512)
-    # padded leaves: whole 128 tiles in rows and columns, the valid inner size
-    # (rounded up to 16) in K for FP64 / FP32 leaves, the padded K for BF16 ones
+    # padded leaves: leaf sizes in steps of 16 (FP64 / FP32 leaves) or whole
+    # 128 tiles (BF16 leaves); executed work over whole 128 tiles in rows and
+    # columns, the valid inner size (rounded up to 16) in K for FP64 / FP32
+    # leaves, the padded K for BF16 ones
     q = mf.mf_plan_query(None, 0, 0, 1040)
-    assert q["leaf_m"] == 1152 and q["gemm_flops"] == 2.0 * 1152 * 1152 * 1040
+    assert q["leaf_m"] == 1040 and q["gemm_flops"] == 2.0 * 1152 * 1152 * 1040
     q = mf.mf_plan_query(None, 0, 0, 1037)
-    assert q["gemm_flops"] == 2.0 * 1152 * 1152 * 1040
+    assert q["leaf_m"] == 1040 and q["gemm_flops"] == 2.0 * 1152 * 1152 * 1040
     q = mf.mf_plan_query(None, 0, 0, 1040, mf.MF_F32 | mf.MF_LEAF_BF16)
-    assert q["gemm_flops"] == 2.0 * 1152 ** 3
-    # Winograd depth 1 at n = 1040: leaf 640, blocks split at 640, so A12 and A22
-    # have 400 valid columns and B21 and B22 400 valid rows.  M1 = A12 B21,
-    # M2 = (..) B22 and M3 = A22 (..) run K = 400; M0 = A11 B11 and the three
-    # products of two materialised (whole 640 x 640) blocks run K = 640.
+    assert q["leaf_m"] == 1152 and q["gemm_flops"] == 2.0 * 1152 ** 3
+    # Winograd depth 1 at n = 1040: leaf 528, blocks split at 528, so A12 and A22
+    # have 512 valid columns and B21 and B22 512 valid rows.  M1 = A12 B21,
+    # M2 = (..) B22 and M3 = A22 (..) run K = 512; M0 = A11 B11 and the three
+    # products of two materialised (whole 528 x 528) blocks run K = 528, each
+    # over 5 x 5 tiles.
     q = mf.mf_plan_query(w, 1, 0, 1040)
-    assert q["leaf_m"] == 640 and q["gemm_flops"] == 2.0 * 640 * 640 * (4 * 640 + 3 * 400)
+    assert q["leaf_m"] == 528 and q["gemm_flops"] == 2.0 * 640 * 640 * (4 * 528 + 3 * 512)
 
 
 def test_workspace_bytes_bf16_staging():
@@ -368,14 +373,14 @@ def test_kron3_plan_closed_form():
 
 @pytest.mark.parametrize("n", [1000, 1001, 1024, 8000])
 def test_kron3_plan_closed_form_ragged(n):
-    """Sizes that 8 x the 128 leaf tile does not divide: the leaf is padded to
-    m = 128 * ceil(ceil(n / 8) / 128).  Input views exclude the virtual padding,
+    """Sizes that 8 x the 16 leaf step does not divide: the leaf is padded to
+    m = 16 * ceil(ceil(n / 8) / 16).  Input views exclude the virtual padding,
     so the quarters of A and B still total n^2 elements read; workspace blocks
     are written whole (m^2 each, zeros in the padding); C is written over its
     n^2 valid elements."""
     w = mf.mf_algo_builtin("winograd")
     c8 = mf.mf_algo_compose(mf.mf_algo_compose(w, w), w)
-    m = 128 * -(-(-(-n // 8)) // 128)
+    m = 16 * -(-(-(-n // 8)) // 16)
     for dtype, eb in ((mf.MF_F64, 8), (mf.MF_F32, 4)):
         q = mf.mf_plan_query(c8, 1, 0, n, dtype)
         assert q["leaf_m"] == m and q["products"] == 343
@@ -445,12 +450,12 @@ def test_mixed_factor_composition_brent_and_shape():
         assert a.info()["n0"] == 6 and a.info()["R"] == 189
         q = mf.mf_plan_query(a, 1, 0, 2048)
         assert q["levels"] == 2 and q["products"] == 189
-        # leaf: ceil(2048 / 6) = 342 rounded up to the 128 tile
-        assert q["leaf_m"] == 384
+        # leaf: ceil(2048 / 6) = 342 rounded up to the leaf step of 16
+        assert q["leaf_m"] == 352
 
 
 def test_mixed_factor_workspace_by_order():
-    """Workspace of the two orders at n = 2048 (m = 384, n' = 6 m), in m^2
+    """Workspace of the two orders at n = 2048 (m = 352, n' = 6 m), in m^2
     elements: Strassen first materialises 4 + 4 blocks of (3m)^2 at level 1
     (the classical level aliases every block), stores 189 products and 7
     level-1 parents of (3m)^2: 72 + 189 + 63 = 324.  Classical first aliases
@@ -458,7 +463,7 @@ def test_mixed_factor_workspace_by_order():
     products and 27 parents of (2m)^2: 216 + 189 + 108 = 513."""
     s = mf.mf_algo_builtin("strassen")
     c3 = mf.mf_algo_builtin("classical3")
-    m = 384
+    m = 352
     assert mf.mf_workspace_bytes(mf.mf_algo_compose(s, c3), 1, 0, 2048) == 8 * 324 * m * m
     assert mf.mf_workspace_bytes(mf.mf_algo_compose(c3, s), 1, 0, 2048) == 8 * 513 * m * m
 

@@ -392,6 +392,11 @@ mf_status build(const Algo* algo, int depth, int cutoff, const Shape& sh, int dt
   }
 
   const bool kron3 = is_kron3(*seq[0]);
+  // A view of the caller's A (B) whose rows are not 16-byte aligned keeps
+  // every GEMM tile reading it on the masked path; at the first level such a
+  // view is copied into a workspace block (a one-term combination) instead of
+  // aliased, so that every leaf operand has aligned rows.
+  const bool unaligned_in[2] = {(sh.lda * (int64_t)pl->elem) % 16 != 0, (sh.ldb * (int64_t)pl->elem) % 16 != 0};
   int64_t Pm = 1, Pk = 1, Pn = 1;
   for (const Algo* f : seq) {
     Pm *= f->m0;
@@ -535,7 +540,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, const Shape& sh, int dt
             Blk child;
             if (nnz == 0) {
               child.zero = true;
-            } else if (nnz == 1) {
+            } else if (nnz == 1 && !(lev == 1 && unaligned_in[side])) {
               child = q[last];
               child.scale = b.scale * X[(size_t)last * R + r];
             } else {

@@ -382,11 +382,40 @@ def test_kron3_plan_closed_form_ragged(n):
     c8 = mf.mf_algo_compose(mf.mf_algo_compose(w, w), w)
     m = 16 * -(-(-(-n // 8)) // 16)
     for dtype, eb in ((mf.MF_F64, 8), (mf.MF_F32, 4)):
+        # rows of A and B not 16-byte aligned (n = 1001): the 27 aliased
+        # operands per side are copied too, so all 343 are stored
+        stored = 343 if (n * eb) % 16 else 316
         q = mf.mf_plan_query(c8, 1, 0, n, dtype)
         assert q["leaf_m"] == m and q["products"] == 343
-        assert q["pre_bytes"] == 2 * eb * (n * n + 316 * m * m)
+        assert q["pre_bytes"] == 2 * eb * (n * n + stored * m * m)
         assert q["post_bytes"] == eb * (343 * m * m + n * n)
-        assert mf.mf_workspace_bytes(c8, 1, 0, n, dtype) == (2 * 316 + 343) * m * m * eb
+        assert mf.mf_workspace_bytes(c8, 1, 0, n, dtype) == (2 * stored + 343) * m * m * eb
+
+
+def test_unaligned_rows_copy_aliased_views_at_the_first_level():
+    """Rows of A and B that are not 16-byte aligned (odd n in FP64, n not a
+    multiple of 4 in FP32): the first level copies its aliased quarters into
+    workspace blocks (Winograd: 3 per side besides the 4 combinations), so
+    every leaf operand has aligned rows; deeper levels and aligned requests
+    alias as before."""
+    w = mf.mf_algo_builtin("winograd")
+    m = 512  # ceil(1001 / 2) = 501 rounded up to 16
+    q = mf.mf_plan_query(w, 1, 0, 1001)  # 8008-byte rows
+    assert q["leaf_m"] == m and q["pre_bytes"] == 2 * 8 * (1001 * 1001 + 7 * m * m)
+    assert mf.mf_workspace_bytes(w, 1, 0, 1001) == 8 * (7 + 7 + 7) * m * m
+    q = mf.mf_plan_query(w, 1, 0, 1002)  # 8016-byte rows: aligned
+    assert q["pre_bytes"] == 2 * 8 * (1002 * 1002 + 4 * m * m)
+    assert mf.mf_workspace_bytes(w, 1, 0, 1002) == 8 * (4 + 4 + 7) * m * m
+    q = mf.mf_plan_query(w, 1, 0, 1002, mf.MF_F32)  # 4008-byte rows: not aligned in FP32
+    assert q["pre_bytes"] == 2 * 4 * (1002 * 1002 + 7 * m * m)
+    # depth 2: level 2 splits workspace blocks only, so it aliases as before
+    q1 = mf.mf_plan_query(w, 2, 0, 2001)
+    q0 = mf.mf_plan_query(w, 2, 0, 2002)
+    m2 = 16 * -(-(-(-2001 // 4)) // 16)
+    assert q1["leaf_m"] == q0["leaf_m"] == m2
+    # three more first-level blocks per side; the second level is unchanged
+    assert (mf.mf_workspace_bytes(w, 2, 0, 2001) - mf.mf_workspace_bytes(w, 2, 0, 2002)
+            == 8 * 2 * 3 * (2 * m2) ** 2)
 
 
 @pytest.mark.parametrize("table", ["WINOGRAD", "STRASSEN_PAPER", "STRASSEN_1969"])

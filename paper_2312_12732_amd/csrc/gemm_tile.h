@@ -545,9 +545,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
     const bool vec_a = pd.a_src == SRC_WS || g.vec_in;
     const bool vec_b = pd.b_src == SRC_WS || g.vec_in;
     // The K loop stops at the product's valid inner size: past the A view's
-    // valid columns or the B view's valid rows every term is zero.  (A plan
-    // pads K to whole tiles: a classical product of n = 64 (2q + 1) has
-    // K = n + 64, and its tiles would all miss the LDS-direct path.)
+    // valid columns or the B view's valid rows every term is zero.  (The leaf
+    // K is padded, and a product of zero-padded views is valid over less of
+    // it; only a valid size of whole K steps takes the LDS-direct path.)
     const int k_eff = FULL ? g.k : min(g.k, min(pd.a_vc, pd.b_vr));
     const int KT = FULL ? g.k / BK : (k_eff + BK - 1) / BK;
 

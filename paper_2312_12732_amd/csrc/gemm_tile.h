@@ -407,31 +407,61 @@ __device__ __forceinline__ void k_loop_dma(T* lds, const T* __restrict__ pa, int
     if (kt < KT) step(kt, 0);
   } else {
     // FP32: one A read per K step serves all four k-steps; the next step's
-    // is read after the barrier into a second set
+    // is read after the barrier into the other set.  At four waves per SIMD
+    // two K steps run per iteration, so that each step's buffer and A set are
+    // constants; the six-wave budget (80 VGPRs) keeps one step per iteration,
+    // since unrolled it spills 21 VGPRs.
     vp fa[WM_T], fn[WM_T];
     read_a(a_buf(0), 0, fa);
     read_b(b_buf(0), 0, fb[0]);
-    for (int kt = 0; kt < KT; ++kt) {
-      const int cur = kt & 1;
+    if constexpr (Cfg::WAVES_PER_SIMD > 4) {
+      for (int kt = 0; kt < KT; ++kt) {
+        const int cur = kt & 1;
+        const bool more = kt + 1 < KT;
+        if (more) issue((kt + 1) * BK, cur ^ 1);
+        const T* Bs = b_buf(cur);
+        read_b(Bs, 1, fb[1]);
+        mma(fa, 0, fb[0]);
+        read_b(Bs, 2, fb[0]);
+        mma(fa, 1, fb[1]);
+        read_b(Bs, 3, fb[1]);
+        mma(fa, 2, fb[0]);
+        wait_vmcnt<0>();
+        __syncthreads();
+        if (more) {
+          read_a(a_buf(cur ^ 1), 0, fn);
+          read_b(b_buf(cur ^ 1), 0, fb[0]);
+        }
+        mma(fa, 3, fb[1]);
+#pragma unroll
+        for (int mi = 0; mi < WM_T; ++mi) fa[mi] = fn[mi];
+      }
+      return;
+    }
+    auto step = [&](int kt, int cur, vp(&fx)[WM_T], vp(&fy)[WM_T]) {
       const bool more = kt + 1 < KT;
       if (more) issue((kt + 1) * BK, cur ^ 1);
       const T* Bs = b_buf(cur);
       read_b(Bs, 1, fb[1]);
-      mma(fa, 0, fb[0]);
+      mma(fx, 0, fb[0]);
       read_b(Bs, 2, fb[0]);
-      mma(fa, 1, fb[1]);
+      mma(fx, 1, fb[1]);
       read_b(Bs, 3, fb[1]);
-      mma(fa, 2, fb[0]);
+      mma(fx, 2, fb[0]);
       wait_vmcnt<0>();
       __syncthreads();
       if (more) {
-        read_a(a_buf(cur ^ 1), 0, fn);
+        read_a(a_buf(cur ^ 1), 0, fy);
         read_b(b_buf(cur ^ 1), 0, fb[0]);
       }
-      mma(fa, 3, fb[1]);
-#pragma unroll
-      for (int mi = 0; mi < WM_T; ++mi) fa[mi] = fn[mi];
+      mma(fx, 3, fb[1]);
+    };
+    int kt = 0;
+    for (; kt + 1 < KT; kt += 2) {
+      step(kt, 0, fa, fn);
+      step(kt + 1, 1, fn, fa);
     }
+    if (kt < KT) step(kt, 0, fa, fn);
   }
 }
 

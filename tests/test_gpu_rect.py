@@ -153,6 +153,26 @@ def test_edge_tiles_int_exact(name, depth, M, K, N, dt):
     assert np.array_equal(got, want.astype(np.float64))
 
 
+def test_random_shapes_int_exact():
+    """Seeded sweep over shapes that mix every tile case: sizes below and above
+    one tile, odd and even (rows of A, B and C aligned to 16 bytes or not),
+    inner sizes that are or are not whole K steps, classical and one or two
+    levels of Winograd and of a rectangular algorithm, FP64 and FP32, beta = 1
+    so that an element written twice or not at all breaks the exact result."""
+    rng = np.random.default_rng(2024)
+    for case in range(24):
+        M, K, N = (int(x) for x in rng.integers(60, 700, size=3))
+        name, depth = [(None, 0), ("winograd", 1), ("winograd", 2), ("hk223", 1)][case % 4]
+        tdt = torch.float64 if case % 3 else torch.float32
+        print(f"random shape {case}: {name} depth {depth} {M}x{K}x{N} {tdt}", flush=True)
+        A = mi.int_uniform_rect(M, K, 300 + case)
+        B = mi.int_uniform_rect(K, N, 400 + case)
+        C0 = mi.int_uniform_rect(M, N, 500 + case)
+        got = run_gemm(name, depth, A.astype(np.float64), B.astype(np.float64), C0.astype(np.float64), 1.0, 1.0,
+                       dt=tdt)
+        assert np.array_equal(got, (om.classical_mm(A, B) + C0).astype(np.float64)), (case, name, depth, M, K, N)
+
+
 @pytest.mark.parametrize("name,depth", [(None, 0), ("winograd", 2), ("six_233_322", 1)])
 def test_beta_zero_does_not_read_c(name, depth):
     M, K, N = (1536, 1536, 1536) if name == "six_233_322" else (700, 300, 500)

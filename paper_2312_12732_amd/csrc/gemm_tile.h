@@ -474,13 +474,13 @@ __device__ __forceinline__ void mfma_step(const T (&fa)[Cfg::WM_T], const T (&fb
     for (int ni = 0; ni < Cfg::WN_T; ++ni) acc[mi][ni] = Mfma<T>::op(fa[mi], fb[ni], acc[mi][ni]);
 }
 
-// Edge tiles: acc = A_view(i0.., :) * B_view(:, j0..) over K = KT * BK with
-// masked loads through registers (entries outside the views are zero).  lds
-// holds the two A buffers (k-major), then the two B buffers.
+// Edge tiles: acc += A_view(i0.., k) * B_view(k, j0..) over K steps kt0 ..
+// KT - 1 with masked loads through registers (entries outside the views are
+// zero).  lds holds the two A buffers (k-major), then the two B buffers.
 template <class T, class Cfg>
 __device__ __forceinline__ void k_loop_masked(T* lds, const T* __restrict__ pa, int lda, int a_vr, int a_vc,
                                               const T* __restrict__ pb, int ldb, int b_vr, int b_vc, int i0, int j0,
-                                              int KT, int t, int wm, int wn, int lr, int lk,
+                                              int kt0, int KT, int t, int wm, int wn, int lr, int lk,
                                               typename Mfma<T>::v4 (&acc)[Cfg::WM_T][Cfg::WN_T]) {
   constexpr int WM_T = Cfg::WM_T, WN_T = Cfg::WN_T, BK = Cfg::BK;
   typename Mfma<T>::v2 ra[Cfg::LPT_A], rb[Cfg::LPT_B];
@@ -488,15 +488,15 @@ __device__ __forceinline__ void k_loop_masked(T* lds, const T* __restrict__ pa, 
   auto a_buf = [&](int b) { return lds + b * Geom<T, Cfg>::LDS_A; };
   auto b_buf = [&](int b) { return lds + 2 * Geom<T, Cfg>::LDS_A + b * Geom<T, Cfg>::LDS_B; };
   constexpr int S = BK / 4;  // MFMA k-steps per K step
-  load(0);
+  load(kt0 * BK);
   store_tiles<T, Cfg>(a_buf(0), b_buf(0), t, ra, rb);
   __syncthreads();
   // fragments double-buffered: the reads of k-step s + 1 are issued before
   // the MFMAs of k-step s
   T fa[2][WM_T], fb[2][WN_T];
   load_frags<T, Cfg>(a_buf(0), b_buf(0), 0, wm, wn, lr, lk, fa[0], fb[0]);
-  for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
+  for (int kt = kt0; kt < KT; ++kt) {
+    const int cur = (kt - kt0) & 1;
     const bool more = kt + 1 < KT;
     if (more) load((kt + 1) * BK);
     const T* As = a_buf(cur);
@@ -607,16 +607,24 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs<T>& g, int grp, int ti,
           if (t0 != j0 && ed.c_vc > t0 + BN) t0 = j0;
         }
     }
-    const bool interior =
-        FULL || (vec_a && vec_b && s0 + BM <= pd.a_vr && t0 + BN <= pd.b_vc && k_eff >= BK && k_eff % BK == 0);
+    // whole K steps take the LDS-direct path and a last partial one the
+    // masked loop (every LDS read of the first loop ends before its last
+    // barrier, so the second may refill the buffers in its own layout; both
+    // feed the MFMAs in the same k order)
+    const int KTf = FULL ? KT : k_eff / BK;
+    const bool interior = FULL || (vec_a && vec_b && s0 + BM <= pd.a_vr && t0 + BN <= pd.b_vc && KTf >= 1);
+    int kt0 = 0;  // first K step of the masked loop
     if (interior) {
-      k_loop_dma<T, Cfg>(lds, pa, pd.lda, pb, pd.ldb, s0, t0, KT, t, wm, wn, lr, lk, acc);
-    } else if constexpr (!FULL) {
+      k_loop_dma<T, Cfg>(lds, pa, pd.lda, pb, pd.ldb, s0, t0, KTf, t, wm, wn, lr, lk, acc);
+      kt0 = KTf;
+    } else {
       s0 = i0;
       t0 = j0;
-      k_loop_masked<T, Cfg>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, i0, j0, KT, t, wm, wn,
-                            lr, lk, acc);
     }
+    if constexpr (!FULL)
+      if (kt0 < KT)
+        k_loop_masked<T, Cfg>(lds, pa, pd.lda, pd.a_vr, pd.a_vc, pb, pd.ldb, pd.b_vr, pd.b_vc, s0, t0, kt0, KT, t, wm,
+                              wn, lr, lk, acc);
 
     product_epilogue<T, Cfg, FULL>(g, pd, s0, t0, i0, j0, wm, wn, lr, lk, acc);
   }

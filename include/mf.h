@@ -191,7 +191,10 @@ mf_status mf_fastmm(const mf_algo* algo, int depth, int cutoff, const void* A, c
  * C_ij = sum_k A_ik B_kj (Section 2, equation "basic"; the same product as
  * the classical blocked recursion of equation "recursion").  dtype as for
  * mf_fastmm.  BF16 leaves stage the operands in workspace from the library's
- * pool. */
+ * pool.  Rows that are not 16-byte aligned (n odd in FP64, not a multiple of
+ * 4 in FP32) are copied, for n >= 192, into aligned workspace blocks from
+ * that pool first (one launch; the GEMM then loads whole K steps straight
+ * into LDS). */
 mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int dtype, mf_stream stream);
 
 /* The general product C = alpha A B + beta C (Section 3 states the
@@ -208,15 +211,19 @@ mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int 
  * precision leaves are available through mf_fastmm).  M or N = 0: nothing to
  * do; K = 0: MF_ERR_SHAPE.  C must not overlap A or B (MF_ERR_ARG, by the
  * byte ranges the three views span).  Workspace from the library's pool, as
- * for mf_fastmm. */
+ * for mf_fastmm; a classical product whose A or B rows are not 16-byte
+ * aligned copies both operands into it first when M, N and K are all at
+ * least 192. */
 mf_status mf_gemm(const mf_algo* algo, int depth, int cutoff, int64_t M, int64_t N, int64_t K, double alpha,
                   const void* A, int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
                   int dtype, mf_stream stream);
 
 /* Bytes of device workspace mf_fastmm_ws needs for this request (0 for a
- * classical product with leaves in the storage type; BF16 leaves stage every
- * leaf operand as BF16 planes, and their last pre-addition level writes those
- * planes directly, so its FP32 sums take no workspace). */
+ * classical product with leaves in the storage type, except that rows which
+ * are not 16-byte aligned, at n >= 192, take two aligned copies of
+ * ceil(n / 16)^2 * 256 elements; BF16 leaves stage every leaf operand as BF16
+ * planes, and their last pre-addition level writes those planes directly, so
+ * its FP32 sums take no workspace). */
 mf_status mf_workspace_bytes(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
                              size_t* bytes);
 
@@ -314,7 +321,8 @@ enum {
 mf_status mf_batch_create_form(int count, const int64_t* n, const mf_algo* const* algos, const int* depth,
                                const int* cutoff, int dtype, int form, mf_batch** out);
 
-/* Device workspace bytes a run needs (0 if every instance is classical). */
+/* Device workspace bytes a run needs (0 if every instance is a classical
+ * product that copies nothing, as mf_workspace_bytes). */
 mf_status mf_batch_workspace_bytes(const mf_batch* b, size_t* bytes);
 
 /* Run the batch on `stream`.  A, B, C: host arrays of `count` device

@@ -218,6 +218,7 @@ __device__ __forceinline__ void combine_acc_body(const CombArgs<T>& g, const Com
 template <class F>
 __device__ __forceinline__ void with_nin(int nin, F&& f) {
   switch (nin) {
+    case 1: f(std::integral_constant<int, 1>()); break;
     case 4: f(std::integral_constant<int, 4>()); break;
     case 7: f(std::integral_constant<int, 7>()); break;
     case 8: f(std::integral_constant<int, 8>()); break;

@@ -222,7 +222,7 @@ __global__ void fill_zero(int* p, int count) {
 }  // namespace
 
 bool batch_stage_supported(int nin, int nout_max, bool persistent) {
-  if (nin == 4 || nin == 7 || nin == 8 || nin == 9 || nin == 16) return true;
+  if (nin == 1 || nin == 4 || nin == 7 || nin == 8 || nin == 9 || nin == 16) return true;
   if (persistent) return false;
   return (nin == 27 && nout_max <= 9) || ((nin == 49 || nin == 64) && nout_max <= 16);
 }

@@ -262,6 +262,7 @@ static hipError_t launch_combine_t(const CombineStage& cs, const char* desc, con
   switch (cs.nin) {
 #define MF_COMB_CASE(N, V) \
   case N: hipLaunchKernelGGL((combine<T, N, V>), grid(V), dim3(256), 0, s, g); break;
+    MF_COMB_CASE(1, 4)
     MF_COMB_CASE(4, 4)
     MF_COMB_CASE(6, 4)
     MF_COMB_CASE(7, 4)
@@ -285,7 +286,8 @@ static hipError_t launch_combine_t(const CombineStage& cs, const char* desc, con
 
 bool combine_supported(int nin) {
   switch (nin) {
-    case 4: case 6: case 7: case 8: case 9: case 11: case 12: case 16: case 17: case 27: case 36: case 49: case 64:
+    case 1: case 4: case 6: case 7: case 8: case 9: case 11: case 12: case 16: case 17: case 27: case 36: case 49:
+    case 64:
     case 81:
       return true;
     default: return false;

@@ -130,6 +130,12 @@ bool bf16_leaves(int dtype) {
 
 int64_t leaf_granule(int dtype) { return bf16_leaves(dtype) ? kLeafTile : kLeafStep; }
 
+// Smallest M, N and K for which a classical product copies operands with
+// unaligned rows: below it the copy's launch costs more than the masked K
+// loop (FP64 n = 129: 0.035 ms without, 0.039 with the copy; n = 193: 0.048
+// and 0.043; n = 1037: 0.215 and 0.142).
+constexpr int64_t kAlignCopyMin = 192;
+
 // BF16 leaves: reserve the staged operands (see Plan::bf_base) after
 // everything else in the workspace, and list the outputs of every staging
 // set: ops_a[z] / ops_b[z] are the leaf blocks of product z.
@@ -194,6 +200,67 @@ mf_status build_classical(const Shape& sh, Plan* pl) {
   ed.coef = 1.0;
   pl->epis.push_back(ed);
   pl->group_beg = {0, 1};
+  // Caller rows of A or B that are not 16-byte aligned keep every GEMM tile
+  // on the masked K loop (the GEMM takes one alignment flag for both caller
+  // operands).  Past a minimum size both operands are then copied once into
+  // workspace blocks with rows of a multiple of 16 elements (a pre-addition
+  // stage of one-term combinations, zeros past the views), and the product
+  // reads the copies.  Blocks of a square product are square, the form
+  // batched stages take.
+  const bool unaligned = (sh.lda * (int64_t)pl->elem) % 16 != 0 || (sh.ldb * (int64_t)pl->elem) % 16 != 0;
+  if (!bf16_leaves(pl->dtype) && unaligned && std::min(sh.M, std::min(sh.N, sh.K)) >= kAlignCopyMin) {
+    const bool cube = sh.M == sh.N && sh.N == sh.K;
+    CombineStage st;
+    st.nin = 1;
+    int64_t ws = 0;
+    for (int side = 0; side < 2; ++side) {
+      const int64_t rows = side == 0 ? sh.M : sh.K, cols = side == 0 ? sh.K : sh.N;
+      int64_t br = round_up(rows, kLeafStep), bc = round_up(cols, kLeafStep);
+      if (cube) br = bc = std::max(br, bc);
+      Blk v;
+      v.src = side == 0 ? SRC_A : SRC_B;
+      v.off = 0;
+      v.ld = (int32_t)(side == 0 ? sh.lda : sh.ldb);
+      v.vr = (int32_t)rows;
+      v.vc = (int32_t)cols;
+      v.zero = false;
+      CombSet set{};
+      set.in_beg = (int32_t)st.ins.size();
+      set.out_beg = (int32_t)st.outs.size();
+      st.ins.push_back(as_input(v));
+      CombOut co{};
+      co.off = ws;
+      co.dst = SRC_WS;
+      co.ld = (int32_t)bc;
+      co.vr = (int32_t)br;
+      co.vc = (int32_t)bc;
+      co.coef_off = (int32_t)st.coef.size();
+      st.coef.push_back(1.0);
+      st.outs.push_back(co);
+      set.out_end = (int32_t)st.outs.size();
+      finish_set(&st, set, br, bc);
+      ws += round_up(br * bc, 64);
+      ProdDesc& q = pl->prods[0];
+      // the copy holds zeros past the view, so its padded inner size (and
+      // B's padded columns) are valid: whole K steps, and a moved edge tile
+      // of B starts on an aligned column
+      if (side == 0) {
+        q.a_src = SRC_WS;
+        q.a_off = co.off;
+        q.lda = (int32_t)bc;
+        q.a_vc = (int32_t)bc;
+      } else {
+        q.b_src = SRC_WS;
+        q.b_off = co.off;
+        q.ldb = (int32_t)bc;
+        q.b_vr = (int32_t)br;
+        q.b_vc = (int32_t)bc;
+      }
+    }
+    st.m = cube ? st.sets[0].rows : 0;
+    pl->pre.push_back(std::move(st));
+    pl->ws_bytes = (size_t)ws * pl->elem;
+  }
   if (bf16_leaves(pl->dtype)) {  // each operand is a set of one input (square plans only)
     const int64_t n = sh.M;
     Blk ops[2];
@@ -392,11 +459,12 @@ mf_status build(const Algo* algo, int depth, int cutoff, const Shape& sh, int dt
   }
 
   const bool kron3 = is_kron3(*seq[0]);
-  // A view of the caller's A (B) whose rows are not 16-byte aligned keeps
-  // every GEMM tile reading it on the masked path; at the first level such a
-  // view is copied into a workspace block (a one-term combination) instead of
+  // Caller rows of A or B that are not 16-byte aligned keep every GEMM tile
+  // reading a view of either caller operand on the masked path (the GEMM
+  // takes one alignment flag for both); at the first level such views are
+  // then copied into workspace blocks (one-term combinations) instead of
   // aliased, so that every leaf operand has aligned rows.
-  const bool unaligned_in[2] = {(sh.lda * (int64_t)pl->elem) % 16 != 0, (sh.ldb * (int64_t)pl->elem) % 16 != 0};
+  const bool unaligned_in = (sh.lda * (int64_t)pl->elem) % 16 != 0 || (sh.ldb * (int64_t)pl->elem) % 16 != 0;
   int64_t Pm = 1, Pk = 1, Pn = 1;
   for (const Algo* f : seq) {
     Pm *= f->m0;
@@ -540,7 +608,7 @@ mf_status build(const Algo* algo, int depth, int cutoff, const Shape& sh, int dt
             Blk child;
             if (nnz == 0) {
               child.zero = true;
-            } else if (nnz == 1 && !(lev == 1 && unaligned_in[side])) {
+            } else if (nnz == 1 && !(lev == 1 && unaligned_in)) {
               child = q[last];
               child.scale = b.scale * X[(size_t)last * R + r];
             } else {

@@ -418,6 +418,28 @@ def test_unaligned_rows_copy_aliased_views_at_the_first_level():
             == 8 * 2 * 3 * (2 * m2) ** 2)
 
 
+def test_classical_copies_unaligned_rows_past_the_threshold():
+    """A classical product over rows that are not 16-byte aligned copies both
+    operands once into square blocks of n rounded up to 16 (one pre-addition
+    stage of one-term combinations: the valid n x n read, the whole block
+    written), from n = 192 on; aligned rows and smaller sizes copy nothing."""
+    cases = [  # (n, dtype, copied)
+        (1037, mf.MF_F64, True), (1040, mf.MF_F64, False), (193, mf.MF_F64, True), (191, mf.MF_F64, False),
+        (129, mf.MF_F64, False), (1038, mf.MF_F32, True), (1036, mf.MF_F32, False), (1037, mf.MF_F32, True),
+    ]
+    w = mf.mf_algo_builtin("winograd")
+    for n, dtype, copied in cases:
+        eb = 8 if dtype == mf.MF_F64 else 4
+        b = 16 * -(-n // 16)
+        q = mf.mf_plan_query(None, 0, 0, n, dtype)
+        assert q["levels"] == 0 and q["products"] == 1, (n, dtype)
+        assert q["pre_stages"] == (1 if copied else 0), (n, dtype)
+        assert q["pre_bytes"] == (2 * eb * (n * n + b * b) if copied else 0), (n, dtype)
+        assert q["ws_bytes"] == mf.mf_workspace_bytes(w, 0, 0, n, dtype) == (2 * eb * b * b if copied else 0)
+        # the copies hold zeros past the views, so the product runs the padded K in whole steps
+        assert q["gemm_flops"] == 2.0 * (128 * -(-n // 128)) ** 2 * b, (n, dtype)
+
+
 @pytest.mark.parametrize("table", ["WINOGRAD", "STRASSEN_PAPER", "STRASSEN_1969"])
 def test_kron3_stored_operands_match_oracle_aliases(table):
     """The library stores every operand of <8,8,8;343> except the aliased

@@ -269,7 +269,8 @@ mf_status mf_fastmm_ws(const mf_algo* algo, int depth, int cutoff, const void* A
  * array on `stream`).  A request whose descriptors (rounded up to 256 bytes)
  * plus mf_workspace_bytes exceed the array is rejected with MF_ERR_SHAPE
  * before anything is enqueued (FP64, Strassen depth 1: up to n of about
- * 2900).  Every call on one GPU uses the same array, and nothing in it is
+ * 2900), unless it fits once operands whose rows are not 16-byte aligned are
+ * read in place instead of copied into aligned blocks (then it runs so).  Every call on one GPU uses the same array, and nothing in it is
  * assumed to be zero: calls on one stream are ordered, but calls that
  * overlap on one GPU (other streams, other host threads) race on it and give
  * wrong results.  The result is bitwise that of mf_fastmm with the same

@@ -210,6 +210,9 @@ struct StageOut {
 struct Shape {
   int64_t M = 0, N = 0, K = 0;
   int64_t lda = 0, ldb = 0, ldc = 0;
+  // operands with unaligned rows are read in place rather than copied into
+  // aligned workspace blocks (plans that must fit a fixed workspace)
+  bool no_copy = false;
   static Shape sq(int64_t n) { return Shape{n, n, n, n, n, n}; }
   bool square() const { return M == N && N == K && lda == M && ldb == M && ldc == M; }
 };

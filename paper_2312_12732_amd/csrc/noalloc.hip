@@ -63,8 +63,18 @@ extern "C" mf_status mf_fastmm_noalloc(const mf_algo* algo, int depth, int cutof
   st = plan_for(algo, depth, cutoff, n, dtype, &pl);
   if (st != MF_OK) return st;
   // [descriptor image | workspace], the workspace 256-byte aligned
-  const size_t img = (pl->image.size() + 255) / 256 * 256;
-  const size_t need = img + pl->ws_bytes;
+  size_t img = (pl->image.size() + 255) / 256 * 256;
+  size_t need = img + pl->ws_bytes;
+  if (need > kScratchBytes) {
+    // rows that are not 16-byte aligned: the plan that reads them in place
+    // takes no workspace blocks for copies of them
+    Shape sh = Shape::sq(n);
+    sh.no_copy = true;
+    st = get_plan(depth > 0 ? algo : nullptr, depth, cutoff, sh, dtype, kStandaloneMinWorkgroups, &pl);
+    if (st != MF_OK) return st;
+    img = (pl->image.size() + 255) / 256 * 256;
+    need = img + pl->ws_bytes;
+  }
   if (need > kScratchBytes)
     return fail(MF_ERR_SHAPE, "request needs " + std::to_string(need) + " bytes of scratch (descriptors " +
                                   std::to_string(pl->image.size()) + ", workspace " + std::to_string(pl->ws_bytes) +

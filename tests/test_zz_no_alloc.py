@@ -80,3 +80,27 @@ def test_noalloc_rejects_beyond_limit():
     Bi = mi.int_uniform(512, 12)
     ref, got = both(algo, 1, Ai.astype(np.float64), Bi.astype(np.float64))
     assert np.array_equal(got, om.classical_mm(Ai, Bi).astype(np.float64))
+
+
+def test_noalloc_reads_unaligned_rows_in_place_when_copies_do_not_fit():
+    """Odd n: mf_fastmm copies both operands into aligned blocks, which at
+    n = 4097 (FP64) need more than the scratch array; the allocation-free call
+    then reads the rows in place (same K steps over the same zero padding),
+    bitwise equal to mf_fastmm.  A smaller odd call after it copies again."""
+    w = mf.mf_algo_builtin("winograd")
+    n = 4097
+    assert mf.mf_workspace_bytes(w, 0, 0, n) > SCRATCH
+    print(f"noalloc classical unaligned n={n} (read in place)", flush=True)
+    Ai = mi.int_uniform(n, 21)
+    Bi = mi.int_uniform(n, 22)
+    ref, got = both(w, 0, Ai.astype(np.float64), Bi.astype(np.float64))
+    assert np.array_equal(ref, got)
+    rows = [0, 1, 2048, n - 1]
+    assert np.array_equal(got[rows], om.rows_reference(Ai, Bi, rows))
+    ref, got = both(w, 0, mi.uniform(n, 23), mi.uniform(n, 24))
+    assert np.array_equal(ref, got)
+    m = 1037
+    assert 0 < mf.mf_workspace_bytes(w, 0, 0, m) < SCRATCH
+    print(f"noalloc classical unaligned n={m} (copies)", flush=True)
+    ref, got = both(w, 0, mi.uniform(m, 25), mi.uniform(m, 26))
+    assert np.array_equal(ref, got)

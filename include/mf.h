@@ -192,9 +192,10 @@ mf_status mf_fastmm(const mf_algo* algo, int depth, int cutoff, const void* A, c
  * the classical blocked recursion of equation "recursion").  dtype as for
  * mf_fastmm.  BF16 leaves stage the operands in workspace from the library's
  * pool.  Rows that are not 16-byte aligned (n odd in FP64, not a multiple of
- * 4 in FP32) are copied, for n >= 192, into aligned workspace blocks from
- * that pool first (one launch; the GEMM then loads whole K steps straight
- * into LDS). */
+ * 4 in FP32, or a base of A or B off a 16-byte boundary) are copied, for
+ * n >= 192, into aligned workspace blocks from that pool first (one launch;
+ * the GEMM then loads whole K steps straight into LDS).  mf_fastmm copies
+ * them at its first level in the same cases. */
 mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int dtype, mf_stream stream);
 
 /* The general product C = alpha A B + beta C (Section 3 states the
@@ -212,8 +213,8 @@ mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int 
  * do; K = 0: MF_ERR_SHAPE.  C must not overlap A or B (MF_ERR_ARG, by the
  * byte ranges the three views span).  Workspace from the library's pool, as
  * for mf_fastmm; a classical product whose A or B rows are not 16-byte
- * aligned copies both operands into it first when M, N and K are all at
- * least 192. */
+ * aligned (leading dimension or base) copies both operands into it first
+ * when M, N and K are all at least 192. */
 mf_status mf_gemm(const mf_algo* algo, int depth, int cutoff, int64_t M, int64_t N, int64_t K, double alpha,
                   const void* A, int64_t lda, const void* B, int64_t ldb, double beta, void* C, int64_t ldc,
                   int dtype, mf_stream stream);
@@ -221,7 +222,8 @@ mf_status mf_gemm(const mf_algo* algo, int depth, int cutoff, int64_t M, int64_t
 /* Bytes of device workspace mf_fastmm_ws needs for this request (0 for a
  * classical product with leaves in the storage type, except that rows which
  * are not 16-byte aligned, at n >= 192, take two aligned copies of
- * ceil(n / 16)^2 * 256 elements; BF16 leaves stage every leaf operand as BF16
+ * ceil(n / 16)^2 * 256 elements (mf_fastmm_ws plans from n alone, so
+ * operand bases off a 16-byte boundary are read in place there); BF16 leaves stage every leaf operand as BF16
  * planes, and their last pre-addition level writes those planes directly, so
  * its FP32 sums take no workspace). */
 mf_status mf_workspace_bytes(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,

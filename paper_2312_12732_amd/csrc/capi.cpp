@@ -75,9 +75,11 @@ mf_status check_request(const mf_algo* algo, bool need_algo, int depth, int cuto
   return MF_OK;
 }
 
-mf_status plan_for(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
-                   std::shared_ptr<const Plan>* pl) {
-  return get_plan(depth > 0 ? algo : nullptr, depth, cutoff, n, dtype, kStandaloneMinWorkgroups, pl);
+mf_status plan_for(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype, std::shared_ptr<const Plan>* pl,
+                   bool copy_in) {
+  Shape sh = Shape::sq(n);
+  sh.copy_in = copy_in;
+  return get_plan(depth > 0 ? algo : nullptr, depth, cutoff, sh, dtype, kStandaloneMinWorkgroups, pl);
 }
 
 namespace {
@@ -428,7 +430,7 @@ mf_status mf_fastmm(const mf_algo* algo, int depth, int cutoff, const void* A, c
   mf_status st = check_request(algo, true, depth, cutoff, A, B, C, n, dtype);
   if (st != MF_OK || n == 0) return st;
   std::shared_ptr<const Plan> pl;
-  st = plan_for(algo, depth, cutoff, n, dtype, &pl);
+  st = plan_for(algo, depth, cutoff, n, dtype, &pl, !aligned16(A) || !aligned16(B));
   if (st != MF_OK) return st;
   return run_with_pool(*pl, A, B, C, static_cast<hipStream_t>(stream));
 }
@@ -438,7 +440,7 @@ mf_status mf_classical_mm(const void* A, const void* B, void* C, int64_t n, int 
   mf_status st = check_request(nullptr, false, 0, 0, A, B, C, n, dtype);
   if (st != MF_OK || n == 0) return st;
   std::shared_ptr<const Plan> pl;
-  st = get_plan(nullptr, 0, 0, n, dtype, kStandaloneMinWorkgroups, &pl);
+  st = plan_for(nullptr, 0, 0, n, dtype, &pl, !aligned16(A) || !aligned16(B));
   if (st != MF_OK) return st;
   return run_with_pool(*pl, A, B, C, static_cast<hipStream_t>(stream));
 }
@@ -524,6 +526,7 @@ mf_status mf_gemm(const mf_algo* algo, int depth, int cutoff, int64_t M, int64_t
   sh.lda = lda;
   sh.ldb = ldb;
   sh.ldc = ldc;
+  sh.copy_in = !aligned16(A) || !aligned16(B);
   std::shared_ptr<const Plan> pl;
   mf_status st = get_plan(depth > 0 ? algo : nullptr, depth, cutoff, sh, dtype, kStandaloneMinWorkgroups, &pl);
   if (st != MF_OK) return st;

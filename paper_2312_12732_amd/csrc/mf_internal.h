@@ -213,6 +213,9 @@ struct Shape {
   // operands with unaligned rows are read in place rather than copied into
   // aligned workspace blocks (plans that must fit a fixed workspace)
   bool no_copy = false;
+  // the caller's A or B base is not 16-byte aligned: copy as for unaligned
+  // rows (plans whose workspace the library allocates)
+  bool copy_in = false;
   static Shape sq(int64_t n) { return Shape{n, n, n, n, n, n}; }
   bool square() const { return M == N && N == K && lda == M && ldb == M && ldc == M; }
 };
@@ -413,9 +416,11 @@ bool batch_stage_supported(int nin, int nout_max, bool persistent);
 // thread's error message on failure).
 mf_status check_request(const mf_algo* algo, bool need_algo, int depth, int cutoff, const void* A, const void* B,
                         void* C, int64_t n, int dtype);
-// The plan of a standalone product (classical when depth is 0).
+// The plan of a standalone product (classical when depth is 0); copy_in:
+// the caller's A or B base is not 16-byte aligned, and the call allocates
+// the workspace itself.
 mf_status plan_for(const mf_algo* algo, int depth, int cutoff, int64_t n, int dtype,
-                   std::shared_ptr<const Plan>* pl);
+                   std::shared_ptr<const Plan>* pl, bool copy_in = false);
 // Enqueues the phases of one product on stream s.  desc: device address of
 // a copy of the plan's descriptor image; ws: the plan's workspace.  may_time:
 // whether the call may record phase-timing events (creating them).

@@ -60,7 +60,8 @@ extern "C" mf_status mf_fastmm_noalloc(const mf_algo* algo, int depth, int cutof
   mf_status st = check_request(algo, true, depth, cutoff, A, B, C, n, dtype);
   if (st != MF_OK || n == 0) return st;
   std::shared_ptr<const Plan> pl;
-  st = plan_for(algo, depth, cutoff, n, dtype, &pl);
+  st = plan_for(algo, depth, cutoff, n, dtype, &pl,
+                ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) != 0);
   if (st != MF_OK) return st;
   // [descriptor image | workspace], the workspace 256-byte aligned
   size_t img = (pl->image.size() + 255) / 256 * 256;

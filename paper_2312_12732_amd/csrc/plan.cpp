@@ -207,8 +207,8 @@ mf_status build_classical(const Shape& sh, Plan* pl) {
   // stage of one-term combinations, zeros past the views), and the product
   // reads the copies.  Blocks of a square product are square, the form
   // batched stages take.
-  const bool unaligned =
-      !sh.no_copy && ((sh.lda * (int64_t)pl->elem) % 16 != 0 || (sh.ldb * (int64_t)pl->elem) % 16 != 0);
+  const bool unaligned = !sh.no_copy && (sh.copy_in || (sh.lda * (int64_t)pl->elem) % 16 != 0 ||
+                                         (sh.ldb * (int64_t)pl->elem) % 16 != 0);
   if (!bf16_leaves(pl->dtype) && unaligned && std::min(sh.M, std::min(sh.N, sh.K)) >= kAlignCopyMin) {
     const bool cube = sh.M == sh.N && sh.N == sh.K;
     CombineStage st;
@@ -465,8 +465,8 @@ mf_status build(const Algo* algo, int depth, int cutoff, const Shape& sh, int dt
   // takes one alignment flag for both); at the first level such views are
   // then copied into workspace blocks (one-term combinations) instead of
   // aliased, so that every leaf operand has aligned rows.
-  const bool unaligned_in =
-      !sh.no_copy && ((sh.lda * (int64_t)pl->elem) % 16 != 0 || (sh.ldb * (int64_t)pl->elem) % 16 != 0);
+  const bool unaligned_in = !sh.no_copy && (sh.copy_in || (sh.lda * (int64_t)pl->elem) % 16 != 0 ||
+                                            (sh.ldb * (int64_t)pl->elem) % 16 != 0);
   int64_t Pm = 1, Pk = 1, Pn = 1;
   for (const Algo* f : seq) {
     Pm *= f->m0;
@@ -922,10 +922,11 @@ struct Key {
   uint64_t algo;
   int levels, dtype, device;
   int64_t M, N, K, lda, ldb, ldc, min_wg;
-  bool no_copy;
+  bool no_copy, copy_in;
   bool operator<(const Key& o) const {
-    return std::tie(algo, levels, dtype, device, M, N, K, lda, ldb, ldc, min_wg, no_copy) <
-           std::tie(o.algo, o.levels, o.dtype, o.device, o.M, o.N, o.K, o.lda, o.ldb, o.ldc, o.min_wg, o.no_copy);
+    return std::tie(algo, levels, dtype, device, M, N, K, lda, ldb, ldc, min_wg, no_copy, copy_in) <
+           std::tie(o.algo, o.levels, o.dtype, o.device, o.M, o.N, o.K, o.lda, o.ldb, o.ldc, o.min_wg, o.no_copy,
+                    o.copy_in);
   }
 };
 
@@ -976,7 +977,7 @@ mf_status get_plan(const mf_algo* algo, int depth, int cutoff, const Shape& sh, 
   const int levels =
       algo ? levels_for(sh.M, sh.K, sh.N, algo->a.m0, algo->a.k0, algo->a.n0, algo->a.R, depth, cutoff) : 0;
   const Key key{levels == 0 ? 0 : algo->id, levels, dtype, current_device(), sh.M, sh.N, sh.K, sh.lda, sh.ldb,
-                sh.ldc, levels == 0 ? 0 : min_wg, sh.no_copy};
+                sh.ldc, levels == 0 ? 0 : min_wg, sh.no_copy, sh.copy_in};
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = cache().find(key);

@@ -1,9 +1,10 @@
 """GPU parity of classical products over rows that are not 16-byte aligned
-(odd n in FP64, n not a multiple of 4 in FP32, odd leading dimensions),
-which copy both operands into aligned workspace blocks before the GEMM from
-n = 192 on: integer inputs bit-exact against the CPU oracle, standalone,
-through mf_gemm with alpha / beta and one-sided odd strides, and as batch
-instances in both batch forms; sizes on either side of the threshold."""
+(odd n in FP64, n not a multiple of 4 in FP32, odd leading dimensions, or
+operand bases 8 bytes past an aligned address), which copy both operands
+into aligned workspace blocks before the GEMM from n = 192 on: integer
+inputs bit-exact against the CPU oracle, standalone, through mf_gemm with
+alpha / beta and one-sided odd strides, and as batch instances in both
+batch forms; sizes on either side of the threshold."""
 import numpy as np
 import pytest
 
@@ -70,3 +71,40 @@ def test_batch_classical_copies_int_exact(form):
     assert not b.aborted()
     for A, B, C in zip(As, Bs, dC):
         assert np.array_equal(C.cpu().numpy(), om.classical_mm(A, B).astype(np.float64))
+
+
+def offset_view(x, dt, ld):
+    """x as a view with leading dimension ld whose base lies 8 bytes past
+    the (256-byte aligned) start of its allocation."""
+    rows, cols = x.shape
+    shift = 8 // torch.tensor([], dtype=dt).element_size()
+    buf = torch.zeros(rows * ld + shift, dtype=dt, device="cuda:0")
+    v = buf[shift:].view(rows, ld)[:, :cols]
+    v.copy_(dev(x.astype(np.float64), dt))
+    assert v.data_ptr() % 16 == 8
+    return v
+
+
+@pytest.mark.parametrize("n,dt", [(1024, torch.float64), (640, torch.float32)])
+def test_offset_bases_int_exact(n, dt):
+    """Square operands at bases 8 bytes off alignment (rows aligned): the
+    classical product and Winograd depth 1 copy them first; mf_gemm takes a
+    rectangular offset view of A."""
+    print(f"offset bases n={n} {dt}", flush=True)
+    A = mi.int_uniform(n, 80 + n)
+    B = mi.int_uniform(n, 90 + n)
+    want = om.classical_mm(A, B).astype(np.float64)
+    dA, dB = offset_view(A, dt, n), dev(B.astype(np.float64), dt)
+    for run in (lambda C: mf.mf_classical_mm(dA, dB, C),
+                lambda C: mf.mf_fastmm(mf.mf_algo_builtin("winograd"), 1, 0, dA, dB, C)):
+        dC = torch.full((n, n), float("nan"), dtype=dt, device="cuda:0")
+        run(dC)
+        torch.cuda.synchronize()
+        assert np.array_equal(dC.cpu().numpy().astype(np.float64), want)
+    M, K, N = 500, 600, 700
+    Ar = mi.int_uniform_rect(M, K, 81)
+    Br = mi.int_uniform_rect(K, N, 82)
+    dC = torch.full((M, N), float("nan"), dtype=dt, device="cuda:0")
+    mf.mf_gemm(None, 0, 0, offset_view(Ar, dt, K + 8), offset_view(Br, dt, N), dC)
+    torch.cuda.synchronize()
+    assert np.array_equal(dC.cpu().numpy().astype(np.float64), om.classical_mm(Ar, Br).astype(np.float64))

@@ -104,3 +104,24 @@ def test_noalloc_reads_unaligned_rows_in_place_when_copies_do_not_fit():
     print(f"noalloc classical unaligned n={m} (copies)", flush=True)
     ref, got = both(w, 0, mi.uniform(m, 25), mi.uniform(m, 26))
     assert np.array_equal(ref, got)
+
+
+def test_noalloc_offset_bases_equal_fastmm():
+    """Operand bases 8 bytes off alignment: the allocation-free call copies
+    them as mf_fastmm does (the copies fit the array), bitwise equal."""
+    w = mf.mf_algo_builtin("winograd")
+    n = 768
+    print(f"noalloc offset bases n={n}", flush=True)
+    buf_a = torch.zeros(n * n + 1, dtype=torch.float64, device="cuda:0")
+    buf_b = torch.zeros(n * n + 1, dtype=torch.float64, device="cuda:0")
+    dA, dB = buf_a[1:].view(n, n), buf_b[1:].view(n, n)
+    dA.copy_(dev(mi.uniform(n, 27)))
+    dB.copy_(dev(mi.uniform(n, 28)))
+    assert dA.data_ptr() % 16 == 8
+    for depth in (0, 1):
+        ref = torch.full_like(dA, float("nan"))
+        got = torch.full_like(dA, float("nan"))
+        mf.mf_fastmm(w, depth, 0, dA, dB, ref)
+        mf.mf_fastmm_noalloc(w, depth, 0, dA, dB, got)
+        torch.cuda.synchronize()
+        assert torch.equal(ref, got)

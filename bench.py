@@ -80,6 +80,16 @@ def parse():
     return ap.parse_args()
 
 
+# The paper's own measurements, on other hardware: context for the line, not a
+# target (its experiments section; it prints no GPU times to compare with).
+PAPER_CONTEXT = {
+    "gpu": "Radeon VII (Vega 20; 3.5 TFLOP/s FP64 peak, 1 TB/s HBM2), rocBLAS GEMM and GEMA calls, n up to 24012: "
+           "Strassen and <4,4,4;49> ahead of DGEMM",
+    "cpu": "16-core Threadripper: classical GEMM about 30 GFLOP/s on one core, where Strassen and <4,4,4;49> win "
+           "from n = 2500; no fast algorithm wins with the GEMM on all 16 cores",
+}
+
+
 def kernel_sha() -> str:
     """Hash of the sources that define the grouped GEMM kernel."""
     h = hashlib.sha256()
@@ -227,6 +237,7 @@ def run_square(args):
                       "postadd": round(phase_avg[2], 4)},
         "workspace_bytes": mat,
         "roofline": roofline,
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.no_cpu_baseline:
         C_host = C.cpu().numpy()
